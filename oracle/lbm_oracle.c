@@ -1,0 +1,475 @@
+/*
+ * Plain FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY (see lbm_oracle.h).
+ *
+ * Each function follows one passage of arXiv:1202.6130 and says which.  The
+ * model is the paper's wall model on a D2Q9 Shan-Chen fluid:
+ *   - fluid-fluid force      : eq. force_SC, written with an explicit coupling
+ *                              G:  F_FF = -G psi(x) sum_i w_i psi(x+c_i) c_i,
+ *                              psi = 1 - exp(-rho)  (the paper's form is G=-1)
+ *   - fluid-solid long range : eq. force_SC_FS with eq. pseudopotential, core
+ *                              repulsive and tail attractive:
+ *                              F_LR = rho sum_i w_i [G_A psiA - G_R psiR](x+c_i) c_i
+ *   - short-range exchange   : eq. wall_shift, with the velocity shift read in
+ *                              velocity units:  dF_S = phi^eps [rho(U - u) - F_FF]
+ *   - forcing                : exact difference method (Sec. II.B):
+ *                              df = feq(rho, u*) - feq(rho, u), u* = u + F/rho
+ *   - collision              : BGK (eq. BE-BGK) with feq from eq. f2
+ *   - streaming              : f_i(x + c_i, t+1) = f'_i(x, t)  (Sec. II.A)
+ */
+#include "lbm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+const int ORC_CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+const int ORC_CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+const double ORC_W[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
+                         1.0 / 9.0,  1.0 / 9.0,  1.0 / 36.0,
+                         1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+const double ORC_THETA = 1.0 / 3.0;
+
+static long node(int nx, int ny, int x, int y)
+{
+    /* periodic wrap in both directions */
+    x = ((x % nx) + nx) % nx;
+    y = ((y % ny) + ny) % ny;
+    return (long)y * nx + x;
+}
+
+/* Eq. f2 at equilibrium: f_i = w_i [M0 + M1.c/theta + (M2 - M0 theta I):(cc - theta I)/(2 theta^2)]
+ * with M0 = rho, M1 = rho u, M2 = rho u u + rho theta I (eqs. M0-M2, feqc). */
+void orc_equilibrium(double rho, double ux, double uy, double feq[9])
+{
+    const double th = ORC_THETA;
+    for (int i = 0; i < 9; ++i) {
+        double cx = ORC_CX[i], cy = ORC_CY[i];
+        double M1c = rho * (ux * cx + uy * cy);
+        /* (M2 - rho theta I) : (c c - theta I) with M2 - rho theta I = rho u u */
+        double uucc = rho * (ux * ux * (cx * cx - th) + 2.0 * ux * uy * cx * cy +
+                             uy * uy * (cy * cy - th));
+        feq[i] = ORC_W[i] * (rho + M1c / th + uucc / (2.0 * th * th));
+    }
+}
+
+/* T(s; w) = (1 - tanh(s/w))/2: 1 deep in the solid, 1/2 on the face, 0 in the
+ * fluid bulk. */
+static double tanh_profile(double s, double w) { return 0.5 * (1.0 - tanh(s / w)); }
+
+void orc_flat_slab_walls(int nx, int ny, int P, double width, double core,
+                         double tail, double *phi, double *psiR, double *psiA)
+{
+    for (int y = 0; y < ny; ++y) {
+        double s;
+        if (P <= 0) {
+            s = INFINITY; /* no solid anywhere */
+        } else if (y <= ny - P) {
+            /* fluid gap (faces on rows 0 and ny-P included) */
+            int a = y, b = ny - P - y;
+            s = (double)(a < b ? a : b);
+        } else {
+            /* inside the solid band */
+            int a = y - (ny - P), b = ny - y;
+            s = -(double)(a < b ? a : b);
+        }
+        for (int x = 0; x < nx; ++x) {
+            long n = (long)y * nx + x;
+            double tp = isinf(s) ? 0.0 : tanh_profile(s, width);
+            double tr = isinf(s) ? 0.0 : tanh_profile(s, core);
+            double tt = isinf(s) ? 0.0 : tanh_profile(s, tail);
+            phi[n] = tp;
+            psiR[n] = tr;
+            psiA[n] = tt - tr;
+        }
+    }
+}
+
+void orc_init(const orc_params *p, const double *rho0, const double *ux0,
+              const double *uy0, double *f)
+{
+    long N = (long)p->nx * p->ny;
+    for (long n = 0; n < N; ++n) {
+        double ux = ux0 ? ux0[n] : 0.0;
+        double uy = uy0 ? uy0[n] : 0.0;
+        orc_equilibrium(rho0[n], ux, uy, &f[n * 9]);
+    }
+}
+
+/* Eqs. M0 and M1: zeroth and first moments of the populations. */
+static void moments(const double *fn, double *rho, double *jx, double *jy)
+{
+    double r = 0.0, a = 0.0, b = 0.0;
+    for (int i = 0; i < 9; ++i) {
+        r += fn[i];
+        a += fn[i] * ORC_CX[i];
+        b += fn[i] * ORC_CY[i];
+    }
+    *rho = r;
+    *jx = a;
+    *jy = b;
+}
+
+/* Shan-Chen pseudo-potential psi(rho) = 1 - exp(-rho). */
+static double psi_of(double rho) { return 1.0 - exp(-rho); }
+
+void orc_forces(const orc_params *p, const double *phi, const double *psiR,
+                const double *psiA, const double *f, double *rho_o, double *ux_o,
+                double *uy_o, double *Fff, double *Flr, double *dFs,
+                double *Ftot, double *usx, double *usy)
+{
+    const int nx = p->nx, ny = p->ny;
+    const long N = (long)nx * ny;
+    double *rho = (double *)malloc(sizeof(double) * N);
+    double *psi = (double *)malloc(sizeof(double) * N);
+    double *psiFS = (double *)malloc(sizeof(double) * N);
+
+    /* moments and pseudo-potentials at every node */
+    for (long n = 0; n < N; ++n) {
+        double jx, jy;
+        moments(&f[n * 9], &rho[n], &jx, &jy);
+        psi[n] = psi_of(rho[n]);
+        /* eq. pseudopotential, with the repulsive core entering with the
+         * opposite sign of the attractive tail */
+        psiFS[n] = p->G_A * psiA[n] - p->G_R * psiR[n];
+    }
+
+    for (int y = 0; y < ny; ++y) {
+        for (int x = 0; x < nx; ++x) {
+            long n = (long)y * nx + x;
+            double r, jx, jy;
+            moments(&f[n * 9], &r, &jx, &jy);
+            double ux = jx / r, uy = jy / r;
+
+            /* eq. force_SC: fluid-fluid force from neighbour pseudo-potentials */
+            double sffx = 0.0, sffy = 0.0;
+            /* eq. force_SC_FS, first term: long-range fluid-solid force */
+            double sfsx = 0.0, sfsy = 0.0;
+            for (int i = 0; i < 9; ++i) {
+                long m = node(nx, ny, x + ORC_CX[i], y + ORC_CY[i]);
+                sffx += ORC_W[i] * psi[m] * ORC_CX[i];
+                sffy += ORC_W[i] * psi[m] * ORC_CY[i];
+                sfsx += ORC_W[i] * psiFS[m] * ORC_CX[i];
+                sfsy += ORC_W[i] * psiFS[m] * ORC_CY[i];
+            }
+            double ffx = -p->G * psi[n] * sffx;
+            double ffy = -p->G * psi[n] * sffy;
+            double lrx = r * sfsx;
+            double lry = r * sfsy;
+
+            /* eq. wall_shift: dF_S = rho phi^eps du_wall, du_wall = U - u - F_FF/rho */
+            double pe = pow(phi[n], p->eps);
+            double dsx = pe * (r * (p->U_wall[0] - ux) - ffx);
+            double dsy = pe * (r * (p->U_wall[1] - uy) - ffy);
+
+            double Fx = ffx + lrx + dsx + p->F_ext[0];
+            double Fy = ffy + lry + dsy + p->F_ext[1];
+
+            if (rho_o) rho_o[n] = r;
+            if (ux_o) ux_o[n] = ux;
+            if (uy_o) uy_o[n] = uy;
+            if (Fff) { Fff[2 * n] = ffx; Fff[2 * n + 1] = ffy; }
+            if (Flr) { Flr[2 * n] = lrx; Flr[2 * n + 1] = lry; }
+            if (dFs) { dFs[2 * n] = dsx; dFs[2 * n + 1] = dsy; }
+            if (Ftot) { Ftot[2 * n] = Fx; Ftot[2 * n + 1] = Fy; }
+            /* exact difference method: shifted velocity u* = u + g dt, g = F/rho */
+            if (usx) usx[n] = ux + Fx / r;
+            if (usy) usy[n] = uy + Fy / r;
+        }
+    }
+    free(rho);
+    free(psi);
+    free(psiFS);
+}
+
+void orc_collide(const orc_params *p, const double *phi, const double *psiR,
+                 const double *psiA, const double *f, double *fpost)
+{
+    const long N = (long)p->nx * p->ny;
+    double *rho = (double *)malloc(sizeof(double) * N);
+    double *ux = (double *)malloc(sizeof(double) * N);
+    double *uy = (double *)malloc(sizeof(double) * N);
+    double *usx = (double *)malloc(sizeof(double) * N);
+    double *usy = (double *)malloc(sizeof(double) * N);
+    orc_forces(p, phi, psiR, psiA, f, rho, ux, uy, NULL, NULL, NULL, NULL, usx, usy);
+    for (long n = 0; n < N; ++n) {
+        double feq_u[9], feq_s[9];
+        orc_equilibrium(rho[n], ux[n], uy[n], feq_u);
+        orc_equilibrium(rho[n], usx[n], usy[n], feq_s);
+        for (int i = 0; i < 9; ++i) {
+            double fi = f[n * 9 + i];
+            /* BGK relaxation (eq. BE-BGK) plus the EDM force term */
+            fpost[n * 9 + i] = fi - (fi - feq_u[i]) / p->tau + (feq_s[i] - feq_u[i]);
+        }
+    }
+    free(rho);
+    free(ux);
+    free(uy);
+    free(usx);
+    free(usy);
+}
+
+void orc_stream(int nx, int ny, const double *fpost, double *fout)
+{
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
+            for (int i = 0; i < 9; ++i) {
+                long src = (long)y * nx + x;
+                long dst = node(nx, ny, x + ORC_CX[i], y + ORC_CY[i]);
+                fout[dst * 9 + i] = fpost[src * 9 + i];
+            }
+}
+
+void orc_step(const orc_params *p, const double *phi, const double *psiR,
+              const double *psiA, const double *f_in, double *f_out)
+{
+    const long N = (long)p->nx * p->ny;
+    double *fpost = (double *)malloc(sizeof(double) * N * 9);
+    orc_collide(p, phi, psiR, psiA, f_in, fpost);
+    orc_stream(p->nx, p->ny, fpost, f_out);
+    free(fpost);
+}
+
+int orc_run(const orc_params *p, const double *phi, const double *psiR,
+            const double *psiA, double *f, long nsteps)
+{
+    const long N = (long)p->nx * p->ny;
+    double *g = (double *)malloc(sizeof(double) * N * 9);
+    if (!g) return -1;
+    for (long s = 0; s < nsteps; ++s) {
+        orc_step(p, phi, psiR, psiA, f, g);
+        memcpy(f, g, sizeof(double) * N * 9);
+    }
+    free(g);
+    return 0;
+}
+
+void orc_macros(const orc_params *p, const double *phi, const double *psiR,
+                const double *psiA, const double *f, double *rho, double *ux,
+                double *uy, double totals[3])
+{
+    const long N = (long)p->nx * p->ny;
+    double *r = (double *)malloc(sizeof(double) * N);
+    double *vx = (double *)malloc(sizeof(double) * N);
+    double *vy = (double *)malloc(sizeof(double) * N);
+    double *F = (double *)malloc(sizeof(double) * N * 2);
+    orc_forces(p, phi, psiR, psiA, f, r, vx, vy, NULL, NULL, NULL, F, NULL, NULL);
+    double sr = 0.0, sx = 0.0, sy = 0.0;
+    for (long n = 0; n < N; ++n) {
+        if (rho) rho[n] = r[n];
+        /* velocity averaged over the step: (j + F/2)/rho */
+        if (ux) ux[n] = vx[n] + 0.5 * F[2 * n] / r[n];
+        if (uy) uy[n] = vy[n] + 0.5 * F[2 * n + 1] / r[n];
+        sr += r[n];
+        sx += r[n] * vx[n];
+        sy += r[n] * vy[n];
+    }
+    if (totals) {
+        totals[0] = sr;
+        totals[1] = sx;
+        totals[2] = sy;
+    }
+    free(r);
+    free(vx);
+    free(vy);
+    free(F);
+}
+
+long orc_isoline_points(int nx, int ny, const double *rho, const double *phi,
+                        double iso, double phi_max, double *px, double *py,
+                        long cap)
+{
+    long k = 0;
+    for (int y = 0; y < ny; ++y) {
+        for (int x = 0; x < nx; ++x) {
+            long a = (long)y * nx + x;
+            if (!(phi[a] < phi_max)) continue;
+            /* edge to the right neighbour (periodic in x) */
+            long b = (long)y * nx + (x + 1) % nx;
+            if (phi[b] < phi_max && ((rho[a] >= iso) != (rho[b] >= iso))) {
+                double t = (iso - rho[a]) / (rho[b] - rho[a]);
+                if (k < cap) { px[k] = x + t; py[k] = y; }
+                ++k;
+            }
+            /* edge to the upper neighbour (no wrap in y) */
+            if (y + 1 < ny) {
+                long c = (long)(y + 1) * nx + x;
+                if (phi[c] < phi_max && ((rho[a] >= iso) != (rho[c] >= iso))) {
+                    double t = (iso - rho[a]) / (rho[c] - rho[a]);
+                    if (k < cap) { px[k] = x; py[k] = y + t; }
+                    ++k;
+                }
+            }
+        }
+    }
+    return k;
+}
+
+/* Solve the 3x3 system A z = b by Gaussian elimination with partial pivoting.
+ * Returns -1 if A is singular to working precision. */
+static int solve3(double A[3][3], double b[3], double z[3])
+{
+    double scale = 0.0;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) scale = fmax(scale, fabs(A[r][c]));
+    if (!(scale > 0.0)) return -1;
+    for (int col = 0; col < 3; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 3; ++r)
+            if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+        if (fabs(A[piv][col]) <= 1e-14 * scale) return -1;
+        if (piv != col) {
+            for (int c = 0; c < 3; ++c) {
+                double t = A[col][c]; A[col][c] = A[piv][c]; A[piv][c] = t;
+            }
+            double t = b[col]; b[col] = b[piv]; b[piv] = t;
+        }
+        for (int r = col + 1; r < 3; ++r) {
+            double m = A[r][col] / A[col][col];
+            for (int c = col; c < 3; ++c) A[r][c] -= m * A[col][c];
+            b[r] -= m * b[col];
+        }
+    }
+    for (int r = 2; r >= 0; --r) {
+        double s = b[r];
+        for (int c = r + 1; c < 3; ++c) s -= A[r][c] * z[c];
+        z[r] = s / A[r][r];
+    }
+    return 0;
+}
+
+int orc_circle_fit(long n, const double *px, const double *py, double out[3])
+{
+    if (n < 3) return -1;
+    /* work about the centroid for conditioning */
+    double mx = 0.0, my = 0.0;
+    for (long k = 0; k < n; ++k) { mx += px[k]; my += py[k]; }
+    mx /= n;
+    my /= n;
+
+    /* Kasa: minimise sum (x^2 + y^2 + D x + E y + F)^2 over (D, E, F) */
+    double A[3][3] = {{0}}, b[3] = {0}, z[3];
+    for (long k = 0; k < n; ++k) {
+        double x = px[k] - mx, y = py[k] - my, q = x * x + y * y;
+        double v[3] = {x, y, 1.0};
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c) A[r][c] += v[r] * v[c];
+            b[r] -= v[r] * q;
+        }
+    }
+    if (solve3(A, b, z) != 0) return -1;
+    double xc = -0.5 * z[0], yc = -0.5 * z[1];
+    double R2 = xc * xc + yc * yc - z[2];
+    if (!(R2 > 0.0)) return -1;
+    double R = sqrt(R2);
+
+    /* Gauss-Newton on r_k = |p_k - c| - R */
+    for (int it = 0; it < 20; ++it) {
+        double J[3][3] = {{0}}, g[3] = {0}, d[3];
+        for (long k = 0; k < n; ++k) {
+            double dx = px[k] - mx - xc, dy = py[k] - my - yc;
+            double dist = sqrt(dx * dx + dy * dy);
+            if (!(dist > 0.0)) return -1;
+            double jr[3] = {-dx / dist, -dy / dist, -1.0};
+            double res = dist - R;
+            for (int r = 0; r < 3; ++r) {
+                for (int c = 0; c < 3; ++c) J[r][c] += jr[r] * jr[c];
+                g[r] -= jr[r] * res;
+            }
+        }
+        if (solve3(J, g, d) != 0) return -1;
+        xc += d[0];
+        yc += d[1];
+        R += d[2];
+        if (fabs(d[0]) + fabs(d[1]) + fabs(d[2]) < 1e-13 * (1.0 + fabs(R))) break;
+    }
+    if (!(R > 0.0) || !isfinite(R)) return -1;
+    out[0] = xc + mx;
+    out[1] = yc + my;
+    out[2] = R;
+    return 0;
+}
+
+int orc_contact_angle(const orc_params *p, const double *phi,
+                      const double *psiR, const double *psiA, const double *f,
+                      double iso, double y_ref, double out[4])
+{
+    const long N = (long)p->nx * p->ny;
+    double *rho = (double *)malloc(sizeof(double) * N);
+    orc_macros(p, phi, psiR, psiA, f, rho, NULL, NULL, NULL);
+    long cap = 2 * N;
+    double *px = (double *)malloc(sizeof(double) * cap);
+    double *py = (double *)malloc(sizeof(double) * cap);
+    /* region III: hydrodynamic region, phi < 0.01 (Sec. III.C) */
+    long n = orc_isoline_points(p->nx, p->ny, rho, phi, iso, 0.01, px, py, cap);
+    int rc = -1;
+    double c[3];
+    if (n >= 16 && orc_circle_fit(n, px, py, c) == 0) {
+        /* theta_Y = acos(1 - h/R) with h = yc + R - y_ref (Sec. III.B) */
+        double cs = (y_ref - c[1]) / c[2];
+        if (cs > 1.0) cs = 1.0;
+        if (cs < -1.0) cs = -1.0;
+        out[0] = acos(cs) * 180.0 / M_PI;
+        out[1] = c[2];
+        out[2] = c[0];
+        out[3] = c[1];
+        rc = 0;
+    }
+    free(rho);
+    free(px);
+    free(py);
+    return rc;
+}
+
+int orc_slip_length(const orc_params *p, const double *phi, const double *psiR,
+                    const double *psiA, const double *f, int P, double width,
+                    double out[3])
+{
+    const int nx = p->nx, ny = p->ny;
+    const long N = (long)nx * ny;
+    double *ux = (double *)malloc(sizeof(double) * N);
+    orc_macros(p, phi, psiR, psiA, f, NULL, ux, NULL, NULL);
+    int top = ny - P;           /* row of the upper face */
+    double yc = 0.5 * top;      /* centre of the gap, for conditioning */
+    double A[3][3] = {{0}}, b[3] = {0}, z[3];
+    int rows = 0;
+    for (int y = 0; y <= top; ++y) {
+        /* region III rows only; phi is uniform along a row for a flat slab */
+        if (!(phi[(long)y * nx] < 0.01)) continue;
+        double m = 0.0;
+        for (int x = 0; x < nx; ++x) m += ux[(long)y * nx + x];
+        m /= nx;
+        double t = y - yc;
+        double v[3] = {1.0, t, t * t};
+        for (int r = 0; r < 3; ++r) {
+            for (int c = 0; c < 3; ++c) A[r][c] += v[r] * v[c];
+            b[r] += v[r] * m;
+        }
+        ++rows;
+    }
+    free(ux);
+    if (rows < 3 || solve3(A, b, z) != 0) return -1;
+    /* hydrodynamic boundary: T(s; width) = 0.01 -> s = width * atanh(0.98) */
+    double sw = width * atanh(0.98);
+    double yb = sw - yc, yt = (top - sw) - yc;
+    double ub = z[0] + z[1] * yb + z[2] * yb * yb;
+    double ut = z[0] + z[1] * yt + z[2] * yt * yt;
+    double gb = fabs(z[1] + 2.0 * z[2] * yb);
+    double gt = fabs(z[1] + 2.0 * z[2] * yt);
+    double us = 0.5 * (ub + ut);
+    double g = 0.5 * (gb + gt);
+    out[0] = g > 0.0 ? us / g : INFINITY;
+    out[1] = us;
+    out[2] = 2.0 * z[2];
+    return 0;
+}
+
+double orc_residual(long n, const double *uxa, const double *uya,
+                    const double *uxb, const double *uyb)
+{
+    double num = 0.0, den = 0.0;
+    for (long k = 0; k < n; ++k) {
+        num += fabs(uxa[k] - uxb[k]) + fabs(uya[k] - uyb[k]);
+        den += fabs(uxa[k]) + fabs(uya[k]);
+    }
+    return den > 0.0 ? num / den : 0.0;
+}

@@ -1,0 +1,123 @@
+/*
+ * Plain FP64 CPU oracle for the wetting-model lattice-Boltzmann update of
+ * Colosqui, Kavousanakis, Papathanasiou & Kevrekidis, "A mesoscopic model for
+ * microscale hydrodynamics and interfacial phenomena" (arXiv:1202.6130).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code exists to check the HIP library.  It is
+ * slow on purpose: straight loops, one formula per function, no blocking, no
+ * fusion.  Nothing in the product path may link, load or call it; only the
+ * test-suite, the smoke check and the benchmark's CPU-baseline leg do.  It
+ * shares no code, header, table or constant with the HIP library.
+ *
+ * State convention: f[(y*nx + x)*9 + i] holds the populations at time t after
+ * streaming (i.e. just before the collision of step t).  Velocity set D2Q9:
+ *   i : 0      1      2      3       4       5      6       7        8
+ *   c : (0,0) (1,0)  (0,1)  (-1,0)  (0,-1)  (1,1)  (-1,1)  (-1,-1)  (1,-1)
+ *   w : 4/9   1/9 x4                        1/36 x4
+ * Lattice temperature theta = sum_i w_i c_ix^2 = 1/3.  Fully periodic nx*ny.
+ */
+#ifndef LBM_ORACLE_H
+#define LBM_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int nx, ny;
+    double tau;        /* BGK relaxation time (Sec. II, eq. BE-BGK), > 0.5   */
+    double G;          /* Shan-Chen coupling of the fluid-fluid force        */
+    double G_R, G_A;   /* repulsive / attractive amplitudes (eq. pseudopotential) */
+    double eps;        /* wall-probability exponent, >= 1 (eq. wall_shift)   */
+    double U_wall[2];  /* wall velocity (eq. wall_shift)                     */
+    double F_ext[2];   /* uniform external force density (Sec. III.A)        */
+} orc_params;
+
+/* D2Q9 tables (the oracle's own copy). */
+extern const int    ORC_CX[9];
+extern const int    ORC_CY[9];
+extern const double ORC_W[9];
+extern const double ORC_THETA;
+
+/* Equilibrium of eq. f2 with M2 = rho u u + rho theta I. */
+void orc_equilibrium(double rho, double ux, double uy, double feq[9]);
+
+/* Flat-slab wall functions (Appendix A allows analytic profiles for flat
+ * walls).  Solid band = rows [ny-P, ny); faces on rows 0 and ny-P.
+ * phi = T(s;width), psiR = T(s;core), psiA = T(s;tail) - T(s;core), with
+ * T(s;w) = (1 - tanh(s/w))/2 and s the signed distance to the nearest face. */
+void orc_flat_slab_walls(int nx, int ny, int P, double width, double core,
+                         double tail, double *phi, double *psiR, double *psiA);
+
+/* f = f^eq(rho0, u0) at every node; u0 may be NULL (fluid at rest). */
+void orc_init(const orc_params *p, const double *rho0, const double *ux0,
+              const double *uy0, double *f);
+
+/* Per-node quantities of one step, for inspection: rho, u (= j/rho), the
+ * three force pieces and the shifted velocity.  Any output may be NULL. */
+void orc_forces(const orc_params *p, const double *phi, const double *psiR,
+                const double *psiA, const double *f, double *rho, double *ux,
+                double *uy, double *Fff, double *Flr, double *dFs,
+                double *Ftot, double *usx, double *usy);
+
+/* Collision at every node (no streaming): fpost = f - (f - feq(u))/tau
+ * + feq(u*) - feq(u).  Exposed separately so the tests can check the
+ * conservation laws of the collision alone. */
+void orc_collide(const orc_params *p, const double *phi, const double *psiR,
+                 const double *psiA, const double *f, double *fpost);
+
+/* Streaming: fout_i(x + c_i) = fpost_i(x), periodic. */
+void orc_stream(int nx, int ny, const double *fpost, double *fout);
+
+/* One full step (collide, then stream). f_in and f_out must differ. */
+void orc_step(const orc_params *p, const double *phi, const double *psiR,
+              const double *psiA, const double *f_in, double *f_out);
+
+/* nsteps steps in place on f (allocates one scratch lattice). Returns 0, or
+ * -1 when the scratch lattice cannot be allocated. */
+int orc_run(const orc_params *p, const double *phi, const double *psiR,
+            const double *psiA, double *f, long nsteps);
+
+/* Reported macroscopic fields: rho, u_out = (j + F/2)/rho, and totals
+ * (sum rho, sum j_x, sum j_y) with j the pre-force momentum. */
+void orc_macros(const orc_params *p, const double *phi, const double *psiR,
+                const double *psiA, const double *f, double *rho, double *ux,
+                double *uy, double totals[3]);
+
+/* Iso-density crossings on lattice edges, restricted to nodes whose phi is
+ * below phi_max.  Writes up to cap points (px, py); returns the number found
+ * (which may exceed cap: then only cap were written). */
+long orc_isoline_points(int nx, int ny, const double *rho, const double *phi,
+                        double iso, double phi_max, double *px, double *py,
+                        long cap);
+
+/* Least-squares circle through n points: algebraic (Kasa) start, then
+ * Gauss-Newton on the geometric distance.  out = (xc, yc, R).  Returns 0 on
+ * success, -1 if the fit is degenerate. */
+int orc_circle_fit(long n, const double *px, const double *py, double out[3]);
+
+/* Contact angle of a sessile drop (Sec. III.B): circle fit to the rho = iso
+ * crossings in region III (phi < 0.01), theta = acos((y_ref - yc)/R).
+ * out = (theta_deg, R, xc, yc).  Returns 0, or -1 if no fit (<16 points or
+ * degenerate). */
+int orc_contact_angle(const orc_params *p, const double *phi,
+                      const double *psiR, const double *psiA, const double *f,
+                      double iso, double y_ref, double out[4]);
+
+/* Slip in a flat channel (Sec. III.A): x-averaged u_out,x(y), a parabola
+ * fitted over region-III rows of the fluid gap [0, ny-P], evaluated at the
+ * hydrodynamic boundary y_w where phi(y_w) = 0.01.  out = (b, u_s, c2) with
+ * u_s the fitted velocity at y_w (mean of both walls), b = u_s / |du/dy|(y_w)
+ * and c2 the second derivative of the fit.  Returns 0 or -1. */
+int orc_slip_length(const orc_params *p, const double *phi, const double *psiR,
+                    const double *psiA, const double *f, int P, double width,
+                    double out[3]);
+
+/* Velocity residual sum|u_a - u_b| / sum|u_a| over both components. */
+double orc_residual(long n, const double *uxa, const double *uya,
+                    const double *uxb, const double *uyb);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
