@@ -1,0 +1,229 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) library for the wetting-model
+ * lattice-Boltzmann update of Colosqui, Kavousanakis, Papathanasiou &
+ * Kevrekidis, "A mesoscopic model for microscale hydrodynamics and interfacial
+ * phenomena: slip, films, and contact angle hysteresis" (arXiv:1202.6130).
+ *
+ * One time step (Sec. II) at every node x of a periodic nx*ny D2Q9 lattice:
+ *   rho = sum_i f_i,  j = sum_i f_i c_i,  u = j/rho           (eqs. M0, M1)
+ *   psi = 1 - exp(-rho)                                       (pseudo-potential)
+ *   F_FF = -G psi(x) sum_i w_i psi(x + c_i) c_i               (eq. force_SC)
+ *   F_LR = rho(x) sum_i w_i [G_A psiA - G_R psiR](x + c_i) c_i (eq. force_SC_FS,
+ *          eq. pseudopotential; repulsive core, attractive tail)
+ *   dF_S = phi^eps [rho (U_wall - u) - F_FF]                  (eq. wall_shift)
+ *   F = F_FF + F_LR + dF_S + F_ext,  u* = u + F/rho
+ *   f'_i = f_i - (f_i - feq_i(rho,u))/tau + feq_i(rho,u*) - feq_i(rho,u)
+ *          (eq. BE-BGK with the exact-difference force term of Sec. II.B;
+ *           feq from eq. f2 at equilibrium, theta = 1/3)
+ *   f_i(x + c_i, t+1) = f'_i(x, t)                            (streaming)
+ * Velocity order i = 0..8: (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1)
+ * (-1,-1) (1,-1); weights 4/9, 1/9 x4, 1/36 x4.
+ *
+ * Conventions for every entry point
+ *  - Status: 0 = LBM_OK, negative = error.  The library never aborts and never
+ *    throws across the ABI; lbm_last_error() returns the calling thread's last
+ *    message.
+ *  - Host arrays are float64, row-major [ny][nx] (index y*nx + x), read or
+ *    written during the call only and never retained.
+ *  - Device memory: the caller owns one workspace (lbm_workspace_bytes) and
+ *    lends it to the context; the library allocates no device memory of its
+ *    own.  The workspace must stay valid until lbm_destroy.
+ *  - Stream: every kernel and copy goes on the caller's hipStream_t (passed as
+ *    void*; NULL = the default stream).  Calls marked "synchronises" block
+ *    until the stream is idle; the others only enqueue work.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int lbm_status;
+#define LBM_OK         0
+#define LBM_EINVAL    (-1)  /* invalid argument or parameter                  */
+#define LBM_ENOMEM    (-2)  /* workspace too small                            */
+#define LBM_EDEVICE   (-3)  /* a HIP runtime call or kernel launch failed     */
+#define LBM_EUNSTABLE (-4)  /* non-finite density or velocity detected        */
+#define LBM_ENOFIT    (-5)  /* contact angle: < 16 points or degenerate fit   */
+#define LBM_ESTATE    (-6)  /* call not valid in the context's current state  */
+
+/* Population storage in HBM and arithmetic type:
+ *  F32     binary32 storage, FP32 arithmetic (72 B per lattice update)
+ *  F16DEV  h_i = f_i / w_i - rho_ref in IEEE binary16, FP32 arithmetic (36 B)
+ *  F64     binary64 storage, FP64 arithmetic (144 B)
+ *  F32X    binary32 storage, FP64 arithmetic (72 B; rounding of the stored
+ *          populations is the only FP32 error) */
+#define LBM_STORE_F32    0
+#define LBM_STORE_F16DEV 1
+#define LBM_STORE_F64    2
+#define LBM_STORE_F32X   3
+
+/* Wall functions (Appendix A).
+ *  NONE      : no solid anywhere (phi = psiR = psiA = 0).
+ *  FLAT_SLAB : a solid band of slab_rows rows [ny - slab_rows, ny), faces on
+ *              rows 0 and ny - slab_rows; with s the signed distance (nodes)
+ *              to the nearest face (negative inside the band) and
+ *              T(s; w) = (1 - tanh(s / w)) / 2:
+ *              phi = T(s; wall_width), psiR = T(s; core_range),
+ *              psiA = T(s; tail_range) - T(s; core_range).
+ *  FIELDS    : per-node (phi, psiR, psiA) given by the caller at creation. */
+#define LBM_WALL_NONE      0
+#define LBM_WALL_FLAT_SLAB 1
+#define LBM_WALL_FIELDS    2
+
+typedef struct {
+    int32_t nx, ny;          /* lattice size, both >= 1; 9*nx*ny*(bytes per
+                                stored population) < 2^32                    */
+    int32_t storage;         /* LBM_STORE_*                                   */
+    int32_t wall_kind;       /* LBM_WALL_*                                    */
+    double tau;              /* relaxation time, > 0.5                        */
+    double G;                /* fluid-fluid coupling (G < 0: cohesion)        */
+    double G_R, G_A;         /* repulsive / attractive wall amplitudes        */
+    double eps;              /* wall-probability exponent, >= 1               */
+    double U_wall[2];        /* wall velocity                                 */
+    double F_ext[2];         /* uniform external force density                */
+    double wall_width;       /* FLAT_SLAB: phi width         (> 0, default 2) */
+    double core_range;       /* FLAT_SLAB: psiR width        (> 0, default 1) */
+    double tail_range;       /* FLAT_SLAB: psiA outer width  (> 0, default 3) */
+    double rho_ref;          /* F16DEV reference density (> 0)                */
+    int32_t slab_rows;       /* FLAT_SLAB: rows of solid, 1 <= P < ny         */
+    int32_t diag_interval;   /* K: a diagnostic pass after every K-th step;
+                                0 = only on request                          */
+    int32_t seg_rows;        /* rows per wave segment; 0 = library's choice   */
+    int32_t reserved;        /* must be 0                                     */
+} lbm_params;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Fills *p with the defaults: tau = 1, G = -5, G_R = G_A = 0, eps = 1,
+ * U_wall = F_ext = 0, wall_width = 2, core_range = 1, tail_range = 3,
+ * rho_ref = 1, slab_rows = 8, storage F32, wall NONE, diag_interval 0. */
+lbm_status lbm_params_default(lbm_params *p);
+
+/* Last error message of the calling thread ("" if none).  Never NULL. */
+const char *lbm_last_error(void);
+
+/* Device bytes a context with these parameters needs (written to *bytes). */
+lbm_status lbm_workspace_bytes(const lbm_params *p, size_t *bytes);
+
+/* Creates a context and sets f = feq(rho0, u0) at every node (post-streaming
+ * populations at t = 0).
+ *  rho0        host [ny][nx], required, every value > 0 and finite.
+ *  ux0, uy0    host [ny][nx] or both NULL (fluid at rest).
+ *  wall_fields host [3][ny][nx] = (phi, psiR, psiA) for LBM_WALL_FIELDS, else
+ *              must be NULL.  phi in [0, 1].
+ *  workspace   device pointer, 256-byte aligned, >= lbm_workspace_bytes.
+ *  stream      hipStream_t or NULL.
+ * Synchronises.  On error *out is NULL and nothing is retained. */
+lbm_status lbm_create(const lbm_params *p, const double *rho0, const double *ux0,
+                      const double *uy0, const double *wall_fields,
+                      void *workspace, size_t workspace_bytes, void *stream,
+                      lbm_ctx **out);
+
+/* Advances nsteps >= 0 time steps (the update above).  With diag_interval K
+ * > 0, a diagnostic pass (totals, velocity residual against the previous pass,
+ * non-finite count) runs after every step whose index is a multiple of K.
+ * Enqueues only. */
+lbm_status lbm_step(lbm_ctx *c, int64_t nsteps);
+
+/* Runs a diagnostic pass now (unless the last step already had one) and
+ * returns, synchronising:
+ *  out[0] step index t      out[1] sum rho       out[2] sum j_x
+ *  out[3] sum j_y (j = pre-force momentum)
+ *  out[4] residual r = sum|u(t) - u(t')| / sum|u(t)| over both components,
+ *         t' = the previous pass (+inf if there was none), u = reported
+ *         velocity (j + F/2)/rho
+ *  out[5] number of nodes with non-finite rho or u
+ * Returns LBM_EUNSTABLE if out[5] > 0. */
+lbm_status lbm_diagnostics(lbm_ctx *c, double out[6]);
+
+/* Macroscopic fields at the current time (eqs. M0, M1): rho, and the reported
+ * velocity u = (j + F/2)/rho (average of the pre- and post-force velocities
+ * of the exact difference method).  Any output may be NULL; totals =
+ * (sum rho, sum j_x, sum j_y), accumulated in FP64.  Synchronises. */
+lbm_status lbm_moments(lbm_ctx *c, double *rho, double *ux, double *uy,
+                       double totals[3]);
+
+/* Static contact angle (Sec. III.B): least-squares circle through the
+ * rho = iso crossings on lattice edges (linear interpolation along the edge;
+ * an edge counts when exactly one end has rho >= iso and both ends have
+ * phi < 0.01, i.e. region III; horizontal edges wrap in x, vertical edges do
+ * not wrap in y), algebraic start then Gauss-Newton on the geometric
+ * distance; theta = acos(1 - h/R) with h = yc + R - y_ref.
+ * out = (theta in degrees, R, xc, yc).  LBM_ENOFIT if fewer than 16 points or
+ * the fit is degenerate.  Synchronises. */
+lbm_status lbm_contact_angle(lbm_ctx *c, double iso, double y_ref, double out[4]);
+
+/* Slip in a FLAT_SLAB channel (Sec. III.A): the x-averaged reported u_x(y)
+ * over region-III rows of the gap [0, ny - slab_rows] is fitted by a parabola
+ * and evaluated at the hydrodynamic boundary y_w, phi(y_w) = 0.01, of both
+ * walls.  out = (b, u_s, c2): slip length u_s / |du/dy|(y_w), slip velocity
+ * and the fit's second derivative.  LBM_EINVAL unless wall_kind is
+ * FLAT_SLAB.  Synchronises. */
+lbm_status lbm_slip_length(lbm_ctx *c, double out[3]);
+
+/* Populations at the current time, post-streaming, as host float64
+ * [9][ny][nx] (velocity order above).  Synchronises. */
+lbm_status lbm_get_state(lbm_ctx *c, double *f);
+
+/* Replaces the populations (same layout as lbm_get_state) and the step index;
+ * forgets the previous diagnostic pass.  Values are rounded to the storage
+ * type.  Synchronises. */
+lbm_status lbm_set_state(lbm_ctx *c, const double *f, int64_t step_index);
+
+/* Current step index. */
+int64_t lbm_step_index(const lbm_ctx *c);
+
+/* Frees the host-side context; the workspace returns to the caller.  Waits
+ * for the context's stream first.  NULL is accepted. */
+lbm_status lbm_destroy(lbm_ctx *c);
+
+/* ------------------------------------------------------------------------
+ * Batched ensembles: many independent lattices (each with its own size and
+ * parameters, all F32 storage) advanced together, one kernel launch per time
+ * step covering every lattice; the steps are replayed from a HIP graph.  Each
+ * lattice follows exactly the single-lattice update above, so a lattice gives
+ * bitwise the same fields alone and inside any batch with the same seg_rows.
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_batch lbm_batch;
+
+/* Device bytes for a batch of n lattices (written to *bytes). */
+lbm_status lbm_batch_workspace_bytes(const lbm_params *ps, int32_t n, size_t *bytes);
+
+/* Creates a batch.  ps[k], rho0s[k], ux0s[k], uy0s[k] describe lattice k as in
+ * lbm_create (wall kinds NONE or FLAT_SLAB; ux0s/uy0s may be NULL or hold NULL
+ * entries).  seg_rows = rows per wave segment for every lattice (0 = the
+ * library's choice).  Synchronises. */
+lbm_status lbm_batch_create(const lbm_params *ps, int32_t n,
+                            const double *const *rho0s, const double *const *ux0s,
+                            const double *const *uy0s, int32_t seg_rows,
+                            void *workspace, size_t workspace_bytes, void *stream,
+                            lbm_batch **out);
+
+/* Advances every lattice of the batch by nsteps steps.  chunk > 0: the steps
+ * are recorded once into a HIP graph of `chunk` steps (even) and replayed;
+ * chunk = 0: plain launches.  Enqueues only. */
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps, int32_t chunk);
+
+/* Per-lattice diagnostics, as lbm_diagnostics, for every lattice: out[6*k ..]
+ * (residual against the previous call of this function).  Synchronises. */
+lbm_status lbm_batch_diagnostics(lbm_batch *b, double *out);
+
+/* A context view of lattice k (valid until lbm_batch_destroy) for
+ * lbm_moments / lbm_contact_angle / lbm_slip_length / lbm_get_state /
+ * lbm_diagnostics.  lbm_step and lbm_set_state on a view return LBM_ESTATE;
+ * lbm_destroy on a view is a no-op. */
+lbm_ctx *lbm_batch_lattice(lbm_batch *b, int32_t k);
+
+/* Frees the host-side batch (waits for its stream).  NULL is accepted. */
+lbm_status lbm_batch_destroy(lbm_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

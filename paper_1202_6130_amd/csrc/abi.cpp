@@ -1,0 +1,798 @@
+// C-ABI implementation of lbm.h: parameter validation, workspace layout,
+// kernel launches on the caller's stream, diagnostics and the small host-side
+// least-squares solves of the contact-angle and slip measurements.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "launch.hpp"
+
+using namespace lbmwet;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbm_status fail(lbm_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(LBM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define TRY(expr)                            \
+    do {                                     \
+        lbm_status s_ = (expr);              \
+        if (s_ != LBM_OK) return s_;         \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+size_t storage_bytes(int st) { return st == LBM_STORE_F16DEV ? 2 : (st == LBM_STORE_F64 ? 8 : 4); }
+size_t compute_bytes(int st) { return (st == LBM_STORE_F64 || st == LBM_STORE_F32X) ? 8 : 4; }
+int kernel_storage(int st) {
+    switch (st) {
+    case LBM_STORE_F16DEV: return STORE_F16;
+    case LBM_STORE_F64: return STORE_F64;
+    case LBM_STORE_F32X: return STORE_F32X;
+    default: return STORE_F32;
+    }
+}
+int compute_is_f64(int st) { return compute_bytes(st) == 8; }
+
+uint32_t default_seg_rows(uint32_t nx, uint32_t ny) {
+    // enough waves to fill 256 CUs several times over, without making the
+    // halo rows (2 per segment) a large share of the loads
+    const uint32_t strips = (nx + kStripColsHost - 1) / kStripColsHost;
+    uint64_t want = 16384;
+    uint32_t rows = 64;
+    while (rows > 8 && uint64_t(strips) * ((ny + rows - 1) / rows) < want) rows /= 2;
+    return rows < ny ? rows : ny;
+}
+
+struct Layout {
+    size_t fa, fb, mom, uprev, row_tab, node_tab, phi_raw, partials, iso_part, small, profile, total;
+    uint32_t strips, segs, seg_rows, waves, iso_blocks;
+};
+
+// Offsets (bytes) into one lattice's workspace.  fb and mom are adjacent: the
+// pair doubles as staging for host float64 arrays at creation.
+Layout make_layout(const lbm_params &p) {
+    Layout L{};
+    const size_t N = size_t(p.nx) * p.ny, s = storage_bytes(p.storage), cb = compute_bytes(p.storage);
+    L.seg_rows = p.seg_rows > 0 ? uint32_t(p.seg_rows) : default_seg_rows(p.nx, p.ny);
+    if (L.seg_rows > uint32_t(p.ny)) L.seg_rows = p.ny;
+    L.strips = (uint32_t(p.nx) + kStripColsHost - 1) / kStripColsHost;
+    L.segs = (uint32_t(p.ny) + L.seg_rows - 1) / L.seg_rows;
+    L.waves = L.strips * L.segs;
+    L.iso_blocks = isoline_blocks(uint32_t(N));
+    size_t o = 0;
+    L.fa = o; o = align_up(o + 9 * N * s);
+    L.fb = o; o = o + 9 * N * s;                       // no padding: fb+mom contiguous
+    L.mom = o; o = align_up(o + 3 * N * cb);
+    L.uprev = o; o = align_up(o + 2 * N * cb);
+    const bool node = p.wall_kind == LBM_WALL_FIELDS;
+    L.row_tab = o; o = align_up(o + 2 * size_t(p.ny) * cb);
+    L.node_tab = o; o = align_up(o + (node ? 3 * N * cb : 0));
+    L.phi_raw = o; o = align_up(o + (node ? N : size_t(p.ny)) * sizeof(double));
+    L.partials = o; o = align_up(o + size_t(L.waves) * 8 * sizeof(double));
+    L.iso_part = o; o = align_up(o + size_t(L.iso_blocks) * 10 * sizeof(double));
+    L.small = o; o = align_up(o + 64 * sizeof(double));
+    L.profile = o; o = align_up(o + size_t(p.ny) * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+lbm_status validate(const lbm_params *p) {
+    if (!p) return fail(LBM_EINVAL, "params is NULL");
+    if (p->nx < 1 || p->ny < 1) return fail(LBM_EINVAL, "nx, ny must be >= 1 (got %d, %d)", p->nx, p->ny);
+    if (p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_F16DEV && p->storage != LBM_STORE_F64 &&
+        p->storage != LBM_STORE_F32X)
+        return fail(LBM_EINVAL, "unknown storage %d", p->storage);
+    if (int64_t(p->nx) * p->ny * 9 * int64_t(storage_bytes(p->storage)) >= (int64_t(1) << 32))
+        return fail(LBM_EINVAL, "lattice too large: 9*nx*ny*bytes must be < 2^32");
+    if (p->wall_kind < LBM_WALL_NONE || p->wall_kind > LBM_WALL_FIELDS)
+        return fail(LBM_EINVAL, "unknown wall_kind %d", p->wall_kind);
+    if (!(p->tau > 0.5) || !isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be > 0.5");
+    if (!(p->eps >= 1.0) || !isfinite(p->eps)) return fail(LBM_EINVAL, "eps must be >= 1");
+    const double vals[] = {p->G, p->G_R, p->G_A, p->U_wall[0], p->U_wall[1], p->F_ext[0], p->F_ext[1]};
+    for (double v : vals)
+        if (!isfinite(v)) return fail(LBM_EINVAL, "non-finite model parameter");
+    if (p->wall_kind == LBM_WALL_FLAT_SLAB) {
+        if (p->slab_rows < 1 || p->slab_rows >= p->ny)
+            return fail(LBM_EINVAL, "slab_rows must be in [1, ny) (got %d)", p->slab_rows);
+        if (!(p->wall_width > 0) || !(p->core_range > 0) || !(p->tail_range > 0))
+            return fail(LBM_EINVAL, "wall_width, core_range, tail_range must be > 0");
+    }
+    if (p->storage == LBM_STORE_F16DEV && !(p->rho_ref > 0) ) return fail(LBM_EINVAL, "rho_ref must be > 0");
+    if (p->seg_rows < 0) return fail(LBM_EINVAL, "seg_rows must be >= 0");
+    if (p->diag_interval < 0) return fail(LBM_EINVAL, "diag_interval must be >= 0");
+    if (p->reserved != 0) return fail(LBM_EINVAL, "reserved must be 0");
+    return LBM_OK;
+}
+
+// 3x3 solve by Gaussian elimination with partial pivoting; false if singular.
+bool solve3(double A[3][3], double b[3], double z[3]) {
+    double big = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) big = fmax(big, fabs(A[i][j]));
+    if (!(big > 0)) return false;
+    for (int c = 0; c < 3; ++c) {
+        int p = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (fabs(A[r][c]) > fabs(A[p][c])) p = r;
+        if (!(fabs(A[p][c]) > 1e-14 * big)) return false;
+        for (int j = 0; j < 3; ++j) { double t = A[c][j]; A[c][j] = A[p][j]; A[p][j] = t; }
+        { double t = b[c]; b[c] = b[p]; b[p] = t; }
+        for (int r = c + 1; r < 3; ++r) {
+            const double m = A[r][c] / A[c][c];
+            for (int j = c; j < 3; ++j) A[r][j] -= m * A[c][j];
+            b[r] -= m * b[c];
+        }
+    }
+    for (int r = 2; r >= 0; --r) {
+        double acc = b[r];
+        for (int j = r + 1; j < 3; ++j) acc -= A[r][j] * z[j];
+        z[r] = acc / A[r][r];
+    }
+    return true;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_params p;
+    Layout lay;
+    hipStream_t stream;
+    char *ws;
+    LatDevAny L;
+    int wall_mode;                 // 0 = per-row tables, 1 = per-node
+    int own_cur;
+    int64_t own_step;
+    int *cur;                      // which buffer holds the state (0: fa, 1: fb)
+    int64_t *step;
+    bool view;
+    // diagnostics bookkeeping
+    bool have_prev;                // a snapshot exists for the residual
+    int64_t last_diag_step;
+    bool last_diag_compared;
+    double *d_small;               // [0..7] diag totals, [8..15] moment totals,
+                                   // [16..25] isoline sums, [32..35] ranges (u32)
+    uint32_t *d_ranges;
+};
+
+struct lbm_batch {
+    std::vector<lbm_ctx *> lat;
+    hipStream_t stream;
+    int cur;
+    int64_t step;
+    void *d_lats;
+    uint4 *d_work;
+    uint32_t nwork;
+    double *d_part;
+    uint32_t *d_ranges;
+    double *d_res;
+    hipGraphExec_t graph[2];
+    int graph_chunk[2];
+    bool have_prev;
+};
+
+namespace {
+
+lbm_status launch_ok(hipError_t e, const char *what) {
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "%s launch failed: %s", what, hipGetErrorString(e));
+    return LBM_OK;
+}
+
+// Runs the diagnostic kernel over the current state and reduces it into
+// d_small[slot*8 .. +6].
+lbm_status run_diag(lbm_ctx *c, int write_mom, int compare, int update, int slot) {
+    TRY(launch_ok(launch_diag(kernel_storage(c->p.storage), nullptr, nullptr, 0, c->L, c->wall_mode, *c->cur,
+                              write_mom, compare, update, c->stream),
+                  "diag"));
+    TRY(launch_ok(launch_reduce(c->L.partials, c->d_ranges, 1, 8, 6, c->d_small + 8 * slot, 8, c->stream),
+                  "reduce"));
+    return LBM_OK;
+}
+
+lbm_status sync(lbm_ctx *c) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+// Builds a context inside `ws` (layout already checked).  Synchronises.
+lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const double *ux0, const double *uy0,
+                    const double *wall_fields, char *ws, hipStream_t stream) {
+    c->p = *p;
+    c->lay = make_layout(*p);
+    c->stream = stream;
+    c->ws = ws;
+    c->own_cur = 0;
+    c->own_step = 0;
+    c->cur = &c->own_cur;
+    c->step = &c->own_step;
+    c->view = false;
+    c->have_prev = false;
+    c->last_diag_step = -1;
+    c->last_diag_compared = false;
+    c->wall_mode = p->wall_kind == LBM_WALL_FIELDS ? 1 : 0;
+    const Layout &Y = c->lay;
+    const size_t N = size_t(p->nx) * p->ny;
+    c->d_small = (double *)(ws + Y.small);
+    c->d_ranges = (uint32_t *)(c->d_small + 32);
+
+    LatDevAny &L = c->L;
+    L.nx = p->nx; L.ny = p->ny; L.plane = uint32_t(N);
+    L.strips = Y.strips; L.segs = Y.segs; L.seg_rows = Y.seg_rows; L.wave0 = 0;
+    L.fa = ws + Y.fa; L.fb = ws + Y.fb;
+    L.row_tab = ws + Y.row_tab;
+    L.node_tab = c->wall_mode ? (const void *)(ws + Y.node_tab) : nullptr;
+    L.mom = ws + Y.mom;
+    L.uprev = ws + Y.uprev;
+    L.partials = (double *)(ws + Y.partials);
+    L.G = p->G; L.omega = 1.0 / p->tau;
+    L.Ux = p->U_wall[0]; L.Uy = p->U_wall[1];
+    L.Fx = p->F_ext[0]; L.Fy = p->F_ext[1];
+    L.rho_ref = p->storage == LBM_STORE_F16DEV ? p->rho_ref : 1.0;
+
+    const uint32_t ranges[4] = {0, Y.waves, 0, Y.iso_blocks};
+    HIPCHK(hipMemcpyAsync(c->d_ranges, ranges, sizeof ranges, hipMemcpyHostToDevice, stream));
+
+    const int f64 = compute_is_f64(p->storage);
+    double *stage = (double *)(ws + Y.fb);   // >= 3N doubles (fb + mom)
+    double *phi_raw = (double *)(ws + Y.phi_raw);
+    if (c->wall_mode == 0) {
+        const int P = p->wall_kind == LBM_WALL_FLAT_SLAB ? p->slab_rows : 0;
+        TRY(launch_ok(launch_walls_row(f64, p->ny, P, p->wall_width, p->core_range, p->tail_range, p->eps,
+                                       p->G_R, p->G_A, ws + Y.row_tab, phi_raw, stream),
+                      "walls_row"));
+    } else {
+        HIPCHK(hipMemcpyAsync(stage, wall_fields, 3 * N * sizeof(double), hipMemcpyHostToDevice, stream));
+        TRY(launch_ok(launch_walls_node(f64, p->nx, p->ny, stage, p->eps, p->G_R, p->G_A, ws + Y.node_tab,
+                                        phi_raw, stream),
+                      "walls_node"));
+    }
+    HIPCHK(hipStreamSynchronize(stream));   // staging is reused below
+    HIPCHK(hipMemcpyAsync(stage, rho0, N * sizeof(double), hipMemcpyHostToDevice, stream));
+    const double *dux = nullptr, *duy = nullptr;
+    if (ux0 && uy0) {
+        HIPCHK(hipMemcpyAsync(stage + N, ux0, N * sizeof(double), hipMemcpyHostToDevice, stream));
+        HIPCHK(hipMemcpyAsync(stage + 2 * N, uy0, N * sizeof(double), hipMemcpyHostToDevice, stream));
+        dux = stage + N;
+        duy = stage + 2 * N;
+    }
+    TRY(launch_ok(launch_init(kernel_storage(p->storage), p->nx, p->ny, stage, dux, duy, L.fa, L.rho_ref, stream),
+                  "init"));
+    HIPCHK(hipStreamSynchronize(stream));
+    return LBM_OK;
+}
+
+lbm_status check_host_fields(const lbm_params *p, const double *rho0, const double *ux0, const double *uy0,
+                             const double *wall_fields) {
+    const size_t N = size_t(p->nx) * p->ny;
+    if (!rho0) return fail(LBM_EINVAL, "rho0 is NULL");
+    if ((ux0 == nullptr) != (uy0 == nullptr)) return fail(LBM_EINVAL, "ux0 and uy0 must both be given or both NULL");
+    for (size_t i = 0; i < N; ++i)
+        if (!(rho0[i] > 0) || !isfinite(rho0[i])) return fail(LBM_EINVAL, "rho0[%zu] must be finite and > 0", i);
+    if (ux0)
+        for (size_t i = 0; i < N; ++i)
+            if (!isfinite(ux0[i]) || !isfinite(uy0[i])) return fail(LBM_EINVAL, "non-finite u0 at %zu", i);
+    if (p->wall_kind == LBM_WALL_FIELDS) {
+        if (!wall_fields) return fail(LBM_EINVAL, "wall_fields required for LBM_WALL_FIELDS");
+        for (size_t i = 0; i < 3 * N; ++i)
+            if (!isfinite(wall_fields[i])) return fail(LBM_EINVAL, "non-finite wall field at %zu", i);
+        for (size_t i = 0; i < N; ++i)
+            if (wall_fields[i] < 0 || wall_fields[i] > 1) return fail(LBM_EINVAL, "phi must be in [0,1]");
+    } else if (wall_fields) {
+        return fail(LBM_EINVAL, "wall_fields must be NULL unless wall_kind is LBM_WALL_FIELDS");
+    }
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_params_default(lbm_params *p) {
+    if (!p) return fail(LBM_EINVAL, "params is NULL");
+    memset(p, 0, sizeof *p);
+    p->storage = LBM_STORE_F32;
+    p->wall_kind = LBM_WALL_NONE;
+    p->tau = 1.0;
+    p->G = -5.0;
+    p->eps = 1.0;
+    p->wall_width = 2.0;
+    p->core_range = 1.0;
+    p->tail_range = 3.0;
+    p->rho_ref = 1.0;
+    p->slab_rows = 8;
+    return LBM_OK;
+}
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+lbm_status lbm_workspace_bytes(const lbm_params *p, size_t *bytes) {
+    TRY(validate(p));
+    if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+    *bytes = make_layout(*p).total;
+    return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_params *p, const double *rho0, const double *ux0, const double *uy0,
+                      const double *wall_fields, void *workspace, size_t workspace_bytes, void *stream,
+                      lbm_ctx **out) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    TRY(validate(p));
+    TRY(check_host_fields(p, rho0, ux0, uy0, wall_fields));
+    const Layout Y = make_layout(*p);
+    if (!workspace) return fail(LBM_EINVAL, "workspace is NULL");
+    if (uintptr_t(workspace) % kAlign) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+    if (workspace_bytes < Y.total)
+        return fail(LBM_ENOMEM, "workspace too small: %zu < %zu bytes", workspace_bytes, Y.total);
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(LBM_EINVAL, "host allocation failed");
+    lbm_status st = init_ctx(c, p, rho0, ux0, uy0, wall_fields, (char *)workspace, (hipStream_t)stream);
+    if (st != LBM_OK) {
+        delete c;
+        return st;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (c->view) return fail(LBM_ESTATE, "lbm_step on a batch lattice view; use lbm_batch_step");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    const int ks = kernel_storage(c->p.storage);
+    const int K = c->p.diag_interval;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        TRY(launch_ok(launch_step(ks, c->L, c->wall_mode, *c->cur, c->stream), "step"));
+        *c->cur ^= 1;
+        ++*c->step;
+        if (K > 0 && *c->step % K == 0) {
+            TRY(run_diag(c, 0, c->have_prev ? 1 : 0, 1, 0));
+            c->last_diag_compared = c->have_prev;
+            c->have_prev = true;
+            c->last_diag_step = *c->step;
+        }
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_diagnostics(lbm_ctx *c, double out[6]) {
+    if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
+    if (c->last_diag_step != *c->step) {
+        TRY(run_diag(c, 0, c->have_prev ? 1 : 0, 1, 0));
+        c->last_diag_compared = c->have_prev;
+        c->have_prev = true;
+        c->last_diag_step = *c->step;
+    }
+    double r[8];
+    HIPCHK(hipMemcpyAsync(r, c->d_small, sizeof r, hipMemcpyDeviceToHost, c->stream));
+    TRY(sync(c));
+    out[0] = double(*c->step);
+    out[1] = r[0];
+    out[2] = r[1];
+    out[3] = r[2];
+    if (!c->last_diag_compared) out[4] = INFINITY;
+    else out[4] = r[4] > 0 ? r[3] / r[4] : (r[3] > 0 ? INFINITY : 0.0);
+    out[5] = r[5];
+    if (r[5] > 0) return fail(LBM_EUNSTABLE, "%.0f nodes with non-finite density or velocity at step %lld", r[5],
+                              (long long)*c->step);
+    return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_ctx *c, double *rho, double *ux, double *uy, double totals[3]) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    TRY(run_diag(c, 1, 0, 0, 1));
+    const size_t N = size_t(c->p.nx) * c->p.ny;
+    const int f64 = compute_is_f64(c->p.storage);
+    double *outs[3] = {rho, ux, uy};
+    std::vector<float> tmp(f64 ? 0 : N);
+    for (int k = 0; k < 3; ++k) {
+        if (!outs[k]) continue;
+        if (f64) {
+            HIPCHK(hipMemcpyAsync(outs[k], (double *)c->L.mom + k * N, N * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+            TRY(sync(c));
+        } else {
+            HIPCHK(hipMemcpyAsync(tmp.data(), (float *)c->L.mom + k * N, N * sizeof(float), hipMemcpyDeviceToHost,
+                                  c->stream));
+            TRY(sync(c));
+            for (size_t i = 0; i < N; ++i) outs[k][i] = double(tmp[i]);
+        }
+    }
+    double r[8];
+    HIPCHK(hipMemcpyAsync(r, c->d_small + 8, sizeof r, hipMemcpyDeviceToHost, c->stream));
+    TRY(sync(c));
+    if (totals) {
+        totals[0] = r[0];
+        totals[1] = r[1];
+        totals[2] = r[2];
+    }
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// One isoline pass; returns the 10 reduced sums.
+lbm_status iso_pass(lbm_ctx *c, IsoParams ip, double sums[10]) {
+    const int f64 = compute_is_f64(c->p.storage);
+    double *part = (double *)(c->ws + c->lay.iso_part);
+    TRY(launch_ok(launch_isoline(f64, ip, c->L.mom, (const double *)(c->ws + c->lay.phi_raw), part, c->stream),
+                  "isoline"));
+    TRY(launch_ok(launch_reduce(part, c->d_ranges + 2, 1, 10, 10, c->d_small + 16, 10, c->stream), "reduce"));
+    HIPCHK(hipMemcpyAsync(sums, c->d_small + 16, 10 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    return sync(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_contact_angle(lbm_ctx *c, double iso, double y_ref, double out[4]) {
+    if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
+    if (!isfinite(iso) || !isfinite(y_ref)) return fail(LBM_EINVAL, "iso and y_ref must be finite");
+    TRY(run_diag(c, 1, 0, 0, 1));
+    IsoParams ip{uint32_t(c->p.nx), uint32_t(c->p.ny), c->wall_mode, 0, iso, 0.01, 0, 0, 0, 0, 0};
+    double s[10];
+    TRY(iso_pass(c, ip, s));
+    const double n = s[0];
+    if (n < 16) return fail(LBM_ENOFIT, "only %.0f isoline points in region III", n);
+    ip.mx = s[1] / n;
+    ip.my = s[2] / n;
+    // algebraic fit about the centroid: x^2 + y^2 + D x + E y + F = 0
+    ip.mode = 1;
+    TRY(iso_pass(c, ip, s));
+    double A[3][3] = {{s[3], s[4], s[1]}, {s[4], s[5], s[2]}, {s[1], s[2], s[0]}};
+    double b[3] = {-s[6], -s[7], -s[8]}, z[3];
+    if (!solve3(A, b, z)) return fail(LBM_ENOFIT, "degenerate algebraic circle fit");
+    double xc = -0.5 * z[0], yc = -0.5 * z[1], R2 = xc * xc + yc * yc - z[2];
+    if (!(R2 > 0)) return fail(LBM_ENOFIT, "degenerate algebraic circle fit");
+    double R = sqrt(R2);
+    // geometric refinement
+    ip.mode = 2;
+    for (int it = 0; it < 20; ++it) {
+        ip.xc = xc; ip.yc = yc; ip.R = R;
+        TRY(iso_pass(c, ip, s));
+        double J[3][3] = {{s[1], s[2], s[3]}, {s[2], s[4], s[5]}, {s[3], s[5], s[6]}};
+        double g[3] = {s[7], s[8], s[9]}, d[3];
+        if (!solve3(J, g, d)) return fail(LBM_ENOFIT, "degenerate geometric circle fit");
+        xc += d[0]; yc += d[1]; R += d[2];
+        if (fabs(d[0]) + fabs(d[1]) + fabs(d[2]) < 1e-13 * (1.0 + fabs(R))) break;
+    }
+    if (!(R > 0) || !isfinite(R) || !isfinite(xc) || !isfinite(yc)) return fail(LBM_ENOFIT, "circle fit diverged");
+    xc += ip.mx;
+    yc += ip.my;
+    double cs = (y_ref - yc) / R;
+    cs = cs > 1 ? 1 : (cs < -1 ? -1 : cs);
+    out[0] = acos(cs) * (180.0 / M_PI);
+    out[1] = R;
+    out[2] = xc;
+    out[3] = yc;
+    return LBM_OK;
+}
+
+lbm_status lbm_slip_length(lbm_ctx *c, double out[3]) {
+    if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
+    if (c->p.wall_kind != LBM_WALL_FLAT_SLAB) return fail(LBM_EINVAL, "slip length needs wall_kind FLAT_SLAB");
+    TRY(run_diag(c, 1, 0, 0, 1));
+    const int nx = c->p.nx, ny = c->p.ny, P = c->p.slab_rows;
+    const int f64 = compute_is_f64(c->p.storage);
+    const size_t N = size_t(nx) * ny;
+    const void *ux = (const char *)c->L.mom + N * compute_bytes(c->p.storage);
+    double *prof = (double *)(c->ws + c->lay.profile);
+    TRY(launch_ok(launch_profile(f64, nx, ny, ux, prof, c->stream), "profile"));
+    std::vector<double> rows(ny), phi(ny);
+    HIPCHK(hipMemcpyAsync(rows.data(), prof, ny * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(phi.data(), c->ws + c->lay.phi_raw, ny * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+    TRY(sync(c));
+    const int top = ny - P;
+    const double mid = 0.5 * top;
+    double A[3][3] = {{0}}, b[3] = {0}, z[3];
+    int used = 0;
+    for (int y = 0; y <= top; ++y) {
+        if (!(phi[y] < 0.01)) continue;       // region III only
+        const double t = y - mid, u = rows[y] / nx;
+        const double v[3] = {1.0, t, t * t};
+        for (int i = 0; i < 3; ++i) {
+            b[i] += v[i] * u;
+            for (int j = 0; j < 3; ++j) A[i][j] += v[i] * v[j];
+        }
+        ++used;
+    }
+    if (used < 3 || !solve3(A, b, z)) return fail(LBM_ENOFIT, "not enough region-III rows for the slip fit");
+    const double yw = c->p.wall_width * atanh(0.98);   // phi(y_w) = 0.01
+    const double tb = yw - mid, tt = (top - yw) - mid;
+    const double ub = z[0] + z[1] * tb + z[2] * tb * tb, ut = z[0] + z[1] * tt + z[2] * tt * tt;
+    const double gb = fabs(z[1] + 2 * z[2] * tb), gt = fabs(z[1] + 2 * z[2] * tt);
+    const double us = 0.5 * (ub + ut), g = 0.5 * (gb + gt);
+    out[0] = g > 0 ? us / g : INFINITY;
+    out[1] = us;
+    out[2] = 2 * z[2];
+    return LBM_OK;
+}
+
+lbm_status lbm_get_state(lbm_ctx *c, double *f) {
+    if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
+    const size_t N = size_t(c->p.nx) * c->p.ny;
+    void *pop = *c->cur ? c->L.fb : c->L.fa;
+    double *stage = (double *)(*c->cur ? c->L.fa : c->L.fb);   // the other buffer is free between steps
+    for (int q = 0; q < 9; ++q) {
+        TRY(launch_ok(launch_plane(kernel_storage(c->p.storage), 0, c->p.nx, c->p.ny, q, pop, stage, c->L.rho_ref,
+                                   c->stream),
+                      "get_plane"));
+        HIPCHK(hipMemcpyAsync(f + q * N, stage, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        TRY(sync(c));
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_set_state(lbm_ctx *c, const double *f, int64_t step_index) {
+    if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
+    if (c->view) return fail(LBM_ESTATE, "lbm_set_state on a batch lattice view");
+    if (step_index < 0) return fail(LBM_EINVAL, "step_index must be >= 0");
+    const size_t N = size_t(c->p.nx) * c->p.ny;
+    void *pop = *c->cur ? c->L.fb : c->L.fa;
+    double *stage = (double *)(*c->cur ? c->L.fa : c->L.fb);
+    for (int q = 0; q < 9; ++q) {
+        HIPCHK(hipMemcpyAsync(stage, f + q * N, N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        TRY(launch_ok(launch_plane(kernel_storage(c->p.storage), 1, c->p.nx, c->p.ny, q, pop, stage, c->L.rho_ref,
+                                   c->stream),
+                      "set_plane"));
+        TRY(sync(c));
+    }
+    *c->step = step_index;
+    c->have_prev = false;
+    c->last_diag_step = -1;
+    c->last_diag_compared = false;
+    return LBM_OK;
+}
+
+int64_t lbm_step_index(const lbm_ctx *c) { return c ? *c->step : -1; }
+
+lbm_status lbm_destroy(lbm_ctx *c) {
+    if (!c || c->view) return LBM_OK;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    delete c;
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+// ------------------------------------------------------------------ batches
+static lbm_status batch_check(const lbm_params *ps, int32_t n) {
+    if (!ps || n < 1) return fail(LBM_EINVAL, "need n >= 1 lattices");
+    for (int32_t k = 0; k < n; ++k) {
+        TRY(validate(&ps[k]));
+        if (ps[k].storage != LBM_STORE_F32) return fail(LBM_EINVAL, "lattice %d: batches take F32 storage only", k);
+        if (ps[k].wall_kind == LBM_WALL_FIELDS)
+            return fail(LBM_EINVAL, "lattice %d: batches take wall kinds NONE or FLAT_SLAB", k);
+    }
+    return LBM_OK;
+}
+
+struct BatchLayout {
+    std::vector<size_t> off;
+    size_t lats, work, part, ranges, res, total;
+    uint32_t nwork;
+};
+
+static BatchLayout batch_layout(const lbm_params *ps, int32_t n, int32_t seg_rows) {
+    BatchLayout B;
+    size_t o = 0;
+    B.nwork = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        lbm_params p = ps[k];
+        p.seg_rows = seg_rows;
+        Layout L = make_layout(p);
+        B.off.push_back(o);
+        o = align_up(o + L.total);
+        B.nwork += L.waves;
+    }
+    B.lats = o; o = align_up(o + size_t(n) * sizeof(LatDev<float>));
+    B.work = o; o = align_up(o + size_t(B.nwork) * sizeof(uint4));
+    B.part = o; o = align_up(o + size_t(B.nwork) * 8 * sizeof(double));
+    B.ranges = o; o = align_up(o + size_t(n) * 2 * sizeof(uint32_t));
+    B.res = o; o = align_up(o + size_t(n) * 8 * sizeof(double));
+    B.total = o;
+    return B;
+}
+
+lbm_status lbm_batch_workspace_bytes(const lbm_params *ps, int32_t n, size_t *bytes) {
+    TRY(batch_check(ps, n));
+    if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+    *bytes = batch_layout(ps, n, ps[0].seg_rows).total;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_create(const lbm_params *ps, int32_t n, const double *const *rho0s,
+                            const double *const *ux0s, const double *const *uy0s, int32_t seg_rows,
+                            void *workspace, size_t workspace_bytes, void *stream, lbm_batch **out) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    TRY(batch_check(ps, n));
+    if (!rho0s) return fail(LBM_EINVAL, "rho0s is NULL");
+    if (seg_rows < 0) return fail(LBM_EINVAL, "seg_rows must be >= 0");
+    if (!workspace || uintptr_t(workspace) % kAlign) return fail(LBM_EINVAL, "workspace NULL or not 256-byte aligned");
+    BatchLayout B = batch_layout(ps, n, seg_rows);
+    if (workspace_bytes < B.total) return fail(LBM_ENOMEM, "workspace too small: %zu < %zu", workspace_bytes, B.total);
+    char *ws = (char *)workspace;
+    hipStream_t st = (hipStream_t)stream;
+    lbm_batch *b = new (std::nothrow) lbm_batch();
+    if (!b) return fail(LBM_EINVAL, "host allocation failed");
+    b->stream = st;
+    b->cur = 0;
+    b->step = 0;
+    b->graph[0] = b->graph[1] = nullptr;
+    b->graph_chunk[0] = b->graph_chunk[1] = 0;
+    b->have_prev = false;
+    b->nwork = B.nwork;
+    b->d_lats = ws + B.lats;
+    b->d_work = (uint4 *)(ws + B.work);
+    b->d_part = (double *)(ws + B.part);
+    b->d_ranges = (uint32_t *)(ws + B.ranges);
+    b->d_res = (double *)(ws + B.res);
+    std::vector<LatDev<float>> lats(n);
+    std::vector<uint4> work;
+    std::vector<uint32_t> ranges(2 * size_t(n));
+    work.reserve(B.nwork);
+    uint32_t w0 = 0;
+    lbm_status stt = LBM_OK;
+    for (int32_t k = 0; k < n && stt == LBM_OK; ++k) {
+        lbm_params p = ps[k];
+        p.seg_rows = seg_rows;
+        stt = check_host_fields(&p, rho0s[k], ux0s ? ux0s[k] : nullptr, uy0s ? uy0s[k] : nullptr, nullptr);
+        if (stt != LBM_OK) break;
+        lbm_ctx *c = new (std::nothrow) lbm_ctx();
+        if (!c) { stt = fail(LBM_EINVAL, "host allocation failed"); break; }
+        stt = init_ctx(c, &p, rho0s[k], ux0s ? ux0s[k] : nullptr, uy0s ? uy0s[k] : nullptr, nullptr,
+                       ws + B.off[k], st);
+        if (stt != LBM_OK) { delete c; break; }
+        // the view shares the batch's time and buffer parity; its partials
+        // live in the batch's global array so both reduction paths agree
+        c->view = true;
+        c->cur = &b->cur;
+        c->step = &b->step;
+        c->L.partials = b->d_part + 8 * size_t(w0);
+        const Layout &Y = c->lay;
+        LatDevAny La = c->L;
+        La.wave0 = w0;
+        lats[k] = La.get<float>();
+        for (uint32_t sg = 0; sg < Y.segs; ++sg)
+            for (uint32_t sp = 0; sp < Y.strips; ++sp) work.push_back(make_uint4(uint32_t(k), sp, sg, 0));
+        ranges[2 * k] = w0;
+        ranges[2 * k + 1] = w0 + Y.waves;
+        w0 += Y.waves;
+        b->lat.push_back(c);
+    }
+    if (stt == LBM_OK) {
+        hipError_t e = hipMemcpyAsync(b->d_lats, lats.data(), lats.size() * sizeof(LatDev<float>),
+                                      hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(b->d_work, work.data(), work.size() * sizeof(uint4),
+                                                hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(b->d_ranges, ranges.data(), ranges.size() * sizeof(uint32_t),
+                                                hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) stt = fail(LBM_EDEVICE, "batch upload: %s", hipGetErrorString(e));
+    }
+    if (stt != LBM_OK) {
+        for (lbm_ctx *c : b->lat) delete c;
+        delete b;
+        return stt;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+static lbm_status batch_plain(lbm_batch *b, int64_t n) {
+    for (int64_t s = 0; s < n; ++s) {
+        TRY(launch_ok(launch_step_batch(b->d_lats, b->d_work, b->nwork, b->cur, b->stream), "step_batch"));
+        b->cur ^= 1;
+        ++b->step;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps, int32_t chunk) {
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (nsteps < 0 || chunk < 0 || (chunk % 2)) return fail(LBM_EINVAL, "nsteps >= 0 and an even chunk >= 0 required");
+    if (chunk == 0) return batch_plain(b, nsteps);
+    if (b->stream == nullptr) return fail(LBM_EINVAL, "graph replay (chunk > 0) needs a non-default stream");
+    while (nsteps >= chunk) {
+        const int par = b->cur;
+        if (b->graph[par] && b->graph_chunk[par] != chunk) {
+            (void)hipGraphExecDestroy(b->graph[par]);
+            b->graph[par] = nullptr;
+        }
+        if (!b->graph[par]) {
+            hipGraph_t g;
+            HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = hipSuccess;
+            for (int s = 0; s < chunk && e == hipSuccess; ++s)
+                e = launch_step_batch(b->d_lats, b->d_work, b->nwork, par ^ (s & 1), b->stream);
+            hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+            if (e != hipSuccess) return fail(LBM_EDEVICE, "capture launch: %s", hipGetErrorString(e));
+            if (e2 != hipSuccess) return fail(LBM_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+            hipError_t e3 = hipGraphInstantiate(&b->graph[par], g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e3 != hipSuccess) return fail(LBM_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e3));
+            b->graph_chunk[par] = chunk;
+        }
+        HIPCHK(hipGraphLaunch(b->graph[par], b->stream));
+        b->step += chunk;          // chunk is even: the parity is unchanged
+        nsteps -= chunk;
+    }
+    return batch_plain(b, nsteps);
+}
+
+lbm_status lbm_batch_diagnostics(lbm_batch *b, double *out) {
+    if (!b || !out) return fail(LBM_EINVAL, "NULL argument");
+    const int n = int(b->lat.size());
+    LatDevAny dummy;
+    TRY(launch_ok(launch_diag(STORE_F32, b->d_lats, b->d_work, b->nwork, dummy, 0, b->cur, 0, b->have_prev ? 1 : 0,
+                              1, b->stream),
+                  "diag_batch"));
+    TRY(launch_ok(launch_reduce(b->d_part, b->d_ranges, n, 8, 6, b->d_res, 8, b->stream), "reduce"));
+    std::vector<double> r(8 * size_t(n));
+    HIPCHK(hipMemcpyAsync(r.data(), b->d_res, r.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    bool bad = false;
+    for (int k = 0; k < n; ++k) {
+        const double *v = &r[8 * size_t(k)];
+        double *o = out + 6 * size_t(k);
+        o[0] = double(b->step);
+        o[1] = v[0]; o[2] = v[1]; o[3] = v[2];
+        o[4] = !b->have_prev ? INFINITY : (v[4] > 0 ? v[3] / v[4] : (v[3] > 0 ? INFINITY : 0.0));
+        o[5] = v[5];
+        bad = bad || v[5] > 0;
+    }
+    b->have_prev = true;
+    // per-lattice views now hold a fresh snapshot too
+    for (lbm_ctx *c : b->lat) {
+        c->have_prev = true;
+        c->last_diag_step = -1;
+    }
+    if (bad) return fail(LBM_EUNSTABLE, "non-finite values in at least one lattice");
+    return LBM_OK;
+}
+
+lbm_ctx *lbm_batch_lattice(lbm_batch *b, int32_t k) {
+    if (!b || k < 0 || k >= int32_t(b->lat.size())) {
+        fail(LBM_EINVAL, "no lattice %d in batch", k);
+        return nullptr;
+    }
+    return b->lat[k];
+}
+
+lbm_status lbm_batch_destroy(lbm_batch *b) {
+    if (!b) return LBM_OK;
+    hipError_t e = hipStreamSynchronize(b->stream);
+    for (int i = 0; i < 2; ++i)
+        if (b->graph[i]) (void)hipGraphExecDestroy(b->graph[i]);
+    for (lbm_ctx *c : b->lat) delete c;
+    delete b;
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+}  // extern "C"

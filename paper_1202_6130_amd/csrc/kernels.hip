@@ -1,0 +1,607 @@
+// HIP kernels (gfx950) of the wetting-model lattice-Boltzmann library and the
+// host launchers the C ABI calls.  See lbm.h for the update they implement.
+//
+// Hot kernel, k_step: one wavefront owns a strip of 62 output columns (lanes
+// 1..62; lanes 0 and 63 are halo columns whose pseudo-potential is recomputed
+// from their own pulled populations) and a segment of rows.  It marches down
+// the rows keeping psi of rows y-1, y, y+1 in registers, so every population
+// is loaded from HBM once per segment (plus one halo row above and below) and
+// x-neighbours of psi come from adjacent lanes.  Pull streaming: the loads of
+// a row are nine coalesced row reads (shifted by -c_i), the stores nine
+// aligned row writes, population planes in SoA [9][ny][nx].
+#include "launch.hpp"
+#include "lbm_device.hpp"
+
+namespace lbmwet {
+
+// ---------------------------------------------------------------- marching
+// Walks one (strip, segment) tile and hands every row's node data to `act`.
+template <class S, class C, int WALL, class Act>
+__device__ inline void march(const LatDev<C> &L, const void *src, uint32_t strip, uint32_t seg, Act &act) {
+    using Raw = typename Codec<S>::Raw;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t nx = L.nx, ny = L.ny;
+    const int col = int(strip * kStripCols) - 1 + lane;             // >= -1
+    const uint32_t x = col < 0 ? nx - 1 : uint32_t(col) % nx;
+    const bool active = lane >= 1 && lane <= kStripCols && col < int(nx);
+
+    RowLoader<S> ld;
+    ld.buf.init(src, 9u * L.plane * uint32_t(sizeof(S)));
+    ld.plane = L.plane;
+    ld.x = x;
+    ld.xm = wrap_dec(x, nx);
+    ld.xp = wrap_inc(x, nx);
+    const uint32_t y0 = seg * L.seg_rows;
+    const uint32_t y1 = min(y0 + L.seg_rows, ny);
+
+    const C w1 = C(1.0 / 9.0), w2 = C(1.0 / 36.0);
+    C f_c[Q], f_n[Q];
+    Raw r_a[Q], r_n[Q];
+
+    // rows y0-1 (psi only) and y0, and the prefetch of y0+1
+    const uint32_t ya = wrap_dec(y0, ny), yb = wrap_inc(y0, ny);
+    ld.load(wrap_dec(ya, ny) * nx, ya * nx, y0 * nx, r_a);
+    ld.load(ya * nx, y0 * nx, yb * nx, r_n);
+    decode_row<S, C>(r_a, f_n, L.rho_ref);
+    C psi_m = psi_of<C>(density<C>(f_n));
+    decode_row<S, C>(r_n, f_c, L.rho_ref);
+    C rho_c = density<C>(f_c);
+    C psi_c = psi_of<C>(rho_c);
+#if LBM_PREFETCH
+    ld.load(y0 * nx, yb * nx, wrap_inc(yb, ny) * nx, r_n);
+#endif
+
+    // One row: consume the populations of row y+1 (cur), optionally after
+    // issuing the loads of row y+2 (into nxt), then hand row y to `act`.  The
+    // two raw buffers swap roles from row to row, so no register holding a
+    // load in flight is ever copied (a copy would wait for the load).
+    auto row = [&](uint32_t y, bool prefetch, Raw(&cur)[Q], Raw(&nxt)[Q]) {
+        const uint32_t yn = wrap_inc(y, ny);
+#if LBM_PREFETCH
+        if (prefetch) {
+            const uint32_t y2 = wrap_inc(yn, ny);
+            ld.load(yn * nx, y2 * nx, wrap_inc(y2, ny) * nx, nxt);
+        }
+#else
+        (void)prefetch;
+        (void)nxt;
+        ld.load(y * nx, yn * nx, wrap_inc(yn, ny) * nx, cur);
+#endif
+        decode_row<S, C>(cur, f_n, L.rho_ref);
+        const C rho_n = density<C>(f_n);
+        const C psi_p = psi_of<C>(rho_n);
+        // sum_i w_i psi(x + c_i) c_i, grouped by column
+        const C a = w1 * psi_c + w2 * (psi_p + psi_m);
+        const C b = psi_p - psi_m;
+        const C sx = from_right<C>(a) - from_left<C>(a);
+        const C sy = w1 * b + w2 * (from_right<C>(b) + from_left<C>(b));
+        act.row(L, y, x, active, f_c, rho_c, psi_c, sx, sy);
+        psi_m = psi_c;
+        psi_c = psi_p;
+        rho_c = rho_n;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f_c[i] = f_n[i];
+    };
+    // r_n holds row y0+1.  Rows come in pairs (r_n -> r_a, then r_a -> r_n);
+    // every row but the last prefetches (the last of all needs nothing more,
+    // the one before it loads the halo row y1 below the segment).
+    uint32_t y = y0;
+    for (; y + 2 < y1; y += 2) {
+        row(y, true, r_n, r_a);
+        row(y + 1, true, r_a, r_n);
+    }
+    if (y + 1 < y1) {
+        row(y, true, r_n, r_a);
+        row(y + 1, false, r_a, r_n);
+    } else {
+        row(y, false, r_n, r_a);
+    }
+}
+
+template <class C, int WALL>
+__device__ inline void wall_terms(const LatDev<C> &L, uint32_t y, uint32_t n, C &phie, C &Sx, C &Sy) {
+    if (WALL == WALL_ROW) {
+        phie = L.row_tab[2 * y];
+        Sx = C(0);
+        Sy = L.row_tab[2 * y + 1];
+    } else {
+        phie = L.node_tab[n];
+        Sx = L.node_tab[L.plane + n];
+        Sy = L.node_tab[2 * L.plane + n];
+    }
+}
+
+// Collide and store (the time step).
+template <class S, class C, int WALL> struct StepAct {
+    PopBuf<S> dst;
+    __device__ inline void row(const LatDev<C> &L, uint32_t y, uint32_t x, bool active, C f[Q],
+                               C rho, C psi_c, C sx, C sy) {
+        const uint32_t n = y * L.nx + x;
+        C phie, Sx, Sy;
+        wall_terms<C, WALL>(L, y, n, phie, Sx, Sy);
+        NodeState<C> s = node_forces<C>(f, rho, psi_c, sx, sy, phie, Sx, Sy, L.G, L.Ux, L.Uy, L.Fx, L.Fy);
+        collide<C>(f, s, L.omega);
+        if (active) {
+            const uint32_t row = y * L.nx;
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                dst.store(Codec<S>::template encode<C>(f[i], i, L.rho_ref), x, i * L.plane + row);
+        }
+    }
+};
+
+// Diagnostics: reported fields, FP64 totals, residual against the snapshot.
+template <class S, class C, int WALL> struct DiagAct {
+    int write_mom, compare, update;
+    double s_rho = 0, s_jx = 0, s_jy = 0, s_du = 0, s_u = 0, s_bad = 0;
+    __device__ inline void row(const LatDev<C> &L, uint32_t y, uint32_t x, bool active, C f[Q],
+                               C rho, C psi_c, C sx, C sy) {
+        const uint32_t n = y * L.nx + x;
+        C phie, Sx, Sy;
+        wall_terms<C, WALL>(L, y, n, phie, Sx, Sy);
+        NodeState<C> s = node_forces<C>(f, rho, psi_c, sx, sy, phie, Sx, Sy, L.G, L.Ux, L.Uy, L.Fx, L.Fy);
+        const C vx = s.ux + C(0.5) * s.Fx * s.inv_rho;
+        const C vy = s.uy + C(0.5) * s.Fy * s.inv_rho;
+        if (!active) return;
+        if (write_mom) {
+            L.mom[n] = rho;
+            L.mom[L.plane + n] = vx;
+            L.mom[2 * L.plane + n] = vy;
+        }
+        const bool ok = isfinite(double(rho)) && isfinite(double(vx)) && isfinite(double(vy));
+        s_bad += ok ? 0.0 : 1.0;
+        s_rho += double(rho);
+        s_jx += double(rho) * double(s.ux);
+        s_jy += double(rho) * double(s.uy);
+        if (compare) s_du += fabs(double(vx) - double(L.uprev[n])) + fabs(double(vy) - double(L.uprev[L.plane + n]));
+        s_u += fabs(double(vx)) + fabs(double(vy));
+        if (update) {
+            L.uprev[n] = vx;
+            L.uprev[L.plane + n] = vy;
+        }
+    }
+};
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Global wave index of the calling wave, uniform across the wave.
+__device__ inline uint32_t logical_wave() {
+    const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    return lb * kBlockWaves + w;
+}
+
+// ---------------------------------------------------------------- kernels
+template <class S, class C, int WALL>
+__global__ __launch_bounds__(256) void k_step(LatDev<C> L, const void *__restrict__ src, void *__restrict__ dst) {
+    const uint32_t gw = logical_wave();
+    if (gw >= L.strips * L.segs) return;
+    const uint32_t seg = gw / L.strips, strip = gw - seg * L.strips;
+    StepAct<S, C, WALL> act;
+    act.dst.init(dst, 9u * L.plane * uint32_t(sizeof(S)));
+    march<S, C, WALL>(L, src, strip, seg, act);
+}
+
+// Batched step: one launch over the tiles of many lattices.  work[g] =
+// (lattice, strip, segment) of global wave g, lattices in order.
+template <class S, class C, int WALL>
+__global__ __launch_bounds__(256) void k_step_batch(const LatDev<C> *__restrict__ lats,
+                                                    const uint4 *__restrict__ work, uint32_t nwork, int parity) {
+    const uint32_t gw = logical_wave();
+    if (gw >= nwork) return;
+    const uint4 wk = work[gw];
+    const LatDev<C> L = lats[wk.x];
+    const void *src = parity ? L.fb : L.fa;
+    StepAct<S, C, WALL> act;
+    act.dst.init(parity ? L.fa : L.fb, 9u * L.plane * uint32_t(sizeof(S)));
+    march<S, C, WALL>(L, src, wk.y, wk.z, act);
+}
+
+template <class S, class C, int WALL>
+__global__ __launch_bounds__(256) void k_diag(const LatDev<C> *__restrict__ lats, const uint4 *__restrict__ work,
+                                              uint32_t nwork, LatDev<C> single, int parity, int write_mom,
+                                              int compare, int update) {
+    const uint32_t gw = logical_wave();
+    uint32_t nw = lats ? nwork : single.strips * single.segs;
+    if (gw >= nw) return;
+    LatDev<C> L;
+    uint32_t strip, seg;
+    if (lats) {
+        const uint4 wk = work[gw];
+        L = lats[wk.x];
+        strip = wk.y;
+        seg = wk.z;
+    } else {
+        L = single;
+        seg = gw / L.strips;
+        strip = gw - seg * L.strips;
+    }
+    const void *src = parity ? L.fb : L.fa;
+    DiagAct<S, C, WALL> act;
+    act.write_mom = write_mom;
+    act.compare = compare;
+    act.update = update;
+    march<S, C, WALL>(L, src, strip, seg, act);
+    const double v[6] = {act.s_rho, act.s_jx, act.s_jy, act.s_du, act.s_u, act.s_bad};
+    double *out = L.partials + 8 * size_t(gw - L.wave0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double t = wave_sum(v[k]);
+        if ((threadIdx.x & (kWave - 1)) == 0) out[k] = t;
+    }
+}
+
+// Deterministic reduction of partial rows: out[b*out_stride + j] = sum over
+// rows r in [ranges[2b], ranges[2b+1]) of part[r*stride + j], j < width, in a
+// fixed order.  One block per output row.
+__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ part, const uint32_t *__restrict__ ranges,
+                                                uint32_t stride, uint32_t width, double *__restrict__ out,
+                                                uint32_t out_stride) {
+    __shared__ double sm[256];
+    const uint32_t b = blockIdx.x;
+    const uint32_t beg = ranges[2 * b], end = ranges[2 * b + 1];
+    for (uint32_t j = 0; j < width; ++j) {
+        double acc = 0.0;
+        for (uint32_t r = beg + threadIdx.x; r < end; r += blockDim.x) acc += part[size_t(r) * stride + j];
+        sm[threadIdx.x] = acc;
+        __syncthreads();
+        for (uint32_t s = blockDim.x / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[size_t(b) * out_stride + j] = sm[0];
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------ contact-angle isoline pass
+// mode 0: (n, sum x, sum y)
+// mode 1: algebraic circle sums about (mx, my):
+//         (n, Sx, Sy, Sxx, Sxy, Syy, Sxq, Syq, Sq), q = x^2 + y^2
+// mode 2: Gauss-Newton normal equations of r = |p - c| - R about (mx, my):
+//         (n, J00, J01, J02, J11, J12, J22, g0, g1, g2), g = -J^T r
+struct IsoArgs {
+    uint32_t nx, ny;
+    int per_node;          // phi indexed per node (else per row)
+    int mode;
+    double iso, phi_max, mx, my, xc, yc, R;
+};
+
+__device__ inline void iso_accumulate(const IsoArgs &a, double px, double py, double acc[10]) {
+    const double x = px - a.mx, y = py - a.my;
+    acc[0] += 1.0;
+    if (a.mode == 0) {
+        acc[1] += px;
+        acc[2] += py;
+    } else if (a.mode == 1) {
+        const double q = x * x + y * y;
+        acc[1] += x; acc[2] += y; acc[3] += x * x; acc[4] += x * y; acc[5] += y * y;
+        acc[6] += x * q; acc[7] += y * q; acc[8] += q;
+    } else {
+        const double dx = x - a.xc, dy = y - a.yc;
+        const double d = sqrt(dx * dx + dy * dy);
+        const double j0 = -dx / d, j1 = -dy / d, j2 = -1.0, r = d - a.R;
+        acc[1] += j0 * j0; acc[2] += j0 * j1; acc[3] += j0 * j2;
+        acc[4] += j1 * j1; acc[5] += j1 * j2; acc[6] += j2 * j2;
+        acc[7] -= j0 * r; acc[8] -= j1 * r; acc[9] -= j2 * r;
+    }
+}
+
+template <class C>
+__global__ __launch_bounds__(256) void k_isoline(IsoArgs a, const C *__restrict__ rho,
+                                                 const double *__restrict__ phi, double *__restrict__ part) {
+    __shared__ double sm[kBlockWaves][10];
+    double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const uint32_t N = a.nx * a.ny;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < N) {
+        const uint32_t y = n / a.nx, x = n - y * a.nx;
+        const double pa = a.per_node ? phi[n] : phi[y];
+        if (pa < a.phi_max) {
+            const double ra = double(rho[n]);
+            const bool ia = ra >= a.iso;
+            const uint32_t xr = x + 1 == a.nx ? 0 : x + 1;
+            const uint32_t nr = y * a.nx + xr;
+            const double pr = a.per_node ? phi[nr] : phi[y];
+            const double rr = double(rho[nr]);
+            if (pr < a.phi_max && ia != (rr >= a.iso)) {
+                const double t = (a.iso - ra) / (rr - ra);
+                iso_accumulate(a, double(x) + t, double(y), acc);
+            }
+            if (y + 1 < a.ny) {
+                const uint32_t nu = n + a.nx;
+                const double pu = a.per_node ? phi[nu] : phi[y + 1];
+                const double ru = double(rho[nu]);
+                if (pu < a.phi_max && ia != (ru >= a.iso)) {
+                    const double t = (a.iso - ra) / (ru - ra);
+                    iso_accumulate(a, double(x), double(y) + t, acc);
+                }
+            }
+        }
+    }
+    const uint32_t w = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) {
+        const double t = wave_sum(acc[k]);
+        if ((threadIdx.x & (kWave - 1)) == 0) sm[w][k] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 10) {
+        double s = 0.0;
+        for (int i = 0; i < kBlockWaves; ++i) s += sm[i][threadIdx.x];
+        part[size_t(blockIdx.x) * 10 + threadIdx.x] = s;
+    }
+}
+
+// x-sums of the reported u_x per row (slip profile); one block per row.
+template <class C>
+__global__ __launch_bounds__(256) void k_profile(uint32_t nx, const C *__restrict__ ux, double *__restrict__ out) {
+    __shared__ double sm[256];
+    const uint32_t y = blockIdx.x;
+    double acc = 0.0;
+    for (uint32_t x = threadIdx.x; x < nx; x += blockDim.x) acc += double(ux[size_t(y) * nx + x]);
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (uint32_t s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[y] = sm[0];
+}
+
+// ------------------------------------------------------------ state copies
+__device__ inline double feq_component(int q, double rho, double ux, double uy) {
+    const double cu = kCx[q] * ux + kCy[q] * uy;
+    return kW[q] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy));
+}
+
+// Stored (pre-stream) populations such that pulling yields feq(rho0, u0):
+// stored_q(x) = feq_q at node x + c_q.
+template <class S, class C>
+__global__ __launch_bounds__(256) void k_init(uint32_t nx, uint32_t ny, const double *__restrict__ rho0,
+                                              const double *__restrict__ ux0, const double *__restrict__ uy0,
+                                              typename Codec<S>::Raw *__restrict__ dst, C rho_ref) {
+    const uint32_t N = nx * ny;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const uint32_t y = n / nx, x = n - y * nx;
+    for (int q = 0; q < Q; ++q) {
+        const uint32_t xs = (x + nx + kCx[q]) % nx, ys = (y + ny + kCy[q]) % ny;
+        const uint32_t m = ys * nx + xs;
+        const double v = feq_component(q, rho0[m], ux0 ? ux0[m] : 0.0, uy0 ? uy0[m] : 0.0);
+        dst[q * N + n] = Codec<S>::template encode<C>(C(v), q, rho_ref);
+    }
+}
+
+// Post-streaming plane q as float64: out(x) = stored_q(x - c_q), decoded
+// exactly as the step kernel decodes it.
+template <class S, class C>
+__global__ __launch_bounds__(256) void k_get_plane(uint32_t nx, uint32_t ny, int q,
+                                                   const typename Codec<S>::Raw *__restrict__ src,
+                                                   double *__restrict__ out, C rho_ref) {
+    const uint32_t N = nx * ny;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const uint32_t y = n / nx, x = n - y * nx;
+    const uint32_t xs = (x + nx - kCx[q]) % nx, ys = (y + ny - kCy[q]) % ny;
+    out[n] = double(Codec<S>::template decode<C>(src[q * N + ys * nx + xs], q, rho_ref));
+}
+
+// Inverse of k_get_plane: stored_q(x) = in(x + c_q).
+template <class S, class C>
+__global__ __launch_bounds__(256) void k_set_plane(uint32_t nx, uint32_t ny, int q, const double *__restrict__ in,
+                                                   typename Codec<S>::Raw *__restrict__ dst, C rho_ref) {
+    const uint32_t N = nx * ny;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const uint32_t y = n / nx, x = n - y * nx;
+    const uint32_t xs = (x + nx + kCx[q]) % nx, ys = (y + ny + kCy[q]) % ny;
+    dst[q * N + n] = Codec<S>::template encode<C>(C(in[ys * nx + xs]), q, rho_ref);
+}
+
+// ------------------------------------------------------------- wall tables
+__device__ inline double step_profile(double s, double w) { return 0.5 * (1.0 - tanh(s / w)); }
+
+// Signed distance of row y to the nearest face of the solid band
+// [ny - P, ny) (faces on rows 0 and ny - P), negative inside the band.
+__device__ inline double slab_distance(int y, int ny, int P) {
+    if (y <= ny - P) {
+        const int a = y, b = ny - P - y;
+        return double(a < b ? a : b);
+    }
+    const int a = y - (ny - P), b = ny - y;
+    return -double(a < b ? a : b);
+}
+
+// Per-row tables for a flat slab (or all zeros when P == 0):
+//   tab[2y] = phi(y)^eps,  tab[2y+1] = S_y(y) = sum_i w_i psi_FS(y + c_iy) c_iy,
+//   psi_FS = G_A psiA - G_R psiR;  phi_raw[y] = phi(y) in float64.
+template <class C>
+__global__ __launch_bounds__(256) void k_walls_row(int ny, int P, double width, double core, double tail,
+                                                   double eps, double GR, double GA, C *__restrict__ tab,
+                                                   double *__restrict__ phi_raw) {
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= ny) return;
+    if (P <= 0) {
+        tab[2 * y] = C(0);
+        tab[2 * y + 1] = C(0);
+        phi_raw[y] = 0.0;
+        return;
+    }
+    auto psi_fs = [&](int yy) {
+        const double s = slab_distance(((yy % ny) + ny) % ny, ny, P);
+        const double r = step_profile(s, core);
+        const double a = step_profile(s, tail) - r;
+        return GA * a - GR * r;
+    };
+    double sy = 0.0;
+    for (int q = 0; q < Q; ++q) sy += kW[q] * psi_fs(y + kCy[q]) * kCy[q];
+    const double phi = step_profile(slab_distance(y, ny, P), width);
+    tab[2 * y] = C(pow(phi, eps));
+    tab[2 * y + 1] = C(sy);
+    phi_raw[y] = phi;
+}
+
+// Per-node tables from caller fields (phi, psiR, psiA), each [ny][nx]:
+//   tab = [phi^eps | S_x | S_y], phi_raw = phi.
+template <class C>
+__global__ __launch_bounds__(256) void k_walls_node(uint32_t nx, uint32_t ny, const double *__restrict__ fields,
+                                                    double eps, double GR, double GA, C *__restrict__ tab,
+                                                    double *__restrict__ phi_raw) {
+    const uint32_t N = nx * ny;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const uint32_t y = n / nx, x = n - y * nx;
+    double sx = 0.0, sy = 0.0;
+    for (int q = 0; q < Q; ++q) {
+        const uint32_t m = ((y + ny + kCy[q]) % ny) * nx + (x + nx + kCx[q]) % nx;
+        const double fs = GA * fields[2 * size_t(N) + m] - GR * fields[size_t(N) + m];
+        sx += kW[q] * fs * kCx[q];
+        sy += kW[q] * fs * kCy[q];
+    }
+    const double phi = fields[n];
+    tab[n] = C(pow(phi, eps));
+    tab[N + n] = C(sx);
+    tab[2 * size_t(N) + n] = C(sy);
+    phi_raw[n] = phi;
+}
+
+// ================================================================ launchers
+static inline uint32_t blocks_for(uint32_t waves) { return (waves + kBlockWaves - 1) / kBlockWaves; }
+static inline uint32_t blocks_nodes(uint32_t n) { return (n + 255) / 256; }
+
+// Calls fn(S{}, C{}) with the storage/arithmetic pair of a storage code.
+template <class Fn> static hipError_t dispatch(int storage, Fn &&fn) {
+    switch (storage) {
+    case STORE_F32: return fn(float{}, float{});
+    case STORE_F16: return fn(__half{}, float{});
+    case STORE_F64: return fn(double{}, double{});
+    case STORE_F32X: return fn(float{}, double{});
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step(int storage, const LatDevAny &L, int wall, int parity, hipStream_t st) {
+    return dispatch(storage, [&](auto s, auto c) {
+        using S = decltype(s);
+        using C = decltype(c);
+        LatDev<C> d = L.get<C>();
+        const uint32_t waves = d.strips * d.segs;
+        const void *src = parity ? d.fb : d.fa;
+        void *dst = parity ? d.fa : d.fb;
+        if (wall == WALL_ROW)
+            hipLaunchKernelGGL((k_step<S, C, WALL_ROW>), dim3(blocks_for(waves)), dim3(256), 0, st, d, src, dst);
+        else
+            hipLaunchKernelGGL((k_step<S, C, WALL_NODE>), dim3(blocks_for(waves)), dim3(256), 0, st, d, src, dst);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_step_batch(const void *lats, const uint4 *work, uint32_t nwork, int parity, hipStream_t st) {
+    hipLaunchKernelGGL((k_step_batch<float, float, WALL_ROW>), dim3(blocks_for(nwork)), dim3(256), 0, st,
+                       (const LatDev<float> *)lats, work, nwork, parity);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag(int storage, const void *lats, const uint4 *work, uint32_t nwork, const LatDevAny &single,
+                       int wall, int parity, int write_mom, int compare, int update, hipStream_t st) {
+    return dispatch(storage, [&](auto s, auto c) {
+        using S = decltype(s);
+        using C = decltype(c);
+        LatDev<C> d = single.get<C>();
+        const uint32_t waves = lats ? nwork : d.strips * d.segs;
+        if (wall == WALL_ROW)
+            hipLaunchKernelGGL((k_diag<S, C, WALL_ROW>), dim3(blocks_for(waves)), dim3(256), 0, st,
+                               (const LatDev<C> *)lats, work, nwork, d, parity, write_mom, compare, update);
+        else
+            hipLaunchKernelGGL((k_diag<S, C, WALL_NODE>), dim3(blocks_for(waves)), dim3(256), 0, st,
+                               (const LatDev<C> *)lats, work, nwork, d, parity, write_mom, compare, update);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_reduce(const double *part, const uint32_t *ranges, uint32_t nout, uint32_t stride,
+                         uint32_t width, double *out, uint32_t out_stride, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce, dim3(nout), dim3(256), 0, st, part, ranges, stride, width, out, out_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_isoline(int f64, const IsoParams &p, const void *rho, const double *phi, double *part,
+                          hipStream_t st) {
+    IsoArgs a{p.nx, p.ny, p.per_node, p.mode, p.iso, p.phi_max, p.mx, p.my, p.xc, p.yc, p.R};
+    const uint32_t nb = blocks_nodes(p.nx * p.ny);
+    if (f64)
+        hipLaunchKernelGGL(k_isoline<double>, dim3(nb), dim3(256), 0, st, a, (const double *)rho, phi, part);
+    else
+        hipLaunchKernelGGL(k_isoline<float>, dim3(nb), dim3(256), 0, st, a, (const float *)rho, phi, part);
+    return hipGetLastError();
+}
+
+uint32_t isoline_blocks(uint32_t nodes) { return blocks_nodes(nodes); }
+
+hipError_t launch_profile(int f64, uint32_t nx, uint32_t ny, const void *ux, double *out, hipStream_t st) {
+    if (f64)
+        hipLaunchKernelGGL(k_profile<double>, dim3(ny), dim3(256), 0, st, nx, (const double *)ux, out);
+    else
+        hipLaunchKernelGGL(k_profile<float>, dim3(ny), dim3(256), 0, st, nx, (const float *)ux, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int storage, uint32_t nx, uint32_t ny, const double *rho0, const double *ux0,
+                       const double *uy0, void *dst, double rho_ref, hipStream_t st) {
+    const uint32_t nb = blocks_nodes(nx * ny);
+    return dispatch(storage, [&](auto s, auto c) {
+        using S = decltype(s);
+        using C = decltype(c);
+        hipLaunchKernelGGL((k_init<S, C>), dim3(nb), dim3(256), 0, st, nx, ny, rho0, ux0, uy0,
+                           (typename Codec<S>::Raw *)dst, C(rho_ref));
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_plane(int storage, int set, uint32_t nx, uint32_t ny, int q, void *pop, double *buf,
+                        double rho_ref, hipStream_t st) {
+    const uint32_t nb = blocks_nodes(nx * ny);
+    return dispatch(storage, [&](auto s, auto c) {
+        using S = decltype(s);
+        using C = decltype(c);
+        using Raw = typename Codec<S>::Raw;
+        if (set)
+            hipLaunchKernelGGL((k_set_plane<S, C>), dim3(nb), dim3(256), 0, st, nx, ny, q, buf, (Raw *)pop,
+                               C(rho_ref));
+        else
+            hipLaunchKernelGGL((k_get_plane<S, C>), dim3(nb), dim3(256), 0, st, nx, ny, q, (const Raw *)pop, buf,
+                               C(rho_ref));
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_walls_row(int f64, int ny, int P, double width, double core, double tail, double eps,
+                            double GR, double GA, void *tab, double *phi_raw, hipStream_t st) {
+    const uint32_t nb = blocks_nodes(uint32_t(ny));
+    if (f64)
+        hipLaunchKernelGGL(k_walls_row<double>, dim3(nb), dim3(256), 0, st, ny, P, width, core, tail, eps, GR,
+                           GA, (double *)tab, phi_raw);
+    else
+        hipLaunchKernelGGL(k_walls_row<float>, dim3(nb), dim3(256), 0, st, ny, P, width, core, tail, eps, GR,
+                           GA, (float *)tab, phi_raw);
+    return hipGetLastError();
+}
+
+hipError_t launch_walls_node(int f64, uint32_t nx, uint32_t ny, const double *fields, double eps, double GR,
+                             double GA, void *tab, double *phi_raw, hipStream_t st) {
+    const uint32_t nb = blocks_nodes(nx * ny);
+    if (f64)
+        hipLaunchKernelGGL(k_walls_node<double>, dim3(nb), dim3(256), 0, st, nx, ny, fields, eps, GR, GA,
+                           (double *)tab, phi_raw);
+    else
+        hipLaunchKernelGGL(k_walls_node<float>, dim3(nb), dim3(256), 0, st, nx, ny, fields, eps, GR, GA,
+                           (float *)tab, phi_raw);
+    return hipGetLastError();
+}
+
+}  // namespace lbmwet

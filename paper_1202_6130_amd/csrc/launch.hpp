@@ -1,0 +1,91 @@
+// Host-visible launchers of the library's kernels (kernels.hip) and the plain
+// descriptors they take.  Included by the C-ABI implementation (abi.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmwet {
+
+// storage code -> (stored type, arithmetic type):
+//   F32 (float, float), F16 (binary16 deviation, float), F64 (double, double),
+//   F32X (float, double)
+enum Storage : int { STORE_F32 = 0, STORE_F16 = 1, STORE_F64 = 2, STORE_F32X = 3 };
+
+template <class C> struct LatDev;
+
+// Type-erased lattice descriptor: float parameters kept in double and narrowed
+// to the arithmetic type when a launcher builds the kernel argument.
+struct LatDevAny {
+    uint32_t nx = 0, ny = 0, plane = 0;
+    uint32_t strips = 0, segs = 0, seg_rows = 0;
+    uint32_t wave0 = 0;
+    void *fa = nullptr, *fb = nullptr;
+    const void *row_tab = nullptr, *node_tab = nullptr;
+    void *mom = nullptr;
+    void *uprev = nullptr;
+    double *partials = nullptr;
+    double G = 0, omega = 1, Ux = 0, Uy = 0, Fx = 0, Fy = 0, rho_ref = 1;
+
+    template <class C> LatDev<C> get() const;
+};
+
+template <class C> struct LatDev {
+    uint32_t nx, ny, plane;
+    uint32_t strips, segs, seg_rows;
+    uint32_t wave0;
+    uint32_t pad0;
+    void *fa, *fb;
+    const C *row_tab;
+    const C *node_tab;
+    C *mom;
+    C *uprev;
+    double *partials;
+    C G, omega, Ux, Uy, Fx, Fy, rho_ref;
+};
+
+template <class C> inline LatDev<C> LatDevAny::get() const {
+    LatDev<C> d;
+    d.nx = nx; d.ny = ny; d.plane = plane;
+    d.strips = strips; d.segs = segs; d.seg_rows = seg_rows;
+    d.wave0 = wave0; d.pad0 = 0;
+    d.fa = fa; d.fb = fb;
+    d.row_tab = (const C *)row_tab;
+    d.node_tab = (const C *)node_tab;
+    d.mom = (C *)mom;
+    d.uprev = (C *)uprev;
+    d.partials = partials;
+    d.G = C(G); d.omega = C(omega); d.Ux = C(Ux); d.Uy = C(Uy);
+    d.Fx = C(Fx); d.Fy = C(Fy); d.rho_ref = C(rho_ref);
+    return d;
+}
+
+struct IsoParams {
+    uint32_t nx, ny;
+    int per_node, mode;
+    double iso, phi_max, mx, my, xc, yc, R;
+};
+
+constexpr uint32_t kStripColsHost = 62;
+constexpr uint32_t kBlockWavesHost = 4;
+
+hipError_t launch_step(int storage, const LatDevAny &L, int wall, int parity, hipStream_t st);
+hipError_t launch_step_batch(const void *lats, const uint4 *work, uint32_t nwork, int parity, hipStream_t st);
+hipError_t launch_diag(int storage, const void *lats, const uint4 *work, uint32_t nwork, const LatDevAny &single,
+                       int wall, int parity, int write_mom, int compare, int update, hipStream_t st);
+hipError_t launch_reduce(const double *part, const uint32_t *ranges, uint32_t nout, uint32_t stride,
+                         uint32_t width, double *out, uint32_t out_stride, hipStream_t st);
+hipError_t launch_isoline(int f64, const IsoParams &p, const void *rho, const double *phi, double *part,
+                          hipStream_t st);
+uint32_t isoline_blocks(uint32_t nodes);
+hipError_t launch_profile(int f64, uint32_t nx, uint32_t ny, const void *ux, double *out, hipStream_t st);
+hipError_t launch_init(int storage, uint32_t nx, uint32_t ny, const double *rho0, const double *ux0,
+                       const double *uy0, void *dst, double rho_ref, hipStream_t st);
+hipError_t launch_plane(int storage, int set, uint32_t nx, uint32_t ny, int q, void *pop, double *buf,
+                        double rho_ref, hipStream_t st);
+hipError_t launch_walls_row(int f64, int ny, int P, double width, double core, double tail, double eps,
+                            double GR, double GA, void *tab, double *phi_raw, hipStream_t st);
+hipError_t launch_walls_node(int f64, uint32_t nx, uint32_t ny, const double *fields, double eps, double GR,
+                             double GA, void *tab, double *phi_raw, hipStream_t st);
+
+}  // namespace lbmwet

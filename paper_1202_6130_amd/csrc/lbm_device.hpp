@@ -1,0 +1,274 @@
+// Device-side building blocks of the wetting-model lattice-Boltzmann step
+// (arXiv:1202.6130, Sec. II) for gfx950.  Shared by every kernel of the
+// library; nothing here is used by anything outside the library.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "launch.hpp"
+
+// Build-time switches (defaults are the production choice).
+#ifndef LBM_USE_BUFFER
+#define LBM_USE_BUFFER 1   // buffer loads/stores: scalar row offsets, 32-bit lane offsets
+#endif
+#ifndef LBM_PREFETCH
+#define LBM_PREFETCH 1     // issue the loads of row y+2 while row y is processed
+#endif
+#ifndef LBM_USE_DPP
+#define LBM_USE_DPP 1      // x-neighbours through DPP wave shifts (else ds_bpermute)
+#endif
+#ifndef LBM_PSI_EXPM1
+#define LBM_PSI_EXPM1 0    // psi = -expm1(-rho) instead of 1 - exp(-rho)
+#endif
+
+namespace lbmwet {
+
+// D2Q9, velocity order (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1).
+constexpr int Q = 9;
+constexpr int kCx[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int kCy[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr double kW[Q] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
+                          1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kStripCols = 62;     // output columns per wave (2 halo lanes)
+constexpr int kBlockWaves = 4;     // waves per 256-thread workgroup
+
+enum WallMode : int { WALL_ROW = 0, WALL_NODE = 1 };
+
+// ------------------------------------------------------------ storage codecs
+// Raw is the register image of one stored population; decode/encode convert
+// between it and the arithmetic type C.
+template <class S> struct Codec;
+template <> struct Codec<float> {
+    using Raw = uint32_t;
+    template <class C> __device__ static inline C decode(Raw r, int, C) { return C(__builtin_bit_cast(float, r)); }
+    template <class C> __device__ static inline Raw encode(C v, int, C) { return __builtin_bit_cast(Raw, float(v)); }
+};
+template <> struct Codec<double> {
+    using Raw = uint64_t;
+    template <class C> __device__ static inline C decode(Raw r, int, C) { return C(__builtin_bit_cast(double, r)); }
+    template <class C> __device__ static inline Raw encode(C v, int, C) { return __builtin_bit_cast(Raw, double(v)); }
+};
+// binary16 deviation from the rest equilibrium, scaled by the weight:
+// h_i = f_i / w_i - rho_ref  <=>  f_i = w_i (rho_ref + h_i)
+template <> struct Codec<__half> {
+    using Raw = uint16_t;
+    __device__ static inline float w(int q) { return q == 0 ? 4.0f / 9.0f : (q < 5 ? 1.0f / 9.0f : 1.0f / 36.0f); }
+    __device__ static inline float winv(int q) { return q == 0 ? 2.25f : (q < 5 ? 9.0f : 36.0f); }
+    template <class C> __device__ static inline C decode(Raw r, int q, C rho_ref) {
+        return C(w(q) * (float(rho_ref) + __half2float(__builtin_bit_cast(__half, r))));
+    }
+    template <class C> __device__ static inline Raw encode(C v, int q, C rho_ref) {
+        return __builtin_bit_cast(Raw, __float2half_rn(float(v) * winv(q) - float(rho_ref)));
+    }
+};
+
+// ------------------------------------------------------------ memory access
+// A population buffer [9][ny][nx] of S.  Element offsets are 32-bit; buffer
+// byte sizes are < 4 GiB (checked by the host).
+template <class S> struct PopBuf {
+    using Raw = typename Codec<S>::Raw;
+#if LBM_USE_BUFFER
+    __amdgpu_buffer_rsrc_t rsrc;
+    __device__ inline void init(const void *p, uint32_t bytes) {
+        // gfx9 raw buffer: stride 0, num_records in bytes, dword3 = 0x00020000
+        rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+    }
+    // lane offset in elements (varies per lane), uniform offset in elements
+    __device__ inline Raw load(uint32_t lane_el, uint32_t uni_el) const {
+        const int vo = int(lane_el * sizeof(S)), so = int(uni_el * sizeof(S));
+        if constexpr (sizeof(S) == 4) return __builtin_amdgcn_raw_buffer_load_b32(rsrc, vo, so, 0);
+        else if constexpr (sizeof(S) == 2) return __builtin_amdgcn_raw_buffer_load_b16(rsrc, vo, so, 0);
+        else return __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b64(rsrc, vo, so, 0));
+    }
+    __device__ inline void store(Raw v, uint32_t lane_el, uint32_t uni_el) const {
+        const int vo = int(lane_el * sizeof(S)), so = int(uni_el * sizeof(S));
+        if constexpr (sizeof(S) == 4) __builtin_amdgcn_raw_buffer_store_b32(v, rsrc, vo, so, 0);
+        else if constexpr (sizeof(S) == 2) __builtin_amdgcn_raw_buffer_store_b16(v, rsrc, vo, so, 0);
+        else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(rsrc, 0, 0, 0)), v), rsrc, vo, so, 0);
+    }
+#else
+    Raw *base;
+    __device__ inline void init(const void *p, uint32_t) { base = (Raw *)p; }
+    __device__ inline Raw load(uint32_t lane_el, uint32_t uni_el) const { return base[uni_el + lane_el]; }
+    __device__ inline void store(Raw v, uint32_t lane_el, uint32_t uni_el) const { base[uni_el + lane_el] = v; }
+#endif
+};
+
+// Wrapped neighbour column/row indices.
+__device__ inline uint32_t wrap_dec(uint32_t v, uint32_t n) { return v == 0 ? n - 1 : v - 1; }
+__device__ inline uint32_t wrap_inc(uint32_t v, uint32_t n) { return v + 1 == n ? 0 : v + 1; }
+
+// Logical workgroup index: consecutive hardware workgroups are dealt round
+// robin to the 8 XCDs, each with its own L2.  Remap so that each XCD owns one
+// contiguous range of logical workgroups (adjacent tiles share halo lines).
+__device__ inline uint32_t xcd_logical_block(uint32_t b, uint32_t nb) {
+    const uint32_t nxcd = 8;
+    uint32_t xcd = b % nxcd, local = b / nxcd;
+    uint32_t base = xcd * (nb / nxcd) + min(xcd, nb % nxcd);
+    return base + local;
+}
+
+template <class C> __device__ inline C cexp(C v);
+template <> __device__ inline float cexp<float>(float v) { return __expf(v); }
+template <> __device__ inline double cexp<double>(double v) { return exp(v); }
+
+// Cross-lane neighbours along x (lane -1 / lane +1).  Halo lanes 0 and 63
+// receive values they never use.
+#if LBM_USE_DPP
+__device__ inline int dpp_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
+__device__ inline int dpp_shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false); }
+template <class C> __device__ inline C from_left(C v);
+template <class C> __device__ inline C from_right(C v);
+template <> __device__ inline float from_left<float>(float v) {
+    return __builtin_bit_cast(float, dpp_shr1(__builtin_bit_cast(int, v)));
+}
+template <> __device__ inline float from_right<float>(float v) {
+    return __builtin_bit_cast(float, dpp_shl1(__builtin_bit_cast(int, v)));
+}
+template <> __device__ inline double from_left<double>(double v) {
+    int2 p = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(dpp_shr1(p.x), dpp_shr1(p.y)));
+}
+template <> __device__ inline double from_right<double>(double v) {
+    int2 p = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(dpp_shl1(p.x), dpp_shl1(p.y)));
+}
+#else
+template <class C> __device__ inline C from_left(C v) { return __shfl_up(v, 1, kWave); }
+template <class C> __device__ inline C from_right(C v) { return __shfl_down(v, 1, kWave); }
+#endif
+
+// Raw post-streaming populations of one row (pull: f_i(x) = f'_i(x - c_i)).
+template <class S> struct RowLoader {
+    using Raw = typename Codec<S>::Raw;
+    PopBuf<S> buf;
+    uint32_t plane;
+    uint32_t x, xm, xp;            // this lane's column and its wrapped neighbours
+
+    // rm/r0/rp: element offsets (row * nx) of rows r-1, r, r+1
+    __device__ inline void load(uint32_t rm, uint32_t r0, uint32_t rp, Raw f[Q]) const {
+        f[0] = buf.load(x, 0 * plane + r0);
+        f[1] = buf.load(xm, 1 * plane + r0);
+        f[2] = buf.load(x, 2 * plane + rm);
+        f[3] = buf.load(xp, 3 * plane + r0);
+        f[4] = buf.load(x, 4 * plane + rp);
+        f[5] = buf.load(xm, 5 * plane + rm);
+        f[6] = buf.load(xp, 6 * plane + rm);
+        f[7] = buf.load(xp, 7 * plane + rp);
+        f[8] = buf.load(xm, 8 * plane + rp);
+    }
+};
+
+template <class S, class C>
+__device__ inline void decode_row(const typename Codec<S>::Raw r[Q], C f[Q], C rho_ref) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = Codec<S>::template decode<C>(r[i], i, rho_ref);
+}
+
+template <class C> __device__ inline C density(const C f[Q]) {
+    return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+}
+
+// Pseudo-potential of the fluid-fluid force.
+template <class C> __device__ inline C psi_of(C rho) {
+#if LBM_PSI_EXPM1
+    return -expm1(rho * C(-1));
+#else
+    return C(1) - cexp<C>(-rho);
+#endif
+}
+
+// Lattice constants in the arithmetic type.  In binary32 the rounded D2Q9
+// weights sum to 1 + 2^-27 and the momentum coefficients 6 w1 + 12 w2 to
+// 1 + 2^-27, so every collision would create mass and momentum at that rate.
+// The binary32 set below keeps w0, w1 and 3 w1 = 1/3 at their nearest values
+// and moves w2 and 3 w2 down by one unit in the last place: then
+// w0 + 4 w1 + 4 w2 = 1 and 2 (3 w1) + 4 (3 w2) = 1 hold exactly.
+template <class C> struct LatConst;
+template <> struct LatConst<float> {
+    static constexpr float w0 = 0x1.c71c72p-2f;   // 4/9
+    static constexpr float w1 = 0x1.c71c72p-4f;   // 1/9
+    static constexpr float w2 = 0x1.c71c70p-6f;   // 1/36, one ulp low
+    static constexpr float m1 = 0x1.555556p-2f;   // 3 w1 = 1/3
+    static constexpr float m2 = 0x1.555554p-4f;   // 3 w2 = 1/12, one ulp low
+};
+template <> struct LatConst<double> {
+    static constexpr double w0 = 4.0 / 9.0, w1 = 1.0 / 9.0, w2 = 1.0 / 36.0;
+    static constexpr double m1 = 1.0 / 3.0, m2 = 1.0 / 12.0;
+};
+
+// Everything the collision needs at one node.
+template <class C> struct NodeState {
+    C rho, inv_rho;
+    C jx, jy;                      // momentum j = sum_i f_i c_i (pre-force)
+    C ux, uy;                      // u = j / rho
+    C Fx, Fy;                      // total force density
+};
+
+// Forces of one node (eqs. force_SC, force_SC_FS, wall_shift) given the
+// neighbour sums of psi.
+//   sx = sum_i w_i psi(x+c_i) c_ix,  sy = sum_i w_i psi(x+c_i) c_iy
+template <class C>
+__device__ inline NodeState<C> node_forces(const C f[Q], C rho, C psi_c, C sx, C sy, C phie,
+                                           C Sx, C Sy, C G, C Ux, C Uy, C Fxe, C Fye) {
+    NodeState<C> s;
+    s.rho = rho;
+    s.inv_rho = C(1) / rho;
+    s.jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    s.jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    s.ux = s.jx * s.inv_rho;
+    s.uy = s.jy * s.inv_rho;
+    C ffx = -G * psi_c * sx;
+    C ffy = -G * psi_c * sy;
+    // long-range wall force: rho * S (S precomputed from the static psi_FS)
+    C lrx = rho * Sx, lry = rho * Sy;
+    // short-range exchange: phi^eps [rho (U - u) - F_FF]
+    C dsx = phie * (rho * (Ux - s.ux) - ffx);
+    C dsy = phie * (rho * (Uy - s.uy) - ffy);
+    s.Fx = ((ffx + lrx) + dsx) + Fxe;
+    s.Fy = ((ffy + lry) + dsy) + Fye;
+    return s;
+}
+
+// Second-order equilibrium (eq. f2 at equilibrium, theta = 1/3) from density
+// and momentum m = rho u.  Opposite velocities share their even part A; the
+// odd part B is the momentum times 3 w_i, so sum_i feq_i c_i = m exactly in
+// real arithmetic with the constants above.
+template <class C> __device__ inline void equilibrium(C rho, C inv_rho, C mx, C my, C feq[Q]) {
+    using K = LatConst<C>;
+    const C ux = mx * inv_rho, uy = my * inv_rho;
+    const C base = C(1) - C(1.5) * (ux * ux + uy * uy);
+    const C r1 = K::w1 * rho, r2 = K::w2 * rho;
+    feq[0] = (K::w0 * rho) * base;
+    const C ax = r1 * (base + C(4.5) * ux * ux), bx = K::m1 * mx;
+    feq[1] = ax + bx;
+    feq[3] = ax - bx;
+    const C ay = r1 * (base + C(4.5) * uy * uy), by = K::m1 * my;
+    feq[2] = ay + by;
+    feq[4] = ay - by;
+    const C s = ux + uy, d = uy - ux;
+    const C as = r2 * (base + C(4.5) * s * s), bs = K::m2 * (mx + my);
+    feq[5] = as + bs;
+    feq[7] = as - bs;
+    const C ad = r2 * (base + C(4.5) * d * d), bd = K::m2 * (my - mx);
+    feq[6] = ad + bd;
+    feq[8] = ad - bd;
+}
+
+// EDM-BGK collision: f' = f - (f - feq(u))/tau + feq(u*) - feq(u)
+//                       = (1 - 1/tau) (f - feq(u)) + feq(u*),
+// with rho u* = j + F.
+template <class C> __device__ inline void collide(C f[Q], const NodeState<C> &s, C omega) {
+    C fu[Q], fs[Q];
+    equilibrium<C>(s.rho, s.inv_rho, s.jx, s.jy, fu);
+    equilibrium<C>(s.rho, s.inv_rho, s.jx + s.Fx, s.jy + s.Fy, fs);
+    const C keep = C(1) - omega;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = keep * (f[i] - fu[i]) + fs[i];
+}
+
+}  // namespace lbmwet

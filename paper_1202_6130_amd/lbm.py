@@ -1,0 +1,365 @@
+"""Python binding of the lbm C ABI (include/lbm.h).
+
+Argument marshalling only: every step of the update runs in the HIP library
+liblbmwet.so.  PyTorch supplies the device workspace (a uint8 tensor) and the
+current HIP stream.  Importing this module does not load the library; the
+first call does, and raises if it is missing or was built for nothing.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "liblbmwet.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ENOFIT, LBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
+STORE_F32, STORE_F16DEV, STORE_F64, STORE_F32X = 0, 1, 2, 3
+WALL_NONE, WALL_FLAT_SLAB, WALL_FIELDS = 0, 1, 2
+
+_NAMES = {LBM_EINVAL: "EINVAL", LBM_ENOMEM: "ENOMEM", LBM_EDEVICE: "EDEVICE", LBM_EUNSTABLE: "EUNSTABLE",
+          LBM_ENOFIT: "ENOFIT", LBM_ESTATE: "ESTATE"}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lbm {_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("wall_kind", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("G", ctypes.c_double),
+                ("G_R", ctypes.c_double), ("G_A", ctypes.c_double), ("eps", ctypes.c_double),
+                ("U_wall", ctypes.c_double * 2), ("F_ext", ctypes.c_double * 2),
+                ("wall_width", ctypes.c_double), ("core_range", ctypes.c_double),
+                ("tail_range", ctypes.c_double), ("rho_ref", ctypes.c_double),
+                ("slab_rows", ctypes.c_int32), ("diag_interval", ctypes.c_int32),
+                ("seg_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """Load liblbmwet.so (in-tree build).  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run python -m paper_1202_6130_amd.build)")
+    # PyTorch bundles its own HIP runtime with the same soname as the system
+    # one.  Load torch first so the library binds to that runtime: one
+    # process must not hold two HIP runtimes (workspace and streams come from
+    # torch).
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(lbm_params)
+    i64 = ctypes.c_int64
+    sig = {
+        "lbm_params_default": ([P], ctypes.c_int),
+        "lbm_last_error": ([], ctypes.c_char_p),
+        "lbm_workspace_bytes": ([P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "lbm_create": ([P, _dp, _dp, _dp, _dp, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+        "lbm_step": ([_vp, i64], ctypes.c_int),
+        "lbm_diagnostics": ([_vp, _dp], ctypes.c_int),
+        "lbm_moments": ([_vp, _dp, _dp, _dp, _dp], ctypes.c_int),
+        "lbm_contact_angle": ([_vp, ctypes.c_double, ctypes.c_double, _dp], ctypes.c_int),
+        "lbm_slip_length": ([_vp, _dp], ctypes.c_int),
+        "lbm_get_state": ([_vp, _dp], ctypes.c_int),
+        "lbm_set_state": ([_vp, _dp, i64], ctypes.c_int),
+        "lbm_step_index": ([_vp], i64),
+        "lbm_destroy": ([_vp], ctypes.c_int),
+        "lbm_batch_workspace_bytes": ([P, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "lbm_batch_create": ([P, ctypes.c_int32, ctypes.POINTER(_dp), ctypes.POINTER(_dp), ctypes.POINTER(_dp),
+                              ctypes.c_int32, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+        "lbm_batch_step": ([_vp, i64, ctypes.c_int32], ctypes.c_int),
+        "lbm_batch_diagnostics": ([_vp, _dp], ctypes.c_int),
+        "lbm_batch_lattice": ([_vp, ctypes.c_int32], _vp),
+        "lbm_batch_destroy": ([_vp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != LBM_OK:
+        raise LbmError(code, lib().lbm_last_error().decode())
+    return code
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"], "float64 C-contiguous array required"
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ------------------------------------------------------------ C names
+def lbm_params_default(**kw):
+    p = lbm_params()
+    _check(lib().lbm_params_default(ctypes.byref(p)))
+    for k, v in kw.items():
+        if k in ("U_wall", "F_ext"):
+            getattr(p, k)[0], getattr(p, k)[1] = v
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def lbm_workspace_bytes(p):
+    n = ctypes.c_size_t()
+    _check(lib().lbm_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
+    return n.value
+
+
+def lbm_create(p, rho0, ux0, uy0, wall_fields, workspace_ptr, workspace_bytes, stream_ptr):
+    out = _vp()
+    _check(lib().lbm_create(ctypes.byref(p), _ptr(rho0), _ptr(ux0), _ptr(uy0), _ptr(wall_fields),
+                            _vp(workspace_ptr), workspace_bytes, _vp(stream_ptr), ctypes.byref(out)))
+    return out
+
+
+def lbm_step(ctx, nsteps):
+    _check(lib().lbm_step(ctx, int(nsteps)))
+
+
+def lbm_diagnostics(ctx, check=True):
+    out = np.zeros(6)
+    code = lib().lbm_diagnostics(ctx, _ptr(out))
+    if check:
+        _check(code)
+    return out, code
+
+
+def lbm_moments(ctx, n, want=(True, True, True)):
+    arrs = [np.zeros(n) if w else None for w in want]
+    tot = np.zeros(3)
+    _check(lib().lbm_moments(ctx, *[_ptr(a) for a in arrs], _ptr(tot)))
+    return arrs, tot
+
+
+def lbm_contact_angle(ctx, iso, y_ref):
+    out = np.zeros(4)
+    code = lib().lbm_contact_angle(ctx, float(iso), float(y_ref), _ptr(out))
+    if code == LBM_ENOFIT:
+        return None
+    _check(code)
+    return out
+
+
+def lbm_slip_length(ctx):
+    out = np.zeros(3)
+    _check(lib().lbm_slip_length(ctx, _ptr(out)))
+    return out
+
+
+def lbm_get_state(ctx, n):
+    f = np.zeros(9 * n)
+    _check(lib().lbm_get_state(ctx, _ptr(f)))
+    return f
+
+
+def lbm_set_state(ctx, f, step_index):
+    f = _f64(f).ravel()
+    _check(lib().lbm_set_state(ctx, _ptr(f), int(step_index)))
+
+
+def lbm_step_index(ctx):
+    return int(lib().lbm_step_index(ctx))
+
+
+def lbm_destroy(ctx):
+    if ctx:
+        _check(lib().lbm_destroy(ctx))
+
+
+def lbm_batch_workspace_bytes(ps):
+    arr = (lbm_params * len(ps))(*ps)
+    n = ctypes.c_size_t()
+    _check(lib().lbm_batch_workspace_bytes(arr, len(ps), ctypes.byref(n)))
+    return n.value
+
+
+def lbm_batch_create(ps, rho0s, ux0s, uy0s, seg_rows, workspace_ptr, workspace_bytes, stream_ptr):
+    n = len(ps)
+    arr = (lbm_params * n)(*ps)
+
+    def plist(lst):
+        if lst is None:
+            return None
+        return (_dp * n)(*[_ptr(a) if a is not None else None for a in lst])
+
+    out = _vp()
+    _check(lib().lbm_batch_create(arr, n, plist(rho0s), plist(ux0s), plist(uy0s), int(seg_rows),
+                                  _vp(workspace_ptr), workspace_bytes, _vp(stream_ptr), ctypes.byref(out)))
+    return out
+
+
+def lbm_batch_step(b, nsteps, chunk=0):
+    _check(lib().lbm_batch_step(b, int(nsteps), int(chunk)))
+
+
+def lbm_batch_diagnostics(b, n, check=True):
+    out = np.zeros(6 * n)
+    code = lib().lbm_batch_diagnostics(b, _ptr(out))
+    if check:
+        _check(code)
+    return out.reshape(n, 6), code
+
+
+def lbm_batch_lattice(b, k):
+    v = lib().lbm_batch_lattice(b, int(k))
+    if not v:
+        raise LbmError(LBM_EINVAL, lib().lbm_last_error().decode())
+    return v
+
+
+def lbm_batch_destroy(b):
+    if b:
+        _check(lib().lbm_batch_destroy(b))
+
+
+# ------------------------------------------------------------ conveniences
+def _workspace(nbytes, device):
+    import torch
+    # over-allocate so the pointer can be aligned to 256 bytes
+    t = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    base = t.data_ptr()
+    off = (-base) % 256
+    return t, base + off
+
+
+def _stream(device, stream):
+    import torch
+    if stream is not None:
+        return stream.cuda_stream
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Lattice:
+    """One lattice on the GPU.  Fields are numpy float64 [ny, nx]."""
+
+    def __init__(self, params, rho0, ux0=None, uy0=None, wall_fields=None, device="cuda:0", stream=None):
+        self.p = params
+        self.nx, self.ny = params.nx, params.ny
+        self.n = self.nx * self.ny
+        nbytes = lbm_workspace_bytes(params)
+        self._ws, ptr = _workspace(nbytes, device)
+        self.stream_ptr = _stream(device, stream)
+        self.ctx = lbm_create(params, _f64(rho0), _f64(ux0), _f64(uy0), _f64(wall_fields), ptr, nbytes,
+                              self.stream_ptr)
+        self.workspace_bytes = nbytes
+
+    def step(self, nsteps=1):
+        lbm_step(self.ctx, nsteps)
+
+    def diagnostics(self, check=True):
+        return lbm_diagnostics(self.ctx, check)[0]
+
+    def moments(self):
+        (rho, ux, uy), tot = lbm_moments(self.ctx, self.n)
+        shp = (self.ny, self.nx)
+        return rho.reshape(shp), ux.reshape(shp), uy.reshape(shp), tot
+
+    def contact_angle(self, iso=1.07, y_ref=0.0):
+        return lbm_contact_angle(self.ctx, iso, y_ref)
+
+    def slip_length(self):
+        return lbm_slip_length(self.ctx)
+
+    def get_state(self):
+        """Populations as float64 [9, ny, nx] (post-streaming)."""
+        return lbm_get_state(self.ctx, self.n).reshape(9, self.ny, self.nx)
+
+    def set_state(self, f, step_index=0):
+        lbm_set_state(self.ctx, f, step_index)
+
+    @property
+    def step_index(self):
+        return lbm_step_index(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            lbm_destroy(self.ctx)
+            self.ctx = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class View:
+    """A lattice inside a Batch (moments, angle, slip, state, diagnostics)."""
+
+    def __init__(self, batch, k, params):
+        self.ctx = lbm_batch_lattice(batch.b, k)
+        self.p = params
+        self.nx, self.ny = params.nx, params.ny
+        self.n = self.nx * self.ny
+
+    moments = Lattice.moments
+    contact_angle = Lattice.contact_angle
+    slip_length = Lattice.slip_length
+    get_state = Lattice.get_state
+    diagnostics = Lattice.diagnostics
+
+
+class Batch:
+    """Many independent F32 lattices advanced by one launch per time step."""
+
+    def __init__(self, params_list, rho0s, ux0s=None, uy0s=None, seg_rows=0, device="cuda:0", stream=None):
+        self.ps = list(params_list)
+        for p in self.ps:
+            p.seg_rows = seg_rows
+        nbytes = lbm_batch_workspace_bytes(self.ps)
+        self._ws, ptr = _workspace(nbytes, device)
+        if stream is None:
+            # graph capture needs a stream other than the legacy default one
+            import torch
+            torch.cuda.synchronize(device)
+            stream = torch.cuda.Stream(device)
+        self._stream_obj = stream
+        self.stream_ptr = _stream(device, stream)
+        rho0s = [_f64(r) for r in rho0s]
+        ux0s = None if ux0s is None else [_f64(u) for u in ux0s]
+        uy0s = None if uy0s is None else [_f64(u) for u in uy0s]
+        self.b = lbm_batch_create(self.ps, rho0s, ux0s, uy0s, seg_rows, ptr, nbytes, self.stream_ptr)
+        self.workspace_bytes = nbytes
+        self.n = len(self.ps)
+
+    def step(self, nsteps, chunk=0):
+        lbm_batch_step(self.b, nsteps, chunk)
+
+    def diagnostics(self, check=True):
+        return lbm_batch_diagnostics(self.b, self.n, check)[0]
+
+    def lattice(self, k):
+        return View(self, k, self.ps[k])
+
+    def close(self):
+        if self.b:
+            lbm_batch_destroy(self.b)
+            self.b = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,116 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every entry point include/lbm.h declares, and validates arguments before any
+device call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1202_6130_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(lbm.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 19
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_params_struct_matches_header():
+    # field order of lbm_params in the header must match the ctypes mirror
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct {"):text.index("} lbm_params;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = re.findall(r"\b([A-Za-z_]+)(?:\[2\])?\s*[,;]", body)
+    assert fields == [f for f, _ in lbm.lbm_params._fields_]
+
+
+def test_defaults():
+    p = lbm.lbm_params_default()
+    assert p.tau == 1.0 and p.G == -5.0 and p.eps == 1.0
+    assert p.wall_width == 2.0 and p.core_range == 1.0 and p.tail_range == 3.0
+    assert p.slab_rows == 8 and p.storage == lbm.STORE_F32 and p.wall_kind == lbm.WALL_NONE
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("tau", 0.5, "tau"), ("eps", 0.9, "eps"), ("nx", 0, "nx"), ("storage", 7, "storage"),
+    ("wall_kind", 9, "wall_kind"), ("reserved", 1, "reserved"), ("seg_rows", -1, "seg_rows"),
+    ("G", float("nan"), "non-finite"),
+])
+def test_validation_errors(field, value, msg):
+    p = lbm.lbm_params_default(nx=16, ny=8)
+    setattr(p, field, value)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_workspace_bytes(p)
+    assert e.value.code == lbm.LBM_EINVAL and msg in str(e.value)
+
+
+def test_slab_validation():
+    p = lbm.lbm_params_default(nx=16, ny=8, wall_kind=lbm.WALL_FLAT_SLAB, slab_rows=8)
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_workspace_bytes(p)
+    p.slab_rows = 3
+    assert lbm.lbm_workspace_bytes(p) > 0
+
+
+def test_too_large_lattice_rejected():
+    p = lbm.lbm_params_default(nx=65536, ny=65536)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_workspace_bytes(p)
+    assert "too large" in str(e.value)
+
+
+def test_workspace_bytes_scale_with_storage():
+    sizes = {}
+    for st in (lbm.STORE_F16DEV, lbm.STORE_F32, lbm.STORE_F64):
+        sizes[st] = lbm.lbm_workspace_bytes(lbm.lbm_params_default(nx=1024, ny=512, storage=st))
+    N = 1024 * 512
+    # two population buffers dominate: 18 N * bytes
+    assert sizes[lbm.STORE_F16DEV] < sizes[lbm.STORE_F32] < sizes[lbm.STORE_F64]
+    assert sizes[lbm.STORE_F32] >= 18 * N * 4
+    assert sizes[lbm.STORE_F32] < 18 * N * 4 * 1.6
+
+
+def test_create_rejects_bad_host_inputs_before_device_work():
+    p = lbm.lbm_params_default(nx=8, ny=8)
+    rho = np.ones((8, 8))
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, None, None, None, None, 0, 0, 0)
+    assert e.value.code == lbm.LBM_EINVAL
+    bad = rho.copy(); bad[3, 3] = -1
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, bad, None, None, None, 0, 0, 0)
+    assert "rho0" in str(e.value)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, rho, np.zeros((8, 8)), None, None, 0, 0, 0)
+    assert "ux0" in str(e.value)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, rho, None, None, np.zeros((3, 8, 8)), 0, 0, 0)
+    assert "wall_fields" in str(e.value)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, rho, None, None, None, 0, 0, 0)
+    assert "workspace" in str(e.value)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create(p, rho, None, None, None, 256, 16, 0)
+    assert e.value.code == lbm.LBM_ENOMEM
+
+
+def test_batch_validation():
+    ps = [lbm.lbm_params_default(nx=64, ny=32, wall_kind=lbm.WALL_FLAT_SLAB) for _ in range(3)]
+    assert lbm.lbm_batch_workspace_bytes(ps) > 3 * lbm.lbm_workspace_bytes(ps[0]) * 0.9
+    ps[1].storage = lbm.STORE_F64
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_batch_workspace_bytes(ps)
+    assert "F32" in str(e.value)

@@ -1,0 +1,362 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs.
+
+Bars (written per test):
+  - FP64 storage: populations/fields within 1e-13 (one step) or 1e-10 (2000
+    steps) absolute; arithmetic identical up to summation order.
+  - FP32 storage: max|rho - rho_o| / max|rho_o| <= 1e-5 and
+    max|u - u_o| / c_s <= 1e-5 (c_s = 1/sqrt(3), the lattice sound speed).
+  - Integer-like results (tiling invariance, batch vs alone, determinism):
+    bitwise.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1202_6130_amd import inputs as I
+from paper_1202_6130_amd import lbm
+
+pytestmark = pytest.mark.gpu
+CS = 1.0 / np.sqrt(3.0)
+
+
+def to_orc(fg):
+    return np.ascontiguousarray(np.moveaxis(fg, 0, -1))
+
+
+def from_orc(fo):
+    return np.ascontiguousarray(np.moveaxis(fo, -1, 0))
+
+
+def rand_walls(nx, ny, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return O.Walls(rng.uniform(0, 1, (ny, nx)), rng.uniform(0, 1, (ny, nx)), rng.uniform(0, 0.5, (ny, nx)))
+
+
+def rand_state(p, seed):
+    rho, ux, uy = I.random_state_field(p.nx, p.ny, seed)
+    f = O.init(p, rho, ux, uy)
+    rng = np.random.Generator(np.random.PCG64(seed + 99))
+    return f * (1 + 0.05 * rng.uniform(-1, 1, f.shape))
+
+
+def gpu_params(nx, ny, **kw):
+    return lbm.lbm_params_default(nx=nx, ny=ny, **kw)
+
+
+def drop_case(storage, walls_kind=lbm.WALL_FLAT_SLAB, seg_rows=0):
+    nx, ny = 64, 32
+    p = gpu_params(nx, ny, storage=storage, wall_kind=walls_kind, G_R=0.5, G_A=0.3, seg_rows=seg_rows)
+    if storage == lbm.STORE_F16DEV:
+        p.rho_ref = 1.0
+    po = O.make_params(nx, ny, tau=1.0, G=-5.0, G_R=0.5, G_A=0.3, eps=1.0)
+    w = O.Walls.flat_slab(nx, ny, 8, 2.0, 1.0, 3.0)
+    return p, po, w, I.drop_field(nx, ny, 12.0)
+
+
+@pytest.mark.parametrize("nx,ny,seg", [(4, 4, 0), (13, 7, 3), (1, 1, 0), (1, 6, 1), (7, 1, 0),
+                                       (64, 32, 8), (130, 70, 16), (125, 33, 5), (62, 5, 2), (63, 9, 4)])
+def test_f64_one_step_all_terms(nx, ny, seg):
+    """Every term of the update (random per-node wall fields, G, G_R, G_A,
+    eps, U_wall, F_ext, tau != 1) on lattices spanning several strips and
+    segments with ragged tails, and degenerate 1-wide lattices."""
+    kw = dict(tau=0.85, G=-5.0, G_R=0.6, G_A=0.35, eps=1.3, U_wall=(0.01, -0.02), F_ext=(1e-3, -5e-4))
+    po = O.make_params(nx, ny, **kw)
+    walls = rand_walls(nx, ny, 100 + nx)
+    f = rand_state(po, 7 + ny)
+    fields = np.stack([walls.phi, walls.psiR, walls.psiA])
+    p = gpu_params(nx, ny, storage=lbm.STORE_F64, wall_kind=lbm.WALL_FIELDS, seg_rows=seg, **kw)
+    L = lbm.Lattice(p, np.ones((ny, nx)), wall_fields=fields)
+    L.set_state(from_orc(f), 0)
+    L.step(1)
+    g = to_orc(L.get_state())
+    want = O.step(po, walls, f)
+    assert np.abs(g - want).max() < 1e-13
+    L.close()
+
+
+def test_f64_drop_2000_steps():
+    """Small sessile-drop case, 2000 steps: fields, totals and contact angle."""
+    p, po, w, rho0 = drop_case(lbm.STORE_F64)
+    L = lbm.Lattice(p, rho0)
+    L.step(2000)
+    rho, ux, uy, tot = L.moments()
+    fo = O.run(po, w, O.init(po, rho0), 2000)
+    r_o, ux_o, uy_o, tot_o = O.macros(po, w, fo)
+    assert np.abs(rho - r_o).max() < 1e-10
+    assert np.abs(ux - ux_o).max() < 1e-10 and np.abs(uy - uy_o).max() < 1e-10
+    assert np.allclose(tot, tot_o, rtol=1e-11, atol=1e-9)
+    a = L.contact_angle(1.07, 0.0)
+    a_o = O.contact_angle(po, w, fo, 1.07, 0.0)
+    assert np.abs(a - a_o).max() < 1e-7
+    L.close()
+
+
+def test_f32_drop_2000_steps_tolerance():
+    """FP32 populations, FP32 arithmetic, 2000 steps vs the FP64 oracle."""
+    p, po, w, rho0 = drop_case(lbm.STORE_F32)
+    L = lbm.Lattice(p, rho0)
+    L.step(2000)
+    rho, ux, uy, tot = L.moments()
+    fo = O.run(po, w, O.init(po, rho0), 2000)
+    r_o, ux_o, uy_o, tot_o = O.macros(po, w, fo)
+    e_rho = np.abs(rho - r_o).max() / np.abs(r_o).max()
+    e_u = max(np.abs(ux - ux_o).max(), np.abs(uy - uy_o).max()) / CS
+    print(f"FP32 drop 64x32 t=2000: rel rho err {e_rho:.3e}, u err / c_s {e_u:.3e}")
+    assert e_rho <= 1e-5
+    assert e_u <= 1e-5
+    assert abs(tot[0] - tot_o[0]) / tot_o[0] < 1e-5
+    a, a_o = L.contact_angle(1.07, 0.0), O.contact_angle(po, w, fo, 1.07, 0.0)
+    assert abs(a[0] - a_o[0]) < 1e-3 and abs(a[1] - a_o[1]) < 1e-3
+    L.close()
+
+
+def test_f16dev_drop_error_bounded():
+    """FP16 deviation storage (rho_ref = mean density) with FP32 arithmetic:
+    the binary16 grid (~5e-4 relative) snaps bulk densities, so the bound is
+    the measured one with margin, not the FP32 bar."""
+    p, po, w, rho0 = drop_case(lbm.STORE_F16DEV)
+    p.rho_ref = float(rho0.mean())
+    L = lbm.Lattice(p, rho0)
+    L.step(2000)
+    rho, ux, uy, _ = L.moments()
+    fo = O.run(po, w, O.init(po, rho0), 2000)
+    r_o, ux_o, uy_o, _ = O.macros(po, w, fo)
+    e_rho = np.abs(rho - r_o).max() / np.abs(r_o).max()
+    e_u = max(np.abs(ux - ux_o).max(), np.abs(uy - uy_o).max()) / CS
+    print(f"FP16-dev drop 64x32 t=2000: rel rho err {e_rho:.3e}, u err / c_s {e_u:.3e}")
+    assert e_rho < 3e-2 and e_u < 1e-2
+    L.close()
+
+
+def test_flat_slab_equals_per_node_fields():
+    """The per-row flat-slab tables and the per-node field path agree."""
+    p, po, w, rho0 = drop_case(lbm.STORE_F64)
+    A = lbm.Lattice(p, rho0)
+    pf = gpu_params(64, 32, storage=lbm.STORE_F64, wall_kind=lbm.WALL_FIELDS, G_R=0.5, G_A=0.3)
+    B = lbm.Lattice(pf, rho0, wall_fields=np.stack([w.phi, w.psiR, w.psiA]))
+    A.step(300)
+    B.step(300)
+    assert np.abs(A.get_state() - B.get_state()).max() < 1e-12
+    A.close(); B.close()
+
+
+@pytest.mark.parametrize("storage", [lbm.STORE_F64, lbm.STORE_F32, lbm.STORE_F16DEV])
+def test_state_roundtrip(storage):
+    nx, ny = 70, 11
+    po = O.make_params(nx, ny)
+    f = from_orc(rand_state(po, 3))
+    L = lbm.Lattice(gpu_params(nx, ny, storage=storage), np.ones((ny, nx)))
+    L.set_state(f, 17)
+    g = L.get_state()
+    assert L.step_index == 17
+    if storage == lbm.STORE_F64:
+        assert np.array_equal(g, f)
+    elif storage == lbm.STORE_F32:
+        assert np.array_equal(g, f.astype(np.float32).astype(np.float64))
+    else:
+        assert np.abs(g - f).max() < 2e-3
+    L.close()
+
+
+def test_init_is_equilibrium():
+    nx, ny = 33, 17
+    rho, ux, uy = I.random_state_field(nx, ny, 5)
+    po = O.make_params(nx, ny)
+    L = lbm.Lattice(gpu_params(nx, ny, storage=lbm.STORE_F64), rho, ux, uy)
+    assert np.abs(to_orc(L.get_state()) - O.init(po, rho, ux, uy)).max() < 1e-15
+    L.close()
+
+
+def test_moments_match_oracle_random_state():
+    nx, ny = 40, 24
+    kw = dict(tau=1.2, G=-4.5, G_R=0.3, G_A=0.2, eps=1.0, F_ext=(2e-4, 0.0))
+    po = O.make_params(nx, ny, **kw)
+    walls = O.Walls.flat_slab(nx, ny, 6)
+    f = rand_state(po, 8)
+    p = gpu_params(nx, ny, storage=lbm.STORE_F64, wall_kind=lbm.WALL_FLAT_SLAB, slab_rows=6, **kw)
+    L = lbm.Lattice(p, np.ones((ny, nx)))
+    L.set_state(from_orc(f))
+    rho, ux, uy, tot = L.moments()
+    r_o, ux_o, uy_o, tot_o = O.macros(po, walls, f)
+    assert np.abs(rho - r_o).max() < 1e-14
+    assert np.abs(ux - ux_o).max() < 1e-14 and np.abs(uy - uy_o).max() < 1e-14
+    assert np.allclose(tot, tot_o, rtol=1e-13, atol=1e-12)
+    L.close()
+
+
+def test_diagnostics_residual_and_unstable():
+    p, po, w, rho0 = drop_case(lbm.STORE_F64)
+    p.diag_interval = 50
+    L = lbm.Lattice(p, rho0)
+    L.step(50)
+    d1 = L.diagnostics()
+    assert d1[0] == 50 and np.isinf(d1[4]) and d1[5] == 0
+    L.step(50)
+    d2 = L.diagnostics()
+    assert 0 < d2[4] < np.inf
+    # residual against the oracle's fields at steps 50 and 100
+    f50 = O.run(po, w, O.init(po, rho0), 50)
+    f100 = O.run(po, w, f50, 50)
+    _, a_x, a_y, _ = O.macros(po, w, f100)
+    _, b_x, b_y, _ = O.macros(po, w, f50)
+    assert abs(d2[4] - O.residual(a_x, a_y, b_x, b_y)) < 1e-10 * d2[4]
+    assert abs(d2[1] - rho0.sum()) < 1e-10
+    # a planted non-finite population is reported, not hidden
+    f = L.get_state()
+    f[3, 10, 20] = np.nan
+    L.set_state(f, 100)
+    out, code = lbm.lbm_diagnostics(L.ctx, check=False)
+    assert code == lbm.LBM_EUNSTABLE and out[5] >= 1
+    L.close()
+
+
+@pytest.mark.parametrize("storage", [lbm.STORE_F64, lbm.STORE_F32])
+def test_slip_length_parity(storage):
+    nx, ny, P = 8, 64, 8
+    kw = dict(tau=1.0, G=-5.0, G_R=0.5, G_A=0.3, eps=1.3, F_ext=(1e-6, 0.0))
+    po = O.make_params(nx, ny, **kw)
+    w = O.Walls.flat_slab(nx, ny, P)
+    rho0 = I.uniform_field(nx, ny, 1.93)
+    fo = O.run(po, w, O.init(po, rho0), 6000)
+    want = O.slip_length(po, w, fo, P, 2.0)
+    L = lbm.Lattice(gpu_params(nx, ny, storage=storage, wall_kind=lbm.WALL_FLAT_SLAB, **kw), rho0)
+    L.step(6000)
+    got = L.slip_length()
+    # FP32 storage rounds each population to ~1e-8 while the body force adds
+    # ~1e-7 per step: the slip length carries a ~0.3% FP32 storage error
+    tol = 1e-9 if storage == lbm.STORE_F64 else 1e-2
+    assert abs(got[0] - want[0]) < tol * abs(want[0])
+    assert abs(got[1] - want[1]) < tol * abs(want[1])
+    L.close()
+
+
+def test_contact_angle_no_fit():
+    nx, ny = 64, 32
+    L = lbm.Lattice(gpu_params(nx, ny, wall_kind=lbm.WALL_FLAT_SLAB), I.uniform_field(nx, ny, 0.15))
+    assert L.contact_angle(1.07, 0.0) is None
+    L.close()
+
+
+def test_tiling_invariance_bitwise():
+    """The per-node arithmetic does not depend on the tile shape."""
+    nx, ny = 200, 96
+    rho0 = I.drop_field(nx, ny, 30.0)
+    ref = None
+    for seg in (1, 5, 16, 96):
+        p = gpu_params(nx, ny, wall_kind=lbm.WALL_FLAT_SLAB, G_R=0.5, G_A=0.3, seg_rows=seg)
+        L = lbm.Lattice(p, rho0)
+        L.step(100)
+        s = L.get_state()
+        L.close()
+        if ref is None:
+            ref = s
+        else:
+            assert np.array_equal(s, ref)
+
+
+def test_determinism_bitwise():
+    nx, ny = 1024, 512
+    gr, ga = I.draw_wall_amplitudes(1)
+    rho0 = I.drop_field(nx, ny, 160.0)
+    out = []
+    for _ in range(2):
+        p = gpu_params(nx, ny, wall_kind=lbm.WALL_FLAT_SLAB, G_R=gr[0], G_A=ga[0])
+        L = lbm.Lattice(p, rho0)
+        L.step(200)
+        out.append(L.get_state())
+        L.close()
+    assert np.array_equal(out[0], out[1])
+
+
+def _patch_one_step(po_full, walls_full, f_full, y, x, r=4):
+    """Oracle one-step result at node (y, x) from a (2r+1)^2 patch of the state
+    (the result depends on the radius-2 neighbourhood only).  walls_full None
+    means no solid."""
+    ny, nx = f_full.shape[:2]
+    ys = (np.arange(y - r, y + r + 1)) % ny
+    xs = (np.arange(x - r, x + r + 1)) % nx
+    sub = lambda a: np.ascontiguousarray(a[np.ix_(ys, xs)])
+    n = 2 * r + 1
+    po = O.make_params(n, n, tau=po_full.tau, G=po_full.G, G_R=po_full.G_R, G_A=po_full.G_A,
+                       eps=po_full.eps, U_wall=tuple(po_full.U_wall), F_ext=tuple(po_full.F_ext))
+    if walls_full is None:
+        w = O.Walls.none(n, n)
+    else:
+        w = O.Walls(sub(walls_full.phi), sub(walls_full.psiR), sub(walls_full.psiA))
+    return O.step(po, w, sub(f_full))[r, r]
+
+
+@pytest.mark.parametrize("case", ["drop_1024x512", "spinodal_4096"])
+def test_full_size_sampled_one_step(case):
+    """Full-size lattices in the benchmark's launch configuration: one GPU step
+    from a GPU state, checked at sampled nodes against the oracle's one-step
+    update of the same (FP32-exact) inputs."""
+    rng = np.random.Generator(np.random.PCG64(11))
+    if case == "drop_1024x512":
+        nx, ny = 1024, 512
+        gr, ga = I.draw_wall_amplitudes(1)
+        p = gpu_params(nx, ny, wall_kind=lbm.WALL_FLAT_SLAB, G_R=gr[0], G_A=ga[0])
+        po = O.make_params(nx, ny, tau=1.0, G=-5.0, G_R=gr[0], G_A=ga[0], eps=1.0)
+        w = O.Walls.flat_slab(nx, ny, 8)
+        rho0 = I.drop_field(nx, ny, 160.0)
+        ys = np.concatenate([rng.integers(0, ny, 40), [0, 1, ny - 1, ny - 8, ny - 9, 160, 161]])
+    else:
+        nx = ny = 4096
+        p = gpu_params(nx, ny)
+        po = O.make_params(nx, ny, tau=1.0, G=-5.0)
+        w = None
+        rho0 = I.spinodal_field(4096, seed=0)
+        ys = np.concatenate([rng.integers(0, ny, 40), [0, ny - 1]])
+    xs = np.concatenate([rng.integers(0, nx, len(ys) - 4), [0, nx - 1, 61, 62]])
+    L = lbm.Lattice(p, rho0)
+    L.step(30)
+    f0 = to_orc(L.get_state())
+    L.step(1)
+    f1 = L.get_state()
+    L.close()
+    worst = 0.0
+    for y, x in zip(ys, xs):
+        want = _patch_one_step(po, w, f0, int(y), int(x))
+        got = f1[:, int(y), int(x)]
+        worst = max(worst, np.abs(got - want).max())
+    print(f"{case}: worst |f_gpu - f_oracle| after one step = {worst:.3e}")
+    assert worst < 2e-6
+
+
+def test_mass_conservation_4096():
+    """Property at full size: total mass is conserved by every step."""
+    nx = ny = 4096
+    rho0 = I.spinodal_field(4096, seed=0)
+    p = gpu_params(nx, ny, diag_interval=100)
+    L = lbm.Lattice(p, rho0)
+    L.step(500)
+    d = L.diagnostics()
+    assert abs(d[1] - rho0.sum()) / rho0.sum() < 1e-5
+    assert d[5] == 0
+    L.close()
+
+
+def test_batch_matches_alone_bitwise():
+    """A lattice gives bitwise the same state alone and inside a batch (uneven
+    sizes, different parameters), with plain launches and graph replays."""
+    cases = I.ensemble_cases(seed=3, count=5)
+    ps, rhos = [], []
+    for c in cases:
+        p = gpu_params(c.nx, c.ny, wall_kind=lbm.WALL_FLAT_SLAB, G=c.G, G_R=c.G_R, G_A=c.G_A)
+        ps.append(p)
+        rhos.append(I.drop_field(c.nx, c.ny, c.radius))
+    B = lbm.Batch(ps, rhos, seg_rows=16)
+    B.step(40, chunk=10)
+    B.step(3, chunk=0)
+    d = B.diagnostics()
+    for k, (p, rho) in enumerate(zip(ps, rhos)):
+        p1 = gpu_params(p.nx, p.ny, wall_kind=lbm.WALL_FLAT_SLAB, G=p.G, G_R=p.G_R, G_A=p.G_A, seg_rows=16)
+        L = lbm.Lattice(p1, rho)
+        L.step(43)
+        assert np.array_equal(B.lattice(k).get_state(), L.get_state())
+        dl = L.diagnostics()
+        assert abs(dl[1] - d[k, 1]) < 1e-9 * dl[1]
+        L.close()
+    assert np.all(d[:, 0] == 43)
+    B.close()
