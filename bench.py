@@ -94,6 +94,21 @@ def time_gpu(name, storage, steps, warmup, seg_rows):
     }
 
 
+COPY_REF_BYTES = 1 << 30
+
+
+def copy_reference():
+    """One device-to-device copy of COPY_REF_BYTES (reads and writes that many
+    bytes once): the known-size dispatch the memory counters are scaled by."""
+    import torch
+    src = torch.ones(COPY_REF_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def cpu_baseline(seconds_hint=15.0):
     """The FP64 oracle (single thread, as it stands) on a bounded sample of the
     same workload recipe: a 1024x1024 periodic spinodal lattice."""
@@ -128,6 +143,9 @@ def main():
     ap.add_argument("--seg-rows", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="after timing, run one plain device copy of 1 GiB (reference dispatch for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the update is measured on a "
@@ -135,6 +153,8 @@ def main():
         sys.exit(2)
 
     r = time_gpu(args.workload, args.storage, args.steps, args.warmup, args.seg_rows)
+    if args.copy_ref:
+        copy_reference()
     mlups = r["nodes"] * args.steps / (r["ms_total"] * 1e-3) / 1e6
     bpu = bytes_per_update(args.storage)
     achieved = bpu * r["nodes"] / (r["kernel_ms_mean"] * 1e-3) / 1e9

@@ -220,7 +220,23 @@ lbm_status lbm_batch_diagnostics(lbm_batch *b, double *out);
  * lbm_destroy on a view is a no-op. */
 lbm_ctx *lbm_batch_lattice(lbm_batch *b, int32_t k);
 
-/* Frees the host-side batch (waits for its stream).  NULL is accepted. */
+/* Device bytes of the tables for lbm_batch_attach over these contexts. */
+lbm_status lbm_batch_attach_bytes(lbm_ctx *const *ctxs, int32_t n, size_t *bytes);
+
+/* Groups n existing contexts (from lbm_create: F32 storage, wall kind NONE or
+ * FLAT_SLAB, all on `stream`) into a batch without touching their state:
+ * lbm_batch_step then advances all of them by one launch per time step.  The
+ * workspace (>= lbm_batch_attach_bytes) holds only the batch's tables; each
+ * context keeps its own.  While attached, lbm_step, lbm_set_state and
+ * lbm_destroy on a context return LBM_ESTATE; the read-out calls remain
+ * valid.  This is the primitive of continuous batching: when membership
+ * changes, destroy the batch and attach the new set. */
+lbm_status lbm_batch_attach(lbm_ctx *const *ctxs, int32_t n, void *workspace,
+                            size_t workspace_bytes, void *stream, lbm_batch **out);
+
+/* Frees the host-side batch (waits for its stream).  A batch from
+ * lbm_batch_create frees its contexts; an attached batch hands its contexts
+ * back with their state and step index.  NULL is accepted. */
 lbm_status lbm_batch_destroy(lbm_batch *b);
 
 #ifdef __cplusplus

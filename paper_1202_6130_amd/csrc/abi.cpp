@@ -67,7 +67,7 @@ uint32_t default_seg_rows(uint32_t nx, uint32_t ny) {
 
 struct Layout {
     size_t fa, fb, mom, uprev, row_tab, node_tab, phi_raw, partials, iso_part, small, profile, total;
-    uint32_t strips, segs, seg_rows, waves, iso_blocks;
+    uint32_t strips, segs, seg_rows, waves, iso_blocks, tiles;
 };
 
 // Offsets (bytes) into one lattice's workspace.  fb and mom are adjacent: the
@@ -80,6 +80,7 @@ Layout make_layout(const lbm_params &p) {
     L.strips = (uint32_t(p.nx) + kStripColsHost - 1) / kStripColsHost;
     L.segs = (uint32_t(p.ny) + L.seg_rows - 1) / L.seg_rows;
     L.waves = L.strips * L.segs;
+    L.tiles = step_tiles(uint32_t(p.nx), uint32_t(p.ny));
     L.iso_blocks = isoline_blocks(uint32_t(N));
     size_t o = 0;
     L.fa = o; o = align_up(o + 9 * N * s);
@@ -166,7 +167,8 @@ struct lbm_ctx {
     int64_t own_step;
     int *cur;                      // which buffer holds the state (0: fa, 1: fb)
     int64_t *step;
-    bool view;
+    bool view;                     // lives inside a batch (lbm_step/lbm_set_state refused)
+    bool attached;                 // an lbm_ctx of the caller grouped by lbm_batch_attach
     // diagnostics bookkeeping
     bool have_prev;                // a snapshot exists for the residual
     int64_t last_diag_step;
@@ -178,12 +180,15 @@ struct lbm_ctx {
 
 struct lbm_batch {
     std::vector<lbm_ctx *> lat;
+    bool owned;                    // contexts created (and freed) by the batch
     hipStream_t stream;
     int cur;
     int64_t step;
     void *d_lats;
-    uint4 *d_work;
+    uint4 *d_work;                 // per-wave (lattice, strip, segment): diagnostics
     uint32_t nwork;
+    uint4 *d_twork;                // per-tile (lattice, strip, tile row): time step
+    uint32_t ntiles;
     double *d_part;
     uint32_t *d_ranges;
     double *d_res;
@@ -227,6 +232,7 @@ lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const d
     c->cur = &c->own_cur;
     c->step = &c->own_step;
     c->view = false;
+    c->attached = false;
     c->have_prev = false;
     c->last_diag_step = -1;
     c->last_diag_compared = false;
@@ -572,6 +578,7 @@ lbm_status lbm_set_state(lbm_ctx *c, const double *f, int64_t step_index) {
 int64_t lbm_step_index(const lbm_ctx *c) { return c ? *c->step : -1; }
 
 lbm_status lbm_destroy(lbm_ctx *c) {
+    if (c && c->attached) return fail(LBM_ESTATE, "context is attached to a batch; destroy the batch first");
     if (!c || c->view) return LBM_OK;
     hipError_t e = hipStreamSynchronize(c->stream);
     delete c;
@@ -591,16 +598,36 @@ static lbm_status batch_check(const lbm_params *ps, int32_t n) {
     return LBM_OK;
 }
 
+// Device tables of a batch: lattice descriptors, the wave work list, the
+// per-wave partial sums and per-lattice reduction ranges and results.
+struct TablesLayout {
+    size_t lats, work, twork, part, ranges, res, total;
+};
+
+static TablesLayout tables_layout(size_t base, int32_t n, uint32_t nwork, uint32_t ntiles) {
+    TablesLayout T;
+    size_t o = base;
+    T.lats = o; o = align_up(o + size_t(n) * sizeof(LatDev<float>));
+    T.work = o; o = align_up(o + size_t(nwork) * sizeof(uint4));
+    T.twork = o; o = align_up(o + size_t(ntiles) * sizeof(uint4));
+    T.part = o; o = align_up(o + size_t(nwork) * 8 * sizeof(double));
+    T.ranges = o; o = align_up(o + size_t(n) * 2 * sizeof(uint32_t));
+    T.res = o; o = align_up(o + size_t(n) * 8 * sizeof(double));
+    T.total = o;
+    return T;
+}
+
 struct BatchLayout {
     std::vector<size_t> off;
     size_t lats, work, part, ranges, res, total;
-    uint32_t nwork;
+    uint32_t nwork, ntiles;
 };
 
 static BatchLayout batch_layout(const lbm_params *ps, int32_t n, int32_t seg_rows) {
     BatchLayout B;
     size_t o = 0;
     B.nwork = 0;
+    B.ntiles = 0;
     for (int32_t k = 0; k < n; ++k) {
         lbm_params p = ps[k];
         p.seg_rows = seg_rows;
@@ -608,13 +635,15 @@ static BatchLayout batch_layout(const lbm_params *ps, int32_t n, int32_t seg_row
         B.off.push_back(o);
         o = align_up(o + L.total);
         B.nwork += L.waves;
+        B.ntiles += L.tiles;
     }
-    B.lats = o; o = align_up(o + size_t(n) * sizeof(LatDev<float>));
-    B.work = o; o = align_up(o + size_t(B.nwork) * sizeof(uint4));
-    B.part = o; o = align_up(o + size_t(B.nwork) * 8 * sizeof(double));
-    B.ranges = o; o = align_up(o + size_t(n) * 2 * sizeof(uint32_t));
-    B.res = o; o = align_up(o + size_t(n) * 8 * sizeof(double));
-    B.total = o;
+    const TablesLayout T = tables_layout(o, n, B.nwork, B.ntiles);
+    B.lats = T.lats;
+    B.work = T.work;
+    B.part = T.part;
+    B.ranges = T.ranges;
+    B.res = T.res;
+    B.total = T.total;
     return B;
 }
 
@@ -622,6 +651,66 @@ lbm_status lbm_batch_workspace_bytes(const lbm_params *ps, int32_t n, size_t *by
     TRY(batch_check(ps, n));
     if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
     *bytes = batch_layout(ps, n, ps[0].seg_rows).total;
+    return LBM_OK;
+}
+
+static lbm_batch *new_batch(char *ws, const TablesLayout &T, uint32_t nwork, uint32_t ntiles, hipStream_t st,
+                            bool owned) {
+    lbm_batch *b = new (std::nothrow) lbm_batch();
+    if (!b) return nullptr;
+    b->owned = owned;
+    b->stream = st;
+    b->cur = 0;
+    b->step = 0;
+    b->graph[0] = b->graph[1] = nullptr;
+    b->graph_chunk[0] = b->graph_chunk[1] = 0;
+    b->have_prev = false;
+    b->nwork = nwork;
+    b->ntiles = ntiles;
+    b->d_lats = ws + T.lats;
+    b->d_work = (uint4 *)(ws + T.work);
+    b->d_twork = (uint4 *)(ws + T.twork);
+    b->d_part = (double *)(ws + T.part);
+    b->d_ranges = (uint32_t *)(ws + T.ranges);
+    b->d_res = (double *)(ws + T.res);
+    return b;
+}
+
+// Builds descriptors and the work list over b->lat (whose current buffer is
+// fa, i.e. batch parity 0) and uploads them.  Synchronises.
+static lbm_status upload_tables(lbm_batch *b) {
+    const int32_t n = int32_t(b->lat.size());
+    std::vector<LatDev<float>> lats(n);
+    std::vector<uint4> work, twork;
+    std::vector<uint32_t> ranges(2 * size_t(n));
+    work.reserve(b->nwork);
+    twork.reserve(b->ntiles);
+    uint32_t w0 = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        lbm_ctx *c = b->lat[k];
+        c->cur = &b->cur;
+        const Layout &Y = c->lay;
+        LatDevAny La = c->L;
+        La.wave0 = w0;
+        La.partials = b->d_part + 8 * size_t(w0);
+        lats[k] = La.get<float>();
+        for (uint32_t sg = 0; sg < Y.segs; ++sg)
+            for (uint32_t sp = 0; sp < Y.strips; ++sp) work.push_back(make_uint4(uint32_t(k), sp, sg, 0));
+        const uint32_t trows = Y.tiles / Y.strips;
+        for (uint32_t tr = 0; tr < trows; ++tr)
+            for (uint32_t sp = 0; sp < Y.strips; ++sp) twork.push_back(make_uint4(uint32_t(k), sp, tr, 0));
+        ranges[2 * k] = w0;
+        ranges[2 * k + 1] = w0 + Y.waves;
+        w0 += Y.waves;
+    }
+    if (w0 != b->nwork || twork.size() != b->ntiles) return fail(LBM_EINVAL, "internal: work list size mismatch");
+    HIPCHK(hipMemcpyAsync(b->d_lats, lats.data(), lats.size() * sizeof(LatDev<float>), hipMemcpyHostToDevice,
+                          b->stream));
+    HIPCHK(hipMemcpyAsync(b->d_work, work.data(), work.size() * sizeof(uint4), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync(b->d_twork, twork.data(), twork.size() * sizeof(uint4), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync(b->d_ranges, ranges.data(), ranges.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                          b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
     return LBM_OK;
 }
 
@@ -638,25 +727,9 @@ lbm_status lbm_batch_create(const lbm_params *ps, int32_t n, const double *const
     if (workspace_bytes < B.total) return fail(LBM_ENOMEM, "workspace too small: %zu < %zu", workspace_bytes, B.total);
     char *ws = (char *)workspace;
     hipStream_t st = (hipStream_t)stream;
-    lbm_batch *b = new (std::nothrow) lbm_batch();
+    TablesLayout T = tables_layout(B.lats, n, B.nwork, B.ntiles);
+    lbm_batch *b = new_batch(ws, T, B.nwork, B.ntiles, st, true);
     if (!b) return fail(LBM_EINVAL, "host allocation failed");
-    b->stream = st;
-    b->cur = 0;
-    b->step = 0;
-    b->graph[0] = b->graph[1] = nullptr;
-    b->graph_chunk[0] = b->graph_chunk[1] = 0;
-    b->have_prev = false;
-    b->nwork = B.nwork;
-    b->d_lats = ws + B.lats;
-    b->d_work = (uint4 *)(ws + B.work);
-    b->d_part = (double *)(ws + B.part);
-    b->d_ranges = (uint32_t *)(ws + B.ranges);
-    b->d_res = (double *)(ws + B.res);
-    std::vector<LatDev<float>> lats(n);
-    std::vector<uint4> work;
-    std::vector<uint32_t> ranges(2 * size_t(n));
-    work.reserve(B.nwork);
-    uint32_t w0 = 0;
     lbm_status stt = LBM_OK;
     for (int32_t k = 0; k < n && stt == LBM_OK; ++k) {
         lbm_params p = ps[k];
@@ -668,33 +741,10 @@ lbm_status lbm_batch_create(const lbm_params *ps, int32_t n, const double *const
         stt = init_ctx(c, &p, rho0s[k], ux0s ? ux0s[k] : nullptr, uy0s ? uy0s[k] : nullptr, nullptr,
                        ws + B.off[k], st);
         if (stt != LBM_OK) { delete c; break; }
-        // the view shares the batch's time and buffer parity; its partials
-        // live in the batch's global array so both reduction paths agree
         c->view = true;
-        c->cur = &b->cur;
-        c->step = &b->step;
-        c->L.partials = b->d_part + 8 * size_t(w0);
-        const Layout &Y = c->lay;
-        LatDevAny La = c->L;
-        La.wave0 = w0;
-        lats[k] = La.get<float>();
-        for (uint32_t sg = 0; sg < Y.segs; ++sg)
-            for (uint32_t sp = 0; sp < Y.strips; ++sp) work.push_back(make_uint4(uint32_t(k), sp, sg, 0));
-        ranges[2 * k] = w0;
-        ranges[2 * k + 1] = w0 + Y.waves;
-        w0 += Y.waves;
         b->lat.push_back(c);
     }
-    if (stt == LBM_OK) {
-        hipError_t e = hipMemcpyAsync(b->d_lats, lats.data(), lats.size() * sizeof(LatDev<float>),
-                                      hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(b->d_work, work.data(), work.size() * sizeof(uint4),
-                                                hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(b->d_ranges, ranges.data(), ranges.size() * sizeof(uint32_t),
-                                                hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) stt = fail(LBM_EDEVICE, "batch upload: %s", hipGetErrorString(e));
-    }
+    if (stt == LBM_OK) stt = upload_tables(b);
     if (stt != LBM_OK) {
         for (lbm_ctx *c : b->lat) delete c;
         delete b;
@@ -704,11 +754,85 @@ lbm_status lbm_batch_create(const lbm_params *ps, int32_t n, const double *const
     return LBM_OK;
 }
 
+static lbm_status attach_check(lbm_ctx *const *ctxs, int32_t n, uint32_t *nwork, uint32_t *ntiles) {
+    if (!ctxs || n < 1) return fail(LBM_EINVAL, "need n >= 1 contexts");
+    uint32_t w = 0, t = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        const lbm_ctx *c = ctxs[k];
+        if (!c) return fail(LBM_EINVAL, "context %d is NULL", k);
+        if (c->view || c->attached) return fail(LBM_ESTATE, "context %d already belongs to a batch", k);
+        if (c->p.storage != LBM_STORE_F32 || c->wall_mode != 0)
+            return fail(LBM_EINVAL, "context %d: batches take F32 storage and wall kinds NONE or FLAT_SLAB", k);
+        for (int32_t j = 0; j < k; ++j)
+            if (ctxs[j] == c) return fail(LBM_EINVAL, "context %d listed twice", k);
+        w += c->lay.waves;
+        t += c->lay.tiles;
+    }
+    *nwork = w;
+    *ntiles = t;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_attach_bytes(lbm_ctx *const *ctxs, int32_t n, size_t *bytes) {
+    uint32_t nwork = 0, ntiles = 0;
+    TRY(attach_check(ctxs, n, &nwork, &ntiles));
+    if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+    *bytes = tables_layout(0, n, nwork, ntiles).total;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_attach(lbm_ctx *const *ctxs, int32_t n, void *workspace, size_t workspace_bytes, void *stream,
+                            lbm_batch **out) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    uint32_t nwork = 0, ntiles = 0;
+    TRY(attach_check(ctxs, n, &nwork, &ntiles));
+    hipStream_t st = (hipStream_t)stream;
+    for (int32_t k = 0; k < n; ++k)
+        if (ctxs[k]->stream != st) return fail(LBM_EINVAL, "context %d uses another stream than the batch", k);
+    if (!workspace || uintptr_t(workspace) % kAlign) return fail(LBM_EINVAL, "workspace NULL or not 256-byte aligned");
+    TablesLayout T = tables_layout(0, n, nwork, ntiles);
+    if (workspace_bytes < T.total) return fail(LBM_ENOMEM, "workspace too small: %zu < %zu", workspace_bytes, T.total);
+    lbm_batch *b = new_batch((char *)workspace, T, nwork, ntiles, st, false);
+    if (!b) return fail(LBM_EINVAL, "host allocation failed");
+    for (int32_t k = 0; k < n; ++k) {
+        lbm_ctx *c = ctxs[k];
+        // make every context's current state its buffer fa: batch parity 0
+        if (*c->cur) {
+            void *t = c->L.fa;
+            c->L.fa = c->L.fb;
+            c->L.fb = t;
+            c->own_cur = 0;
+        }
+        c->attached = true;
+        c->view = true;
+        b->lat.push_back(c);
+    }
+    lbm_status stt = upload_tables(b);
+    if (stt != LBM_OK) {
+        for (lbm_ctx *c : b->lat) {
+            c->cur = &c->own_cur;
+            c->attached = false;
+            c->view = false;
+        }
+        delete b;
+        return stt;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+static void batch_advance(lbm_batch *b, int64_t n) {
+    b->step += n;
+    for (lbm_ctx *c : b->lat) *c->step += n;
+}
+
 static lbm_status batch_plain(lbm_batch *b, int64_t n) {
     for (int64_t s = 0; s < n; ++s) {
-        TRY(launch_ok(launch_step_batch(b->d_lats, b->d_work, b->nwork, b->cur, b->stream), "step_batch"));
+        TRY(launch_ok(launch_step_batch(b->d_lats, b->d_work, b->nwork, b->d_twork, b->ntiles, b->cur, b->stream),
+                      "step_batch"));
         b->cur ^= 1;
-        ++b->step;
+        batch_advance(b, 1);
     }
     return LBM_OK;
 }
@@ -729,7 +853,8 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps, int32_t chunk) {
             HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
             hipError_t e = hipSuccess;
             for (int s = 0; s < chunk && e == hipSuccess; ++s)
-                e = launch_step_batch(b->d_lats, b->d_work, b->nwork, par ^ (s & 1), b->stream);
+                e = launch_step_batch(b->d_lats, b->d_work, b->nwork, b->d_twork, b->ntiles, par ^ (s & 1),
+                                      b->stream);
             hipError_t e2 = hipStreamEndCapture(b->stream, &g);
             if (e != hipSuccess) return fail(LBM_EDEVICE, "capture launch: %s", hipGetErrorString(e));
             if (e2 != hipSuccess) return fail(LBM_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e2));
@@ -739,7 +864,7 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps, int32_t chunk) {
             b->graph_chunk[par] = chunk;
         }
         HIPCHK(hipGraphLaunch(b->graph[par], b->stream));
-        b->step += chunk;          // chunk is even: the parity is unchanged
+        batch_advance(b, chunk);   // chunk is even: the parity is unchanged
         nsteps -= chunk;
     }
     return batch_plain(b, nsteps);
@@ -789,7 +914,17 @@ lbm_status lbm_batch_destroy(lbm_batch *b) {
     hipError_t e = hipStreamSynchronize(b->stream);
     for (int i = 0; i < 2; ++i)
         if (b->graph[i]) (void)hipGraphExecDestroy(b->graph[i]);
-    for (lbm_ctx *c : b->lat) delete c;
+    for (lbm_ctx *c : b->lat) {
+        if (b->owned) {
+            delete c;
+        } else {
+            // hand the context back with its state, step index and parity
+            c->own_cur = b->cur;
+            c->cur = &c->own_cur;
+            c->attached = false;
+            c->view = false;
+        }
+    }
     delete b;
     if (e != hipSuccess) return fail(LBM_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
     return LBM_OK;

@@ -14,96 +14,27 @@
 
 namespace lbmwet {
 
-// ---------------------------------------------------------------- marching
-// Walks one (strip, segment) tile and hands every row's node data to `act`.
-template <class S, class C, int WALL, class Act>
-__device__ inline void march(const LatDev<C> &L, const void *src, uint32_t strip, uint32_t seg, Act &act) {
-    using Raw = typename Codec<S>::Raw;
-    const int lane = threadIdx.x & (kWave - 1);
-    const uint32_t nx = L.nx, ny = L.ny;
-    const int col = int(strip * kStripCols) - 1 + lane;             // >= -1
-    const uint32_t x = col < 0 ? nx - 1 : uint32_t(col) % nx;
-    const bool active = lane >= 1 && lane <= kStripCols && col < int(nx);
+// Wall terms of one row (WALL_ROW: per-row scalars) or node (WALL_NODE).
+template <class C> struct RowWall {
+    C phie, Sy;
+};
 
-    RowLoader<S> ld;
-    ld.buf.init(src, 9u * L.plane * uint32_t(sizeof(S)));
-    ld.plane = L.plane;
-    ld.x = x;
-    ld.xm = wrap_dec(x, nx);
-    ld.xp = wrap_inc(x, nx);
-    const uint32_t y0 = seg * L.seg_rows;
-    const uint32_t y1 = min(y0 + L.seg_rows, ny);
-
-    const C w1 = C(1.0 / 9.0), w2 = C(1.0 / 36.0);
-    C f_c[Q], f_n[Q];
-    Raw r_a[Q], r_n[Q];
-
-    // rows y0-1 (psi only) and y0, and the prefetch of y0+1
-    const uint32_t ya = wrap_dec(y0, ny), yb = wrap_inc(y0, ny);
-    ld.load(wrap_dec(ya, ny) * nx, ya * nx, y0 * nx, r_a);
-    ld.load(ya * nx, y0 * nx, yb * nx, r_n);
-    decode_row<S, C>(r_a, f_n, L.rho_ref);
-    C psi_m = psi_of<C>(density<C>(f_n));
-    decode_row<S, C>(r_n, f_c, L.rho_ref);
-    C rho_c = density<C>(f_c);
-    C psi_c = psi_of<C>(rho_c);
-#if LBM_PREFETCH
-    ld.load(y0 * nx, yb * nx, wrap_inc(yb, ny) * nx, r_n);
-#endif
-
-    // One row: consume the populations of row y+1 (cur), optionally after
-    // issuing the loads of row y+2 (into nxt), then hand row y to `act`.  The
-    // two raw buffers swap roles from row to row, so no register holding a
-    // load in flight is ever copied (a copy would wait for the load).
-    auto row = [&](uint32_t y, bool prefetch, Raw(&cur)[Q], Raw(&nxt)[Q]) {
-        const uint32_t yn = wrap_inc(y, ny);
-#if LBM_PREFETCH
-        if (prefetch) {
-            const uint32_t y2 = wrap_inc(yn, ny);
-            ld.load(yn * nx, y2 * nx, wrap_inc(y2, ny) * nx, nxt);
-        }
-#else
-        (void)prefetch;
-        (void)nxt;
-        ld.load(y * nx, yn * nx, wrap_inc(yn, ny) * nx, cur);
-#endif
-        decode_row<S, C>(cur, f_n, L.rho_ref);
-        const C rho_n = density<C>(f_n);
-        const C psi_p = psi_of<C>(rho_n);
-        // sum_i w_i psi(x + c_i) c_i, grouped by column
-        const C a = w1 * psi_c + w2 * (psi_p + psi_m);
-        const C b = psi_p - psi_m;
-        const C sx = from_right<C>(a) - from_left<C>(a);
-        const C sy = w1 * b + w2 * (from_right<C>(b) + from_left<C>(b));
-        act.row(L, y, x, active, f_c, rho_c, psi_c, sx, sy);
-        psi_m = psi_c;
-        psi_c = psi_p;
-        rho_c = rho_n;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) f_c[i] = f_n[i];
-    };
-    // r_n holds row y0+1.  Rows come in pairs (r_n -> r_a, then r_a -> r_n);
-    // every row but the last prefetches (the last of all needs nothing more,
-    // the one before it loads the halo row y1 below the segment).
-    uint32_t y = y0;
-    for (; y + 2 < y1; y += 2) {
-        row(y, true, r_n, r_a);
-        row(y + 1, true, r_a, r_n);
+template <class C, int WALL>
+__device__ inline RowWall<C> row_wall(const LatDev<C> &L, uint32_t y) {
+    RowWall<C> w{C(0), C(0)};
+    if (WALL == WALL_ROW) {
+        w.phie = L.row_tab[2 * y];
+        w.Sy = L.row_tab[2 * y + 1];
     }
-    if (y + 1 < y1) {
-        row(y, true, r_n, r_a);
-        row(y + 1, false, r_a, r_n);
-    } else {
-        row(y, false, r_n, r_a);
-    }
+    return w;
 }
 
 template <class C, int WALL>
-__device__ inline void wall_terms(const LatDev<C> &L, uint32_t y, uint32_t n, C &phie, C &Sx, C &Sy) {
+__device__ inline void wall_terms(const LatDev<C> &L, const RowWall<C> &rw, uint32_t n, C &phie, C &Sx, C &Sy) {
     if (WALL == WALL_ROW) {
-        phie = L.row_tab[2 * y];
+        phie = rw.phie;
         Sx = C(0);
-        Sy = L.row_tab[2 * y + 1];
+        Sy = rw.Sy;
     } else {
         phie = L.node_tab[n];
         Sx = L.node_tab[L.plane + n];
@@ -111,16 +42,172 @@ __device__ inline void wall_terms(const LatDev<C> &L, uint32_t y, uint32_t n, C 
     }
 }
 
+// ---------------------------------------------------------------- marching
+// Walks one (strip, segment) tile and hands every row's node data to `act`.
+//
+// Lane l owns column x0 + l (x0 = 64 * strip, wrapped mod nx), so every
+// population row is read and written as whole 64-lane rows.  The
+// pseudo-potential of the two columns just outside the strip comes from a
+// tenth, gathered load per row (lanes 0..8 and 32..40 fetch the nine
+// populations of those two nodes) summed within 16-lane rows.
+//
+// Software pipeline: the loads of row y+1+D are issued before row y+1 is
+// consumed (D = LBM_PF_DEPTH).  Raw and decoded row buffers rotate through
+// the unrolled iterations instead of being copied: a copy of a register whose
+// load is in flight would wait for that load.
+template <class S, class C, int WALL, class Act>
+__device__ inline void march(const LatDev<C> &L, const void *src, uint32_t strip, uint32_t seg, Act &act) {
+    using Raw = typename Codec<S>::Raw;
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint32_t nx = L.nx, ny = L.ny;
+    const uint32_t x0 = strip * kStripCols;
+    const uint32_t x = (x0 + uint32_t(lane)) % nx;
+    const bool active = x0 + uint32_t(lane) < nx;
+
+    RowLoader<S> ld;
+    ld.buf.init(src, 9u * L.plane * uint32_t(sizeof(S)));
+    ld.plane = L.plane;
+    ld.x = x;
+    ld.xm = wrap_dec(x, nx);
+    ld.xp = wrap_inc(x, nx);
+    // halo gather lanes
+    const bool g_left = lane < Q, g_right = lane >= 32 && lane < 32 + Q;
+    const bool g_on = g_left || g_right;
+    const int g_q = g_left ? lane : (g_right ? lane - 32 : 0);
+    {
+        const uint32_t h = g_left ? (x0 + nx - 1) % nx : (x0 + kStripCols) % nx;
+        const uint32_t hc = uint32_t(int(h) + int(nx) - kCx[g_q]) % nx;   // h - c_x, wrapped
+        ld.g_col = g_on ? uint32_t(g_q) * L.plane + hc : 0u;
+        ld.g_cy = g_on ? kCy[g_q] : 0;
+    }
+    const uint32_t y0 = seg * L.seg_rows;
+    const uint32_t y1 = min(y0 + L.seg_rows, ny);
+
+    const C w1 = C(1.0 / 9.0), w2 = C(1.0 / 36.0);
+    // loads of row r (its pulled populations come from rows r-1, r, r+1)
+    auto load_row = [&](uint32_t r, Raw(&dst)[Q], Raw &g) {
+        ld.load(wrap_dec(r, ny) * nx, r * nx, wrap_inc(r, ny) * nx, dst, g);
+    };
+    // psi of the two halo nodes of a row, from its gathered populations
+    auto halo_psi = [&](Raw g, C &pl, C &pr) {
+        const C v = g_on ? Codec<S>::template decode<C>(g, g_q, L.rho_ref) : C(0);
+        const C s = row_sum9<C>(v);
+        pl = psi_of<C>(Lanes<C>::lane(s, 15));
+        pr = psi_of<C>(Lanes<C>::lane(s, 47));
+    };
+
+    C fA[Q], fB[Q];
+    Raw rA[Q], rB[Q], gA, gB;
+#if LBM_PF_DEPTH >= 2
+    Raw rC[Q], gC;
+#endif
+    // prologue: psi of row y0-1, populations of row y0, prefetches
+    load_row(wrap_dec(y0, ny), rA, gA);
+    load_row(y0, rB, gB);
+    decode_row<S, C>(rA, fB, L.rho_ref);
+    C psi_m = psi_of<C>(density<C>(fB));
+    C hl_m, hr_m, hl_c, hr_c;
+    halo_psi(gA, hl_m, hr_m);
+    decode_row<S, C>(rB, fA, L.rho_ref);
+    C rho_c = density<C>(fA);
+    C psi_c = psi_of<C>(rho_c);
+    halo_psi(gB, hl_c, hr_c);
+    RowWall<C> wall_c = row_wall<C, WALL>(L, y0);
+    load_row(wrap_inc(y0, ny), rA, gA);                           // row y0+1 (always <= y1)
+#if LBM_PF_DEPTH >= 2
+    if (y0 + 2 <= y1) load_row(wrap_inc(wrap_inc(y0, ny), ny), rB, gB);   // row y0+2
+#endif
+
+    // Row y: raw row y+1 in `cur`, optionally prefetch row y+1+D into `nxt`;
+    // decoded row y in `fc`, row y+1 is decoded into `fn`.
+    auto row = [&](uint32_t y, bool prefetch, Raw(&cur)[Q], Raw &gcur, Raw(&nxt)[Q], Raw &gnxt, C(&fc)[Q],
+                   C(&fn)[Q]) {
+        const uint32_t yn = wrap_inc(y, ny);
+        if (prefetch) {
+            uint32_t yp = wrap_inc(yn, ny);
+#if LBM_PF_DEPTH >= 2
+            yp = wrap_inc(yp, ny);
+#endif
+            load_row(yp, nxt, gnxt);
+        }
+        const RowWall<C> wall_n = row_wall<C, WALL>(L, yn);      // scalar loads, one row ahead
+        decode_row<S, C>(cur, fn, L.rho_ref);
+        const C rho_n = density<C>(fn);
+        const C psi_p = psi_of<C>(rho_n);
+        C hl_p, hr_p;
+        halo_psi(gcur, hl_p, hr_p);
+        // sum_i w_i psi(x + c_i) c_i, grouped by column:
+        //   a(x) = w1 psi(x,y) + w2 (psi(x,y+1) + psi(x,y-1)),  sx = a(x+1) - a(x-1)
+        //   b(x) = psi(x,y+1) - psi(x,y-1),  sy = w1 b(x) + w2 (b(x+1) + b(x-1))
+        const C a = w1 * psi_c + w2 * (psi_p + psi_m);
+        const C b = psi_p - psi_m;
+        const C al = w1 * hl_c + w2 * (hl_p + hl_m), ar = w1 * hr_c + w2 * (hr_p + hr_m);
+        const C bl = hl_p - hl_m, br = hr_p - hr_m;
+        const C sx = Lanes<C>::right(a, ar) - Lanes<C>::left(a, al);
+        const C sy = w1 * b + w2 * (Lanes<C>::right(b, br) + Lanes<C>::left(b, bl));
+        act.row(L, wall_c, y, x, active, fc, rho_c, psi_c, sx, sy);
+        psi_m = psi_c;
+        psi_c = psi_p;
+        rho_c = rho_n;
+        hl_m = hl_c;
+        hl_c = hl_p;
+        hr_m = hr_c;
+        hr_c = hr_p;
+        wall_c = wall_n;
+    };
+
+    uint32_t y = y0;
+#if LBM_PF_DEPTH >= 2
+    // rA = row y0+1, rB = row y0+2 (if any); ring rA -> rB -> rC.  A row
+    // prefetches when row y+3 <= y1.  Decoded rows alternate, with a copy.
+    auto row3 = [&](uint32_t yy, Raw(&cur)[Q], Raw &gc, Raw(&nxt)[Q], Raw &gn) {
+        row(yy, yy + 3 <= y1, cur, gc, nxt, gn, fA, fB);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) fA[i] = fB[i];
+    };
+    for (; y + 5 <= y1; y += 3) {
+        row(y, true, rA, gA, rC, gC, fA, fB);
+        row(y + 1, true, rB, gB, rA, gA, fB, fA);
+        row(y + 2, true, rC, gC, rB, gB, fA, fB);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) fA[i] = fB[i];
+    }
+    if (y < y1) row3(y, rA, gA, rC, gC);
+    if (y + 1 < y1) row3(y + 1, rB, gB, rA, gA);
+    if (y + 2 < y1) row3(y + 2, rC, gC, rB, gB);
+    if (y + 3 < y1) row3(y + 3, rA, gA, rC, gC);
+    if (y + 4 < y1) row3(y + 4, rB, gB, rA, gA);
+#else
+    // rA = row y0+1.  Rows come in pairs (rA -> rB, then rB -> rA); every
+    // row but the last prefetches (the last of all needs nothing more, the
+    // one before it loads the halo row y1 below the segment).
+    for (; y + 2 < y1; y += 2) {
+        row(y, true, rA, gA, rB, gB, fA, fB);
+        row(y + 1, true, rB, gB, rA, gA, fB, fA);
+    }
+    if (y + 1 < y1) {
+        row(y, true, rA, gA, rB, gB, fA, fB);
+        row(y + 1, false, rB, gB, rA, gA, fB, fA);
+    } else {
+        row(y, false, rA, gA, rB, gB, fA, fB);
+    }
+#endif
+}
+
 // Collide and store (the time step).
 template <class S, class C, int WALL> struct StepAct {
     PopBuf<S> dst;
-    __device__ inline void row(const LatDev<C> &L, uint32_t y, uint32_t x, bool active, C f[Q],
-                               C rho, C psi_c, C sx, C sy) {
+    __device__ inline void row(const LatDev<C> &L, const RowWall<C> &rw, uint32_t y, uint32_t x, bool active,
+                               C f[Q], C rho, C psi_c, C sx, C sy) {
         const uint32_t n = y * L.nx + x;
         C phie, Sx, Sy;
-        wall_terms<C, WALL>(L, y, n, phie, Sx, Sy);
+        wall_terms<C, WALL>(L, rw, n, phie, Sx, Sy);
         NodeState<C> s = node_forces<C>(f, rho, psi_c, sx, sy, phie, Sx, Sy, L.G, L.Ux, L.Uy, L.Fx, L.Fy);
+#if !LBM_PROBE_NOCOLLIDE
         collide<C>(f, s, L.omega);
+#else
+        f[0] += C(1e-30) * s.Fx;   // probe build: keep the forces alive, skip the collision
+#endif
         if (active) {
             const uint32_t row = y * L.nx;
 #pragma unroll
@@ -134,11 +221,11 @@ template <class S, class C, int WALL> struct StepAct {
 template <class S, class C, int WALL> struct DiagAct {
     int write_mom, compare, update;
     double s_rho = 0, s_jx = 0, s_jy = 0, s_du = 0, s_u = 0, s_bad = 0;
-    __device__ inline void row(const LatDev<C> &L, uint32_t y, uint32_t x, bool active, C f[Q],
-                               C rho, C psi_c, C sx, C sy) {
+    __device__ inline void row(const LatDev<C> &L, const RowWall<C> &rw, uint32_t y, uint32_t x, bool active,
+                               C f[Q], C rho, C psi_c, C sx, C sy) {
         const uint32_t n = y * L.nx + x;
         C phie, Sx, Sy;
-        wall_terms<C, WALL>(L, y, n, phie, Sx, Sy);
+        wall_terms<C, WALL>(L, rw, n, phie, Sx, Sy);
         NodeState<C> s = node_forces<C>(f, rho, psi_c, sx, sy, phie, Sx, Sy, L.G, L.Ux, L.Uy, L.Fx, L.Fy);
         const C vx = s.ux + C(0.5) * s.Fx * s.inv_rho;
         const C vy = s.uy + C(0.5) * s.Fy * s.inv_rho;
@@ -175,9 +262,108 @@ __device__ inline uint32_t logical_wave() {
     return lb * kBlockWaves + w;
 }
 
+// ---------------------------------------------------------------- tiles
+// The time step proper.  One workgroup of kTileWaves waves owns a 64-column
+// strip and kTileRowsIn = kTileWaves * kRowsPerWave consecutive rows, of which
+// the first and last are halo rows: wave w loads rows y0 - 1 + w R + j
+// (j < R), all at once.  Each wave computes density and pseudo-potential of
+// its rows (and of the two columns beside the strip, from the gathered load),
+// publishes them in LDS, and after one barrier every row between the halo
+// rows reads its neighbours above and below, forms the forces, collides and
+// stores.  No wave walks through rows one after another: every population row
+// of the tile is in flight at the same time.
+template <class C> struct TileLds {
+    C psi[kTileRowsIn][kWave];
+    C hal[kTileRowsIn][2];
+};
+
+template <class S, class C, int WALL>
+__device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst, uint32_t strip, uint32_t trow,
+                                 TileLds<C> &sm) {
+    using Raw = typename Codec<S>::Raw;
+    constexpr int R = kRowsPerWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
+    const uint32_t nx = L.nx, ny = L.ny;
+    const uint32_t x0 = strip * kStripCols;
+    const uint32_t x = (x0 + uint32_t(lane)) % nx;
+    const bool active = x0 + uint32_t(lane) < nx;
+    const uint32_t y0 = trow * kTileRows;
+    const uint32_t out_rows = min(uint32_t(kTileRows), ny - y0);
+
+    RowLoader<S> ld;
+    ld.buf.init(src, 9u * L.plane * uint32_t(sizeof(S)));
+    ld.plane = L.plane;
+    ld.x = x;
+    ld.xm = wrap_dec(x, nx);
+    ld.xp = wrap_inc(x, nx);
+    const bool g_left = lane < Q, g_right = lane >= 32 && lane < 32 + Q;
+    const bool g_on = g_left || g_right;
+    const int g_q = g_left ? lane : (g_right ? lane - 32 : 0);
+    {
+        const uint32_t h = g_left ? (x0 + nx - 1) % nx : (x0 + kStripCols) % nx;
+        const uint32_t hc = uint32_t(int(h) + int(nx) - kCx[g_q]) % nx;   // h - c_x, wrapped
+        ld.g_col = g_on ? uint32_t(g_q) * L.plane + hc : 0u;
+        ld.g_cy = g_on ? kCy[g_q] : 0;
+    }
+
+    // rows of this wave: tile row index k = w R + j, lattice row y0 - 1 + k
+    C f[R][Q], rho[R], psi[R];
+    Raw raw[R][Q], g[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const uint32_t k = uint32_t(w * R + j);
+        const uint32_t r = (y0 + ny - 1 + k) % ny;
+        if (k <= out_rows + 1) ld.load(wrap_dec(r, ny) * nx, r * nx, wrap_inc(r, ny) * nx, raw[j], g[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const uint32_t k = uint32_t(w * R + j);
+        rho[j] = C(0);
+        psi[j] = C(0);
+        if (k <= out_rows + 1) {
+            decode_row<S, C>(raw[j], f[j], L.rho_ref);
+            rho[j] = density<C>(f[j]);
+            psi[j] = psi_of<C>(rho[j]);
+            // the halo nodes' density is read out of lanes 15 and 47 by every
+            // lane, outside divergent control flow
+            const C v = g_on ? Codec<S>::template decode<C>(g[j], g_q, L.rho_ref) : C(0);
+            const C sum = row_sum9<C>(v);
+            const C hl = psi_of<C>(Lanes<C>::lane(sum, 15));
+            const C hr = psi_of<C>(Lanes<C>::lane(sum, 47));
+            sm.psi[k][lane] = psi[j];
+            if (lane == 0) {
+                sm.hal[k][0] = hl;
+                sm.hal[k][1] = hr;
+            }
+        }
+    }
+    __syncthreads();
+    const C w1 = C(1.0 / 9.0), w2 = C(1.0 / 36.0);
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const uint32_t k = uint32_t(w * R + j);
+        if (k < 1 || k > out_rows) continue;
+        const uint32_t r = (y0 - 1 + k) % ny;
+        const C psi_m = sm.psi[k - 1][lane], psi_p = sm.psi[k + 1][lane];
+        const C hl_m = sm.hal[k - 1][0], hl_c = sm.hal[k][0], hl_p = sm.hal[k + 1][0];
+        const C hr_m = sm.hal[k - 1][1], hr_c = sm.hal[k][1], hr_p = sm.hal[k + 1][1];
+        // sum_i w_i psi(x + c_i) c_i, grouped by column (see march)
+        const C a = w1 * psi[j] + w2 * (psi_p + psi_m);
+        const C b = psi_p - psi_m;
+        const C al = w1 * hl_c + w2 * (hl_p + hl_m), ar = w1 * hr_c + w2 * (hr_p + hr_m);
+        const C bl = hl_p - hl_m, br = hr_p - hr_m;
+        const C sx = Lanes<C>::right(a, ar) - Lanes<C>::left(a, al);
+        const C sy = w1 * b + w2 * (Lanes<C>::right(b, br) + Lanes<C>::left(b, bl));
+        StepAct<S, C, WALL> act;
+        act.dst.init(dst, 9u * L.plane * uint32_t(sizeof(S)));
+        act.row(L, row_wall<C, WALL>(L, r), r, x, active, f[j], rho[j], psi[j], sx, sy);
+    }
+}
+
 // ---------------------------------------------------------------- kernels
 template <class S, class C, int WALL>
-__global__ __launch_bounds__(256) void k_step(LatDev<C> L, const void *__restrict__ src, void *__restrict__ dst) {
+__global__ __launch_bounds__(kBlockThreads) void k_step(LatDev<C> L, const void *__restrict__ src, void *__restrict__ dst) {
     const uint32_t gw = logical_wave();
     if (gw >= L.strips * L.segs) return;
     const uint32_t seg = gw / L.strips, strip = gw - seg * L.strips;
@@ -186,10 +372,31 @@ __global__ __launch_bounds__(256) void k_step(LatDev<C> L, const void *__restric
     march<S, C, WALL>(L, src, strip, seg, act);
 }
 
+template <class S, class C, int WALL>
+__global__ __launch_bounds__(kTileThreads) void k_step_tiles(LatDev<C> L, const void *__restrict__ src,
+                                                             void *__restrict__ dst) {
+    __shared__ TileLds<C> sm;
+    const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const uint32_t trow = lb / L.strips, strip = lb - trow * L.strips;
+    tile_step<S, C, WALL>(L, src, dst, strip, trow, sm);
+}
+
+// Batched step over tiles: twork[b] = (lattice, strip, tile row) of logical
+// workgroup b, lattices in order.
+template <class S, class C, int WALL>
+__global__ __launch_bounds__(kTileThreads) void k_step_tiles_batch(const LatDev<C> *__restrict__ lats,
+                                                                   const uint4 *__restrict__ twork, int parity) {
+    __shared__ TileLds<C> sm;
+    const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const uint4 wk = twork[lb];
+    const LatDev<C> L = lats[wk.x];
+    tile_step<S, C, WALL>(L, parity ? L.fb : L.fa, parity ? L.fa : L.fb, wk.y, wk.z, sm);
+}
+
 // Batched step: one launch over the tiles of many lattices.  work[g] =
 // (lattice, strip, segment) of global wave g, lattices in order.
 template <class S, class C, int WALL>
-__global__ __launch_bounds__(256) void k_step_batch(const LatDev<C> *__restrict__ lats,
+__global__ __launch_bounds__(kBlockThreads) void k_step_batch(const LatDev<C> *__restrict__ lats,
                                                     const uint4 *__restrict__ work, uint32_t nwork, int parity) {
     const uint32_t gw = logical_wave();
     if (gw >= nwork) return;
@@ -202,7 +409,7 @@ __global__ __launch_bounds__(256) void k_step_batch(const LatDev<C> *__restrict_
 }
 
 template <class S, class C, int WALL>
-__global__ __launch_bounds__(256) void k_diag(const LatDev<C> *__restrict__ lats, const uint4 *__restrict__ work,
+__global__ __launch_bounds__(kBlockThreads) void k_diag(const LatDev<C> *__restrict__ lats, const uint4 *__restrict__ work,
                                               uint32_t nwork, LatDev<C> single, int parity, int write_mom,
                                               int compare, int update) {
     const uint32_t gw = logical_wave();
@@ -294,7 +501,8 @@ __device__ inline void iso_accumulate(const IsoArgs &a, double px, double py, do
 template <class C>
 __global__ __launch_bounds__(256) void k_isoline(IsoArgs a, const C *__restrict__ rho,
                                                  const double *__restrict__ phi, double *__restrict__ part) {
-    __shared__ double sm[kBlockWaves][10];
+    constexpr int kIsoWaves = 256 / kWave;   // launched with 256 threads
+    __shared__ double sm[kIsoWaves][10];
     double acc[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const uint32_t N = a.nx * a.ny;
     const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -332,7 +540,7 @@ __global__ __launch_bounds__(256) void k_isoline(IsoArgs a, const C *__restrict_
     __syncthreads();
     if (threadIdx.x < 10) {
         double s = 0.0;
-        for (int i = 0; i < kBlockWaves; ++i) s += sm[i][threadIdx.x];
+        for (int i = 0; i < kIsoWaves; ++i) s += sm[i][threadIdx.x];
         part[size_t(blockIdx.x) * 10 + threadIdx.x] = s;
     }
 }
@@ -485,25 +693,47 @@ template <class Fn> static hipError_t dispatch(int storage, Fn &&fn) {
     }
 }
 
+uint32_t step_tiles(uint32_t nx, uint32_t ny) {
+    return ((nx + kStripCols - 1) / kStripCols) * ((ny + kTileRows - 1) / kTileRows);
+}
+
 hipError_t launch_step(int storage, const LatDevAny &L, int wall, int parity, hipStream_t st) {
     return dispatch(storage, [&](auto s, auto c) {
         using S = decltype(s);
         using C = decltype(c);
         LatDev<C> d = L.get<C>();
-        const uint32_t waves = d.strips * d.segs;
         const void *src = parity ? d.fb : d.fa;
         void *dst = parity ? d.fa : d.fb;
+#if LBM_STEP_TILES
+        const uint32_t nb = step_tiles(d.nx, d.ny);
         if (wall == WALL_ROW)
-            hipLaunchKernelGGL((k_step<S, C, WALL_ROW>), dim3(blocks_for(waves)), dim3(256), 0, st, d, src, dst);
+            hipLaunchKernelGGL((k_step_tiles<S, C, WALL_ROW>), dim3(nb), dim3(kTileThreads), 0, st, d, src, dst);
         else
-            hipLaunchKernelGGL((k_step<S, C, WALL_NODE>), dim3(blocks_for(waves)), dim3(256), 0, st, d, src, dst);
+            hipLaunchKernelGGL((k_step_tiles<S, C, WALL_NODE>), dim3(nb), dim3(kTileThreads), 0, st, d, src, dst);
+#else
+        const uint32_t waves = d.strips * d.segs;
+        if (wall == WALL_ROW)
+            hipLaunchKernelGGL((k_step<S, C, WALL_ROW>), dim3(blocks_for(waves)), dim3(kBlockThreads), 0, st, d, src, dst);
+        else
+            hipLaunchKernelGGL((k_step<S, C, WALL_NODE>), dim3(blocks_for(waves)), dim3(kBlockThreads), 0, st, d, src, dst);
+#endif
         return hipGetLastError();
     });
 }
 
-hipError_t launch_step_batch(const void *lats, const uint4 *work, uint32_t nwork, int parity, hipStream_t st) {
-    hipLaunchKernelGGL((k_step_batch<float, float, WALL_ROW>), dim3(blocks_for(nwork)), dim3(256), 0, st,
+hipError_t launch_step_batch(const void *lats, const uint4 *work, uint32_t nwork, const uint4 *twork, uint32_t ntiles,
+                             int parity, hipStream_t st) {
+#if LBM_STEP_TILES
+    (void)work;
+    (void)nwork;
+    hipLaunchKernelGGL((k_step_tiles_batch<float, float, WALL_ROW>), dim3(ntiles), dim3(kTileThreads), 0, st,
+                       (const LatDev<float> *)lats, twork, parity);
+#else
+    (void)twork;
+    (void)ntiles;
+    hipLaunchKernelGGL((k_step_batch<float, float, WALL_ROW>), dim3(blocks_for(nwork)), dim3(kBlockThreads), 0, st,
                        (const LatDev<float> *)lats, work, nwork, parity);
+#endif
     return hipGetLastError();
 }
 
@@ -515,10 +745,10 @@ hipError_t launch_diag(int storage, const void *lats, const uint4 *work, uint32_
         LatDev<C> d = single.get<C>();
         const uint32_t waves = lats ? nwork : d.strips * d.segs;
         if (wall == WALL_ROW)
-            hipLaunchKernelGGL((k_diag<S, C, WALL_ROW>), dim3(blocks_for(waves)), dim3(256), 0, st,
+            hipLaunchKernelGGL((k_diag<S, C, WALL_ROW>), dim3(blocks_for(waves)), dim3(kBlockThreads), 0, st,
                                (const LatDev<C> *)lats, work, nwork, d, parity, write_mom, compare, update);
         else
-            hipLaunchKernelGGL((k_diag<S, C, WALL_NODE>), dim3(blocks_for(waves)), dim3(256), 0, st,
+            hipLaunchKernelGGL((k_diag<S, C, WALL_NODE>), dim3(blocks_for(waves)), dim3(kBlockThreads), 0, st,
                                (const LatDev<C> *)lats, work, nwork, d, parity, write_mom, compare, update);
         return hipGetLastError();
     });

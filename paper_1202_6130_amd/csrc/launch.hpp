@@ -66,11 +66,28 @@ struct IsoParams {
     double iso, phi_max, mx, my, xc, yc, R;
 };
 
-constexpr uint32_t kStripColsHost = 62;
-constexpr uint32_t kBlockWavesHost = 4;
+constexpr uint32_t kStripColsHost = 64;
 
+#ifndef LBM_BLOCK_WAVES
+#define LBM_BLOCK_WAVES 4   // waves per workgroup of the marching kernels
+#endif
+constexpr uint32_t kBlockWavesHost = LBM_BLOCK_WAVES;
+
+#ifndef LBM_TILE_WAVES
+#define LBM_TILE_WAVES 16  // waves per step tile
+#endif
+#ifndef LBM_TILE_ROWS_PER_WAVE
+#define LBM_TILE_ROWS_PER_WAVE 2   // rows each wave of a step tile loads and updates
+#endif
+#ifndef LBM_STEP_TILES
+#define LBM_STEP_TILES 1   // time step by LDS tiles (1) or by marching waves (0)
+#endif
+constexpr uint32_t kTileRowsHost = LBM_TILE_WAVES * LBM_TILE_ROWS_PER_WAVE - 2;
+
+uint32_t step_tiles(uint32_t nx, uint32_t ny);
 hipError_t launch_step(int storage, const LatDevAny &L, int wall, int parity, hipStream_t st);
-hipError_t launch_step_batch(const void *lats, const uint4 *work, uint32_t nwork, int parity, hipStream_t st);
+hipError_t launch_step_batch(const void *lats, const uint4 *work, uint32_t nwork, const uint4 *twork, uint32_t ntiles,
+                             int parity, hipStream_t st);
 hipError_t launch_diag(int storage, const void *lats, const uint4 *work, uint32_t nwork, const LatDevAny &single,
                        int wall, int parity, int write_mom, int compare, int update, hipStream_t st);
 hipError_t launch_reduce(const double *part, const uint32_t *ranges, uint32_t nout, uint32_t stride,

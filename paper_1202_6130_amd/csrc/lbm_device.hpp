@@ -22,6 +22,21 @@
 #ifndef LBM_PSI_EXPM1
 #define LBM_PSI_EXPM1 0    // psi = -expm1(-rho) instead of 1 - exp(-rho)
 #endif
+#ifndef LBM_PF_DEPTH
+#define LBM_PF_DEPTH 1     // rows of loads in flight ahead of the row being consumed (1 or 2)
+#endif
+#ifndef LBM_STORE_AUX
+#define LBM_STORE_AUX 0    // cache-policy bits of population stores (gfx950: 1 sc0, 2 nt, 16 sc1)
+#endif
+#ifndef LBM_LOAD_AUX
+#define LBM_LOAD_AUX 0     // cache-policy bits of population loads
+#endif
+#ifndef LBM_PROBE_NOGATHER
+#define LBM_PROBE_NOGATHER 0    // measurement builds only: replace the halo gather
+#endif
+#ifndef LBM_PROBE_NOCOLLIDE
+#define LBM_PROBE_NOCOLLIDE 0   // measurement builds only: skip the collision arithmetic
+#endif
 
 namespace lbmwet {
 
@@ -33,8 +48,14 @@ constexpr double kW[Q] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9
                           1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
 constexpr int kWave = 64;          // CDNA wavefront width
-constexpr int kStripCols = 62;     // output columns per wave (2 halo lanes)
-constexpr int kBlockWaves = 4;     // waves per 256-thread workgroup
+constexpr int kStripCols = 64;     // output columns per wave (one per lane, 64-aligned)
+constexpr int kBlockWaves = LBM_BLOCK_WAVES;   // waves per workgroup
+constexpr int kBlockThreads = kWave * kBlockWaves;
+constexpr int kTileWaves = LBM_TILE_WAVES;        // waves per step tile
+constexpr int kRowsPerWave = LBM_TILE_ROWS_PER_WAVE;
+constexpr int kTileRowsIn = kTileWaves * kRowsPerWave;   // rows loaded per tile, incl. 2 halo rows
+constexpr int kTileRows = kTileRowsIn - 2;        // output rows per step tile
+constexpr int kTileThreads = kWave * kTileWaves;
 
 enum WallMode : int { WALL_ROW = 0, WALL_NODE = 1 };
 
@@ -80,15 +101,15 @@ template <class S> struct PopBuf {
     // lane offset in elements (varies per lane), uniform offset in elements
     __device__ inline Raw load(uint32_t lane_el, uint32_t uni_el) const {
         const int vo = int(lane_el * sizeof(S)), so = int(uni_el * sizeof(S));
-        if constexpr (sizeof(S) == 4) return __builtin_amdgcn_raw_buffer_load_b32(rsrc, vo, so, 0);
-        else if constexpr (sizeof(S) == 2) return __builtin_amdgcn_raw_buffer_load_b16(rsrc, vo, so, 0);
-        else return __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b64(rsrc, vo, so, 0));
+        if constexpr (sizeof(S) == 4) return __builtin_amdgcn_raw_buffer_load_b32(rsrc, vo, so, LBM_LOAD_AUX);
+        else if constexpr (sizeof(S) == 2) return __builtin_amdgcn_raw_buffer_load_b16(rsrc, vo, so, LBM_LOAD_AUX);
+        else return __builtin_bit_cast(Raw, __builtin_amdgcn_raw_buffer_load_b64(rsrc, vo, so, LBM_LOAD_AUX));
     }
     __device__ inline void store(Raw v, uint32_t lane_el, uint32_t uni_el) const {
         const int vo = int(lane_el * sizeof(S)), so = int(uni_el * sizeof(S));
-        if constexpr (sizeof(S) == 4) __builtin_amdgcn_raw_buffer_store_b32(v, rsrc, vo, so, 0);
-        else if constexpr (sizeof(S) == 2) __builtin_amdgcn_raw_buffer_store_b16(v, rsrc, vo, so, 0);
-        else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(rsrc, 0, 0, 0)), v), rsrc, vo, so, 0);
+        if constexpr (sizeof(S) == 4) __builtin_amdgcn_raw_buffer_store_b32(v, rsrc, vo, so, LBM_STORE_AUX);
+        else if constexpr (sizeof(S) == 2) __builtin_amdgcn_raw_buffer_store_b16(v, rsrc, vo, so, LBM_STORE_AUX);
+        else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(rsrc, 0, 0, 0)), v), rsrc, vo, so, LBM_STORE_AUX);
     }
 #else
     Raw *base;
@@ -116,41 +137,77 @@ template <class C> __device__ inline C cexp(C v);
 template <> __device__ inline float cexp<float>(float v) { return __expf(v); }
 template <> __device__ inline double cexp<double>(double v) { return exp(v); }
 
-// Cross-lane neighbours along x (lane -1 / lane +1).  Halo lanes 0 and 63
-// receive values they never use.
-#if LBM_USE_DPP
-__device__ inline int dpp_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xF, 0xF, false); }
-__device__ inline int dpp_shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xF, 0xF, false); }
-template <class C> __device__ inline C from_left(C v);
-template <class C> __device__ inline C from_right(C v);
-template <> __device__ inline float from_left<float>(float v) {
-    return __builtin_bit_cast(float, dpp_shr1(__builtin_bit_cast(int, v)));
+// Cross-lane neighbours along x: from_left(v, e) gives lane l the value of
+// lane l-1 and lane 0 the value e (the column left of the strip);
+// from_right(v, e) gives lane l the value of lane l+1 and lane 63 the value e.
+// DPP wave shifts keep the `old` operand in the lane that has no source.
+__device__ inline int dpp_shr1(int old, int v) { return __builtin_amdgcn_update_dpp(old, v, 0x138, 0xF, 0xF, false); }
+__device__ inline int dpp_shl1(int old, int v) { return __builtin_amdgcn_update_dpp(old, v, 0x130, 0xF, 0xF, false); }
+// row_shr:n within 16-lane rows, zero where the source lane is outside the row
+template <int N> __device__ inline int dpp_row_shr(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, 0x110 + N, 0xF, 0xF, true);
 }
-template <> __device__ inline float from_right<float>(float v) {
-    return __builtin_bit_cast(float, dpp_shl1(__builtin_bit_cast(int, v)));
-}
-template <> __device__ inline double from_left<double>(double v) {
-    int2 p = __builtin_bit_cast(int2, v);
-    return __builtin_bit_cast(double, make_int2(dpp_shr1(p.x), dpp_shr1(p.y)));
-}
-template <> __device__ inline double from_right<double>(double v) {
-    int2 p = __builtin_bit_cast(int2, v);
-    return __builtin_bit_cast(double, make_int2(dpp_shl1(p.x), dpp_shl1(p.y)));
-}
-#else
-template <class C> __device__ inline C from_left(C v) { return __shfl_up(v, 1, kWave); }
-template <class C> __device__ inline C from_right(C v) { return __shfl_down(v, 1, kWave); }
-#endif
 
-// Raw post-streaming populations of one row (pull: f_i(x) = f'_i(x - c_i)).
+template <class C> struct Lanes;
+template <> struct Lanes<float> {
+    static __device__ inline float left(float v, float e) {
+        return __builtin_bit_cast(float, dpp_shr1(__builtin_bit_cast(int, e), __builtin_bit_cast(int, v)));
+    }
+    static __device__ inline float right(float v, float e) {
+        return __builtin_bit_cast(float, dpp_shl1(__builtin_bit_cast(int, e), __builtin_bit_cast(int, v)));
+    }
+    template <int N> static __device__ inline float shr(float v) {
+        return __builtin_bit_cast(float, dpp_row_shr<N>(__builtin_bit_cast(int, v)));
+    }
+    static __device__ inline float lane(float v, int l) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+    }
+};
+template <> struct Lanes<double> {
+    static __device__ inline double left(double v, double e) {
+        const int2 p = __builtin_bit_cast(int2, v), q = __builtin_bit_cast(int2, e);
+        return __builtin_bit_cast(double, make_int2(dpp_shr1(q.x, p.x), dpp_shr1(q.y, p.y)));
+    }
+    static __device__ inline double right(double v, double e) {
+        const int2 p = __builtin_bit_cast(int2, v), q = __builtin_bit_cast(int2, e);
+        return __builtin_bit_cast(double, make_int2(dpp_shl1(q.x, p.x), dpp_shl1(q.y, p.y)));
+    }
+    template <int N> static __device__ inline double shr(double v) {
+        const int2 p = __builtin_bit_cast(int2, v);
+        return __builtin_bit_cast(double, make_int2(dpp_row_shr<N>(p.x), dpp_row_shr<N>(p.y)));
+    }
+    static __device__ inline double lane(double v, int l) {
+        const int2 p = __builtin_bit_cast(int2, v);
+        return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readlane(p.x, l),
+                                                     __builtin_amdgcn_readlane(p.y, l)));
+    }
+};
+
+// Sum of lanes 16r .. 16r+8 of each 16-lane row r, left in lane 16r+15, when
+// lanes 16r+9 .. 16r+15 hold zero.  The tree is ((v0+v1)+(v2+v3)) +
+// ((v4+v5)+(v6+v7)) + v8 up to operand order, i.e. exactly density() below.
+template <class C> __device__ inline C row_sum9(C v) {
+    v = v + Lanes<C>::template shr<1>(v);
+    v = v + Lanes<C>::template shr<2>(v);
+    v = v + Lanes<C>::template shr<4>(v);
+    v = v + Lanes<C>::template shr<8>(v);
+    return v;
+}
+
+// Raw post-streaming populations of one row (pull: f_i(x) = f'_i(x - c_i)),
+// plus the halo gather: lanes 0..8 load population q = lane of the node left
+// of the strip, lanes 32..40 population q = lane - 32 of the node right of
+// it; the other lanes load a harmless in-bounds word and later use zero.
 template <class S> struct RowLoader {
     using Raw = typename Codec<S>::Raw;
     PopBuf<S> buf;
     uint32_t plane;
     uint32_t x, xm, xp;            // this lane's column and its wrapped neighbours
+    uint32_t g_col;                // gather: q * plane + source column (elements)
+    int g_cy;                      // gather: row shift of population q
 
     // rm/r0/rp: element offsets (row * nx) of rows r-1, r, r+1
-    __device__ inline void load(uint32_t rm, uint32_t r0, uint32_t rp, Raw f[Q]) const {
+    __device__ inline void load(uint32_t rm, uint32_t r0, uint32_t rp, Raw f[Q], Raw &g) const {
         f[0] = buf.load(x, 0 * plane + r0);
         f[1] = buf.load(xm, 1 * plane + r0);
         f[2] = buf.load(x, 2 * plane + rm);
@@ -160,6 +217,12 @@ template <class S> struct RowLoader {
         f[6] = buf.load(xp, 6 * plane + rm);
         f[7] = buf.load(xp, 7 * plane + rp);
         f[8] = buf.load(xm, 8 * plane + rp);
+#if LBM_PROBE_NOGATHER
+        g = buf.load(x, 0 * plane + r0);   // measurement builds only: contiguous stand-in
+#else
+        const uint32_t rs = g_cy > 0 ? rm : (g_cy == 0 ? r0 : rp);
+        g = buf.load(g_col + rs, 0);
+#endif
     }
 };
 
@@ -201,6 +264,12 @@ template <> struct LatConst<double> {
     static constexpr double m1 = 1.0 / 3.0, m2 = 1.0 / 12.0;
 };
 
+// 1/rho: the hardware reciprocal in binary32 (1 ulp; the momentum of the
+// equilibrium does not go through it), a correctly rounded division in FP64.
+template <class C> __device__ inline C recip(C v);
+template <> __device__ inline float recip<float>(float v) { return __builtin_amdgcn_rcpf(v); }
+template <> __device__ inline double recip<double>(double v) { return 1.0 / v; }
+
 // Everything the collision needs at one node.
 template <class C> struct NodeState {
     C rho, inv_rho;
@@ -217,7 +286,7 @@ __device__ inline NodeState<C> node_forces(const C f[Q], C rho, C psi_c, C sx, C
                                            C Sx, C Sy, C G, C Ux, C Uy, C Fxe, C Fye) {
     NodeState<C> s;
     s.rho = rho;
-    s.inv_rho = C(1) / rho;
+    s.inv_rho = recip<C>(rho);
     s.jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
     s.jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
     s.ux = s.jx * s.inv_rho;
@@ -263,9 +332,16 @@ template <class C> __device__ inline void equilibrium(C rho, C inv_rho, C mx, C 
 //                       = (1 - 1/tau) (f - feq(u)) + feq(u*),
 // with rho u* = j + F.
 template <class C> __device__ inline void collide(C f[Q], const NodeState<C> &s, C omega) {
-    C fu[Q], fs[Q];
-    equilibrium<C>(s.rho, s.inv_rho, s.jx, s.jy, fu);
+    C fs[Q];
     equilibrium<C>(s.rho, s.inv_rho, s.jx + s.Fx, s.jy + s.Fy, fs);
+    if (omega == C(1)) {
+        // tau = 1: the factor (1 - 1/tau) is exactly zero, f' = feq(u*)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = fs[i];
+        return;
+    }
+    C fu[Q];
+    equilibrium<C>(s.rho, s.inv_rho, s.jx, s.jy, fu);
     const C keep = C(1) - omega;
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[i] = keep * (f[i] - fu[i]) + fs[i];

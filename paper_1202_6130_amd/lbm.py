@@ -81,6 +81,10 @@ def lib():
         "lbm_batch_diagnostics": ([_vp, _dp], ctypes.c_int),
         "lbm_batch_lattice": ([_vp, ctypes.c_int32], _vp),
         "lbm_batch_destroy": ([_vp], ctypes.c_int),
+        "lbm_batch_attach_bytes": ([ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
+                                   ctypes.c_int),
+        "lbm_batch_attach": ([ctypes.POINTER(_vp), ctypes.c_int32, _vp, ctypes.c_size_t, _vp,
+                              ctypes.POINTER(_vp)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -232,6 +236,21 @@ def lbm_batch_destroy(b):
         _check(lib().lbm_batch_destroy(b))
 
 
+def lbm_batch_attach_bytes(ctxs):
+    arr = (_vp * len(ctxs))(*ctxs)
+    n = ctypes.c_size_t()
+    _check(lib().lbm_batch_attach_bytes(arr, len(ctxs), ctypes.byref(n)))
+    return n.value
+
+
+def lbm_batch_attach(ctxs, workspace_ptr, workspace_bytes, stream_ptr):
+    arr = (_vp * len(ctxs))(*ctxs)
+    out = _vp()
+    _check(lib().lbm_batch_attach(arr, len(ctxs), _vp(workspace_ptr), workspace_bytes, _vp(stream_ptr),
+                                  ctypes.byref(out)))
+    return out
+
+
 # ------------------------------------------------------------ conveniences
 def _workspace(nbytes, device):
     import torch
@@ -295,6 +314,41 @@ class Lattice:
         if self.ctx:
             lbm_destroy(self.ctx)
             self.ctx = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Attached:
+    """A batch over existing Lattice objects (all on one non-default stream):
+    one launch per time step for all of them; closing hands them back."""
+
+    def __init__(self, lattices, device="cuda:0"):
+        self.lattices = list(lattices)
+        ctxs = [L.ctx for L in self.lattices]
+        streams = {L.stream_ptr for L in self.lattices}
+        if len(streams) != 1:
+            raise ValueError("attached lattices must share one stream")
+        self.stream_ptr = streams.pop()
+        nbytes = lbm_batch_attach_bytes(ctxs)
+        self._ws, ptr = _workspace(nbytes, device)
+        self.b = lbm_batch_attach(ctxs, ptr, nbytes, self.stream_ptr)
+        self.n = len(ctxs)
+
+    def step(self, nsteps, chunk=0):
+        lbm_batch_step(self.b, nsteps, chunk)
+
+    def diagnostics(self, check=True):
+        return lbm_batch_diagnostics(self.b, self.n, check)
+
+    def close(self):
+        if self.b:
+            lbm_batch_destroy(self.b)
+            self.b = None
             self._ws = None
 
     def __del__(self):

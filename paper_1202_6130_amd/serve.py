@@ -1,0 +1,196 @@
+"""Continuous-batching server for contact-angle and slip-length queries.
+
+Each request is one lattice (sessile drop -> static contact angle, Sec. III.B;
+body-force channel -> slip length, Sec. III.A).  Requests are admitted in
+arrival order while their device footprint fits the memory budget and a slot
+is free; all resident lattices advance together, one kernel launch per time
+step (lbm_batch_attach), replayed from a HIP graph in chunks of `diag_every`
+steps.  After every chunk the velocity residual of each lattice is read; a
+lattice whose residual falls below `tol` (or that reaches `max_steps`) is
+measured and retired, and its slot and memory go to the next request.  The
+batch is rebuilt whenever membership changes; resident lattices keep their
+state across rebuilds.  A request whose lattice turns non-finite fails alone.
+
+`Server(batched=False, max_resident=1)` is the plain sequential baseline.
+"""
+import collections
+import dataclasses
+import time
+
+import numpy as np
+
+from . import inputs as I
+from . import lbm
+
+CHANNEL_FORCE = 1e-6      # body force density of the slip queries
+CHANNEL_RHO = 2.0         # liquid filling the channel
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    kind: str
+    nx: int
+    ny: int
+    arrival: float
+    admitted: float = float("nan")
+    finished: float = float("nan")
+    steps: int = 0
+    converged: bool = False
+    residual: float = float("inf")
+    value: tuple = ()
+    error: str = ""
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+
+def request_params(req, seg_rows=0):
+    """Lattice parameters and initial density of one request."""
+    common = dict(nx=req.nx, ny=req.ny, storage=lbm.STORE_F32, wall_kind=lbm.WALL_FLAT_SLAB, G=req.G,
+                  G_R=req.G_R, G_A=req.G_A, eps=req.eps, seg_rows=seg_rows)
+    if req.kind == "angle":
+        p = lbm.lbm_params_default(**common)
+        rho0 = I.drop_field(req.nx, req.ny, 0.3 * min(req.nx, req.ny))
+    else:
+        p = lbm.lbm_params_default(F_ext=(CHANNEL_FORCE, 0.0), **common)
+        rho0 = I.uniform_field(req.nx, req.ny, CHANNEL_RHO)
+    return p, rho0
+
+
+class Server:
+    def __init__(self, budget_bytes=96 << 30, max_resident=64, diag_every=100, max_steps=20000, tol=1e-8,
+                 batched=True, device="cuda:0", seg_rows=0):
+        import torch
+        if diag_every % 2:
+            raise ValueError("diag_every must be even (graph replays keep the buffer parity)")
+        self.budget = int(budget_bytes)
+        self.max_resident = int(max_resident)
+        self.K = int(diag_every)
+        self.max_steps = int(max_steps)
+        self.tol = float(tol)
+        self.batched = bool(batched)
+        self.device = device
+        self.seg_rows = seg_rows
+        torch.cuda.synchronize(device)
+        self.stream = torch.cuda.Stream(device)
+        self.log = []
+
+    def footprint(self, req):
+        p, _ = request_params(req, self.seg_rows)
+        return lbm.lbm_workspace_bytes(p)
+
+    def _measure(self, req, lat):
+        if req.kind == "angle":
+            out = lat.contact_angle(I.ISO, 0.0)
+            return tuple(out) if out is not None else ()
+        return tuple(lat.slip_length())
+
+    def run(self, requests, realtime=True):
+        """Serve `requests` (inputs.Request, arrival in seconds from the start).
+        Returns the list of Result in request order."""
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        results = {r.rid: Result(r.rid, r.kind, r.nx, r.ny, r.arrival) for r in requests}
+        waiting = collections.deque()
+        resident = []            # [(req, Lattice, footprint)]
+        used = 0
+        batch = None
+        t0 = time.perf_counter()
+        clock = (lambda: time.perf_counter() - t0) if realtime else None
+        virtual = [0.0]
+        if not realtime:
+            # all requests are present from the start; latency is measured
+            # from time zero on the same wall clock
+            clock = lambda: time.perf_counter() - t0  # noqa: E731
+            for r in requests:
+                results[r.rid].arrival = 0.0
+        while pending or waiting or resident:
+            now = clock()
+            while pending and (not realtime or pending[0].arrival <= now):
+                waiting.append(pending.popleft())
+            changed = False
+            while waiting and len(resident) < self.max_resident:
+                req = waiting[0]
+                fp = self.footprint(req)
+                if fp > self.budget:
+                    waiting.popleft()
+                    res = results[req.rid]
+                    res.error = f"footprint {fp} B exceeds the budget"
+                    res.finished = clock()
+                    continue
+                if used + fp > self.budget:
+                    break
+                waiting.popleft()
+                p, rho0 = request_params(req, self.seg_rows)
+                lat = lbm.Lattice(p, rho0, device=self.device, stream=self.stream)
+                resident.append((req, lat, fp))
+                used += fp
+                results[req.rid].admitted = clock()
+                changed = True
+            if not resident:
+                if pending:
+                    time.sleep(max(0.0, pending[0].arrival - clock()))
+                continue
+            if self.batched:
+                if changed or batch is None:
+                    if batch is not None:
+                        batch.close()
+                    batch = lbm.Attached([lat for _, lat, _ in resident], device=self.device)
+                batch.step(self.K, chunk=self.K)
+                diag, code = batch.diagnostics(check=False)
+            else:
+                diag = []
+                for _, lat, _ in resident:
+                    lat.step(self.K)
+                    d, _ = lbm.lbm_diagnostics(lat.ctx, check=False)
+                    diag.append(d)
+                diag = np.array(diag)
+            retire = []
+            for k, (req, lat, fp) in enumerate(resident):
+                res = results[req.rid]
+                res.steps = int(diag[k][0]) if not self.batched else lat.step_index
+                res.residual = float(diag[k][4])
+                bad = diag[k][5] > 0
+                done = res.residual < self.tol or res.steps >= self.max_steps
+                if bad:
+                    res.error = "non-finite state"
+                    retire.append(k)
+                elif done:
+                    res.converged = res.residual < self.tol
+                    try:
+                        res.value = self._measure(req, lat)
+                    except lbm.LbmError as e:
+                        res.error = str(e)
+                    retire.append(k)
+            if retire:
+                if batch is not None:
+                    batch.close()
+                    batch = None
+                now = clock()
+                for k in sorted(retire, reverse=True):
+                    req, lat, fp = resident.pop(k)
+                    results[req.rid].finished = now
+                    lat.close()
+                    used -= fp
+        if batch is not None:
+            batch.close()
+        virtual[0] = clock()
+        self.elapsed = virtual[0]
+        return [results[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
+
+
+def summarize(results, elapsed):
+    lat = np.array([r.latency for r in results if not r.error])
+    done = [r for r in results if not r.error]
+    return {
+        "requests": len(results),
+        "completed": len(done),
+        "failed": len(results) - len(done),
+        "converged": sum(r.converged for r in done),
+        "solves_per_s": len(done) / elapsed if elapsed > 0 else 0.0,
+        "p50_s": float(np.percentile(lat, 50)) if lat.size else None,
+        "p99_s": float(np.percentile(lat, 99)) if lat.size else None,
+        "elapsed_s": elapsed,
+        "lattice_updates": int(sum(r.steps * r.nx * r.ny for r in done)),
+    }
