@@ -211,7 +211,8 @@ lbm_status lbm_batch_create(const lbm_params *ps, int32_t n,
 lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps, int32_t chunk);
 
 /* Per-lattice diagnostics, as lbm_diagnostics, for every lattice: out[6*k ..]
- * (residual against the previous call of this function).  Synchronises. */
+ * (out[0] is that lattice's step index; the residual compares with the
+ * lattice's previous diagnostic pass, +inf if it has none).  Synchronises. */
 lbm_status lbm_batch_diagnostics(lbm_batch *b, double *out);
 
 /* A context view of lattice k (valid until lbm_batch_destroy) for

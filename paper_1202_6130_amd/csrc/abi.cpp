@@ -194,7 +194,6 @@ struct lbm_batch {
     double *d_res;
     hipGraphExec_t graph[2];
     int graph_chunk[2];
-    bool have_prev;
 };
 
 namespace {
@@ -664,7 +663,6 @@ static lbm_batch *new_batch(char *ws, const TablesLayout &T, uint32_t nwork, uin
     b->step = 0;
     b->graph[0] = b->graph[1] = nullptr;
     b->graph_chunk[0] = b->graph_chunk[1] = 0;
-    b->have_prev = false;
     b->nwork = nwork;
     b->ntiles = ntiles;
     b->d_lats = ws + T.lats;
@@ -874,8 +872,9 @@ lbm_status lbm_batch_diagnostics(lbm_batch *b, double *out) {
     if (!b || !out) return fail(LBM_EINVAL, "NULL argument");
     const int n = int(b->lat.size());
     LatDevAny dummy;
-    TRY(launch_ok(launch_diag(STORE_F32, b->d_lats, b->d_work, b->nwork, dummy, 0, b->cur, 0, b->have_prev ? 1 : 0,
-                              1, b->stream),
+    // every lattice is compared with its own snapshot; a lattice without one
+    // (new, or just after lbm_set_state) reports +inf and gets one now
+    TRY(launch_ok(launch_diag(STORE_F32, b->d_lats, b->d_work, b->nwork, dummy, 0, b->cur, 0, 1, 1, b->stream),
                   "diag_batch"));
     TRY(launch_ok(launch_reduce(b->d_part, b->d_ranges, n, 8, 6, b->d_res, 8, b->stream), "reduce"));
     std::vector<double> r(8 * size_t(n));
@@ -883,17 +882,14 @@ lbm_status lbm_batch_diagnostics(lbm_batch *b, double *out) {
     HIPCHK(hipStreamSynchronize(b->stream));
     bool bad = false;
     for (int k = 0; k < n; ++k) {
+        lbm_ctx *c = b->lat[k];
         const double *v = &r[8 * size_t(k)];
         double *o = out + 6 * size_t(k);
-        o[0] = double(b->step);
+        o[0] = double(*c->step);
         o[1] = v[0]; o[2] = v[1]; o[3] = v[2];
-        o[4] = !b->have_prev ? INFINITY : (v[4] > 0 ? v[3] / v[4] : (v[3] > 0 ? INFINITY : 0.0));
+        o[4] = !c->have_prev ? INFINITY : (v[4] > 0 ? v[3] / v[4] : (v[3] > 0 ? INFINITY : 0.0));
         o[5] = v[5];
         bad = bad || v[5] > 0;
-    }
-    b->have_prev = true;
-    // per-lattice views now hold a fresh snapshot too
-    for (lbm_ctx *c : b->lat) {
         c->have_prev = true;
         c->last_diag_step = -1;
     }

@@ -61,7 +61,7 @@ def request_params(req, seg_rows=0):
 
 class Server:
     def __init__(self, budget_bytes=96 << 30, max_resident=64, diag_every=100, max_steps=20000, tol=1e-8,
-                 batched=True, device="cuda:0", seg_rows=0):
+                 batched=True, device="cuda:0", seg_rows=0, on_admit=None):
         import torch
         if diag_every % 2:
             raise ValueError("diag_every must be even (graph replays keep the buffer parity)")
@@ -73,9 +73,11 @@ class Server:
         self.batched = bool(batched)
         self.device = device
         self.seg_rows = seg_rows
+        self.on_admit = on_admit          # called as on_admit(request, lattice) after creation
+        self.max_seen_resident = 0
+        self.max_seen_used = 0            # largest sum of resident footprints (bytes)
         torch.cuda.synchronize(device)
         self.stream = torch.cuda.Stream(device)
-        self.log = []
 
     def footprint(self, req):
         p, _ = request_params(req, self.seg_rows)
@@ -97,12 +99,12 @@ class Server:
         used = 0
         batch = None
         t0 = time.perf_counter()
-        clock = (lambda: time.perf_counter() - t0) if realtime else None
-        virtual = [0.0]
+
+        def clock():
+            return time.perf_counter() - t0
+
         if not realtime:
-            # all requests are present from the start; latency is measured
-            # from time zero on the same wall clock
-            clock = lambda: time.perf_counter() - t0  # noqa: E731
+            # every request is present from time zero
             for r in requests:
                 results[r.rid].arrival = 0.0
         while pending or waiting or resident:
@@ -124,8 +126,12 @@ class Server:
                 waiting.popleft()
                 p, rho0 = request_params(req, self.seg_rows)
                 lat = lbm.Lattice(p, rho0, device=self.device, stream=self.stream)
+                if self.on_admit is not None:
+                    self.on_admit(req, lat)
                 resident.append((req, lat, fp))
+                self.max_seen_resident = max(self.max_seen_resident, len(resident))
                 used += fp
+                self.max_seen_used = max(self.max_seen_used, used)
                 results[req.rid].admitted = clock()
                 changed = True
             if not resident:
@@ -149,7 +155,7 @@ class Server:
             retire = []
             for k, (req, lat, fp) in enumerate(resident):
                 res = results[req.rid]
-                res.steps = int(diag[k][0]) if not self.batched else lat.step_index
+                res.steps = int(diag[k][0])
                 res.residual = float(diag[k][4])
                 bad = diag[k][5] > 0
                 done = res.residual < self.tol or res.steps >= self.max_steps
@@ -175,8 +181,7 @@ class Server:
                     used -= fp
         if batch is not None:
             batch.close()
-        virtual[0] = clock()
-        self.elapsed = virtual[0]
+        self.elapsed = clock()
         return [results[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
 
 
