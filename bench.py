@@ -56,7 +56,10 @@ def bytes_per_update(storage):
     return {"f32": 72, "f16dev": 36, "f64": 144}[storage]
 
 
-TILE = "64 columns x 30 rows per workgroup (16 waves x 2 rows, 2 halo rows)"
+def tile_desc(shape):
+    from paper_1202_6130_amd import lbm
+    w, r = lbm.lbm_tile_shapes()[shape]
+    return f"shape {shape}: 64 columns x {w * r - 2} rows per workgroup ({w} waves x {r} rows, 2 halo rows)"
 
 WORKLOADS = {
     # name: (nx, ny, description)
@@ -85,11 +88,20 @@ def make_lattice(name, storage, seg_rows):
     return lbm.Lattice(p, rho0), p
 
 
-def time_gpu(name, storage, steps, warmup, seg_rows):
+def time_gpu(name, storage, steps, warmup, seg_rows, tile=None):
+    """tile None: the autotuner picks the tile shape during the warm-up
+    (its steps count as warm-up); else the given shape."""
     import torch
     L, p = make_lattice(name, storage, seg_rows)
     nodes = p.nx * p.ny
-    L.step(warmup)
+    tune_ms = None
+    if tile is None:
+        tune_steps = max(2, min(10, warmup // 5))
+        shape, tune_ms = L.tune(tune_steps)
+        tune_ms = [round(float(v), 5) for v in tune_ms]
+    else:
+        L.tile_shape = tile
+    L.step(max(0, warmup - L.step_index))
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     # per-launch events on the launch stream for steps without a diagnostic pass
@@ -115,11 +127,13 @@ def time_gpu(name, storage, steps, warmup, seg_rows):
     total_ms = t0.elapsed_time(t1)
     kern_ms = np.array([a.elapsed_time(b) for a, b in ev])
     d = L.diagnostics()
+    shape = L.tile_shape
     L.close()
     return {
         "nodes": nodes, "ms_total": total_ms, "ms_per_step": total_ms / steps,
         "kernel_ms_mean": float(kern_ms.mean()), "kernel_ms_median": float(np.median(kern_ms)),
-        "mass": float(d[1]), "nonfinite": float(d[5]), "seg_rows": p.seg_rows,
+        "mass": float(d[1]), "nonfinite": float(d[5]), "seg_rows": p.seg_rows, "tile_shape": shape,
+        "tune_ms": tune_ms,
     }
 
 
@@ -162,7 +176,7 @@ def cpu_baseline(seconds_hint=15.0):
                       f"{steps} steps in {dt:.1f} s"}
 
 
-def ensemble(steps, seq_steps, seed=0, count=256, chunk=100):
+def ensemble(steps, seq_steps, seed=0, count=256, chunk=100, tune_steps=5):
     """Batched ensemble of `count` sessile drops of uneven size and wall
     parameters: one launch per time step over all lattices, replayed from a
     HIP graph, against the same lattices stepped one after another alone."""
@@ -176,6 +190,7 @@ def ensemble(steps, seq_steps, seed=0, count=256, chunk=100):
     nodes = sum(c.nx * c.ny for c in cases)
     B = lbm.Batch(ps, rhos)
     stream = B._stream_obj
+    shapes, tune_ms = B.tune(tune_steps)
     B.step(chunk, chunk=chunk)
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True); b = torch.cuda.Event(enable_timing=True)
@@ -189,8 +204,9 @@ def ensemble(steps, seq_steps, seed=0, count=256, chunk=100):
     B.close()
     # sequential baseline: each lattice alone, plain launches, seq_steps steps
     seq_ms = 0.0
-    for p, rho in zip(ps, rhos):
+    for p, rho, shape in zip(ps, rhos, shapes):
         L = lbm.Lattice(p, rho)
+        L.tile_shape = int(shape)      # same tile shape as in the batch: the speedup is batching alone
         L.step(2)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -214,7 +230,129 @@ def ensemble(steps, seq_steps, seed=0, count=256, chunk=100):
                        "measured_steps_per_lattice": seq_steps, "extrapolated_to": steps},
         "speedup_vs_sequential": round(seq_ms_full / ms_batch, 2),
         "nonfinite_nodes": bad,
+        "tiles": {"tuner_ms_per_step": [None if np.isnan(v) else round(float(v), 4) for v in tune_ms],
+                  "shape_counts": np.bincount(shapes, minlength=len(tune_ms) - 1).tolist()},
     }
+
+
+CS = 1.0 / np.sqrt(3.0)
+
+
+def field_errors(test, ref, iso=1.07):
+    """Error of one run's (rho, ux, uy, totals) against the FP64 run's."""
+    rho, ux, uy, tot = test
+    r0, x0, y0, t0 = ref
+    du = np.hypot(ux - x0, uy - y0)
+    return {
+        "rho_maxrel": float(np.abs(rho - r0).max() / np.abs(r0).max()),
+        "rho_l2rel": float(np.linalg.norm(rho - r0) / np.linalg.norm(r0)),
+        "u_max_over_cs": float(du.max() / CS),
+        "u_l2rel": float(np.linalg.norm(du) / max(np.linalg.norm(np.hypot(x0, y0)), 1e-300)),
+        "mass_rel": float(abs(tot[0] - t0[0]) / t0[0]),
+        "phase_flip_frac": float(np.mean((rho > iso) != (r0 > iso))),
+    }
+
+
+def precision_study(steps=5000, checkpoints=(100, 500, 1000, 2000, 5000)):
+    """4096x4096 spinodal lattice from one initial state with populations
+    stored in FP32 and as FP16 deviations (rho_ref = mean density), both with
+    FP32 arithmetic, against FP64 storage and arithmetic (the configuration
+    the FP64 parity tests pin to the oracle); fields compared at checkpoints."""
+    from paper_1202_6130_amd import inputs as I
+    from paper_1202_6130_amd import lbm
+    n = 4096
+    rho0 = I.spinodal_field(n, seed=0)
+    runs = {}
+    for name, st in (("f64", lbm.STORE_F64), ("f32", lbm.STORE_F32), ("f16dev", lbm.STORE_F16DEV)):
+        p = lbm.lbm_params_default(nx=n, ny=n, storage=st, rho_ref=float(rho0.mean()), diag_interval=0)
+        runs[name] = lbm.Lattice(p, rho0)
+    out = {"metric": "field error vs FP64 storage (precision study)", "n_gpus": 1, "dtype": "f32/f16dev vs f64",
+           "data": "synthetic",
+           "config": {"workload": "periodic 4096x4096 phase separation from seeded Gaussian-smoothed noise "
+                                  "(sigma 4), 50% liquid, G=-5, tau=1, no solid", "steps": steps},
+           "checkpoints": []}
+    t_prev = 0
+    for t in [c for c in checkpoints if c <= steps]:
+        for L in runs.values():
+            L.step(t - t_prev)
+        t_prev = t
+        ref = runs["f64"].moments()
+        row = {"t": t}
+        for name in ("f32", "f16dev"):
+            row[name] = field_errors(runs[name].moments(), ref)
+        out["checkpoints"].append(row)
+        print(json.dumps({"precision_checkpoint": row}), file=sys.stderr, flush=True)
+    for L in runs.values():
+        L.close()
+    return out
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def wetting(drop_steps=20000, channel_steps=600000):
+    """The 1024x512 sessile drop (radius 160, seeded wall amplitudes, 20000
+    steps): contact angle from the rho = 1.07 isoline, in FP32 and FP64
+    storage; and the 32x256 channel driven by a body force 1e-6: slip length
+    against a Poiseuille fit.  Compared with the FP64 oracle's stored results
+    when tests/golden holds them."""
+    import torch
+    from paper_1202_6130_amd import inputs as I
+    from paper_1202_6130_amd import lbm
+    gr, ga = I.draw_wall_amplitudes(0)
+    res = {"metric": "contact angle and slip length (wetting model)", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "sessile drop 1024x512 radius 160, 20000 steps; channel 32x256, body force 1e-6, "
+                                  "600000 steps; G=-5, tau=1, wall amplitudes seed 0",
+                      "G_R": float(gr[0]), "G_A": float(ga[0])}}
+    gold_drop = os.path.join(GOLDEN, "drop_1024x512_fp64.json")
+    gold_chan = os.path.join(GOLDEN, "channel_32x256_fp64.json")
+    for name, st in (("f32", lbm.STORE_F32), ("f64", lbm.STORE_F64)):
+        p = lbm.lbm_params_default(nx=1024, ny=512, storage=st, wall_kind=lbm.WALL_FLAT_SLAB, G_R=float(gr[0]),
+                                   G_A=float(ga[0]), diag_interval=0)
+        L = lbm.Lattice(p, I.drop_field(1024, 512, 160.0))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        L.step(drop_steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        ang = L.contact_angle(I.ISO, 0.0)
+        rho, ux, uy, tot = L.moments()
+        d = {"angle_deg": None if ang is None else float(ang[0]), "fit": None if ang is None else ang.tolist(),
+             "mlups": round(1024 * 512 * drop_steps / dt / 1e6, 1), "totals": tot.tolist()}
+        if os.path.exists(gold_drop):
+            g = json.load(open(gold_drop))
+            ys = np.array([s["y"] for s in g["samples"]]); xs = np.array([s["x"] for s in g["samples"]])
+            rg = np.array([s["rho"] for s in g["samples"]])
+            ug = np.hypot([s["ux"] for s in g["samples"]], [s["uy"] for s in g["samples"]])
+            d["vs_oracle"] = {
+                "angle_diff_deg": None if ang is None or g["contact_angle"] is None
+                else float(ang[0] - g["contact_angle"][0]),
+                "rho_maxrel_samples": float(np.abs(rho[ys, xs] - rg).max() / np.abs(rg).max()),
+                "u_max_over_cs_samples": float(np.abs(np.hypot(ux[ys, xs], uy[ys, xs]) - ug).max() / CS),
+                "mass_rel": float(abs(tot[0] - g["totals"][0]) / g["totals"][0]),
+            }
+        res["drop_" + name] = d
+        L.close()
+        p = lbm.lbm_params_default(nx=32, ny=256, storage=st, wall_kind=lbm.WALL_FLAT_SLAB, G_R=float(gr[0]),
+                                   G_A=float(ga[0]), F_ext=(1e-6, 0.0), diag_interval=0)
+        L = lbm.Lattice(p, I.uniform_field(32, 256, 2.0))
+        t = time.perf_counter()
+        L.step(channel_steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        slip = L.slip_length()
+        rho, ux, uy, tot = L.moments()
+        c = {"slip": slip.tolist(), "seconds": round(dt, 2)}
+        if os.path.exists(gold_chan):
+            g = json.load(open(gold_chan))
+            prof = ux.mean(axis=1)
+            c["vs_oracle"] = {"slip_rel": float(abs(slip[0] - g["slip"][0]) / abs(g["slip"][0])),
+                              "ux_profile_maxrel": float(np.abs(prof - np.array(g["ux_profile"])).max()
+                                                         / np.abs(g["ux_profile"]).max())}
+        res["channel_" + name] = c
+        L.close()
+        print(json.dumps({name: [d, c]}), file=sys.stderr, flush=True)
+    return res
 
 
 def serving(count, max_steps, seed=0, rate=20.0):
@@ -246,7 +384,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="spinodal4096", choices=sorted(WORKLOADS) + ["ensemble256", "serve"])
+    ap.add_argument("--workload", default="spinodal4096",
+                    choices=sorted(WORKLOADS) + ["ensemble256", "serve", "precision4096", "wetting1024"])
+    ap.add_argument("--tile", type=int, default=None, help="tile shape index (default: autotuned in the warm-up)")
     ap.add_argument("--seq-steps", type=int, default=500, help="ensemble: steps per lattice of the sequential leg")
     ap.add_argument("--requests", type=int, default=60, help="serve: number of requests")
     ap.add_argument("--max-steps", type=int, default=20000, help="serve: step cap per request")
@@ -269,7 +409,13 @@ def main():
     if args.workload == "serve":
         print(json.dumps(serving(args.requests, args.max_steps)), flush=True)
         return
-    r = time_gpu(args.workload, args.storage, args.steps, args.warmup, args.seg_rows)
+    if args.workload == "precision4096":
+        print(json.dumps(precision_study()), flush=True)
+        return
+    if args.workload == "wetting1024":
+        print(json.dumps(wetting()), flush=True)
+        return
+    r = time_gpu(args.workload, args.storage, args.steps, args.warmup, args.seg_rows, args.tile)
     if args.copy_ref:
         copy_reference()
     mlups = r["nodes"] * args.steps / (r["ms_total"] * 1e-3) / 1e6
@@ -281,8 +427,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.storage, "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload][2], "nx": WORKLOADS[args.workload][0],
-                   "ny": WORKLOADS[args.workload][1], "storage": args.storage, "tile": TILE,
-                   "diag_every": DIAG_EVERY},
+                   "ny": WORKLOADS[args.workload][1], "storage": args.storage,
+                   "tile": tile_desc(r["tile_shape"]), "tile_tuned": args.tile is None,
+                   "tune_ms_per_shape": r["tune_ms"], "diag_every": DIAG_EVERY},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": bpu * r["nodes"],

@@ -94,7 +94,7 @@ typedef struct {
     int32_t slab_rows;       /* FLAT_SLAB: rows of solid, 1 <= P < ny         */
     int32_t diag_interval;   /* K: a diagnostic pass after every K-th step;
                                 0 = only on request                          */
-    int32_t seg_rows;        /* rows per wave segment; 0 = library's choice   */
+    int32_t seg_rows;        /* rows per wave segment of the diagnostic pass; 0 = library choice */
     int32_t reserved;        /* must be 0                                     */
 } lbm_params;
 
@@ -184,11 +184,36 @@ int64_t lbm_step_index(const lbm_ctx *c);
 lbm_status lbm_destroy(lbm_ctx *c);
 
 /* ------------------------------------------------------------------------
+ * Step tile shapes.  The time step runs as workgroups over 64-column strips;
+ * shape s has waves[s] wavefronts per workgroup, each loading rows[s] rows,
+ * and updates waves[s]*rows[s] - 2 rows per workgroup (the first and last
+ * loaded rows are halo).  Every shape computes bitwise the same update; the
+ * choice only changes speed.  Shape 0 is the default of a new context.
+ * ------------------------------------------------------------------------ */
+
+/* Writes up to cap (waves, rows) pairs (either array may be NULL) and returns
+ * the number of shapes. */
+int32_t lbm_tile_shapes(int32_t *waves, int32_t *rows, int32_t cap);
+
+/* Sets / returns the tile shape of a context (not one inside a batch:
+ * LBM_ESTATE).  lbm_get_tile_shape returns -1 for NULL. */
+lbm_status lbm_set_tile_shape(lbm_ctx *c, int32_t shape);
+int32_t lbm_get_tile_shape(const lbm_ctx *c);
+
+/* Autotuner for one lattice: runs steps+1 ordinary time steps with every
+ * shape (the first untimed), times each step with events, and keeps the shape
+ * of smallest median step time.  shape_out (nullable) gets the choice,
+ * ms_out (nullable, one entry per shape) the medians.  The lattice advances
+ * by (steps + 1) * lbm_tile_shapes(...) steps.  Synchronises. */
+lbm_status lbm_tune(lbm_ctx *c, int32_t steps, int32_t *shape_out, double *ms_out);
+
+/* ------------------------------------------------------------------------
  * Batched ensembles: many independent lattices (each with its own size and
  * parameters, all F32 storage) advanced together, one kernel launch per time
- * step covering every lattice; the steps are replayed from a HIP graph.  Each
- * lattice follows exactly the single-lattice update above, so a lattice gives
- * bitwise the same fields alone and inside any batch with the same seg_rows.
+ * step and tile shape in use, covering every lattice; the steps are replayed
+ * from a HIP graph.  Each lattice follows exactly the single-lattice update
+ * above, so a lattice gives bitwise the same fields alone and inside any
+ * batch, whatever the tile shapes.
  * ------------------------------------------------------------------------ */
 typedef struct lbm_batch lbm_batch;
 
@@ -235,9 +260,25 @@ lbm_status lbm_batch_attach_bytes(lbm_ctx *const *ctxs, int32_t n, size_t *bytes
 lbm_status lbm_batch_attach(lbm_ctx *const *ctxs, int32_t n, void *workspace,
                             size_t workspace_bytes, void *stream, lbm_batch **out);
 
+/* Per-lattice tile shapes of a batch (shapes[k] for lattice k; NULL sets
+ * shape 0 everywhere).  A batch starts with each context's own shape (0 for
+ * lbm_batch_create).  Recorded graphs are dropped.  Synchronises. */
+lbm_status lbm_batch_set_tile_shapes(lbm_batch *b, const int32_t *shapes);
+lbm_status lbm_batch_get_tile_shapes(const lbm_batch *b, int32_t *shapes);
+
+/* Autotuner for a batch.  Times every shape on the whole batch (median of
+ * `steps` single steps after one untimed step), derives a per-tile cost for
+ * each shape, gives every lattice the shape of least predicted cost (its tile
+ * count times that cost), times that mixed assignment too when it is not
+ * uniform, and keeps the fastest candidate.  shapes_out (nullable, n entries)
+ * gets the choice; ms_out (nullable, lbm_tile_shapes() + 1 entries) the
+ * median step times of the uniform candidates and of the mixed one (NaN when
+ * not timed).  The tuning steps are ordinary time steps.  Synchronises. */
+lbm_status lbm_batch_tune(lbm_batch *b, int32_t steps, int32_t *shapes_out, double *ms_out);
+
 /* Frees the host-side batch (waits for its stream).  A batch from
  * lbm_batch_create frees its contexts; an attached batch hands its contexts
- * back with their state and step index.  NULL is accepted. */
+ * back with their state, step index and tile shape.  NULL is accepted. */
 lbm_status lbm_batch_destroy(lbm_batch *b);
 
 #ifdef __cplusplus

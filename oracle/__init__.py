@@ -13,6 +13,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm_oracle.so")
+LIB_OMP_PATH = os.path.join(HERE, "liblbm_oracle_omp.so")
 
 CX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
 CY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
@@ -28,15 +29,26 @@ class Params(ctypes.Structure):
 
 
 _lib = None
+_path = LIB_PATH
+
+
+def use_threads(n):
+    """Switch to the OpenMP build of the same source with n threads (long
+    reference runs; bitwise the same results).  Call before the first use."""
+    global _lib, _path
+    if _lib is not None:
+        raise RuntimeError("use_threads must be called before the oracle is loaded")
+    os.environ["OMP_NUM_THREADS"] = str(int(n))
+    _path = LIB_OMP_PATH
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        if not os.path.exists(_path):
             from . import build as _b
-            _b.build()
-        L = ctypes.CDLL(LIB_PATH)
+            _b.build(parallel=_path == LIB_OMP_PATH)
+        L = ctypes.CDLL(_path)
         dp = ctypes.POINTER(ctypes.c_double)
         P = ctypes.POINTER(Params)
         L.orc_equilibrium.argtypes = [ctypes.c_double] * 3 + [dp]

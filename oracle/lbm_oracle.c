@@ -15,6 +15,11 @@
  *                              df = feq(rho, u*) - feq(rho, u), u* = u + F/rho
  *   - collision              : BGK (eq. BE-BGK) with feq from eq. f2
  *   - streaming              : f_i(x + c_i, t+1) = f'_i(x, t)  (Sec. II.A)
+ *
+ * The per-node loops carry OpenMP annotations.  The default build ignores
+ * them (one thread); a second build with -fopenmp serves long reference runs
+ * only.  Each node's arithmetic and every sum keep their order, so both
+ * builds give bitwise the same results.
  */
 #include "lbm_oracle.h"
 
@@ -124,6 +129,7 @@ void orc_forces(const orc_params *p, const double *phi, const double *psiR,
     double *psiFS = (double *)malloc(sizeof(double) * N);
 
     /* moments and pseudo-potentials at every node */
+#pragma omp parallel for schedule(static)
     for (long n = 0; n < N; ++n) {
         double jx, jy;
         moments(&f[n * 9], &rho[n], &jx, &jy);
@@ -133,6 +139,7 @@ void orc_forces(const orc_params *p, const double *phi, const double *psiR,
         psiFS[n] = p->G_A * psiA[n] - p->G_R * psiR[n];
     }
 
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y) {
         for (int x = 0; x < nx; ++x) {
             long n = (long)y * nx + x;
@@ -191,6 +198,7 @@ void orc_collide(const orc_params *p, const double *phi, const double *psiR,
     double *usx = (double *)malloc(sizeof(double) * N);
     double *usy = (double *)malloc(sizeof(double) * N);
     orc_forces(p, phi, psiR, psiA, f, rho, ux, uy, NULL, NULL, NULL, NULL, usx, usy);
+#pragma omp parallel for schedule(static)
     for (long n = 0; n < N; ++n) {
         double feq_u[9], feq_s[9];
         orc_equilibrium(rho[n], ux[n], uy[n], feq_u);
@@ -210,6 +218,7 @@ void orc_collide(const orc_params *p, const double *phi, const double *psiR,
 
 void orc_stream(int nx, int ny, const double *fpost, double *fout)
 {
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x)
             for (int i = 0; i < 9; ++i) {

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -67,8 +68,25 @@ uint32_t default_seg_rows(uint32_t nx, uint32_t ny) {
 
 struct Layout {
     size_t fa, fb, mom, uprev, row_tab, node_tab, phi_raw, partials, iso_part, small, profile, total;
-    uint32_t strips, segs, seg_rows, waves, iso_blocks, tiles;
+    uint32_t strips, segs, seg_rows, waves, iso_blocks;
+    uint32_t tiles;                // largest step-tile count over the tile shapes
+    uint32_t pstride;              // population plane stride (elements)
 };
+
+#ifndef LBM_PLANE_PAD_BYTES
+#define LBM_PLANE_PAD_BYTES 3840
+#endif
+
+// Population plane stride.  Planes of a lattice above 1 MiB per plane are
+// spaced by nx*ny plus a pad of LBM_PLANE_PAD_BYTES (a multiple of 256, so
+// rows keep their alignment): the nine load and nine store streams of a tile
+// then do not all start at one offset modulo large powers of two, which costs
+// the tiled step several percent of bandwidth on MI355X.
+uint32_t plane_stride(const lbm_params &p) {
+    const size_t N = size_t(p.nx) * p.ny, s = storage_bytes(p.storage);
+    if (N * s < (size_t(1) << 20)) return uint32_t(N);
+    return uint32_t(N + LBM_PLANE_PAD_BYTES / s);
+}
 
 // Offsets (bytes) into one lattice's workspace.  fb and mom are adjacent: the
 // pair doubles as staging for host float64 arrays at creation.
@@ -80,11 +98,14 @@ Layout make_layout(const lbm_params &p) {
     L.strips = (uint32_t(p.nx) + kStripColsHost - 1) / kStripColsHost;
     L.segs = (uint32_t(p.ny) + L.seg_rows - 1) / L.seg_rows;
     L.waves = L.strips * L.segs;
-    L.tiles = step_tiles(uint32_t(p.nx), uint32_t(p.ny));
+    L.tiles = 0;                       // largest tile count over the shapes
+    for (int s = 0; s < kNumTileShapes; ++s) L.tiles = std::max(L.tiles, step_tiles(uint32_t(p.nx), uint32_t(p.ny), s));
     L.iso_blocks = isoline_blocks(uint32_t(N));
     size_t o = 0;
-    L.fa = o; o = align_up(o + 9 * N * s);
-    L.fb = o; o = o + 9 * N * s;                       // no padding: fb+mom contiguous
+    L.pstride = plane_stride(p);
+    const size_t P = L.pstride;
+    L.fa = o; o = align_up(o + 9 * P * s);
+    L.fb = o; o = o + 9 * P * s;                       // no padding: fb+mom contiguous
     L.mom = o; o = align_up(o + 3 * N * cb);
     L.uprev = o; o = align_up(o + 2 * N * cb);
     const bool node = p.wall_kind == LBM_WALL_FIELDS;
@@ -105,8 +126,8 @@ lbm_status validate(const lbm_params *p) {
     if (p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_F16DEV && p->storage != LBM_STORE_F64 &&
         p->storage != LBM_STORE_F32X)
         return fail(LBM_EINVAL, "unknown storage %d", p->storage);
-    if (int64_t(p->nx) * p->ny * 9 * int64_t(storage_bytes(p->storage)) >= (int64_t(1) << 32))
-        return fail(LBM_EINVAL, "lattice too large: 9*nx*ny*bytes must be < 2^32");
+    if ((int64_t(p->nx) * p->ny + LBM_PLANE_PAD_BYTES) * 9 * int64_t(storage_bytes(p->storage)) >= (int64_t(1) << 32))
+        return fail(LBM_EINVAL, "lattice too large: 9*(nx*ny + pad)*bytes must be < 2^32");
     if (p->wall_kind < LBM_WALL_NONE || p->wall_kind > LBM_WALL_FIELDS)
         return fail(LBM_EINVAL, "unknown wall_kind %d", p->wall_kind);
     if (!(p->tau > 0.5) || !isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be > 0.5");
@@ -167,6 +188,7 @@ struct lbm_ctx {
     int64_t own_step;
     int *cur;                      // which buffer holds the state (0: fa, 1: fb)
     int64_t *step;
+    int shape;                     // step tile shape (index into kShapeWaves/kShapeRows)
     bool view;                     // lives inside a batch (lbm_step/lbm_set_state refused)
     bool attached;                 // an lbm_ctx of the caller grouped by lbm_batch_attach
     // diagnostics bookkeeping
@@ -187,8 +209,11 @@ struct lbm_batch {
     void *d_lats;
     uint4 *d_work;                 // per-wave (lattice, strip, segment): diagnostics
     uint32_t nwork;
-    uint4 *d_twork;                // per-tile (lattice, strip, tile row): time step
-    uint32_t ntiles;
+    uint4 *d_twork;                // per-tile (lattice, strip, tile row), grouped by tile shape
+    uint32_t ntiles;               // capacity of d_twork (largest tile count of every lattice)
+    std::vector<int> shapes;       // tile shape of each lattice
+    uint32_t toff[kNumTileShapes + 1];   // d_twork[toff[s], toff[s+1]): tiles of shape s
+    std::vector<uint4> h_twork;    // host image of d_twork (kept until the next upload)
     double *d_part;
     uint32_t *d_ranges;
     double *d_res;
@@ -230,6 +255,7 @@ lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const d
     c->own_step = 0;
     c->cur = &c->own_cur;
     c->step = &c->own_step;
+    c->shape = 0;
     c->view = false;
     c->attached = false;
     c->have_prev = false;
@@ -242,7 +268,7 @@ lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const d
     c->d_ranges = (uint32_t *)(c->d_small + 32);
 
     LatDevAny &L = c->L;
-    L.nx = p->nx; L.ny = p->ny; L.plane = uint32_t(N);
+    L.nx = p->nx; L.ny = p->ny; L.plane = uint32_t(N); L.pstride = Y.pstride;
     L.strips = Y.strips; L.segs = Y.segs; L.seg_rows = Y.seg_rows; L.wave0 = 0;
     L.fa = ws + Y.fa; L.fb = ws + Y.fb;
     L.row_tab = ws + Y.row_tab;
@@ -281,7 +307,7 @@ lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const d
         dux = stage + N;
         duy = stage + 2 * N;
     }
-    TRY(launch_ok(launch_init(kernel_storage(p->storage), p->nx, p->ny, stage, dux, duy, L.fa, L.rho_ref, stream),
+    TRY(launch_ok(launch_init(kernel_storage(p->storage), p->nx, p->ny, L.pstride, stage, dux, duy, L.fa, L.rho_ref, stream),
                   "init"));
     HIPCHK(hipStreamSynchronize(stream));
     return LBM_OK;
@@ -368,7 +394,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     const int ks = kernel_storage(c->p.storage);
     const int K = c->p.diag_interval;
     for (int64_t s = 0; s < nsteps; ++s) {
-        TRY(launch_ok(launch_step(ks, c->L, c->wall_mode, *c->cur, c->stream), "step"));
+        TRY(launch_ok(launch_step(ks, c->L, c->wall_mode, c->shape, *c->cur, c->stream), "step"));
         *c->cur ^= 1;
         ++*c->step;
         if (K > 0 && *c->step % K == 0) {
@@ -544,7 +570,7 @@ lbm_status lbm_get_state(lbm_ctx *c, double *f) {
     void *pop = *c->cur ? c->L.fb : c->L.fa;
     double *stage = (double *)(*c->cur ? c->L.fa : c->L.fb);   // the other buffer is free between steps
     for (int q = 0; q < 9; ++q) {
-        TRY(launch_ok(launch_plane(kernel_storage(c->p.storage), 0, c->p.nx, c->p.ny, q, pop, stage, c->L.rho_ref,
+        TRY(launch_ok(launch_plane(kernel_storage(c->p.storage), 0, c->p.nx, c->p.ny, c->L.pstride, q, pop, stage, c->L.rho_ref,
                                    c->stream),
                       "get_plane"));
         HIPCHK(hipMemcpyAsync(f + q * N, stage, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -562,7 +588,7 @@ lbm_status lbm_set_state(lbm_ctx *c, const double *f, int64_t step_index) {
     double *stage = (double *)(*c->cur ? c->L.fa : c->L.fb);
     for (int q = 0; q < 9; ++q) {
         HIPCHK(hipMemcpyAsync(stage, f + q * N, N * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        TRY(launch_ok(launch_plane(kernel_storage(c->p.storage), 1, c->p.nx, c->p.ny, q, pop, stage, c->L.rho_ref,
+        TRY(launch_ok(launch_plane(kernel_storage(c->p.storage), 1, c->p.nx, c->p.ny, c->L.pstride, q, pop, stage, c->L.rho_ref,
                                    c->stream),
                       "set_plane"));
         TRY(sync(c));
@@ -665,6 +691,7 @@ static lbm_batch *new_batch(char *ws, const TablesLayout &T, uint32_t nwork, uin
     b->graph_chunk[0] = b->graph_chunk[1] = 0;
     b->nwork = nwork;
     b->ntiles = ntiles;
+    for (int s = 0; s <= kNumTileShapes; ++s) b->toff[s] = 0;
     b->d_lats = ws + T.lats;
     b->d_work = (uint4 *)(ws + T.work);
     b->d_twork = (uint4 *)(ws + T.twork);
@@ -674,15 +701,60 @@ static lbm_batch *new_batch(char *ws, const TablesLayout &T, uint32_t nwork, uin
     return b;
 }
 
+static void drop_graphs(lbm_batch *b) {
+    for (int i = 0; i < 2; ++i) {
+        if (b->graph[i]) (void)hipGraphExecDestroy(b->graph[i]);
+        b->graph[i] = nullptr;
+        b->graph_chunk[i] = 0;
+    }
+}
+
+// Builds the step-tile list from b->shapes, grouped by shape (one launch per
+// non-empty group), and uploads it.  Recorded graphs are dropped.  Synchronises.
+static lbm_status upload_twork(lbm_batch *b) {
+    const int32_t n = int32_t(b->lat.size());
+    std::vector<uint4> &tw = b->h_twork;
+    HIPCHK(hipStreamSynchronize(b->stream));     // the previous image may still be in flight
+    tw.clear();
+    for (int s = 0; s < kNumTileShapes; ++s) {
+        b->toff[s] = uint32_t(tw.size());
+        for (int32_t k = 0; k < n; ++k) {
+            if (b->shapes[k] != s) continue;
+            const lbm_ctx *c = b->lat[k];
+            const uint32_t trows = step_tiles(uint32_t(c->p.nx), uint32_t(c->p.ny), s) / c->lay.strips;
+            for (uint32_t tr = 0; tr < trows; ++tr)
+                for (uint32_t sp = 0; sp < c->lay.strips; ++sp) tw.push_back(make_uint4(uint32_t(k), sp, tr, 0));
+        }
+    }
+    b->toff[kNumTileShapes] = uint32_t(tw.size());
+    if (tw.size() > b->ntiles) return fail(LBM_EINVAL, "internal: tile list exceeds its capacity");
+    HIPCHK(hipMemcpyAsync(b->d_twork, tw.data(), tw.size() * sizeof(uint4), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    drop_graphs(b);
+    return LBM_OK;
+}
+
+// One time step of every lattice of the batch: one launch per tile shape in use.
+static hipError_t batch_launch(lbm_batch *b, int parity) {
+    for (int s = 0; s < kNumTileShapes; ++s) {
+        const uint32_t cnt = b->toff[s + 1] - b->toff[s];
+        if (!cnt) continue;
+        hipError_t e = launch_step_batch(b->d_lats, b->d_twork + b->toff[s], cnt, s, parity, b->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // Builds descriptors and the work list over b->lat (whose current buffer is
 // fa, i.e. batch parity 0) and uploads them.  Synchronises.
 static lbm_status upload_tables(lbm_batch *b) {
     const int32_t n = int32_t(b->lat.size());
     std::vector<LatDev<float>> lats(n);
-    std::vector<uint4> work, twork;
+    std::vector<uint4> work;
     std::vector<uint32_t> ranges(2 * size_t(n));
     work.reserve(b->nwork);
-    twork.reserve(b->ntiles);
+    b->shapes.resize(size_t(n));
+    for (int32_t k = 0; k < n; ++k) b->shapes[k] = b->lat[k]->shape;
     uint32_t w0 = 0;
     for (int32_t k = 0; k < n; ++k) {
         lbm_ctx *c = b->lat[k];
@@ -694,22 +766,18 @@ static lbm_status upload_tables(lbm_batch *b) {
         lats[k] = La.get<float>();
         for (uint32_t sg = 0; sg < Y.segs; ++sg)
             for (uint32_t sp = 0; sp < Y.strips; ++sp) work.push_back(make_uint4(uint32_t(k), sp, sg, 0));
-        const uint32_t trows = Y.tiles / Y.strips;
-        for (uint32_t tr = 0; tr < trows; ++tr)
-            for (uint32_t sp = 0; sp < Y.strips; ++sp) twork.push_back(make_uint4(uint32_t(k), sp, tr, 0));
         ranges[2 * k] = w0;
         ranges[2 * k + 1] = w0 + Y.waves;
         w0 += Y.waves;
     }
-    if (w0 != b->nwork || twork.size() != b->ntiles) return fail(LBM_EINVAL, "internal: work list size mismatch");
+    if (w0 != b->nwork) return fail(LBM_EINVAL, "internal: work list size mismatch");
     HIPCHK(hipMemcpyAsync(b->d_lats, lats.data(), lats.size() * sizeof(LatDev<float>), hipMemcpyHostToDevice,
                           b->stream));
     HIPCHK(hipMemcpyAsync(b->d_work, work.data(), work.size() * sizeof(uint4), hipMemcpyHostToDevice, b->stream));
-    HIPCHK(hipMemcpyAsync(b->d_twork, twork.data(), twork.size() * sizeof(uint4), hipMemcpyHostToDevice, b->stream));
     HIPCHK(hipMemcpyAsync(b->d_ranges, ranges.data(), ranges.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
                           b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
-    return LBM_OK;
+    return upload_twork(b);
 }
 
 lbm_status lbm_batch_create(const lbm_params *ps, int32_t n, const double *const *rho0s,
@@ -827,8 +895,7 @@ static void batch_advance(lbm_batch *b, int64_t n) {
 
 static lbm_status batch_plain(lbm_batch *b, int64_t n) {
     for (int64_t s = 0; s < n; ++s) {
-        TRY(launch_ok(launch_step_batch(b->d_lats, b->d_work, b->nwork, b->d_twork, b->ntiles, b->cur, b->stream),
-                      "step_batch"));
+        TRY(launch_ok(batch_launch(b, b->cur), "step_batch"));
         b->cur ^= 1;
         batch_advance(b, 1);
     }
@@ -851,8 +918,7 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps, int32_t chunk) {
             HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
             hipError_t e = hipSuccess;
             for (int s = 0; s < chunk && e == hipSuccess; ++s)
-                e = launch_step_batch(b->d_lats, b->d_work, b->nwork, b->d_twork, b->ntiles, par ^ (s & 1),
-                                      b->stream);
+                e = batch_launch(b, par ^ (s & 1));
             hipError_t e2 = hipStreamEndCapture(b->stream, &g);
             if (e != hipSuccess) return fail(LBM_EDEVICE, "capture launch: %s", hipGetErrorString(e));
             if (e2 != hipSuccess) return fail(LBM_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e2));
@@ -905,11 +971,168 @@ lbm_ctx *lbm_batch_lattice(lbm_batch *b, int32_t k) {
     return b->lat[k];
 }
 
+// ------------------------------------------------------- tile shapes, tuner
+int32_t lbm_tile_shapes(int32_t *waves, int32_t *rows, int32_t cap) {
+    for (int s = 0; s < kNumTileShapes && s < cap; ++s) {
+        if (waves) waves[s] = kShapeWaves[s];
+        if (rows) rows[s] = kShapeRows[s];
+    }
+    return kNumTileShapes;
+}
+
+lbm_status lbm_set_tile_shape(lbm_ctx *c, int32_t shape) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (c->view) return fail(LBM_ESTATE, "lattice belongs to a batch; use lbm_batch_set_tile_shapes");
+    if (shape < 0 || shape >= kNumTileShapes) return fail(LBM_EINVAL, "tile shape %d out of range", shape);
+    c->shape = shape;
+    return LBM_OK;
+}
+
+int32_t lbm_get_tile_shape(const lbm_ctx *c) { return c ? c->shape : -1; }
+
+}  // extern "C"
+
+namespace {
+
+// Median duration (ms) of `steps` single steps issued by `one`, each bracketed
+// by events and waited for.
+template <class Fn> lbm_status time_steps(hipStream_t st, int32_t steps, Fn &&one, double *median_ms) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(LBM_EDEVICE, "hipEventCreate: %s", hipGetErrorString(he));
+    }
+    std::vector<double> t;
+    lbm_status stt = LBM_OK;
+    for (int32_t i = 0; i < steps && stt == LBM_OK; ++i) {
+        he = hipEventRecord(e0, st);
+        if (he == hipSuccess) stt = one();
+        if (stt == LBM_OK && he == hipSuccess) he = hipEventRecord(e1, st);
+        if (stt == LBM_OK && he == hipSuccess) he = hipEventSynchronize(e1);
+        float ms = 0;
+        if (stt == LBM_OK && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        if (he != hipSuccess && stt == LBM_OK) stt = fail(LBM_EDEVICE, "timing events: %s", hipGetErrorString(he));
+        t.push_back(ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (stt != LBM_OK) return stt;
+    std::sort(t.begin(), t.end());
+    *median_ms = t[t.size() / 2];
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_tune(lbm_ctx *c, int32_t steps, int32_t *shape_out, double *ms_out) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (c->view) return fail(LBM_ESTATE, "lattice belongs to a batch; use lbm_batch_tune");
+    if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
+    int best = c->shape;
+    double best_ms = INFINITY;
+    for (int s = 0; s < kNumTileShapes; ++s) {
+        c->shape = s;
+        TRY(lbm_step(c, 1));                      // first launch of this shape: not timed
+        double ms = 0;
+        TRY(time_steps(c->stream, steps, [&]() { return lbm_step(c, 1); }, &ms));
+        if (ms_out) ms_out[s] = ms;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = s;
+        }
+    }
+    c->shape = best;
+    if (shape_out) *shape_out = best;
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_set_tile_shapes(lbm_batch *b, const int32_t *shapes) {
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    const size_t n = b->lat.size();
+    for (size_t k = 0; k < n; ++k) {
+        const int s = shapes ? shapes[k] : 0;
+        if (s < 0 || s >= kNumTileShapes) return fail(LBM_EINVAL, "lattice %zu: tile shape %d out of range", k, s);
+    }
+    for (size_t k = 0; k < n; ++k) {
+        b->shapes[k] = shapes ? shapes[k] : 0;
+        b->lat[k]->shape = b->shapes[k];
+    }
+    return upload_twork(b);
+}
+
+lbm_status lbm_batch_get_tile_shapes(const lbm_batch *b, int32_t *shapes) {
+    if (!b || !shapes) return fail(LBM_EINVAL, "NULL argument");
+    for (size_t k = 0; k < b->lat.size(); ++k) shapes[k] = b->shapes[k];
+    return LBM_OK;
+}
+
+// Autotuner.  Times every shape on the whole batch (median of `steps` single
+// steps), derives a per-tile cost for each shape, gives every lattice the shape
+// with the smallest predicted cost (tiles x per-tile cost; small lattices
+// favour shapes that waste fewer rows at their edge), times that mixed
+// assignment too, and keeps the fastest of all candidates.  The tuning steps
+// are ordinary time steps of the batch.
+lbm_status lbm_batch_tune(lbm_batch *b, int32_t steps, int32_t *shapes_out, double *ms_out) {
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
+    const size_t n = b->lat.size();
+    auto one = [&]() -> lbm_status {
+        TRY(launch_ok(batch_launch(b, b->cur), "step_batch"));
+        b->cur ^= 1;
+        batch_advance(b, 1);
+        return LBM_OK;
+    };
+    std::vector<int32_t> cand(n);
+    double uni[kNumTileShapes], tile_cost[kNumTileShapes];
+    int best = 0;
+    for (int s = 0; s < kNumTileShapes; ++s) {
+        std::fill(cand.begin(), cand.end(), s);
+        TRY(lbm_batch_set_tile_shapes(b, cand.data()));
+        TRY(one());
+        TRY(time_steps(b->stream, steps, one, &uni[s]));
+        tile_cost[s] = uni[s] / double(b->toff[kNumTileShapes]);
+        if (ms_out) ms_out[s] = uni[s];
+        if (uni[s] < uni[best]) best = s;
+    }
+    std::vector<int32_t> mix(n);
+    bool uniform = true;
+    for (size_t k = 0; k < n; ++k) {
+        const lbm_ctx *c = b->lat[k];
+        int bs = 0;
+        double bc = INFINITY;
+        for (int s = 0; s < kNumTileShapes; ++s) {
+            const double cost = double(step_tiles(uint32_t(c->p.nx), uint32_t(c->p.ny), s)) * tile_cost[s];
+            if (cost < bc) {
+                bc = cost;
+                bs = s;
+            }
+        }
+        mix[k] = bs;
+        uniform = uniform && bs == mix[0];
+    }
+    double mix_ms = NAN;
+    if (!uniform) {
+        TRY(lbm_batch_set_tile_shapes(b, mix.data()));
+        TRY(one());
+        TRY(time_steps(b->stream, steps, one, &mix_ms));
+    }
+    if (ms_out) ms_out[kNumTileShapes] = mix_ms;
+    if (!(mix_ms < uni[best])) {
+        std::fill(cand.begin(), cand.end(), best);
+        TRY(lbm_batch_set_tile_shapes(b, cand.data()));
+    }
+    if (shapes_out) TRY(lbm_batch_get_tile_shapes(b, shapes_out));
+    return LBM_OK;
+}
+
 lbm_status lbm_batch_destroy(lbm_batch *b) {
     if (!b) return LBM_OK;
     hipError_t e = hipStreamSynchronize(b->stream);
-    for (int i = 0; i < 2; ++i)
-        if (b->graph[i]) (void)hipGraphExecDestroy(b->graph[i]);
+    drop_graphs(b);
     for (lbm_ctx *c : b->lat) {
         if (b->owned) {
             delete c;

@@ -1,14 +1,15 @@
 // HIP kernels (gfx950) of the wetting-model lattice-Boltzmann library and the
 // host launchers the C ABI calls.  See lbm.h for the update they implement.
 //
-// Hot kernel, k_step: one wavefront owns a strip of 62 output columns (lanes
-// 1..62; lanes 0 and 63 are halo columns whose pseudo-potential is recomputed
-// from their own pulled populations) and a segment of rows.  It marches down
-// the rows keeping psi of rows y-1, y, y+1 in registers, so every population
-// is loaded from HBM once per segment (plus one halo row above and below) and
-// x-neighbours of psi come from adjacent lanes.  Pull streaming: the loads of
-// a row are nine coalesced row reads (shifted by -c_i), the stores nine
-// aligned row writes, population planes in SoA [9][ny][nx].
+// Hot kernel, k_step_tiles: one workgroup owns a 64-column strip (lane l holds
+// column x0 + l) and a band of rows; every wave loads its rows at once (pull
+// streaming: nine coalesced row reads shifted by -c_i, plus one gathered load
+// for the two columns beside the strip), publishes density and
+// pseudo-potential in LDS, and after one barrier forms the forces, collides
+// and writes nine aligned rows.  Population planes are SoA [9][ny][nx] with a
+// padded plane stride.  The marching walk (march) serves the diagnostic pass.
+#include <type_traits>
+
 #include "launch.hpp"
 #include "lbm_device.hpp"
 
@@ -65,8 +66,8 @@ __device__ inline void march(const LatDev<C> &L, const void *src, uint32_t strip
     const bool active = x0 + uint32_t(lane) < nx;
 
     RowLoader<S> ld;
-    ld.buf.init(src, 9u * L.plane * uint32_t(sizeof(S)));
-    ld.plane = L.plane;
+    ld.buf.init(src, 9u * L.pstride * uint32_t(sizeof(S)));
+    ld.plane = L.pstride;
     ld.x = x;
     ld.xm = wrap_dec(x, nx);
     ld.xp = wrap_inc(x, nx);
@@ -77,7 +78,7 @@ __device__ inline void march(const LatDev<C> &L, const void *src, uint32_t strip
     {
         const uint32_t h = g_left ? (x0 + nx - 1) % nx : (x0 + kStripCols) % nx;
         const uint32_t hc = uint32_t(int(h) + int(nx) - kCx[g_q]) % nx;   // h - c_x, wrapped
-        ld.g_col = g_on ? uint32_t(g_q) * L.plane + hc : 0u;
+        ld.g_col = g_on ? uint32_t(g_q) * L.pstride + hc : 0u;
         ld.g_cy = g_on ? kCy[g_q] : 0;
     }
     const uint32_t y0 = seg * L.seg_rows;
@@ -212,7 +213,7 @@ template <class S, class C, int WALL> struct StepAct {
             const uint32_t row = y * L.nx;
 #pragma unroll
             for (int i = 0; i < Q; ++i)
-                dst.store(Codec<S>::template encode<C>(f[i], i, L.rho_ref), x, i * L.plane + row);
+                dst.store(Codec<S>::template encode<C>(f[i], i, L.rho_ref), x, i * L.pstride + row);
         }
     }
 };
@@ -263,37 +264,37 @@ __device__ inline uint32_t logical_wave() {
 }
 
 // ---------------------------------------------------------------- tiles
-// The time step proper.  One workgroup of kTileWaves waves owns a 64-column
-// strip and kTileRowsIn = kTileWaves * kRowsPerWave consecutive rows, of which
-// the first and last are halo rows: wave w loads rows y0 - 1 + w R + j
-// (j < R), all at once.  Each wave computes density and pseudo-potential of
+// The time step proper.  One workgroup of TW waves owns a 64-column strip and
+// TW * TR consecutive rows, of which the first and last are halo rows: wave w
+// loads rows y0 - 1 + w TR + j (j < TR), all at once.  Each wave computes density and pseudo-potential of
 // its rows (and of the two columns beside the strip, from the gathered load),
 // publishes them in LDS, and after one barrier every row between the halo
 // rows reads its neighbours above and below, forms the forces, collides and
 // stores.  No wave walks through rows one after another: every population row
 // of the tile is in flight at the same time.
-template <class C> struct TileLds {
-    C psi[kTileRowsIn][kWave];
-    C hal[kTileRowsIn][2];
+template <class C, int ROWS> struct TileLds {
+    C psi[ROWS][kWave];
+    C hal[ROWS][2];
 };
 
-template <class S, class C, int WALL>
+template <class S, class C, int WALL, int TW, int TR>
 __device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst, uint32_t strip, uint32_t trow,
-                                 TileLds<C> &sm) {
+                                 TileLds<C, TW * TR> &sm) {
     using Raw = typename Codec<S>::Raw;
-    constexpr int R = kRowsPerWave;
+    constexpr int R = TR;
+    constexpr uint32_t kOut = uint32_t(TW * TR - 2);
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
     const uint32_t nx = L.nx, ny = L.ny;
     const uint32_t x0 = strip * kStripCols;
     const uint32_t x = (x0 + uint32_t(lane)) % nx;
     const bool active = x0 + uint32_t(lane) < nx;
-    const uint32_t y0 = trow * kTileRows;
-    const uint32_t out_rows = min(uint32_t(kTileRows), ny - y0);
+    const uint32_t y0 = trow * kOut;
+    const uint32_t out_rows = min(kOut, ny - y0);
 
     RowLoader<S> ld;
-    ld.buf.init(src, 9u * L.plane * uint32_t(sizeof(S)));
-    ld.plane = L.plane;
+    ld.buf.init(src, 9u * L.pstride * uint32_t(sizeof(S)));
+    ld.plane = L.pstride;
     ld.x = x;
     ld.xm = wrap_dec(x, nx);
     ld.xp = wrap_inc(x, nx);
@@ -303,7 +304,7 @@ __device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst,
     {
         const uint32_t h = g_left ? (x0 + nx - 1) % nx : (x0 + kStripCols) % nx;
         const uint32_t hc = uint32_t(int(h) + int(nx) - kCx[g_q]) % nx;   // h - c_x, wrapped
-        ld.g_col = g_on ? uint32_t(g_q) * L.plane + hc : 0u;
+        ld.g_col = g_on ? uint32_t(g_q) * L.pstride + hc : 0u;
         ld.g_cy = g_on ? kCy[g_q] : 0;
     }
 
@@ -356,56 +357,34 @@ __device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst,
         const C sx = Lanes<C>::right(a, ar) - Lanes<C>::left(a, al);
         const C sy = w1 * b + w2 * (Lanes<C>::right(b, br) + Lanes<C>::left(b, bl));
         StepAct<S, C, WALL> act;
-        act.dst.init(dst, 9u * L.plane * uint32_t(sizeof(S)));
+        act.dst.init(dst, 9u * L.pstride * uint32_t(sizeof(S)));
         act.row(L, row_wall<C, WALL>(L, r), r, x, active, f[j], rho[j], psi[j], sx, sy);
     }
 }
 
 // ---------------------------------------------------------------- kernels
-template <class S, class C, int WALL>
-__global__ __launch_bounds__(kBlockThreads) void k_step(LatDev<C> L, const void *__restrict__ src, void *__restrict__ dst) {
-    const uint32_t gw = logical_wave();
-    if (gw >= L.strips * L.segs) return;
-    const uint32_t seg = gw / L.strips, strip = gw - seg * L.strips;
-    StepAct<S, C, WALL> act;
-    act.dst.init(dst, 9u * L.plane * uint32_t(sizeof(S)));
-    march<S, C, WALL>(L, src, strip, seg, act);
-}
-
-template <class S, class C, int WALL>
-__global__ __launch_bounds__(kTileThreads) void k_step_tiles(LatDev<C> L, const void *__restrict__ src,
-                                                             void *__restrict__ dst) {
-    __shared__ TileLds<C> sm;
+template <class S, class C, int WALL, int SHAPE>
+__global__ __launch_bounds__(kShapeWaves[SHAPE] * kWave) void k_step_tiles(LatDev<C> L, const void *__restrict__ src,
+                                                                          void *__restrict__ dst) {
+    constexpr int TW = kShapeWaves[SHAPE], TR = kShapeRows[SHAPE];
+    __shared__ TileLds<C, TW * TR> sm;
     const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const uint32_t trow = lb / L.strips, strip = lb - trow * L.strips;
-    tile_step<S, C, WALL>(L, src, dst, strip, trow, sm);
+    tile_step<S, C, WALL, TW, TR>(L, src, dst, strip, trow, sm);
 }
 
-// Batched step over tiles: twork[b] = (lattice, strip, tile row) of logical
-// workgroup b, lattices in order.
-template <class S, class C, int WALL>
-__global__ __launch_bounds__(kTileThreads) void k_step_tiles_batch(const LatDev<C> *__restrict__ lats,
-                                                                   const uint4 *__restrict__ twork, int parity) {
-    __shared__ TileLds<C> sm;
+// Batched step over tiles of one shape: twork[b] = (lattice, strip, tile row)
+// of logical workgroup b.
+template <class S, class C, int WALL, int SHAPE>
+__global__ __launch_bounds__(kShapeWaves[SHAPE] * kWave) void k_step_tiles_batch(const LatDev<C> *__restrict__ lats,
+                                                                                const uint4 *__restrict__ twork,
+                                                                                int parity) {
+    constexpr int TW = kShapeWaves[SHAPE], TR = kShapeRows[SHAPE];
+    __shared__ TileLds<C, TW * TR> sm;
     const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const uint4 wk = twork[lb];
     const LatDev<C> L = lats[wk.x];
-    tile_step<S, C, WALL>(L, parity ? L.fb : L.fa, parity ? L.fa : L.fb, wk.y, wk.z, sm);
-}
-
-// Batched step: one launch over the tiles of many lattices.  work[g] =
-// (lattice, strip, segment) of global wave g, lattices in order.
-template <class S, class C, int WALL>
-__global__ __launch_bounds__(kBlockThreads) void k_step_batch(const LatDev<C> *__restrict__ lats,
-                                                    const uint4 *__restrict__ work, uint32_t nwork, int parity) {
-    const uint32_t gw = logical_wave();
-    if (gw >= nwork) return;
-    const uint4 wk = work[gw];
-    const LatDev<C> L = lats[wk.x];
-    const void *src = parity ? L.fb : L.fa;
-    StepAct<S, C, WALL> act;
-    act.dst.init(parity ? L.fa : L.fb, 9u * L.plane * uint32_t(sizeof(S)));
-    march<S, C, WALL>(L, src, wk.y, wk.z, act);
+    tile_step<S, C, WALL, TW, TR>(L, parity ? L.fb : L.fa, parity ? L.fa : L.fb, wk.y, wk.z, sm);
 }
 
 template <class S, class C, int WALL>
@@ -570,7 +549,7 @@ __device__ inline double feq_component(int q, double rho, double ux, double uy) 
 // Stored (pre-stream) populations such that pulling yields feq(rho0, u0):
 // stored_q(x) = feq_q at node x + c_q.
 template <class S, class C>
-__global__ __launch_bounds__(256) void k_init(uint32_t nx, uint32_t ny, const double *__restrict__ rho0,
+__global__ __launch_bounds__(256) void k_init(uint32_t nx, uint32_t ny, uint32_t P, const double *__restrict__ rho0,
                                               const double *__restrict__ ux0, const double *__restrict__ uy0,
                                               typename Codec<S>::Raw *__restrict__ dst, C rho_ref) {
     const uint32_t N = nx * ny;
@@ -581,14 +560,14 @@ __global__ __launch_bounds__(256) void k_init(uint32_t nx, uint32_t ny, const do
         const uint32_t xs = (x + nx + kCx[q]) % nx, ys = (y + ny + kCy[q]) % ny;
         const uint32_t m = ys * nx + xs;
         const double v = feq_component(q, rho0[m], ux0 ? ux0[m] : 0.0, uy0 ? uy0[m] : 0.0);
-        dst[q * N + n] = Codec<S>::template encode<C>(C(v), q, rho_ref);
+        dst[q * P + n] = Codec<S>::template encode<C>(C(v), q, rho_ref);
     }
 }
 
 // Post-streaming plane q as float64: out(x) = stored_q(x - c_q), decoded
 // exactly as the step kernel decodes it.
 template <class S, class C>
-__global__ __launch_bounds__(256) void k_get_plane(uint32_t nx, uint32_t ny, int q,
+__global__ __launch_bounds__(256) void k_get_plane(uint32_t nx, uint32_t ny, uint32_t P, int q,
                                                    const typename Codec<S>::Raw *__restrict__ src,
                                                    double *__restrict__ out, C rho_ref) {
     const uint32_t N = nx * ny;
@@ -596,19 +575,20 @@ __global__ __launch_bounds__(256) void k_get_plane(uint32_t nx, uint32_t ny, int
     if (n >= N) return;
     const uint32_t y = n / nx, x = n - y * nx;
     const uint32_t xs = (x + nx - kCx[q]) % nx, ys = (y + ny - kCy[q]) % ny;
-    out[n] = double(Codec<S>::template decode<C>(src[q * N + ys * nx + xs], q, rho_ref));
+    out[n] = double(Codec<S>::template decode<C>(src[q * P + ys * nx + xs], q, rho_ref));
 }
 
 // Inverse of k_get_plane: stored_q(x) = in(x + c_q).
 template <class S, class C>
-__global__ __launch_bounds__(256) void k_set_plane(uint32_t nx, uint32_t ny, int q, const double *__restrict__ in,
+__global__ __launch_bounds__(256) void k_set_plane(uint32_t nx, uint32_t ny, uint32_t P, int q,
+                                                   const double *__restrict__ in,
                                                    typename Codec<S>::Raw *__restrict__ dst, C rho_ref) {
     const uint32_t N = nx * ny;
     const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     const uint32_t y = n / nx, x = n - y * nx;
     const uint32_t xs = (x + nx + kCx[q]) % nx, ys = (y + ny + kCy[q]) % ny;
-    dst[q * N + n] = Codec<S>::template encode<C>(C(in[ys * nx + xs]), q, rho_ref);
+    dst[q * P + n] = Codec<S>::template encode<C>(C(in[ys * nx + xs]), q, rho_ref);
 }
 
 // ------------------------------------------------------------- wall tables
@@ -693,48 +673,52 @@ template <class Fn> static hipError_t dispatch(int storage, Fn &&fn) {
     }
 }
 
-uint32_t step_tiles(uint32_t nx, uint32_t ny) {
-    return ((nx + kStripCols - 1) / kStripCols) * ((ny + kTileRows - 1) / kTileRows);
+// Calls fn(integral_constant<int, s>) for a tile shape index.
+template <class Fn> static hipError_t with_shape(int shape, Fn &&fn) {
+    switch (shape) {
+    case 0: return fn(std::integral_constant<int, 0>{});
+    case 1: return fn(std::integral_constant<int, 1>{});
+    case 2: return fn(std::integral_constant<int, 2>{});
+    case 3: return fn(std::integral_constant<int, 3>{});
+    default: return hipErrorInvalidValue;
+    }
+}
+static_assert(kNumTileShapes == 4, "with_shape lists every tile shape");
+
+uint32_t step_tiles(uint32_t nx, uint32_t ny, int shape) {
+    const uint32_t out = shape_out_rows(shape);
+    return ((nx + kStripCols - 1) / kStripCols) * ((ny + out - 1) / out);
 }
 
-hipError_t launch_step(int storage, const LatDevAny &L, int wall, int parity, hipStream_t st) {
+hipError_t launch_step(int storage, const LatDevAny &L, int wall, int shape, int parity, hipStream_t st) {
     return dispatch(storage, [&](auto s, auto c) {
         using S = decltype(s);
         using C = decltype(c);
         LatDev<C> d = L.get<C>();
         const void *src = parity ? d.fb : d.fa;
         void *dst = parity ? d.fa : d.fb;
-#if LBM_STEP_TILES
-        const uint32_t nb = step_tiles(d.nx, d.ny);
-        if (wall == WALL_ROW)
-            hipLaunchKernelGGL((k_step_tiles<S, C, WALL_ROW>), dim3(nb), dim3(kTileThreads), 0, st, d, src, dst);
-        else
-            hipLaunchKernelGGL((k_step_tiles<S, C, WALL_NODE>), dim3(nb), dim3(kTileThreads), 0, st, d, src, dst);
-#else
-        const uint32_t waves = d.strips * d.segs;
-        if (wall == WALL_ROW)
-            hipLaunchKernelGGL((k_step<S, C, WALL_ROW>), dim3(blocks_for(waves)), dim3(kBlockThreads), 0, st, d, src, dst);
-        else
-            hipLaunchKernelGGL((k_step<S, C, WALL_NODE>), dim3(blocks_for(waves)), dim3(kBlockThreads), 0, st, d, src, dst);
-#endif
-        return hipGetLastError();
+        return with_shape(shape, [&](auto sh) {
+            constexpr int SH = decltype(sh)::value;
+            const uint32_t nb = step_tiles(d.nx, d.ny, SH);
+            const dim3 block(kShapeWaves[SH] * kWave);
+            if (wall == WALL_ROW)
+                hipLaunchKernelGGL((k_step_tiles<S, C, WALL_ROW, SH>), dim3(nb), block, 0, st, d, src, dst);
+            else
+                hipLaunchKernelGGL((k_step_tiles<S, C, WALL_NODE, SH>), dim3(nb), block, 0, st, d, src, dst);
+            return hipGetLastError();
+        });
     });
 }
 
-hipError_t launch_step_batch(const void *lats, const uint4 *work, uint32_t nwork, const uint4 *twork, uint32_t ntiles,
-                             int parity, hipStream_t st) {
-#if LBM_STEP_TILES
-    (void)work;
-    (void)nwork;
-    hipLaunchKernelGGL((k_step_tiles_batch<float, float, WALL_ROW>), dim3(ntiles), dim3(kTileThreads), 0, st,
-                       (const LatDev<float> *)lats, twork, parity);
-#else
-    (void)twork;
-    (void)ntiles;
-    hipLaunchKernelGGL((k_step_batch<float, float, WALL_ROW>), dim3(blocks_for(nwork)), dim3(kBlockThreads), 0, st,
-                       (const LatDev<float> *)lats, work, nwork, parity);
-#endif
-    return hipGetLastError();
+hipError_t launch_step_batch(const void *lats, const uint4 *twork, uint32_t ntiles, int shape, int parity,
+                             hipStream_t st) {
+    if (ntiles == 0) return hipSuccess;
+    return with_shape(shape, [&](auto sh) {
+        constexpr int SH = decltype(sh)::value;
+        hipLaunchKernelGGL((k_step_tiles_batch<float, float, WALL_ROW, SH>), dim3(ntiles),
+                           dim3(kShapeWaves[SH] * kWave), 0, st, (const LatDev<float> *)lats, twork, parity);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_diag(int storage, const void *lats, const uint4 *work, uint32_t nwork, const LatDevAny &single,
@@ -781,30 +765,30 @@ hipError_t launch_profile(int f64, uint32_t nx, uint32_t ny, const void *ux, dou
     return hipGetLastError();
 }
 
-hipError_t launch_init(int storage, uint32_t nx, uint32_t ny, const double *rho0, const double *ux0,
-                       const double *uy0, void *dst, double rho_ref, hipStream_t st) {
+hipError_t launch_init(int storage, uint32_t nx, uint32_t ny, uint32_t pstride, const double *rho0,
+                       const double *ux0, const double *uy0, void *dst, double rho_ref, hipStream_t st) {
     const uint32_t nb = blocks_nodes(nx * ny);
     return dispatch(storage, [&](auto s, auto c) {
         using S = decltype(s);
         using C = decltype(c);
-        hipLaunchKernelGGL((k_init<S, C>), dim3(nb), dim3(256), 0, st, nx, ny, rho0, ux0, uy0,
+        hipLaunchKernelGGL((k_init<S, C>), dim3(nb), dim3(256), 0, st, nx, ny, pstride, rho0, ux0, uy0,
                            (typename Codec<S>::Raw *)dst, C(rho_ref));
         return hipGetLastError();
     });
 }
 
-hipError_t launch_plane(int storage, int set, uint32_t nx, uint32_t ny, int q, void *pop, double *buf,
-                        double rho_ref, hipStream_t st) {
+hipError_t launch_plane(int storage, int set, uint32_t nx, uint32_t ny, uint32_t pstride, int q, void *pop,
+                        double *buf, double rho_ref, hipStream_t st) {
     const uint32_t nb = blocks_nodes(nx * ny);
     return dispatch(storage, [&](auto s, auto c) {
         using S = decltype(s);
         using C = decltype(c);
         using Raw = typename Codec<S>::Raw;
         if (set)
-            hipLaunchKernelGGL((k_set_plane<S, C>), dim3(nb), dim3(256), 0, st, nx, ny, q, buf, (Raw *)pop,
+            hipLaunchKernelGGL((k_set_plane<S, C>), dim3(nb), dim3(256), 0, st, nx, ny, pstride, q, buf, (Raw *)pop,
                                C(rho_ref));
         else
-            hipLaunchKernelGGL((k_get_plane<S, C>), dim3(nb), dim3(256), 0, st, nx, ny, q, (const Raw *)pop, buf,
+            hipLaunchKernelGGL((k_get_plane<S, C>), dim3(nb), dim3(256), 0, st, nx, ny, pstride, q, (const Raw *)pop, buf,
                                C(rho_ref));
         return hipGetLastError();
     });

@@ -18,6 +18,7 @@ template <class C> struct LatDev;
 // to the arithmetic type when a launcher builds the kernel argument.
 struct LatDevAny {
     uint32_t nx = 0, ny = 0, plane = 0;
+    uint32_t pstride = 0;          // population plane stride (elements), >= plane
     uint32_t strips = 0, segs = 0, seg_rows = 0;
     uint32_t wave0 = 0;
     void *fa = nullptr, *fb = nullptr;
@@ -34,7 +35,7 @@ template <class C> struct LatDev {
     uint32_t nx, ny, plane;
     uint32_t strips, segs, seg_rows;
     uint32_t wave0;
-    uint32_t pad0;
+    uint32_t pstride;              // population plane stride (elements)
     void *fa, *fb;
     const C *row_tab;
     const C *node_tab;
@@ -48,7 +49,7 @@ template <class C> inline LatDev<C> LatDevAny::get() const {
     LatDev<C> d;
     d.nx = nx; d.ny = ny; d.plane = plane;
     d.strips = strips; d.segs = segs; d.seg_rows = seg_rows;
-    d.wave0 = wave0; d.pad0 = 0;
+    d.wave0 = wave0; d.pstride = pstride;
     d.fa = fa; d.fb = fb;
     d.row_tab = (const C *)row_tab;
     d.node_tab = (const C *)node_tab;
@@ -73,21 +74,24 @@ constexpr uint32_t kStripColsHost = 64;
 #endif
 constexpr uint32_t kBlockWavesHost = LBM_BLOCK_WAVES;
 
-#ifndef LBM_TILE_WAVES
-#define LBM_TILE_WAVES 16  // waves per step tile
+#ifndef LBM_XCD_REMAP
+#define LBM_XCD_REMAP 0     // 1: each XCD owns a contiguous range of workgroups
 #endif
-#ifndef LBM_TILE_ROWS_PER_WAVE
-#define LBM_TILE_ROWS_PER_WAVE 2   // rows each wave of a step tile loads and updates
-#endif
-#ifndef LBM_STEP_TILES
-#define LBM_STEP_TILES 1   // time step by LDS tiles (1) or by marching waves (0)
-#endif
-constexpr uint32_t kTileRowsHost = LBM_TILE_WAVES * LBM_TILE_ROWS_PER_WAVE - 2;
 
-uint32_t step_tiles(uint32_t nx, uint32_t ny);
-hipError_t launch_step(int storage, const LatDevAny &L, int wall, int parity, hipStream_t st);
-hipError_t launch_step_batch(const void *lats, const uint4 *work, uint32_t nwork, const uint4 *twork, uint32_t ntiles,
-                             int parity, hipStream_t st);
+// Step tile shapes.  A tile is a workgroup of kShapeWaves[s] wavefronts over a
+// 64-column strip; each wave loads kShapeRows[s] rows, and the tile updates all
+// of them but the first and last (halo) rows.  Every shape computes bitwise the
+// same update; they differ in halo overhead, edge waste on small lattices and
+// occupancy, which is what the autotuner measures.
+constexpr int kNumTileShapes = 4;
+constexpr int kShapeWaves[kNumTileShapes] = {16, 8, 8, 16};
+constexpr int kShapeRows[kNumTileShapes] = {2, 2, 4, 3};
+constexpr uint32_t shape_out_rows(int s) { return uint32_t(kShapeWaves[s] * kShapeRows[s] - 2); }
+
+uint32_t step_tiles(uint32_t nx, uint32_t ny, int shape);
+hipError_t launch_step(int storage, const LatDevAny &L, int wall, int shape, int parity, hipStream_t st);
+hipError_t launch_step_batch(const void *lats, const uint4 *twork, uint32_t ntiles, int shape, int parity,
+                             hipStream_t st);
 hipError_t launch_diag(int storage, const void *lats, const uint4 *work, uint32_t nwork, const LatDevAny &single,
                        int wall, int parity, int write_mom, int compare, int update, hipStream_t st);
 hipError_t launch_reduce(const double *part, const uint32_t *ranges, uint32_t nout, uint32_t stride,
@@ -96,10 +100,10 @@ hipError_t launch_isoline(int f64, const IsoParams &p, const void *rho, const do
                           hipStream_t st);
 uint32_t isoline_blocks(uint32_t nodes);
 hipError_t launch_profile(int f64, uint32_t nx, uint32_t ny, const void *ux, double *out, hipStream_t st);
-hipError_t launch_init(int storage, uint32_t nx, uint32_t ny, const double *rho0, const double *ux0,
-                       const double *uy0, void *dst, double rho_ref, hipStream_t st);
-hipError_t launch_plane(int storage, int set, uint32_t nx, uint32_t ny, int q, void *pop, double *buf,
-                        double rho_ref, hipStream_t st);
+hipError_t launch_init(int storage, uint32_t nx, uint32_t ny, uint32_t pstride, const double *rho0,
+                       const double *ux0, const double *uy0, void *dst, double rho_ref, hipStream_t st);
+hipError_t launch_plane(int storage, int set, uint32_t nx, uint32_t ny, uint32_t pstride, int q, void *pop,
+                        double *buf, double rho_ref, hipStream_t st);
 hipError_t launch_walls_row(int f64, int ny, int P, double width, double core, double tail, double eps,
                             double GR, double GA, void *tab, double *phi_raw, hipStream_t st);
 hipError_t launch_walls_node(int f64, uint32_t nx, uint32_t ny, const double *fields, double eps, double GR,

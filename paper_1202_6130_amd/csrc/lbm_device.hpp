@@ -51,11 +51,6 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kStripCols = 64;     // output columns per wave (one per lane, 64-aligned)
 constexpr int kBlockWaves = LBM_BLOCK_WAVES;   // waves per workgroup
 constexpr int kBlockThreads = kWave * kBlockWaves;
-constexpr int kTileWaves = LBM_TILE_WAVES;        // waves per step tile
-constexpr int kRowsPerWave = LBM_TILE_ROWS_PER_WAVE;
-constexpr int kTileRowsIn = kTileWaves * kRowsPerWave;   // rows loaded per tile, incl. 2 halo rows
-constexpr int kTileRows = kTileRowsIn - 2;        // output rows per step tile
-constexpr int kTileThreads = kWave * kTileWaves;
 
 enum WallMode : int { WALL_ROW = 0, WALL_NODE = 1 };
 
@@ -123,14 +118,21 @@ template <class S> struct PopBuf {
 __device__ inline uint32_t wrap_dec(uint32_t v, uint32_t n) { return v == 0 ? n - 1 : v - 1; }
 __device__ inline uint32_t wrap_inc(uint32_t v, uint32_t n) { return v + 1 == n ? 0 : v + 1; }
 
-// Logical workgroup index: consecutive hardware workgroups are dealt round
-// robin to the 8 XCDs, each with its own L2.  Remap so that each XCD owns one
-// contiguous range of logical workgroups (adjacent tiles share halo lines).
+// Logical workgroup index.  Consecutive hardware workgroups are dealt round
+// robin to the 8 XCDs, each with its own L2.  With LBM_XCD_REMAP each XCD owns
+// one contiguous range of logical workgroups instead; measured on MI355X, the
+// plain order is faster for these streaming kernels (all XCDs then work on one
+// narrow band of rows at a time), so the remap is off by default.
 __device__ inline uint32_t xcd_logical_block(uint32_t b, uint32_t nb) {
+#if LBM_XCD_REMAP
     const uint32_t nxcd = 8;
     uint32_t xcd = b % nxcd, local = b / nxcd;
     uint32_t base = xcd * (nb / nxcd) + min(xcd, nb % nxcd);
     return base + local;
+#else
+    (void)nb;
+    return b;
+#endif
 }
 
 template <class C> __device__ inline C cexp(C v);

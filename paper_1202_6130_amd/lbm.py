@@ -41,6 +41,7 @@ class lbm_params(ctypes.Structure):
 
 _lib = None
 _dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
 _vp = ctypes.c_void_p
 
 
@@ -85,6 +86,13 @@ def lib():
                                    ctypes.c_int),
         "lbm_batch_attach": ([ctypes.POINTER(_vp), ctypes.c_int32, _vp, ctypes.c_size_t, _vp,
                               ctypes.POINTER(_vp)], ctypes.c_int),
+        "lbm_tile_shapes": ([_ip, _ip, ctypes.c_int32], ctypes.c_int32),
+        "lbm_set_tile_shape": ([_vp, ctypes.c_int32], ctypes.c_int),
+        "lbm_get_tile_shape": ([_vp], ctypes.c_int32),
+        "lbm_tune": ([_vp, ctypes.c_int32, _ip, _dp], ctypes.c_int),
+        "lbm_batch_set_tile_shapes": ([_vp, _ip], ctypes.c_int),
+        "lbm_batch_get_tile_shapes": ([_vp, _ip], ctypes.c_int),
+        "lbm_batch_tune": ([_vp, ctypes.c_int32, _ip, _dp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -105,6 +113,11 @@ def _ptr(a):
         return None
     assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"], "float64 C-contiguous array required"
     return a.ctypes.data_as(_dp)
+
+
+def _iptr(a):
+    assert a.dtype == np.int32 and a.flags["C_CONTIGUOUS"], "int32 C-contiguous array required"
+    return a.ctypes.data_as(_ip)
 
 
 def _f64(a):
@@ -251,6 +264,51 @@ def lbm_batch_attach(ctxs, workspace_ptr, workspace_bytes, stream_ptr):
     return out
 
 
+def lbm_tile_shapes():
+    """[(waves, rows), ...] of the step tile shapes, indexed by shape id."""
+    n = lib().lbm_tile_shapes(None, None, 0)
+    w = np.zeros(n, dtype=np.int32)
+    r = np.zeros(n, dtype=np.int32)
+    lib().lbm_tile_shapes(_iptr(w), _iptr(r), n)
+    return [(int(a), int(b)) for a, b in zip(w, r)]
+
+
+def lbm_set_tile_shape(ctx, shape):
+    _check(lib().lbm_set_tile_shape(ctx, int(shape)))
+
+
+def lbm_get_tile_shape(ctx):
+    return int(lib().lbm_get_tile_shape(ctx))
+
+
+def lbm_tune(ctx, steps):
+    """Returns (chosen shape, median ms per step of every shape)."""
+    shape = np.zeros(1, dtype=np.int32)
+    ms = np.zeros(len(lbm_tile_shapes()))
+    _check(lib().lbm_tune(ctx, int(steps), _iptr(shape), _ptr(ms)))
+    return int(shape[0]), ms
+
+
+def lbm_batch_set_tile_shapes(b, shapes):
+    arr = None if shapes is None else np.ascontiguousarray(shapes, dtype=np.int32)
+    _check(lib().lbm_batch_set_tile_shapes(b, None if arr is None else _iptr(arr)))
+
+
+def lbm_batch_get_tile_shapes(b, n):
+    out = np.zeros(n, dtype=np.int32)
+    _check(lib().lbm_batch_get_tile_shapes(b, _iptr(out)))
+    return out
+
+
+def lbm_batch_tune(b, n, steps):
+    """Returns (per-lattice shapes, median ms per step of each uniform shape
+    and of the mixed assignment (NaN if not timed))."""
+    shapes = np.zeros(n, dtype=np.int32)
+    ms = np.zeros(len(lbm_tile_shapes()) + 1)
+    _check(lib().lbm_batch_tune(b, int(steps), _iptr(shapes), _ptr(ms)))
+    return shapes, ms
+
+
 # ------------------------------------------------------------ conveniences
 def _workspace(nbytes, device):
     import torch
@@ -310,6 +368,18 @@ class Lattice:
     def step_index(self):
         return lbm_step_index(self.ctx)
 
+    @property
+    def tile_shape(self):
+        return lbm_get_tile_shape(self.ctx)
+
+    @tile_shape.setter
+    def tile_shape(self, shape):
+        lbm_set_tile_shape(self.ctx, shape)
+
+    def tune(self, steps=10):
+        """Autotune the tile shape (advances the lattice; see lbm_tune)."""
+        return lbm_tune(self.ctx, steps)
+
     def close(self):
         if self.ctx:
             lbm_destroy(self.ctx)
@@ -344,6 +414,17 @@ class Attached:
 
     def diagnostics(self, check=True):
         return lbm_batch_diagnostics(self.b, self.n, check)
+
+    @property
+    def tile_shapes(self):
+        return lbm_batch_get_tile_shapes(self.b, self.n)
+
+    @tile_shapes.setter
+    def tile_shapes(self, shapes):
+        lbm_batch_set_tile_shapes(self.b, shapes)
+
+    def tune(self, steps=10):
+        return lbm_batch_tune(self.b, self.n, steps)
 
     def close(self):
         if self.b:
@@ -402,6 +483,9 @@ class Batch:
 
     def diagnostics(self, check=True):
         return lbm_batch_diagnostics(self.b, self.n, check)[0]
+
+    tile_shapes = Attached.tile_shapes
+    tune = Attached.tune
 
     def lattice(self, k):
         return View(self, k, self.ps[k])

@@ -11,10 +11,16 @@ measured and retired, and its slot and memory go to the next request.  The
 batch is rebuilt whenever membership changes; resident lattices keep their
 state across rebuilds.  A request whose lattice turns non-finite fails alone.
 
+Tile shapes: at start-up the batch autotuner measures a per-tile step cost
+for every tile shape on a small calibration ensemble; each admitted lattice
+then gets the shape of least predicted cost (tile count x per-tile cost).
+Shapes change speed only, never results.
+
 `Server(batched=False, max_resident=1)` is the plain sequential baseline.
 """
 import collections
 import dataclasses
+import math
 import time
 
 import numpy as np
@@ -46,6 +52,29 @@ class Result:
         return self.finished - self.arrival
 
 
+def tile_count(nx, ny, shape):
+    """Workgroups of one step of an nx x ny lattice with this tile shape."""
+    w, r = lbm.lbm_tile_shapes()[shape]
+    return math.ceil(nx / 64) * math.ceil(ny / (w * r - 2))
+
+
+def calibrate_tile_costs(seed=0, count=16, steps=3, device="cuda:0"):
+    """Per-tile step time (ms) of every tile shape, from the batch autotuner's
+    uniform-shape timings on a calibration ensemble of sessile drops."""
+    cases = I.ensemble_cases(seed=seed, count=count)
+    ps = [lbm.lbm_params_default(nx=c.nx, ny=c.ny, wall_kind=lbm.WALL_FLAT_SLAB, G=c.G, G_R=c.G_R, G_A=c.G_A)
+          for c in cases]
+    B = lbm.Batch(ps, [I.drop_field(c.nx, c.ny, c.radius) for c in cases], device=device)
+    _, ms = B.tune(steps)
+    B.close()
+    nshape = len(lbm.lbm_tile_shapes())
+    return [float(ms[s]) / sum(tile_count(c.nx, c.ny, s) for c in cases) for s in range(nshape)]
+
+
+def pick_tile_shape(nx, ny, costs):
+    return min(range(len(costs)), key=lambda s: tile_count(nx, ny, s) * costs[s])
+
+
 def request_params(req, seg_rows=0):
     """Lattice parameters and initial density of one request."""
     common = dict(nx=req.nx, ny=req.ny, storage=lbm.STORE_F32, wall_kind=lbm.WALL_FLAT_SLAB, G=req.G,
@@ -61,7 +90,7 @@ def request_params(req, seg_rows=0):
 
 class Server:
     def __init__(self, budget_bytes=96 << 30, max_resident=64, diag_every=100, max_steps=20000, tol=1e-8,
-                 batched=True, device="cuda:0", seg_rows=0, on_admit=None):
+                 batched=True, device="cuda:0", seg_rows=0, on_admit=None, tile_costs="calibrate"):
         import torch
         if diag_every % 2:
             raise ValueError("diag_every must be even (graph replays keep the buffer parity)")
@@ -76,6 +105,8 @@ class Server:
         self.on_admit = on_admit          # called as on_admit(request, lattice) after creation
         self.max_seen_resident = 0
         self.max_seen_used = 0            # largest sum of resident footprints (bytes)
+        # per-tile cost of every tile shape: measured, given, or None (shape 0)
+        self.tile_costs = calibrate_tile_costs(device=device) if tile_costs == "calibrate" else tile_costs
         torch.cuda.synchronize(device)
         self.stream = torch.cuda.Stream(device)
 
@@ -126,6 +157,8 @@ class Server:
                 waiting.popleft()
                 p, rho0 = request_params(req, self.seg_rows)
                 lat = lbm.Lattice(p, rho0, device=self.device, stream=self.stream)
+                if self.tile_costs is not None:
+                    lat.tile_shape = pick_tile_shape(req.nx, req.ny, self.tile_costs)
                 if self.on_admit is not None:
                     self.on_admit(req, lat)
                 resident.append((req, lat, fp))

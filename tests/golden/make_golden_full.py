@@ -1,0 +1,144 @@
+"""Write the full-size expected values from the FP64 oracle only.
+
+    python tests/golden/make_golden_full.py drop      # about an hour, one core
+    python tests/golden/make_golden_full.py channel   # about half an hour
+    python tests/golden/make_golden_full.py spinodal --threads 6   # about an hour on 6 cores
+
+drop: 1024x512 sessile drop of radius 160 on the lower face of a flat solid
+band of 8 rows (tanh wall functions of width 2, core range 1, tail range 3,
+eps = 1), G = -5, tau = 1, core and tail amplitudes drawn with seed 0
+(U[0,1] and U[0,0.6]), 20000 steps.  Stores the totals, the contact angle of
+the rho = 1.07 isoline (circle fit, Sec. III.B) and rho, u at 256 seeded nodes.
+
+channel: 32x256 periodic channel between the faces of the same band, filled
+with liquid at rho = 2.0 and driven by a body force 1e-6 along x, same wall
+amplitudes, 600000 steps.  Stores the slip length fitted against a Poiseuille
+parabola (Sec. III.A) and the x-averaged velocity profile.
+
+spinodal: 4096x4096 periodic lattice, no solid, G = -5, tau = 1, from the
+seeded phase-separation field (Gaussian-smoothed noise, sigma 4, 50% liquid);
+rho, u at 1024 seeded nodes and the totals after 100, 500, 1000, 2000 and
+5000 steps (OpenMP build of the oracle: bitwise the serial result).
+
+Only the oracle computes these values; a change to its arithmetic regenerates
+them in a commit that names the passage of the paper justifying it.
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle as O  # noqa: E402
+from paper_1202_6130_amd import inputs as I  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DROP = dict(nx=1024, ny=512, radius=160.0, steps=20000, seed=0)
+CHANNEL = dict(nx=32, ny=256, rho=2.0, force=1e-6, steps=600000, seed=0)
+SPINODAL = dict(n=4096, seed=0, checkpoints=(100, 500, 1000, 2000, 5000))
+
+
+def sample_nodes(nx, ny, count, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return sorted({(int(y), int(x)) for y, x in zip(rng.integers(0, ny, count), rng.integers(0, nx, count))})
+
+
+def run_chunks(p, w, f, steps, chunk, label):
+    t0 = time.time()
+    done = 0
+    while done < steps:
+        k = min(chunk, steps - done)
+        f = O.run(p, w, f, k)
+        done += k
+        print(f"{label}: {done}/{steps} steps, {time.time() - t0:.0f} s", flush=True)
+    return f
+
+
+def drop():
+    c = DROP
+    gr, ga = I.draw_wall_amplitudes(c["seed"])
+    p = O.make_params(c["nx"], c["ny"], tau=1.0, G=-5.0, G_R=float(gr[0]), G_A=float(ga[0]), eps=1.0)
+    w = O.Walls.flat_slab(c["nx"], c["ny"], I.SLAB_ROWS, 2.0, 1.0, 3.0)
+    f = O.init(p, I.drop_field(c["nx"], c["ny"], c["radius"]))
+    f = run_chunks(p, w, f, c["steps"], 500, "drop")
+    rho, ux, uy, tot = O.macros(p, w, f)
+    ang = O.contact_angle(p, w, f, I.ISO, 0.0)
+    nodes = sample_nodes(c["nx"], c["ny"], 256, 11)
+    data = {
+        "workload": "sessile drop 1024x512, radius 160, seeded wall amplitudes, 20000 steps, FP64 oracle",
+        "params": dict(c, G=-5.0, G_R=float(gr[0]), G_A=float(ga[0]), eps=1.0, iso=I.ISO),
+        "totals": tot.tolist(),
+        "contact_angle": None if ang is None else ang.tolist(),
+        "samples": [{"y": y, "x": x, "rho": rho[y, x], "ux": ux[y, x], "uy": uy[y, x]} for y, x in nodes],
+    }
+    out = os.path.join(HERE, "drop_1024x512_fp64.json")
+    with open(out, "w") as fh:
+        json.dump(data, fh, indent=0)
+    print("wrote", out)
+
+
+def channel():
+    c = CHANNEL
+    gr, ga = I.draw_wall_amplitudes(c["seed"])
+    p = O.make_params(c["nx"], c["ny"], tau=1.0, G=-5.0, G_R=float(gr[0]), G_A=float(ga[0]), eps=1.0,
+                      F_ext=(c["force"], 0.0))
+    w = O.Walls.flat_slab(c["nx"], c["ny"], I.SLAB_ROWS, 2.0, 1.0, 3.0)
+    f = O.init(p, I.uniform_field(c["nx"], c["ny"], c["rho"]))
+    f = run_chunks(p, w, f, c["steps"], 20000, "channel")
+    rho, ux, uy, tot = O.macros(p, w, f)
+    slip = O.slip_length(p, w, f, I.SLAB_ROWS, 2.0)
+    data = {
+        "workload": "channel 32x256, body force 1e-6, seeded wall amplitudes, 600000 steps, FP64 oracle",
+        "params": dict(c, G=-5.0, G_R=float(gr[0]), G_A=float(ga[0]), eps=1.0),
+        "totals": tot.tolist(),
+        "slip": None if slip is None else slip.tolist(),
+        "ux_profile": ux.mean(axis=1).tolist(),
+        "rho_profile": rho.mean(axis=1).tolist(),
+    }
+    out = os.path.join(HERE, "channel_32x256_fp64.json")
+    with open(out, "w") as fh:
+        json.dump(data, fh, indent=0)
+    print("wrote", out)
+
+
+def spinodal():
+    c = SPINODAL
+    n = c["n"]
+    p = O.make_params(n, n, tau=1.0, G=-5.0)
+    w = O.Walls.none(n, n)
+    f = O.init(p, I.spinodal_field(n, seed=c["seed"]))
+    nodes = sample_nodes(n, n, 1024, 12)
+    ys = np.array([y for y, _ in nodes])
+    xs = np.array([x for _, x in nodes])
+    data = {"workload": "periodic 4096x4096 phase separation, sigma 4, 50% liquid, G=-5, tau=1, FP64 oracle",
+            "params": dict(c, G=-5.0), "nodes_y": ys.tolist(), "nodes_x": xs.tolist(), "checkpoints": []}
+    t = 0
+    for tc in c["checkpoints"]:
+        f = run_chunks(p, w, f, tc - t, 50, f"spinodal to {tc}")
+        t = tc
+        rho, ux, uy, tot = O.macros(p, w, f)
+        data["checkpoints"].append({"t": tc, "totals": tot.tolist(), "rho": rho[ys, xs].tolist(),
+                                    "ux": ux[ys, xs].tolist(), "uy": uy[ys, xs].tolist()})
+        out = os.path.join(HERE, "spinodal_4096_fp64.json")
+        with open(out, "w") as fh:
+            json.dump(data, fh)
+        print("wrote", out, "through t =", tc, flush=True)
+
+
+if __name__ == "__main__":
+    args = sys.argv[1:]
+    if "--threads" in args:
+        k = args.index("--threads")
+        O.use_threads(int(args[k + 1]))
+        del args[k:k + 2]
+    which = args or ["drop", "channel"]
+    if "spinodal" in which:
+        spinodal()
+    if "drop" in which:
+        drop()
+    if "channel" in which:
+        channel()

@@ -23,9 +23,21 @@ def declared_functions():
 def test_library_exports_every_declared_symbol():
     L = ctypes.CDLL(lbm.LIB_PATH)
     names = declared_functions()
-    assert len(names) >= 19
+    assert len(names) >= 26
     missing = [n for n in names if not hasattr(L, n)]
     assert not missing, missing
+
+
+def test_tile_shape_table_and_null_context():
+    shapes = lbm.lbm_tile_shapes()
+    assert len(shapes) >= 2 and shapes[0] == (16, 2)
+    assert all(w in (4, 8, 16) and 1 <= r <= 4 for w, r in shapes)
+    L = lbm.lib()
+    assert L.lbm_get_tile_shape(None) == -1
+    assert L.lbm_set_tile_shape(None, 0) == lbm.LBM_EINVAL
+    assert L.lbm_tune(None, 1, None, None) == lbm.LBM_EINVAL
+    assert L.lbm_batch_tune(None, 1, None, None) == lbm.LBM_EINVAL
+    assert L.lbm_batch_set_tile_shapes(None, None) == lbm.LBM_EINVAL
 
 
 def test_params_struct_matches_header():

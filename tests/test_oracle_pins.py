@@ -7,12 +7,15 @@ Laplace law, symmetry, geometric fits on exact curves, and the paper's
 qualitative trends for the wall model (Sec. III).
 """
 import ctypes
+import os
 
 import numpy as np
 import pytest
 from scipy import integrate, optimize
 
 from paper_1202_6130_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def walls_random(orc, nx, ny, seed):
@@ -543,3 +546,25 @@ def test_brute_force_4x4(orc):
     h = brute_force_step(nx, ny, 0.85, -5.0, 0.6, 0.35, 1.3, (0.01, 0.02), (1e-3, -2e-3),
                          walls.phi, walls.psiR, walls.psiA, f)
     assert np.abs(g - h).max() < 1e-14
+
+
+def test_parallel_build_is_bitwise_serial(orc, tmp_path):
+    """The OpenMP build of the oracle (long reference runs) gives bitwise the
+    serial build's result."""
+    import subprocess
+    import sys
+    nx, ny = 40, 24
+    p = orc.make_params(nx, ny, tau=0.9, G=-5.0, G_R=0.5, G_A=0.3, eps=1.3, F_ext=(1e-4, 0.0))
+    w = orc.Walls.flat_slab(nx, ny, 6)
+    f = orc.run(p, w, orc.init(p, I.drop_field(nx, ny, 8.0)), 30)
+    out = tmp_path / "f_omp.npy"
+    code = (
+        "import sys, numpy as np; sys.path.insert(0, %r)\n"
+        "import oracle as O; O.use_threads(3)\n"
+        "from paper_1202_6130_amd import inputs as I\n"
+        "p = O.make_params(40, 24, tau=0.9, G=-5.0, G_R=0.5, G_A=0.3, eps=1.3, F_ext=(1e-4, 0.0))\n"
+        "w = O.Walls.flat_slab(40, 24, 6)\n"
+        "np.save(%r, O.run(p, w, O.init(p, I.drop_field(40, 24, 8.0)), 30))\n"
+    ) % (ROOT, str(out))
+    subprocess.check_call([sys.executable, "-c", code])
+    assert np.array_equal(np.load(out), f)
