@@ -58,8 +58,9 @@ def bytes_per_update(storage):
 
 def tile_desc(shape):
     from paper_1202_6130_amd import lbm
-    w, r = lbm.lbm_tile_shapes()[shape]
-    return f"shape {shape}: 64 columns x {w * r - 2} rows per workgroup ({w} waves x {r} rows, 2 halo rows)"
+    w, r, s = lbm.lbm_tile_shapes()[shape]
+    return (f"shape {shape}: {64 * s} columns x {w // s * r - 2} rows per workgroup ({w} waves: {s} strip(s) x "
+            f"{w // s} waves x {r} rows, 2 halo rows)")
 
 WORKLOADS = {
     # name: (nx, ny, description)

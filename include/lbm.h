@@ -184,16 +184,17 @@ int64_t lbm_step_index(const lbm_ctx *c);
 lbm_status lbm_destroy(lbm_ctx *c);
 
 /* ------------------------------------------------------------------------
- * Step tile shapes.  The time step runs as workgroups over 64-column strips;
- * shape s has waves[s] wavefronts per workgroup, each loading rows[s] rows,
- * and updates waves[s]*rows[s] - 2 rows per workgroup (the first and last
- * loaded rows are halo).  Every shape computes bitwise the same update; the
- * choice only changes speed.  Shape 0 is the default of a new context.
+ * Step tile shapes.  The time step runs as workgroups over blocks of
+ * strips[s] adjacent 64-column strips; shape s has waves[s] wavefronts per
+ * workgroup, waves[s]/strips[s] per strip, each loading rows[s] rows, and
+ * updates waves[s]/strips[s]*rows[s] - 2 rows per workgroup (the first and
+ * last loaded rows are halo).  Every shape computes bitwise the same update;
+ * the choice only changes speed.  Shape 0 is the default of a new context.
  * ------------------------------------------------------------------------ */
 
-/* Writes up to cap (waves, rows) pairs (either array may be NULL) and returns
- * the number of shapes. */
-int32_t lbm_tile_shapes(int32_t *waves, int32_t *rows, int32_t cap);
+/* Writes up to cap (waves, rows, strips) triples (any array may be NULL) and
+ * returns the number of shapes. */
+int32_t lbm_tile_shapes(int32_t *waves, int32_t *rows, int32_t *strips, int32_t cap);
 
 /* Sets / returns the tile shape of a context (not one inside a batch:
  * LBM_ESTATE).  lbm_get_tile_shape returns -1 for NULL. */

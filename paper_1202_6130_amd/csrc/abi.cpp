@@ -721,9 +721,9 @@ static lbm_status upload_twork(lbm_batch *b) {
         for (int32_t k = 0; k < n; ++k) {
             if (b->shapes[k] != s) continue;
             const lbm_ctx *c = b->lat[k];
-            const uint32_t trows = step_tiles(uint32_t(c->p.nx), uint32_t(c->p.ny), s) / c->lay.strips;
+            const uint32_t trows = tile_rows(uint32_t(c->p.ny), s), groups = tile_groups(uint32_t(c->p.nx), s);
             for (uint32_t tr = 0; tr < trows; ++tr)
-                for (uint32_t sp = 0; sp < c->lay.strips; ++sp) tw.push_back(make_uint4(uint32_t(k), sp, tr, 0));
+                for (uint32_t gp = 0; gp < groups; ++gp) tw.push_back(make_uint4(uint32_t(k), gp, tr, 0));
         }
     }
     b->toff[kNumTileShapes] = uint32_t(tw.size());
@@ -972,10 +972,11 @@ lbm_ctx *lbm_batch_lattice(lbm_batch *b, int32_t k) {
 }
 
 // ------------------------------------------------------- tile shapes, tuner
-int32_t lbm_tile_shapes(int32_t *waves, int32_t *rows, int32_t cap) {
+int32_t lbm_tile_shapes(int32_t *waves, int32_t *rows, int32_t *strips, int32_t cap) {
     for (int s = 0; s < kNumTileShapes && s < cap; ++s) {
         if (waves) waves[s] = kShapeWaves[s];
         if (rows) rows[s] = kShapeRows[s];
+        if (strips) strips[s] = kShapeStrips[s];
     }
     return kNumTileShapes;
 }

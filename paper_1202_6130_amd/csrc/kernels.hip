@@ -204,11 +204,7 @@ template <class S, class C, int WALL> struct StepAct {
         C phie, Sx, Sy;
         wall_terms<C, WALL>(L, rw, n, phie, Sx, Sy);
         NodeState<C> s = node_forces<C>(f, rho, psi_c, sx, sy, phie, Sx, Sy, L.G, L.Ux, L.Uy, L.Fx, L.Fy);
-#if !LBM_PROBE_NOCOLLIDE
         collide<C>(f, s, L.omega);
-#else
-        f[0] += C(1e-30) * s.Fx;   // probe build: keep the forces alive, skip the collision
-#endif
         if (active) {
             const uint32_t row = y * L.nx;
 #pragma unroll
@@ -264,31 +260,36 @@ __device__ inline uint32_t logical_wave() {
 }
 
 // ---------------------------------------------------------------- tiles
-// The time step proper.  One workgroup of TW waves owns a 64-column strip and
-// TW * TR consecutive rows, of which the first and last are halo rows: wave w
-// loads rows y0 - 1 + w TR + j (j < TR), all at once.  Each wave computes density and pseudo-potential of
-// its rows (and of the two columns beside the strip, from the gathered load),
-// publishes them in LDS, and after one barrier every row between the halo
-// rows reads its neighbours above and below, forms the forces, collides and
-// stores.  No wave walks through rows one after another: every population row
-// of the tile is in flight at the same time.
-template <class C, int ROWS> struct TileLds {
-    C psi[ROWS][kWave];
+// The time step proper.  One workgroup of TW waves owns TS adjacent 64-column
+// strips and TW / TS * TR consecutive rows, of which the first and last are
+// halo rows: wave w works in strip w / (TW / TS) and loads its rows
+// y0 - 1 + (w mod TW / TS) TR + j (j < TR), all at once.  Each wave computes
+// density and pseudo-potential of its rows, the outermost waves also of the
+// column beside the block (from one gathered load per row), and publishes
+// them in LDS; after one barrier every row between the halo rows reads its
+// neighbours above, below and across strip boundaries, forms the forces,
+// collides and stores.  No wave walks through rows one after another: every
+// population row of the tile is in flight at the same time.
+template <class C, int ROWS, int COLS> struct TileLds {
+    C psi[ROWS][COLS];
     C hal[ROWS][2];
 };
 
-template <class S, class C, int WALL, int TW, int TR>
-__device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst, uint32_t strip, uint32_t trow,
-                                 TileLds<C, TW * TR> &sm) {
+template <class S, class C, int WALL, int TW, int TR, int TS>
+__device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst, uint32_t group, uint32_t trow,
+                                 TileLds<C, TW / TS * TR, TS * kWave> &sm) {
     using Raw = typename Codec<S>::Raw;
-    constexpr int R = TR;
-    constexpr uint32_t kOut = uint32_t(TW * TR - 2);
+    constexpr int R = TR, WS = TW / TS;
+    constexpr uint32_t kOut = uint32_t(WS * TR - 2);
+    static_assert(TW % TS == 0, "waves must split evenly over the strips");
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
+    const int sj = w / WS, wr = w - sj * WS;          // strip within the block, wave within the strip
     const uint32_t nx = L.nx, ny = L.ny;
-    const uint32_t x0 = strip * kStripCols;
-    const uint32_t x = (x0 + uint32_t(lane)) % nx;
-    const bool active = x0 + uint32_t(lane) < nx;
+    const uint32_t X0 = group * uint32_t(TS * kStripCols);   // first column of the block
+    const uint32_t pos = uint32_t(sj * kStripCols + lane);    // column offset within the block
+    const uint32_t x = (X0 + pos) % nx;
+    const bool active = X0 + pos < nx;
     const uint32_t y0 = trow * kOut;
     const uint32_t out_rows = min(kOut, ny - y0);
 
@@ -298,28 +299,31 @@ __device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst,
     ld.x = x;
     ld.xm = wrap_dec(x, nx);
     ld.xp = wrap_inc(x, nx);
-    const bool g_left = lane < Q, g_right = lane >= 32 && lane < 32 + Q;
+    // gathered halo columns: lanes 0..8 of the waves of the first strip fetch
+    // the nine pulled populations of column X0 - 1, lanes 32..40 of the waves
+    // of the last strip those of column X0 + 64 TS (both wrapped)
+    const bool g_left = lane < Q && sj == 0, g_right = lane >= 32 && lane < 32 + Q && sj == TS - 1;
     const bool g_on = g_left || g_right;
     const int g_q = g_left ? lane : (g_right ? lane - 32 : 0);
     {
-        const uint32_t h = g_left ? (x0 + nx - 1) % nx : (x0 + kStripCols) % nx;
+        const uint32_t h = g_left ? (X0 + nx - 1) % nx : (X0 + uint32_t(TS * kStripCols)) % nx;
         const uint32_t hc = uint32_t(int(h) + int(nx) - kCx[g_q]) % nx;   // h - c_x, wrapped
         ld.g_col = g_on ? uint32_t(g_q) * L.pstride + hc : 0u;
         ld.g_cy = g_on ? kCy[g_q] : 0;
     }
 
-    // rows of this wave: tile row index k = w R + j, lattice row y0 - 1 + k
+    // rows of this wave: tile row index k = wr R + j, lattice row y0 - 1 + k
     C f[R][Q], rho[R], psi[R];
     Raw raw[R][Q], g[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        const uint32_t k = uint32_t(w * R + j);
+        const uint32_t k = uint32_t(wr * R + j);
         const uint32_t r = (y0 + ny - 1 + k) % ny;
         if (k <= out_rows + 1) ld.load(wrap_dec(r, ny) * nx, r * nx, wrap_inc(r, ny) * nx, raw[j], g[j]);
     }
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        const uint32_t k = uint32_t(w * R + j);
+        const uint32_t k = uint32_t(wr * R + j);
         rho[j] = C(0);
         psi[j] = C(0);
         if (k <= out_rows + 1) {
@@ -332,23 +336,32 @@ __device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst,
             const C sum = row_sum9<C>(v);
             const C hl = psi_of<C>(Lanes<C>::lane(sum, 15));
             const C hr = psi_of<C>(Lanes<C>::lane(sum, 47));
-            sm.psi[k][lane] = psi[j];
-            if (lane == 0) {
-                sm.hal[k][0] = hl;
-                sm.hal[k][1] = hr;
-            }
+            sm.psi[k][pos] = psi[j];
+            if (lane == 0 && sj == 0) sm.hal[k][0] = hl;
+            if (lane == 0 && sj == TS - 1) sm.hal[k][1] = hr;
         }
     }
     __syncthreads();
     const C w1 = C(1.0 / 9.0), w2 = C(1.0 / 36.0);
+    // pseudo-potential just left of lane 0 / right of lane 63 of this strip
+    const int cl = sj * kStripCols - 1, cr = (sj + 1) * kStripCols;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        const uint32_t k = uint32_t(w * R + j);
+        const uint32_t k = uint32_t(wr * R + j);
         if (k < 1 || k > out_rows) continue;
         const uint32_t r = (y0 - 1 + k) % ny;
-        const C psi_m = sm.psi[k - 1][lane], psi_p = sm.psi[k + 1][lane];
-        const C hl_m = sm.hal[k - 1][0], hl_c = sm.hal[k][0], hl_p = sm.hal[k + 1][0];
-        const C hr_m = sm.hal[k - 1][1], hr_c = sm.hal[k][1], hr_p = sm.hal[k + 1][1];
+        const C psi_m = sm.psi[k - 1][pos], psi_p = sm.psi[k + 1][pos];
+        C hl_m, hl_c, hl_p, hr_m, hr_c, hr_p;
+        if (sj == 0) {
+            hl_m = sm.hal[k - 1][0]; hl_c = sm.hal[k][0]; hl_p = sm.hal[k + 1][0];
+        } else {
+            hl_m = sm.psi[k - 1][cl]; hl_c = sm.psi[k][cl]; hl_p = sm.psi[k + 1][cl];
+        }
+        if (sj == TS - 1) {
+            hr_m = sm.hal[k - 1][1]; hr_c = sm.hal[k][1]; hr_p = sm.hal[k + 1][1];
+        } else {
+            hr_m = sm.psi[k - 1][cr]; hr_c = sm.psi[k][cr]; hr_p = sm.psi[k + 1][cr];
+        }
         // sum_i w_i psi(x + c_i) c_i, grouped by column (see march)
         const C a = w1 * psi[j] + w2 * (psi_p + psi_m);
         const C b = psi_p - psi_m;
@@ -366,25 +379,26 @@ __device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst,
 template <class S, class C, int WALL, int SHAPE>
 __global__ __launch_bounds__(kShapeWaves[SHAPE] * kWave) void k_step_tiles(LatDev<C> L, const void *__restrict__ src,
                                                                           void *__restrict__ dst) {
-    constexpr int TW = kShapeWaves[SHAPE], TR = kShapeRows[SHAPE];
-    __shared__ TileLds<C, TW * TR> sm;
+    constexpr int TW = kShapeWaves[SHAPE], TR = kShapeRows[SHAPE], TS = kShapeStrips[SHAPE];
+    __shared__ TileLds<C, TW / TS * TR, TS * kWave> sm;
     const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
-    const uint32_t trow = lb / L.strips, strip = lb - trow * L.strips;
-    tile_step<S, C, WALL, TW, TR>(L, src, dst, strip, trow, sm);
+    const uint32_t groups = (L.strips + TS - 1) / TS;
+    const uint32_t trow = lb / groups, group = lb - trow * groups;
+    tile_step<S, C, WALL, TW, TR, TS>(L, src, dst, group, trow, sm);
 }
 
-// Batched step over tiles of one shape: twork[b] = (lattice, strip, tile row)
-// of logical workgroup b.
+// Batched step over tiles of one shape: twork[b] = (lattice, strip group, tile
+// row) of logical workgroup b.
 template <class S, class C, int WALL, int SHAPE>
 __global__ __launch_bounds__(kShapeWaves[SHAPE] * kWave) void k_step_tiles_batch(const LatDev<C> *__restrict__ lats,
                                                                                 const uint4 *__restrict__ twork,
                                                                                 int parity) {
-    constexpr int TW = kShapeWaves[SHAPE], TR = kShapeRows[SHAPE];
-    __shared__ TileLds<C, TW * TR> sm;
+    constexpr int TW = kShapeWaves[SHAPE], TR = kShapeRows[SHAPE], TS = kShapeStrips[SHAPE];
+    __shared__ TileLds<C, TW / TS * TR, TS * kWave> sm;
     const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const uint4 wk = twork[lb];
     const LatDev<C> L = lats[wk.x];
-    tile_step<S, C, WALL, TW, TR>(L, parity ? L.fb : L.fa, parity ? L.fa : L.fb, wk.y, wk.z, sm);
+    tile_step<S, C, WALL, TW, TR, TS>(L, parity ? L.fb : L.fa, parity ? L.fa : L.fb, wk.y, wk.z, sm);
 }
 
 template <class S, class C, int WALL>
@@ -680,14 +694,18 @@ template <class Fn> static hipError_t with_shape(int shape, Fn &&fn) {
     case 1: return fn(std::integral_constant<int, 1>{});
     case 2: return fn(std::integral_constant<int, 2>{});
     case 3: return fn(std::integral_constant<int, 3>{});
+    case 4: return fn(std::integral_constant<int, 4>{});
+    case 5: return fn(std::integral_constant<int, 5>{});
+    case 6: return fn(std::integral_constant<int, 6>{});
+    case 7: return fn(std::integral_constant<int, 7>{});
+    case 8: return fn(std::integral_constant<int, 8>{});
     default: return hipErrorInvalidValue;
     }
 }
-static_assert(kNumTileShapes == 4, "with_shape lists every tile shape");
+static_assert(kNumTileShapes == 9, "with_shape lists every tile shape");
 
 uint32_t step_tiles(uint32_t nx, uint32_t ny, int shape) {
-    const uint32_t out = shape_out_rows(shape);
-    return ((nx + kStripCols - 1) / kStripCols) * ((ny + out - 1) / out);
+    return tile_groups(nx, shape) * tile_rows(ny, shape);
 }
 
 hipError_t launch_step(int storage, const LatDevAny &L, int wall, int shape, int parity, hipStream_t st) {

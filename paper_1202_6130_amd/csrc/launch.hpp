@@ -75,18 +75,27 @@ constexpr uint32_t kStripColsHost = 64;
 constexpr uint32_t kBlockWavesHost = LBM_BLOCK_WAVES;
 
 #ifndef LBM_XCD_REMAP
-#define LBM_XCD_REMAP 0     // 1: each XCD owns a contiguous range of workgroups
+#define LBM_XCD_REMAP 2     // workgroup-to-XCD mapping (see xcd_logical_block)
+#endif
+#ifndef LBM_XCD_GROUP
+#define LBM_XCD_GROUP 8     // consecutive workgroups per XCD in mapping 2
 #endif
 
-// Step tile shapes.  A tile is a workgroup of kShapeWaves[s] wavefronts over a
-// 64-column strip; each wave loads kShapeRows[s] rows, and the tile updates all
-// of them but the first and last (halo) rows.  Every shape computes bitwise the
-// same update; they differ in halo overhead, edge waste on small lattices and
-// occupancy, which is what the autotuner measures.
-constexpr int kNumTileShapes = 4;
-constexpr int kShapeWaves[kNumTileShapes] = {16, 8, 8, 16};
-constexpr int kShapeRows[kNumTileShapes] = {2, 2, 4, 3};
-constexpr uint32_t shape_out_rows(int s) { return uint32_t(kShapeWaves[s] * kShapeRows[s] - 2); }
+// Step tile shapes.  A tile is a workgroup of kShapeWaves[s] wavefronts over
+// kShapeStrips[s] adjacent 64-column strips; each wave loads kShapeRows[s]
+// rows of one strip, and the tile updates all of them but the first and last
+// (halo) rows: waves / strips * rows - 2 rows of 64 * strips columns.  Every
+// shape computes bitwise the same update; they differ in halo overhead, edge
+// waste on small lattices and occupancy, which is what the autotuner measures.
+constexpr int kNumTileShapes = 9;
+constexpr int kShapeWaves[kNumTileShapes] = {16, 8, 8, 16, 16, 8, 16, 16, 16};
+constexpr int kShapeRows[kNumTileShapes] = {2, 2, 4, 3, 2, 4, 4, 4, 3};
+constexpr int kShapeStrips[kNumTileShapes] = {1, 1, 1, 1, 2, 2, 2, 4, 2};
+constexpr uint32_t shape_out_rows(int s) { return uint32_t(kShapeWaves[s] / kShapeStrips[s] * kShapeRows[s] - 2); }
+constexpr uint32_t tile_groups(uint32_t nx, int s) {
+    return ((nx + 63) / 64 + uint32_t(kShapeStrips[s]) - 1) / uint32_t(kShapeStrips[s]);
+}
+constexpr uint32_t tile_rows(uint32_t ny, int s) { return (ny + shape_out_rows(s) - 1) / shape_out_rows(s); }
 
 uint32_t step_tiles(uint32_t nx, uint32_t ny, int shape);
 hipError_t launch_step(int storage, const LatDevAny &L, int wall, int shape, int parity, hipStream_t st);

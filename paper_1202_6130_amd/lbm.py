@@ -86,7 +86,7 @@ def lib():
                                    ctypes.c_int),
         "lbm_batch_attach": ([ctypes.POINTER(_vp), ctypes.c_int32, _vp, ctypes.c_size_t, _vp,
                               ctypes.POINTER(_vp)], ctypes.c_int),
-        "lbm_tile_shapes": ([_ip, _ip, ctypes.c_int32], ctypes.c_int32),
+        "lbm_tile_shapes": ([_ip, _ip, _ip, ctypes.c_int32], ctypes.c_int32),
         "lbm_set_tile_shape": ([_vp, ctypes.c_int32], ctypes.c_int),
         "lbm_get_tile_shape": ([_vp], ctypes.c_int32),
         "lbm_tune": ([_vp, ctypes.c_int32, _ip, _dp], ctypes.c_int),
@@ -265,12 +265,13 @@ def lbm_batch_attach(ctxs, workspace_ptr, workspace_bytes, stream_ptr):
 
 
 def lbm_tile_shapes():
-    """[(waves, rows), ...] of the step tile shapes, indexed by shape id."""
-    n = lib().lbm_tile_shapes(None, None, 0)
+    """[(waves, rows, strips), ...] of the step tile shapes, by shape id."""
+    n = lib().lbm_tile_shapes(None, None, None, 0)
     w = np.zeros(n, dtype=np.int32)
     r = np.zeros(n, dtype=np.int32)
-    lib().lbm_tile_shapes(_iptr(w), _iptr(r), n)
-    return [(int(a), int(b)) for a, b in zip(w, r)]
+    s = np.zeros(n, dtype=np.int32)
+    lib().lbm_tile_shapes(_iptr(w), _iptr(r), _iptr(s), n)
+    return [(int(a), int(b), int(c)) for a, b, c in zip(w, r, s)]
 
 
 def lbm_set_tile_shape(ctx, shape):

@@ -54,8 +54,8 @@ class Result:
 
 def tile_count(nx, ny, shape):
     """Workgroups of one step of an nx x ny lattice with this tile shape."""
-    w, r = lbm.lbm_tile_shapes()[shape]
-    return math.ceil(nx / 64) * math.ceil(ny / (w * r - 2))
+    w, r, s = lbm.lbm_tile_shapes()[shape]
+    return math.ceil(math.ceil(nx / 64) / s) * math.ceil(ny / (w // s * r - 2))
 
 
 def calibrate_tile_costs(seed=0, count=16, steps=3, device="cuda:0"):

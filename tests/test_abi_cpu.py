@@ -30,8 +30,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_tile_shape_table_and_null_context():
     shapes = lbm.lbm_tile_shapes()
-    assert len(shapes) >= 2 and shapes[0] == (16, 2)
-    assert all(w in (4, 8, 16) and 1 <= r <= 4 for w, r in shapes)
+    assert len(shapes) >= 2 and shapes[0] == (16, 2, 1)
+    assert all(w in (4, 8, 16) and 1 <= r <= 4 and s in (1, 2, 4) and w % s == 0 for w, r, s in shapes)
     L = lbm.lib()
     assert L.lbm_get_tile_shape(None) == -1
     assert L.lbm_set_tile_shape(None, 0) == lbm.LBM_EINVAL

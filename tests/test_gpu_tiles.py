@@ -9,7 +9,7 @@ from paper_1202_6130_amd import inputs as I
 from paper_1202_6130_amd import lbm
 
 pytestmark = pytest.mark.gpu
-SHAPES = [(16, 2), (8, 2), (8, 4), (16, 3)]
+SHAPES = [(16, 2, 1), (8, 2, 1), (8, 4, 1), (16, 3, 1), (16, 2, 2), (8, 4, 2), (16, 4, 2), (16, 4, 4), (16, 3, 2)]
 
 
 def _fields(nx, ny, seed):
@@ -126,13 +126,13 @@ def test_attached_keeps_context_shapes():
     st = torch.cuda.Stream()
     lats = [lbm.Lattice(p, r, stream=st) for p, r in zip(ps, rhos)]
     for k, L in enumerate(lats):
-        L.tile_shape = k + 1
+        L.tile_shape = 2 * k + 1
     A = lbm.Attached(lats)
-    assert list(A.tile_shapes) == [1, 2, 3]
-    A.tile_shapes = [3, 2, 1]
+    assert list(A.tile_shapes) == [1, 3, 5]
+    A.tile_shapes = [6, 2, 4]
     A.step(10, chunk=10)
     A.close()
-    assert [L.tile_shape for L in lats] == [3, 2, 1]
+    assert [L.tile_shape for L in lats] == [6, 2, 4]
     for L, p, r in zip(lats, ps, rhos):
         assert np.array_equal(L.get_state(), _alone(p, r, 10))
         L.close()
