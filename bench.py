@@ -97,7 +97,9 @@ def time_gpu(name, storage, steps, warmup, seg_rows, tile=None):
     nodes = p.nx * p.ny
     tune_ms = None
     if tile is None:
-        tune_steps = max(2, min(10, warmup // 5))
+        from paper_1202_6130_amd import lbm
+        # (tune_steps + 1) trial steps per shape, within the warm-up when it is long enough
+        tune_steps = max(2, warmup // len(lbm.lbm_tile_shapes()) - 1)
         shape, tune_ms = L.tune(tune_steps)
         tune_ms = [round(float(v), 5) for v in tune_ms]
     else:

@@ -26,7 +26,8 @@
 #define LBM_PF_DEPTH 1     // rows of loads in flight ahead of the row being consumed (1 or 2)
 #endif
 #ifndef LBM_STORE_AUX
-#define LBM_STORE_AUX 0    // cache-policy bits of population stores (gfx950: 1 sc0, 2 nt, 16 sc1)
+#define LBM_STORE_AUX 2    // cache-policy bits of population stores (gfx950: 1 sc0, 2 nt, 16 sc1);
+                           // non-temporal stores measured 3-4% faster for the tiled step
 #endif
 #ifndef LBM_LOAD_AUX
 #define LBM_LOAD_AUX 0     // cache-policy bits of population loads
