@@ -40,8 +40,9 @@ def kernel_sources_digest():
 
 
 def stored_traffic(path, key):
-    """HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE runs,
-    scaled by a 1 GiB copy; None if absent or counted on other kernels."""
+    """HBM bytes per launch of the step kernel (workload:storage:shape) from
+    rocprofv3 FETCH_SIZE + WRITE_SIZE runs, scaled by a 1 GiB copy; None if
+    absent or counted on other kernels."""
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -358,14 +359,15 @@ def wetting(drop_steps=20000, channel_steps=600000):
     return res
 
 
-def serving(count, max_steps, seed=0, rate=20.0):
+def serving(count, max_steps, seed=0, rate=20.0, max_nodes=16 << 20):
     """Served stream of contact-angle and slip-length queries (Poisson
     arrivals): continuous batching against plain sequential solves."""
     from paper_1202_6130_amd import inputs as I
     from paper_1202_6130_amd import serve
     reqs = I.request_stream(seed=seed, rate=rate, count=count)
     out = {}
-    for name, kw in (("continuous", dict(batched=True)), ("sequential", dict(batched=False, max_resident=1))):
+    for name, kw in (("continuous", dict(batched=True, max_nodes=max_nodes)),
+                     ("sequential", dict(batched=False, max_resident=1))):
         srv = serve.Server(max_steps=max_steps, **kw)
         res = srv.run(reqs, realtime=True)
         out[name] = serve.summarize(res, srv.elapsed)
@@ -376,7 +378,8 @@ def serving(count, max_steps, seed=0, rate=20.0):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{count} requests, Poisson arrivals at {rate}/s, lattices 128x128..2048x1024 "
                                "(multiples of 32), half sessile drops (angle), half body-force channels (slip), "
-                               f"residual < 1e-8 or {max_steps} steps"},
+                               f"residual < 1e-8 or {max_steps} steps",
+                   "max_resident_nodes": max_nodes},
         "continuous": c, "sequential": q,
         "p99_speedup": round(q["p99_s"] / c["p99_s"], 2) if c["p99_s"] else None,
     }
@@ -393,6 +396,7 @@ def main():
     ap.add_argument("--seq-steps", type=int, default=500, help="ensemble: steps per lattice of the sequential leg")
     ap.add_argument("--requests", type=int, default=60, help="serve: number of requests")
     ap.add_argument("--max-steps", type=int, default=20000, help="serve: step cap per request")
+    ap.add_argument("--serve-max-nodes", type=int, default=16 << 20, help="serve: resident lattice nodes cap")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16dev", "f64"])
     ap.add_argument("--seg-rows", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -410,7 +414,7 @@ def main():
         print(json.dumps(ensemble(args.steps, args.seq_steps)), flush=True)
         return
     if args.workload == "serve":
-        print(json.dumps(serving(args.requests, args.max_steps)), flush=True)
+        print(json.dumps(serving(args.requests, args.max_steps, max_nodes=args.serve_max_nodes)), flush=True)
         return
     if args.workload == "precision4096":
         print(json.dumps(precision_study()), flush=True)
@@ -424,7 +428,7 @@ def main():
     mlups = r["nodes"] * args.steps / (r["ms_total"] * 1e-3) / 1e6
     bpu = bytes_per_update(args.storage)
     achieved = bpu * r["nodes"] / (r["kernel_ms_mean"] * 1e-3) / 1e9
-    traffic = stored_traffic(args.traffic_json, f"{args.workload}:{args.storage}")
+    traffic = stored_traffic(args.traffic_json, f"{args.workload}:{args.storage}:shape{r['tile_shape']}")
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 4), "higher_is_better": True,

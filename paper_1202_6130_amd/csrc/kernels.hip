@@ -62,7 +62,7 @@ __device__ inline void march(const LatDev<C> &L, const void *src, uint32_t strip
     const int lane = threadIdx.x & (kWave - 1);
     const uint32_t nx = L.nx, ny = L.ny;
     const uint32_t x0 = strip * kStripCols;
-    const uint32_t x = (x0 + uint32_t(lane)) % nx;
+    const uint32_t x = wrap_fast(x0 + uint32_t(lane), nx);
     const bool active = x0 + uint32_t(lane) < nx;
 
     RowLoader<S> ld;
@@ -76,10 +76,10 @@ __device__ inline void march(const LatDev<C> &L, const void *src, uint32_t strip
     const bool g_on = g_left || g_right;
     const int g_q = g_left ? lane : (g_right ? lane - 32 : 0);
     {
-        const uint32_t h = g_left ? (x0 + nx - 1) % nx : (x0 + kStripCols) % nx;
-        const uint32_t hc = uint32_t(int(h) + int(nx) - kCx[g_q]) % nx;   // h - c_x, wrapped
+        const uint32_t h = g_left ? wrap_fast(x0 + nx - 1, nx) : wrap_fast(x0 + kStripCols, nx);
+        const uint32_t hc = wrap_fast(uint32_t(int(h) + int(nx) - cx_dyn(g_q)), nx);   // h - c_x, wrapped
         ld.g_col = g_on ? uint32_t(g_q) * L.pstride + hc : 0u;
-        ld.g_cy = g_on ? kCy[g_q] : 0;
+        ld.g_cy = g_on ? cy_dyn(g_q) : 0;
     }
     const uint32_t y0 = seg * L.seg_rows;
     const uint32_t y1 = min(y0 + L.seg_rows, ny);
@@ -288,7 +288,7 @@ __device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst,
     const uint32_t nx = L.nx, ny = L.ny;
     const uint32_t X0 = group * uint32_t(TS * kStripCols);   // first column of the block
     const uint32_t pos = uint32_t(sj * kStripCols + lane);    // column offset within the block
-    const uint32_t x = (X0 + pos) % nx;
+    const uint32_t x = wrap_fast(X0 + pos, nx);
     const bool active = X0 + pos < nx;
     const uint32_t y0 = trow * kOut;
     const uint32_t out_rows = min(kOut, ny - y0);
@@ -306,10 +306,10 @@ __device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst,
     const bool g_on = g_left || g_right;
     const int g_q = g_left ? lane : (g_right ? lane - 32 : 0);
     {
-        const uint32_t h = g_left ? (X0 + nx - 1) % nx : (X0 + uint32_t(TS * kStripCols)) % nx;
-        const uint32_t hc = uint32_t(int(h) + int(nx) - kCx[g_q]) % nx;   // h - c_x, wrapped
+        const uint32_t h = g_left ? wrap_fast(X0 + nx - 1, nx) : wrap_fast(X0 + uint32_t(TS * kStripCols), nx);
+        const uint32_t hc = wrap_fast(uint32_t(int(h) + int(nx) - cx_dyn(g_q)), nx);   // h - c_x, wrapped
         ld.g_col = g_on ? uint32_t(g_q) * L.pstride + hc : 0u;
-        ld.g_cy = g_on ? kCy[g_q] : 0;
+        ld.g_cy = g_on ? cy_dyn(g_q) : 0;
     }
 
     // rows of this wave: tile row index k = wr R + j, lattice row y0 - 1 + k
@@ -318,7 +318,7 @@ __device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst,
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const uint32_t k = uint32_t(wr * R + j);
-        const uint32_t r = (y0 + ny - 1 + k) % ny;
+        const uint32_t r = wrap_fast(y0 + ny - 1 + k, ny);
         if (k <= out_rows + 1) ld.load(wrap_dec(r, ny) * nx, r * nx, wrap_inc(r, ny) * nx, raw[j], g[j]);
     }
 #pragma unroll
@@ -349,7 +349,7 @@ __device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst,
     for (int j = 0; j < R; ++j) {
         const uint32_t k = uint32_t(wr * R + j);
         if (k < 1 || k > out_rows) continue;
-        const uint32_t r = (y0 - 1 + k) % ny;
+        const uint32_t r = wrap_fast(y0 - 1 + k, ny);
         const C psi_m = sm.psi[k - 1][pos], psi_p = sm.psi[k + 1][pos];
         C hl_m, hl_c, hl_p, hr_m, hr_c, hr_p;
         if (sj == 0) {

@@ -112,6 +112,26 @@ template <class S> struct PopBuf {
 // Wrapped neighbour column/row indices.
 __device__ inline uint32_t wrap_dec(uint32_t v, uint32_t n) { return v == 0 ? n - 1 : v - 1; }
 __device__ inline uint32_t wrap_inc(uint32_t v, uint32_t n) { return v + 1 == n ? 0 : v + 1; }
+// v mod n by repeated subtraction: the arguments here exceed n by less than
+// one tile width, so this is one or two compares except on lattices narrower
+// than a tile (an integer division would cost ~25 instructions before the
+// first load of every wave).
+__device__ inline uint32_t wrap_fast(uint32_t v, uint32_t n) {
+    while (v >= n) v -= n;
+    return v;
+}
+
+// c_x, c_y of a velocity index that differs between lanes, from packed 2-bit
+// codes (c + 1): a lane-indexed constant table would be read from memory, and
+// that read would stall every wave before its first population load.
+__host__ __device__ constexpr int cx_dyn(int q) { return int((0x20919u >> (2 * q)) & 3u) - 1; }
+__host__ __device__ constexpr int cy_dyn(int q) { return int((0x2865u >> (2 * q)) & 3u) - 1; }
+constexpr bool velocity_codes_ok() {
+    for (int q = 0; q < Q; ++q)
+        if (cx_dyn(q) != kCx[q] || cy_dyn(q) != kCy[q]) return false;
+    return true;
+}
+static_assert(velocity_codes_ok(), "packed velocity codes disagree with kCx/kCy");
 
 // Logical workgroup index.  Consecutive hardware workgroups are dealt round
 // robin to the 8 XCDs, each with its own L2.

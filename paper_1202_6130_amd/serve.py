@@ -2,8 +2,10 @@
 
 Each request is one lattice (sessile drop -> static contact angle, Sec. III.B;
 body-force channel -> slip length, Sec. III.A).  Requests are admitted in
-arrival order while their device footprint fits the memory budget and a slot
-is free; all resident lattices advance together, one kernel launch per time
+arrival order while their device footprint fits the memory budget, a slot is
+free and the resident lattice nodes stay under `max_nodes` (enough to fill the
+GPU: more resident work only delays every request without raising
+throughput); all resident lattices advance together, one kernel launch per time
 step (lbm_batch_attach), replayed from a HIP graph in chunks of `diag_every`
 steps.  After every chunk the velocity residual of each lattice is read; a
 lattice whose residual falls below `tol` (or that reaches `max_steps`) is
@@ -75,27 +77,34 @@ def pick_tile_shape(nx, ny, costs):
     return min(range(len(costs)), key=lambda s: tile_count(nx, ny, s) * costs[s])
 
 
-def request_params(req, seg_rows=0):
-    """Lattice parameters and initial density of one request."""
+def lattice_params(req, seg_rows=0):
+    """Lattice parameters of one request."""
     common = dict(nx=req.nx, ny=req.ny, storage=lbm.STORE_F32, wall_kind=lbm.WALL_FLAT_SLAB, G=req.G,
                   G_R=req.G_R, G_A=req.G_A, eps=req.eps, seg_rows=seg_rows)
     if req.kind == "angle":
-        p = lbm.lbm_params_default(**common)
+        return lbm.lbm_params_default(**common)
+    return lbm.lbm_params_default(F_ext=(CHANNEL_FORCE, 0.0), **common)
+
+
+def request_params(req, seg_rows=0):
+    """Lattice parameters and initial density of one request."""
+    if req.kind == "angle":
         rho0 = I.drop_field(req.nx, req.ny, 0.3 * min(req.nx, req.ny))
     else:
-        p = lbm.lbm_params_default(F_ext=(CHANNEL_FORCE, 0.0), **common)
         rho0 = I.uniform_field(req.nx, req.ny, CHANNEL_RHO)
-    return p, rho0
+    return lattice_params(req, seg_rows), rho0
 
 
 class Server:
     def __init__(self, budget_bytes=96 << 30, max_resident=64, diag_every=100, max_steps=20000, tol=1e-8,
-                 batched=True, device="cuda:0", seg_rows=0, on_admit=None, tile_costs="calibrate"):
+                 batched=True, device="cuda:0", seg_rows=0, on_admit=None, tile_costs="calibrate",
+                 max_nodes=16 << 20):
         import torch
         if diag_every % 2:
             raise ValueError("diag_every must be even (graph replays keep the buffer parity)")
         self.budget = int(budget_bytes)
         self.max_resident = int(max_resident)
+        self.max_nodes = int(max_nodes)
         self.K = int(diag_every)
         self.max_steps = int(max_steps)
         self.tol = float(tol)
@@ -103,6 +112,7 @@ class Server:
         self.device = device
         self.seg_rows = seg_rows
         self.on_admit = on_admit          # called as on_admit(request, lattice) after creation
+        self._footprints = {}
         self.max_seen_resident = 0
         self.max_seen_used = 0            # largest sum of resident footprints (bytes)
         # per-tile cost of every tile shape: measured, given, or None (shape 0)
@@ -111,8 +121,10 @@ class Server:
         self.stream = torch.cuda.Stream(device)
 
     def footprint(self, req):
-        p, _ = request_params(req, self.seg_rows)
-        return lbm.lbm_workspace_bytes(p)
+        fp = self._footprints.get(req.rid)
+        if fp is None:
+            fp = self._footprints[req.rid] = lbm.lbm_workspace_bytes(lattice_params(req, self.seg_rows))
+        return fp
 
     def _measure(self, req, lat):
         if req.kind == "angle":
@@ -128,6 +140,7 @@ class Server:
         waiting = collections.deque()
         resident = []            # [(req, Lattice, footprint)]
         used = 0
+        nodes = 0
         batch = None
         t0 = time.perf_counter()
 
@@ -154,6 +167,8 @@ class Server:
                     continue
                 if used + fp > self.budget:
                     break
+                if resident and nodes + req.nx * req.ny > self.max_nodes:
+                    break
                 waiting.popleft()
                 p, rho0 = request_params(req, self.seg_rows)
                 lat = lbm.Lattice(p, rho0, device=self.device, stream=self.stream)
@@ -164,6 +179,7 @@ class Server:
                 resident.append((req, lat, fp))
                 self.max_seen_resident = max(self.max_seen_resident, len(resident))
                 used += fp
+                nodes += req.nx * req.ny
                 self.max_seen_used = max(self.max_seen_used, used)
                 results[req.rid].admitted = clock()
                 changed = True
@@ -212,6 +228,7 @@ class Server:
                     results[req.rid].finished = now
                     lat.close()
                     used -= fp
+                    nodes -= req.nx * req.ny
         if batch is not None:
             batch.close()
         self.elapsed = clock()
