@@ -99,8 +99,8 @@ def time_gpu(name, storage, steps, warmup, seg_rows, tile=None):
     tune_ms = None
     if tile is None:
         from paper_1202_6130_amd import lbm
-        # (tune_steps + 1) trial steps per shape, within the warm-up when it is long enough
-        tune_steps = max(2, warmup // len(lbm.lbm_tile_shapes()) - 1)
+        # 3 * tune_steps + 1 trial steps per shape, within the warm-up when it is long enough
+        tune_steps = max(2, (warmup // len(lbm.lbm_tile_shapes()) - 1) // 3)
         shape, tune_ms = L.tune(tune_steps)
         tune_ms = [round(float(v), 5) for v in tune_ms]
     else:
@@ -389,7 +389,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="spinodal4096",
                     choices=sorted(WORKLOADS) + ["ensemble256", "serve", "precision4096", "wetting1024"])
     ap.add_argument("--tile", type=int, default=None, help="tile shape index (default: autotuned in the warm-up)")

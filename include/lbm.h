@@ -201,11 +201,12 @@ int32_t lbm_tile_shapes(int32_t *waves, int32_t *rows, int32_t *strips, int32_t 
 lbm_status lbm_set_tile_shape(lbm_ctx *c, int32_t shape);
 int32_t lbm_get_tile_shape(const lbm_ctx *c);
 
-/* Autotuner for one lattice: runs steps+1 ordinary time steps with every
- * shape (the first untimed), times each step with events, and keeps the shape
- * of smallest median step time.  shape_out (nullable) gets the choice,
- * ms_out (nullable, one entry per shape) the medians.  The lattice advances
- * by (steps + 1) * lbm_tile_shapes(...) steps.  Synchronises. */
+/* Autotuner for one lattice: for every shape runs one untimed step, then
+ * three timed blocks of `steps` consecutive ordinary time steps (events
+ * around each block), and keeps the shape of smallest median per-step time.
+ * shape_out (nullable) gets the choice, ms_out (nullable, one entry per
+ * shape) the medians.  The lattice advances by (3 steps + 1) *
+ * lbm_tile_shapes(...) steps.  Synchronises. */
 lbm_status lbm_tune(lbm_ctx *c, int32_t steps, int32_t *shape_out, double *ms_out);
 
 /* ------------------------------------------------------------------------
@@ -267,8 +268,9 @@ lbm_status lbm_batch_attach(lbm_ctx *const *ctxs, int32_t n, void *workspace,
 lbm_status lbm_batch_set_tile_shapes(lbm_batch *b, const int32_t *shapes);
 lbm_status lbm_batch_get_tile_shapes(const lbm_batch *b, int32_t *shapes);
 
-/* Autotuner for a batch.  Times every shape on the whole batch (median of
- * `steps` single steps after one untimed step), derives a per-tile cost for
+/* Autotuner for a batch.  Times every shape on the whole batch (median over
+ * three blocks of `steps` consecutive steps, after one untimed step; each
+ * candidate advances the batch by 3 steps + 1), derives a per-tile cost for
  * each shape, gives every lattice the shape of least predicted cost (its tile
  * count times that cost), times that mixed assignment too when it is not
  * uniform, and keeps the fastest candidate.  shapes_out (nullable, n entries)

@@ -995,8 +995,11 @@ int32_t lbm_get_tile_shape(const lbm_ctx *c) { return c ? c->shape : -1; }
 
 namespace {
 
-// Median duration (ms) of `steps` single steps issued by `one`, each bracketed
-// by events and waited for.
+// Per-step time (ms): the median over kTuneReps blocks of `steps` consecutive
+// steps issued by `one`, each block bracketed by events and waited for.  Steps
+// run back to back as in production (a wait after every single step would
+// time each step from an idle GPU and favour other shapes).
+constexpr int kTuneReps = 3;
 template <class Fn> lbm_status time_steps(hipStream_t st, int32_t steps, Fn &&one, double *median_ms) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(hipEventCreate(&e0));
@@ -1007,15 +1010,15 @@ template <class Fn> lbm_status time_steps(hipStream_t st, int32_t steps, Fn &&on
     }
     std::vector<double> t;
     lbm_status stt = LBM_OK;
-    for (int32_t i = 0; i < steps && stt == LBM_OK; ++i) {
+    for (int rep = 0; rep < kTuneReps && stt == LBM_OK; ++rep) {
         he = hipEventRecord(e0, st);
-        if (he == hipSuccess) stt = one();
+        for (int32_t i = 0; i < steps && stt == LBM_OK && he == hipSuccess; ++i) stt = one();
         if (stt == LBM_OK && he == hipSuccess) he = hipEventRecord(e1, st);
         if (stt == LBM_OK && he == hipSuccess) he = hipEventSynchronize(e1);
         float ms = 0;
         if (stt == LBM_OK && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
         if (he != hipSuccess && stt == LBM_OK) stt = fail(LBM_EDEVICE, "timing events: %s", hipGetErrorString(he));
-        t.push_back(ms);
+        t.push_back(ms / steps);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -61,7 +61,7 @@ def test_tune_single_is_plain_stepping():
     assert 0 <= shape < len(SHAPES) and L.tile_shape == shape
     assert np.all(np.isfinite(ms)) and np.all(ms > 0) and ms[shape] == ms.min()
     n = L.step_index
-    assert n == 5 * len(SHAPES)
+    assert n == (3 * 4 + 1) * len(SHAPES)
     ref = lbm.Lattice(p, rho0)
     ref.step(n)
     assert np.array_equal(L.get_state(), ref.get_state())
@@ -112,7 +112,7 @@ def test_batch_tune_is_plain_stepping():
     assert len(shapes) == len(ps) and all(0 <= s < nshape for s in shapes)
     assert list(B.tile_shapes) == list(shapes)
     assert np.all(np.isfinite(ms[:nshape]))
-    tuned_steps = (nshape + (0 if np.isnan(ms[nshape]) else 1)) * 4
+    tuned_steps = (nshape + (0 if np.isnan(ms[nshape]) else 1)) * (3 * 3 + 1)
     B.step(10, chunk=10)
     for k, (p, rho) in enumerate(zip(ps, rhos)):
         assert np.array_equal(B.lattice(k).get_state(), _alone(p, rho, tuned_steps + 10)), k
