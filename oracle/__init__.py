@@ -25,7 +25,14 @@ class Params(ctypes.Structure):
                 ("tau", ctypes.c_double), ("G", ctypes.c_double),
                 ("G_R", ctypes.c_double), ("G_A", ctypes.c_double),
                 ("eps", ctypes.c_double),
-                ("U_wall", ctypes.c_double * 2), ("F_ext", ctypes.c_double * 2)]
+                ("U_wall", ctypes.c_double * 2), ("F_ext", ctypes.c_double * 2),
+                ("lattice", ctypes.c_int), ("psi_kind", ctypes.c_int),
+                ("eos", ctypes.c_double * 5)]
+
+
+# eq. EOS parameters of the paper: theta_V/theta, theta_U/theta, theta_L/theta,
+# rho_1, rho_2 (Sec. II.B)
+EOS_PAPER = (0.25, -0.25, 1.0, 0.222, 0.869)
 
 
 _lib = None
@@ -52,6 +59,12 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         P = ctypes.POINTER(Params)
         L.orc_equilibrium.argtypes = [ctypes.c_double] * 3 + [dp]
+        L.orc_equilibrium_q.argtypes = [ctypes.c_int] + [ctypes.c_double] * 3 + [dp]
+        L.orc_psi.argtypes = [P, ctypes.c_double]
+        L.orc_psi.restype = ctypes.c_double
+        L.orc_p_eos.argtypes = [P, ctypes.c_double]
+        L.orc_p_eos.restype = ctypes.c_double
+        L.orc_stream_q.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
         L.orc_flat_slab_walls.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                           ctypes.c_double, ctypes.c_double,
                                           ctypes.c_double, dp, dp, dp]
@@ -89,13 +102,41 @@ def _p(a):
 
 
 def make_params(nx, ny, tau=1.0, G=-5.0, G_R=0.0, G_A=0.0, eps=1.0,
-                U_wall=(0.0, 0.0), F_ext=(0.0, 0.0)):
+                U_wall=(0.0, 0.0), F_ext=(0.0, 0.0), lattice=9, psi_kind=0, eos=EOS_PAPER):
     p = Params()
     p.nx, p.ny = int(nx), int(ny)
     p.tau, p.G, p.G_R, p.G_A, p.eps = tau, G, G_R, G_A, eps
     p.U_wall[0], p.U_wall[1] = U_wall
     p.F_ext[0], p.F_ext[1] = F_ext
+    p.lattice, p.psi_kind = int(lattice), int(psi_kind)
+    for k, v in enumerate(eos):
+        p.eos[k] = v
     return p
+
+
+def nq(p):
+    """Populations per node of the parameters' lattice."""
+    return 21 if p.lattice == 21 else 9
+
+
+def lattice_tables(lattice=9):
+    """(cx, cy, w, theta) of the oracle's velocity set."""
+    L = lib()
+    q = 21 if lattice == 21 else 9
+    pre = "ORC21_" if q == 21 else "ORC_"
+    cx = np.array((ctypes.c_int * q).in_dll(L, pre + "CX")[:])
+    cy = np.array((ctypes.c_int * q).in_dll(L, pre + "CY")[:])
+    w = np.array((ctypes.c_double * q).in_dll(L, pre + "W")[:])
+    th = ctypes.c_double.in_dll(L, pre + "THETA").value
+    return cx, cy, w, th
+
+
+def psi(p, rho):
+    return lib().orc_psi(ctypes.byref(p), float(rho))
+
+
+def p_eos(p, rho):
+    return lib().orc_p_eos(ctypes.byref(p), float(rho))
 
 
 class Walls:
@@ -118,14 +159,14 @@ class Walls:
         return Walls(phi, psiR, psiA)
 
 
-def equilibrium(rho, ux, uy):
-    out = np.zeros(9)
-    lib().orc_equilibrium(rho, ux, uy, _p(out))
+def equilibrium(rho, ux, uy, lattice=9):
+    out = np.zeros(21 if lattice == 21 else 9)
+    lib().orc_equilibrium_q(lattice, rho, ux, uy, _p(out))
     return out
 
 
 def init(p, rho0, ux0=None, uy0=None):
-    f = np.zeros((p.ny, p.nx, 9))
+    f = np.zeros((p.ny, p.nx, nq(p)))
     rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
     ux0 = None if ux0 is None else np.ascontiguousarray(ux0, dtype=np.float64)
     uy0 = None if uy0 is None else np.ascontiguousarray(uy0, dtype=np.float64)
@@ -152,9 +193,9 @@ def collide(p, walls, f):
     return g
 
 
-def stream(nx, ny, fpost):
+def stream(nx, ny, fpost, lattice=9):
     g = np.zeros_like(fpost)
-    lib().orc_stream(nx, ny, _p(np.ascontiguousarray(fpost)), _p(g))
+    lib().orc_stream_q(lattice, nx, ny, _p(np.ascontiguousarray(fpost)), _p(g))
     return g
 
 

@@ -16,6 +16,11 @@
  *   - collision              : BGK (eq. BE-BGK) with feq from eq. f2
  *   - streaming              : f_i(x + c_i, t+1) = f'_i(x, t)  (Sec. II.A)
  *
+ * The paper's own model (Sec. II.A-B) uses the D2Q21 lattice of Tab. I and
+ * the equation-of-state pseudo-potential of eq. EOS with an attractive
+ * fluid-fluid force (G = -1 in the notation above); both are selected by the
+ * parameters, every loop runs over the chosen velocity set.
+ *
  * The per-node loops carry OpenMP annotations.  The default build ignores
  * them (one thread); a second build with -fopenmp serves long reference runs
  * only.  Each node's arithmetic and every sum keep their order, so both
@@ -34,6 +39,35 @@ const double ORC_W[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,
                          1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 const double ORC_THETA = 1.0 / 3.0;
 
+/* Tab. I: D2Q21 abscissas and Gauss-Hermite weights (rest state first). */
+const int ORC21_CX[21] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 2, 0, -2, 0, 2, -2, -2, 2, 3, 0, -3, 0};
+const int ORC21_CY[21] = {0, 0, 1, 0, -1, 1, 1, -1, -1, 0, 2, 0, -2, 2, 2, -2, -2, 0, 3, 0, -3};
+const double ORC21_W[21] = {91.0 / 324.0,
+                            1.0 / 12.0, 1.0 / 12.0, 1.0 / 12.0, 1.0 / 12.0,
+                            2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0,
+                            7.0 / 360.0, 7.0 / 360.0, 7.0 / 360.0, 7.0 / 360.0,
+                            1.0 / 432.0, 1.0 / 432.0, 1.0 / 432.0, 1.0 / 432.0,
+                            1.0 / 1620.0, 1.0 / 1620.0, 1.0 / 1620.0, 1.0 / 1620.0};
+const double ORC21_THETA = 2.0 / 3.0;
+
+typedef struct {
+    int Q;
+    const int *cx, *cy;
+    const double *w;
+    double theta;
+} orc_lattice;
+
+static orc_lattice lattice_of(int lattice)
+{
+    orc_lattice L;
+    if (lattice == 21) {
+        L.Q = 21; L.cx = ORC21_CX; L.cy = ORC21_CY; L.w = ORC21_W; L.theta = ORC21_THETA;
+    } else {
+        L.Q = 9; L.cx = ORC_CX; L.cy = ORC_CY; L.w = ORC_W; L.theta = ORC_THETA;
+    }
+    return L;
+}
+
 static long node(int nx, int ny, int x, int y)
 {
     /* periodic wrap in both directions */
@@ -44,17 +78,23 @@ static long node(int nx, int ny, int x, int y)
 
 /* Eq. f2 at equilibrium: f_i = w_i [M0 + M1.c/theta + (M2 - M0 theta I):(cc - theta I)/(2 theta^2)]
  * with M0 = rho, M1 = rho u, M2 = rho u u + rho theta I (eqs. M0-M2, feqc). */
-void orc_equilibrium(double rho, double ux, double uy, double feq[9])
+void orc_equilibrium_q(int lattice, double rho, double ux, double uy, double *feq)
 {
-    const double th = ORC_THETA;
-    for (int i = 0; i < 9; ++i) {
-        double cx = ORC_CX[i], cy = ORC_CY[i];
+    const orc_lattice L = lattice_of(lattice);
+    const double th = L.theta;
+    for (int i = 0; i < L.Q; ++i) {
+        double cx = L.cx[i], cy = L.cy[i];
         double M1c = rho * (ux * cx + uy * cy);
         /* (M2 - rho theta I) : (c c - theta I) with M2 - rho theta I = rho u u */
         double uucc = rho * (ux * ux * (cx * cx - th) + 2.0 * ux * uy * cx * cy +
                              uy * uy * (cy * cy - th));
-        feq[i] = ORC_W[i] * (rho + M1c / th + uucc / (2.0 * th * th));
+        feq[i] = L.w[i] * (rho + M1c / th + uucc / (2.0 * th * th));
     }
+}
+
+void orc_equilibrium(double rho, double ux, double uy, double feq[9])
+{
+    orc_equilibrium_q(9, rho, ux, uy, feq);
 }
 
 /* T(s; w) = (1 - tanh(s/w))/2: 1 deep in the solid, 1/2 on the face, 0 in the
@@ -92,30 +132,58 @@ void orc_flat_slab_walls(int nx, int ny, int P, double width, double core,
 void orc_init(const orc_params *p, const double *rho0, const double *ux0,
               const double *uy0, double *f)
 {
+    const int Q = lattice_of(p->lattice).Q;
     long N = (long)p->nx * p->ny;
     for (long n = 0; n < N; ++n) {
         double ux = ux0 ? ux0[n] : 0.0;
         double uy = uy0 ? uy0[n] : 0.0;
-        orc_equilibrium(rho0[n], ux, uy, &f[n * 9]);
+        orc_equilibrium_q(p->lattice, rho0[n], ux, uy, &f[n * Q]);
     }
 }
 
 /* Eqs. M0 and M1: zeroth and first moments of the populations. */
-static void moments(const double *fn, double *rho, double *jx, double *jy)
+static void moments(const orc_lattice *L, const double *fn, double *rho, double *jx, double *jy)
 {
     double r = 0.0, a = 0.0, b = 0.0;
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 0; i < L->Q; ++i) {
         r += fn[i];
-        a += fn[i] * ORC_CX[i];
-        b += fn[i] * ORC_CY[i];
+        a += fn[i] * L->cx[i];
+        b += fn[i] * L->cy[i];
     }
     *rho = r;
     *jx = a;
     *jy = b;
 }
 
-/* Shan-Chen pseudo-potential psi(rho) = 1 - exp(-rho). */
-static double psi_of(double rho) { return 1.0 - exp(-rho); }
+/* Eq. EOS: vapour, unstable and liquid branches of slopes theta_V, theta_U,
+ * theta_L, joined continuously at rho_1 and rho_2. */
+double orc_p_eos(const orc_params *p, double rho)
+{
+    const double th = lattice_of(p->lattice).theta;
+    const double tV = p->eos[0] * th, tU = p->eos[1] * th, tL = p->eos[2] * th;
+    const double r1 = p->eos[3], r2 = p->eos[4];
+    const double p1 = r1 * tV, p2 = p1 + (r2 - r1) * tU;
+    if (rho <= r1) return rho * tV;
+    if (rho <= r2) return p1 + (rho - r1) * tU;
+    return p2 + (rho - r2) * tL;
+}
+
+/* Pseudo-potential of eq. force_SC.  psi_kind 0: 1 - exp(-rho).  psi_kind 1:
+ * the EOS pseudo-potential.  A Taylor expansion of eq. force_SC gives
+ * sum_i w_i psi(x + r_i) r_i = theta grad psi + ..., so an attractive force
+ * (G = -1) adds -theta psi^2 / 2 to the ideal pressure rho theta; the bulk
+ * pressure equals p_EOS when psi^2 = 2 (rho theta - p_EOS) / theta.  The
+ * printed form lacks the 1/theta; this reading restores the stated
+ * coexistence (checked against the mechanical-stability integral). */
+double orc_psi(const orc_params *p, double rho)
+{
+    if (p->psi_kind == 1) {
+        const double th = lattice_of(p->lattice).theta;
+        double a = 2.0 * (rho * th - orc_p_eos(p, rho)) / th;
+        return sqrt(a > 0.0 ? a : 0.0);
+    }
+    return 1.0 - exp(-rho);
+}
 
 void orc_forces(const orc_params *p, const double *phi, const double *psiR,
                 const double *psiA, const double *f, double *rho_o, double *ux_o,
@@ -124,6 +192,8 @@ void orc_forces(const orc_params *p, const double *phi, const double *psiR,
 {
     const int nx = p->nx, ny = p->ny;
     const long N = (long)nx * ny;
+    const orc_lattice L = lattice_of(p->lattice);
+    const int Q = L.Q;
     double *rho = (double *)malloc(sizeof(double) * N);
     double *psi = (double *)malloc(sizeof(double) * N);
     double *psiFS = (double *)malloc(sizeof(double) * N);
@@ -132,8 +202,8 @@ void orc_forces(const orc_params *p, const double *phi, const double *psiR,
 #pragma omp parallel for schedule(static)
     for (long n = 0; n < N; ++n) {
         double jx, jy;
-        moments(&f[n * 9], &rho[n], &jx, &jy);
-        psi[n] = psi_of(rho[n]);
+        moments(&L, &f[n * Q], &rho[n], &jx, &jy);
+        psi[n] = orc_psi(p, rho[n]);
         /* eq. pseudopotential, with the repulsive core entering with the
          * opposite sign of the attractive tail */
         psiFS[n] = p->G_A * psiA[n] - p->G_R * psiR[n];
@@ -144,19 +214,19 @@ void orc_forces(const orc_params *p, const double *phi, const double *psiR,
         for (int x = 0; x < nx; ++x) {
             long n = (long)y * nx + x;
             double r, jx, jy;
-            moments(&f[n * 9], &r, &jx, &jy);
+            moments(&L, &f[n * Q], &r, &jx, &jy);
             double ux = jx / r, uy = jy / r;
 
             /* eq. force_SC: fluid-fluid force from neighbour pseudo-potentials */
             double sffx = 0.0, sffy = 0.0;
             /* eq. force_SC_FS, first term: long-range fluid-solid force */
             double sfsx = 0.0, sfsy = 0.0;
-            for (int i = 0; i < 9; ++i) {
-                long m = node(nx, ny, x + ORC_CX[i], y + ORC_CY[i]);
-                sffx += ORC_W[i] * psi[m] * ORC_CX[i];
-                sffy += ORC_W[i] * psi[m] * ORC_CY[i];
-                sfsx += ORC_W[i] * psiFS[m] * ORC_CX[i];
-                sfsy += ORC_W[i] * psiFS[m] * ORC_CY[i];
+            for (int i = 0; i < Q; ++i) {
+                long m = node(nx, ny, x + L.cx[i], y + L.cy[i]);
+                sffx += L.w[i] * psi[m] * L.cx[i];
+                sffy += L.w[i] * psi[m] * L.cy[i];
+                sfsx += L.w[i] * psiFS[m] * L.cx[i];
+                sfsy += L.w[i] * psiFS[m] * L.cy[i];
             }
             double ffx = -p->G * psi[n] * sffx;
             double ffy = -p->G * psi[n] * sffy;
@@ -192,6 +262,7 @@ void orc_collide(const orc_params *p, const double *phi, const double *psiR,
                  const double *psiA, const double *f, double *fpost)
 {
     const long N = (long)p->nx * p->ny;
+    const int Q = lattice_of(p->lattice).Q;
     double *rho = (double *)malloc(sizeof(double) * N);
     double *ux = (double *)malloc(sizeof(double) * N);
     double *uy = (double *)malloc(sizeof(double) * N);
@@ -200,13 +271,13 @@ void orc_collide(const orc_params *p, const double *phi, const double *psiR,
     orc_forces(p, phi, psiR, psiA, f, rho, ux, uy, NULL, NULL, NULL, NULL, usx, usy);
 #pragma omp parallel for schedule(static)
     for (long n = 0; n < N; ++n) {
-        double feq_u[9], feq_s[9];
-        orc_equilibrium(rho[n], ux[n], uy[n], feq_u);
-        orc_equilibrium(rho[n], usx[n], usy[n], feq_s);
-        for (int i = 0; i < 9; ++i) {
-            double fi = f[n * 9 + i];
+        double feq_u[21], feq_s[21];
+        orc_equilibrium_q(p->lattice, rho[n], ux[n], uy[n], feq_u);
+        orc_equilibrium_q(p->lattice, rho[n], usx[n], usy[n], feq_s);
+        for (int i = 0; i < Q; ++i) {
+            double fi = f[n * Q + i];
             /* BGK relaxation (eq. BE-BGK) plus the EDM force term */
-            fpost[n * 9 + i] = fi - (fi - feq_u[i]) / p->tau + (feq_s[i] - feq_u[i]);
+            fpost[n * Q + i] = fi - (fi - feq_u[i]) / p->tau + (feq_s[i] - feq_u[i]);
         }
     }
     free(rho);
@@ -216,25 +287,33 @@ void orc_collide(const orc_params *p, const double *phi, const double *psiR,
     free(usy);
 }
 
-void orc_stream(int nx, int ny, const double *fpost, double *fout)
+void orc_stream_q(int lattice, int nx, int ny, const double *fpost, double *fout)
 {
+    const orc_lattice L = lattice_of(lattice);
+    const int Q = L.Q;
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x)
-            for (int i = 0; i < 9; ++i) {
+            for (int i = 0; i < Q; ++i) {
                 long src = (long)y * nx + x;
-                long dst = node(nx, ny, x + ORC_CX[i], y + ORC_CY[i]);
-                fout[dst * 9 + i] = fpost[src * 9 + i];
+                long dst = node(nx, ny, x + L.cx[i], y + L.cy[i]);
+                fout[dst * Q + i] = fpost[src * Q + i];
             }
+}
+
+void orc_stream(int nx, int ny, const double *fpost, double *fout)
+{
+    orc_stream_q(9, nx, ny, fpost, fout);
 }
 
 void orc_step(const orc_params *p, const double *phi, const double *psiR,
               const double *psiA, const double *f_in, double *f_out)
 {
     const long N = (long)p->nx * p->ny;
-    double *fpost = (double *)malloc(sizeof(double) * N * 9);
+    const int Q = lattice_of(p->lattice).Q;
+    double *fpost = (double *)malloc(sizeof(double) * N * Q);
     orc_collide(p, phi, psiR, psiA, f_in, fpost);
-    orc_stream(p->nx, p->ny, fpost, f_out);
+    orc_stream_q(p->lattice, p->nx, p->ny, fpost, f_out);
     free(fpost);
 }
 
@@ -242,11 +321,12 @@ int orc_run(const orc_params *p, const double *phi, const double *psiR,
             const double *psiA, double *f, long nsteps)
 {
     const long N = (long)p->nx * p->ny;
-    double *g = (double *)malloc(sizeof(double) * N * 9);
+    const int Q = lattice_of(p->lattice).Q;
+    double *g = (double *)malloc(sizeof(double) * N * Q);
     if (!g) return -1;
     for (long s = 0; s < nsteps; ++s) {
         orc_step(p, phi, psiR, psiA, f, g);
-        memcpy(f, g, sizeof(double) * N * 9);
+        memcpy(f, g, sizeof(double) * N * Q);
     }
     free(g);
     return 0;

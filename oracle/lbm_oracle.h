@@ -9,12 +9,20 @@
  * test-suite, the smoke check and the benchmark's CPU-baseline leg do.  It
  * shares no code, header, table or constant with the HIP library.
  *
- * State convention: f[(y*nx + x)*9 + i] holds the populations at time t after
- * streaming (i.e. just before the collision of step t).  Velocity set D2Q9:
- *   i : 0      1      2      3       4       5      6       7        8
- *   c : (0,0) (1,0)  (0,1)  (-1,0)  (0,-1)  (1,1)  (-1,1)  (-1,-1)  (1,-1)
- *   w : 4/9   1/9 x4                        1/36 x4
- * Lattice temperature theta = sum_i w_i c_ix^2 = 1/3.  Fully periodic nx*ny.
+ * State convention: f[(y*nx + x)*Q + i] holds the populations at time t after
+ * streaming (i.e. just before the collision of step t).  Velocity sets
+ * (Sec. II.A):
+ *   D2Q9  (Q = 9):
+ *     i : 0      1      2      3       4       5      6       7        8
+ *     c : (0,0) (1,0)  (0,1)  (-1,0)  (0,-1)  (1,1)  (-1,1)  (-1,-1)  (1,-1)
+ *     w : 4/9   1/9 x4                        1/36 x4
+ *     theta = sum_i w_i c_ix^2 = 1/3
+ *   D2Q21 (Q = 21, Tab. I), indices 0..8 as D2Q9, then
+ *     9..12 (2,0) (0,2) (-2,0) (0,-2); 13..16 (2,2) (-2,2) (-2,-2) (2,-2);
+ *     17..20 (3,0) (0,3) (-3,0) (0,-3);
+ *     w : 91/324 (rest), 1/12 (|c|=1 axes), 2/27 ((+-1,+-1)), 7/360 (|c|=2
+ *     axes), 1/432 ((+-2,+-2)), 1/1620 (|c|=3 axes); theta = 2/3
+ * Fully periodic nx*ny.
  */
 #ifndef LBM_ORACLE_H
 #define LBM_ORACLE_H
@@ -31,6 +39,10 @@ typedef struct {
     double eps;        /* wall-probability exponent, >= 1 (eq. wall_shift)   */
     double U_wall[2];  /* wall velocity (eq. wall_shift)                     */
     double F_ext[2];   /* uniform external force density (Sec. III.A)        */
+    int lattice;       /* 9 (D2Q9) or 21 (D2Q21, Tab. I); 0 reads as 9       */
+    int psi_kind;      /* 0: psi = 1 - exp(-rho); 1: EOS, eq. EOS            */
+    double eos[5];     /* EOS: theta_V/theta, theta_U/theta, theta_L/theta,
+                          rho_1, rho_2 (eq. EOS)                              */
 } orc_params;
 
 /* D2Q9 tables (the oracle's own copy). */
@@ -39,8 +51,27 @@ extern const int    ORC_CY[9];
 extern const double ORC_W[9];
 extern const double ORC_THETA;
 
-/* Equilibrium of eq. f2 with M2 = rho u u + rho theta I. */
+/* D2Q21 tables (Tab. I). */
+extern const int    ORC21_CX[21];
+extern const int    ORC21_CY[21];
+extern const double ORC21_W[21];
+extern const double ORC21_THETA;
+
+/* Equilibrium of eq. f2 with M2 = rho u u + rho theta I (D2Q9). */
 void orc_equilibrium(double rho, double ux, double uy, double feq[9]);
+
+/* The same for a lattice (9 or 21); feq holds Q values. */
+void orc_equilibrium_q(int lattice, double rho, double ux, double uy, double *feq);
+
+/* Pseudo-potential of the fluid-fluid force at density rho:
+ *   psi_kind 0: 1 - exp(-rho);
+ *   psi_kind 1: sqrt(2 (rho theta - p_EOS(rho)) / theta) with the
+ *   piecewise-linear p_EOS of eq. EOS (see the reading of the 1/theta factor
+ *   in the source). */
+double orc_psi(const orc_params *p, double rho);
+
+/* Piecewise-linear equation of state p_EOS(rho) (eq. EOS). */
+double orc_p_eos(const orc_params *p, double rho);
 
 /* Flat-slab wall functions (Appendix A allows analytic profiles for flat
  * walls).  Solid band = rows [ny-P, ny); faces on rows 0 and ny-P.
@@ -66,8 +97,11 @@ void orc_forces(const orc_params *p, const double *phi, const double *psiR,
 void orc_collide(const orc_params *p, const double *phi, const double *psiR,
                  const double *psiA, const double *f, double *fpost);
 
-/* Streaming: fout_i(x + c_i) = fpost_i(x), periodic. */
+/* Streaming: fout_i(x + c_i) = fpost_i(x), periodic (D2Q9). */
 void orc_stream(int nx, int ny, const double *fpost, double *fout);
+
+/* The same for a lattice (9 or 21). */
+void orc_stream_q(int lattice, int nx, int ny, const double *fpost, double *fout);
 
 /* One full step (collide, then stream). f_in and f_out must differ. */
 void orc_step(const orc_params *p, const double *phi, const double *psiR,

@@ -1,0 +1,196 @@
+"""Pins of the oracle's D2Q21 lattice (Tab. I) and equation-of-state
+pseudo-potential (eq. EOS), the paper's own model (Sec. II.A-B).
+
+Each test names the mistake it would expose.  The lattice is pinned by its
+quadrature properties (the paper states seventh-order precision and moment
+isotropy to sixth order), the collision by conservation and by the viscous
+decay of a shear wave (nu = theta (tau - 1/2) with theta = 2/3), the EOS
+pseudo-potential by the phase equilibrium the paper states (rho_V = 0.1,
+rho_L = 1.0 from the continuum calculation) and by the failure of the
+literal printed form to separate phases at all.
+"""
+import numpy as np
+import pytest
+from scipy import integrate, optimize
+
+from paper_1202_6130_amd import inputs as I
+
+
+def test_d2q21_quadrature(orc):
+    """Tab. I: sum w = 1, theta = 2/3 per component (the table's footnote), and
+    Gauss-Hermite moments to sixth order.  Catches a wrong weight, a missing
+    or doubled velocity (the table prints (+-2,0) twice)."""
+    cx, cy, w, th = orc.lattice_tables(21)
+    assert len(w) == 21 and abs(th - 2.0 / 3.0) < 1e-16
+    assert len({(a, b) for a, b in zip(cx, cy)}) == 21
+    assert abs(w.sum() - 1.0) < 1e-15
+    m = lambda a, b: (w * cx.astype(float) ** a * cy.astype(float) ** b).sum()
+    for a, b in [(1, 0), (0, 1), (3, 0), (1, 2), (5, 0), (3, 2), (1, 1), (3, 1), (1, 3)]:
+        assert abs(m(a, b)) < 1e-14
+    assert abs(m(2, 0) - th) < 1e-15 and abs(m(0, 2) - th) < 1e-15
+    assert abs(m(4, 0) - 3 * th ** 2) < 1e-14 and abs(m(2, 2) - th ** 2) < 1e-14
+    assert abs(m(6, 0) - 15 * th ** 3) < 1e-13 and abs(m(4, 2) - 3 * th ** 3) < 1e-13
+    assert abs(m(2, 4) - 3 * th ** 3) < 1e-13
+
+
+def test_d2q21_equilibrium_moments(orc):
+    """Eqs. M0-M2 with eq. f2 on D2Q21.  Catches theta = 1/3 left over from
+    D2Q9 or a dropped u^2 term."""
+    cx, cy, w, th = orc.lattice_tables(21)
+    rng = np.random.Generator(np.random.PCG64(3))
+    for _ in range(30):
+        rho = rng.uniform(0.05, 2.0)
+        ux, uy = rng.uniform(-0.2, 0.2, 2)
+        f = orc.equilibrium(rho, ux, uy, lattice=21)
+        assert abs(f.sum() - rho) < 1e-14 * rho
+        assert abs((f * cx).sum() - rho * ux) < 1e-15 and abs((f * cy).sum() - rho * uy) < 1e-15
+        assert abs((f * cx * cx).sum() - rho * (ux * ux + th)) < 1e-14
+        assert abs((f * cx * cy).sum() - rho * ux * uy) < 1e-14
+        assert abs((f * cy * cy).sum() - rho * (uy * uy + th)) < 1e-14
+
+
+def test_d2q21_collision_conserves(orc):
+    """Sec. II.B: the collision conserves mass and adds exactly the force to
+    the momentum, on D2Q21 with the EOS fluid and random wall fields."""
+    nx, ny = 12, 10
+    p = orc.make_params(nx, ny, tau=0.8, G=-1.0, G_R=0.4, G_A=0.2, eps=1.3, F_ext=(1e-3, -2e-3),
+                        lattice=21, psi_kind=1)
+    rng = np.random.Generator(np.random.PCG64(5))
+    walls = orc.Walls(rng.uniform(0, 1, (ny, nx)), rng.uniform(0, 1, (ny, nx)), rng.uniform(0, 0.4, (ny, nx)))
+    rho, ux, uy = I.random_state_field(nx, ny, 7, lo=0.08, hi=1.1)
+    f = orc.init(p, rho, ux, uy) * (1 + 0.05 * rng.uniform(-1, 1, (ny, nx, 21)))
+    cx, cy, w, th = orc.lattice_tables(21)
+    fo = orc.forces(p, walls, f)
+    g = orc.collide(p, walls, f)
+    assert np.abs(g.sum(-1) - f.sum(-1)).max() < 1e-14
+    jx0, jy0 = (f * cx).sum(-1), (f * cy).sum(-1)
+    assert np.abs((g * cx).sum(-1) - jx0 - fo["F"][..., 0]).max() < 1e-14
+    assert np.abs((g * cy).sum(-1) - jy0 - fo["F"][..., 1]).max() < 1e-14
+
+
+def test_d2q21_shear_wave_viscosity(orc):
+    """A decaying shear wave u_x = A sin(k y) on D2Q21 with no interaction
+    forces decays as exp(-nu k^2 t) with nu = theta (tau - 1/2), theta = 2/3.
+    Catches a lattice temperature or a relaxation taken from D2Q9."""
+    nx, ny, tau = 4, 64, 0.8
+    p = orc.make_params(nx, ny, tau=tau, G=0.0, lattice=21)
+    k = 2 * np.pi / ny
+    y = np.arange(ny)
+    ux0 = (1e-4 * np.sin(k * y))[:, None] * np.ones((1, nx))
+    w = orc.Walls.none(nx, ny)
+    f = orc.init(p, np.ones((ny, nx)), ux0, np.zeros((ny, nx)))
+    t = 400
+    f = orc.run(p, w, f, t)
+    rho, ux, uy, tot = orc.macros(p, w, f)
+    amp = (ux[:, 0] * np.sin(k * y)).sum() / (np.sin(k * y) ** 2).sum()
+    nu_meas = -np.log(amp / 1e-4) / (k * k * t)
+    nu = (2.0 / 3.0) * (tau - 0.5)
+    assert abs(nu_meas - nu) / nu < 5e-3
+
+
+def eos_paper(rho, th=2.0 / 3.0):
+    """Eq. EOS with the paper's parameters (written out here for the
+    continuum predictions)."""
+    tV, tU, tL, r1, r2 = 0.25 * th, -0.25 * th, th, 0.222, 0.869
+    p1 = r1 * tV
+    p2 = p1 + (r2 - r1) * tU
+    return np.where(rho <= r1, rho * tV, np.where(rho <= r2, p1 + (rho - r1) * tU, p2 + (rho - r2) * tL))
+
+
+def test_eos_parameters_give_the_stated_density_ratio():
+    """The paper states that its EOS parameters give phase equilibrium at
+    rho_V = 0.1, rho_L = 1.0 (continuum calculation): Maxwell's equal-area
+    construction on eq. EOS reproduces that.  Catches misread slopes or
+    branch end points."""
+    def eqs(v):
+        g, l = v
+        p0 = float(eos_paper(g))
+        area = integrate.quad(lambda r: (p0 - eos_paper(r)) / r ** 2, g, l, points=[0.222, 0.869], limit=200)[0]
+        return [float(eos_paper(l)) - p0, area]
+    g, l = optimize.fsolve(eqs, [0.1, 1.0], xtol=1e-13)
+    assert abs(g - 0.1) < 1e-3 and abs(l - 1.0) < 1e-3
+
+
+def _flat_interface(orc, eos, steps=8000):
+    nx, ny = 4, 128
+    p = orc.make_params(nx, ny, tau=1.0, G=-1.0, lattice=21, psi_kind=1, eos=eos)
+    y = np.arange(ny)
+    rho0 = np.where((y >= 32) & (y < 96), 1.0, 0.1)[:, None] * np.ones((1, nx))
+    w = orc.Walls.none(nx, ny)
+    f = orc.run(p, w, orc.init(p, rho0), steps)
+    rho, ux, uy, tot = orc.macros(p, w, f)
+    return rho[:, 0], tot
+
+
+def test_eos_flat_interface_coexistence(orc):
+    """Eq. EOS with the paper's parameters, D2Q21, G = -1: a flat liquid slab
+    settles to bulk densities between the pseudo-potential stability rule
+    (0.0864, 0.9968) and Maxwell's construction (0.0995, 1.0001); mass is
+    conserved.  With the literal printed pseudo-potential
+    sqrt(2 (rho theta - p_EOS)) the effective pressure rho theta (1 - theta) +
+    theta p_EOS has no unstable branch and the slab dissolves -- the reading
+    with the 1/theta factor is the one that separates phases."""
+    rho, tot = _flat_interface(orc, (0.25, -0.25, 1.0, 0.222, 0.869))
+    liq, vap = rho[64], rho[0]
+    assert 0.0864 * 0.97 < vap < 0.0995 * 1.03
+    assert abs(liq - 1.0) < 0.005
+    assert 9.0 < liq / vap < 12.0
+    assert abs(tot[0] - 4 * (64 * 1.0 + 64 * 0.1)) < 1e-9
+    # literal reading: psi^2 = 2 (rho theta - p) equals 2 (rho theta - p') / theta
+    # with p' = rho theta (1 - theta) + theta p, i.e. slopes 1/3 + (2/3) s / theta
+    th = 2.0 / 3.0
+    lit = ((1 - th) + th * 0.25, (1 - th) + th * -0.25, (1 - th) + th * 1.0, 0.222, 0.869)
+    rho_lit, _ = _flat_interface(orc, lit, steps=4000)
+    assert rho_lit.max() - rho_lit.min() < 0.05 * (1.0 - 0.1)
+
+
+def test_d2q21_one_step_brute_force(orc):
+    """One full step on an 8x8 D2Q21 lattice with the EOS fluid, walls and
+    forcing, against a dense numpy formulation written from Sec. II:
+    moments, EOS pseudo-potential, force sums over Tab. I, EDM-BGK collision,
+    streaming.  Catches an index, table-order or streaming-direction error."""
+    nx = ny = 8
+    th = 2.0 / 3.0
+    kw = dict(tau=0.9, G=-1.0, G_R=0.3, G_A=0.15, eps=1.2, U_wall=(0.01, 0.0), F_ext=(2e-4, 0.0))
+    p = orc.make_params(nx, ny, lattice=21, psi_kind=1, **kw)
+    rng = np.random.Generator(np.random.PCG64(9))
+    phi, psiR, psiA = rng.uniform(0, 1, (ny, nx)), rng.uniform(0, 1, (ny, nx)), rng.uniform(0, 0.4, (ny, nx))
+    walls = orc.Walls(phi, psiR, psiA)
+    rho, ux, uy = I.random_state_field(nx, ny, 11, lo=0.08, hi=1.1)
+    f = orc.init(p, rho, ux, uy) * (1 + 0.05 * rng.uniform(-1, 1, (ny, nx, 21)))
+    got = orc.step(p, walls, f)
+
+    # independent dense formulation
+    vel = [(0, 0)] + [(1, 0), (0, 1), (-1, 0), (0, -1)] + [(1, 1), (-1, 1), (-1, -1), (1, -1)] \
+        + [(2, 0), (0, 2), (-2, 0), (0, -2)] + [(2, 2), (-2, 2), (-2, -2), (2, -2)] \
+        + [(3, 0), (0, 3), (-3, 0), (0, -3)]
+    wts = [91 / 324] + [1 / 12] * 4 + [2 / 27] * 4 + [7 / 360] * 4 + [1 / 432] * 4 + [1 / 1620] * 4
+    C = np.array(vel, dtype=float)
+    W = np.array(wts)
+    r = f.sum(-1)
+    j = f @ C
+    u = j / r[..., None]
+    psi = np.sqrt(2 * (r * th - eos_paper(r, th)) / th)
+    psifs = kw["G_A"] * psiA - kw["G_R"] * psiR
+
+    def shift(a, c):      # a(x + c) on the periodic lattice, a indexed [y, x]
+        return np.roll(np.roll(a, -c[0], axis=1), -c[1], axis=0)
+
+    sff = sum(W[i] * shift(psi, vel[i])[..., None] * C[i] for i in range(21))
+    sfs = sum(W[i] * shift(psifs, vel[i])[..., None] * C[i] for i in range(21))
+    ff = -kw["G"] * psi[..., None] * sff
+    lr = r[..., None] * sfs
+    ds = (phi ** kw["eps"])[..., None] * (r[..., None] * (np.array(kw["U_wall"]) - u) - ff)
+    F = ff + lr + ds + np.array(kw["F_ext"])
+    us = u + F / r[..., None]
+
+    def feq(v):
+        cu = v @ C.T
+        vv = (v * v).sum(-1)[..., None]
+        return W * r[..., None] * (1 + cu / th + (cu * cu - th * vv) / (2 * th * th))
+
+    post = f - (f - feq(u)) / kw["tau"] + feq(us) - feq(u)
+    want = np.zeros_like(post)
+    for i in range(21):
+        want[..., i] = np.roll(np.roll(post[..., i], vel[i][0], axis=1), vel[i][1], axis=0)
+    assert np.abs(got - want).max() < 1e-14
