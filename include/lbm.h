@@ -76,8 +76,23 @@ typedef int lbm_status;
 #define LBM_WALL_FLAT_SLAB 1
 #define LBM_WALL_FIELDS    2
 
+/* Velocity sets (Sec. II.A): D2Q9, and D2Q21 of Tab. I (theta = 2/3, each
+ * node reaching three sites per step; storage F32 or F64, no batches). */
+#define LBM_D2Q9  9
+#define LBM_D2Q21 21
+
+/* Pseudo-potential of the fluid-fluid force (eq. force_SC):
+ *  EXP : psi = 1 - exp(-rho)                              (D2Q9 or D2Q21)
+ *  EOS : psi = sqrt(2 (rho theta - p_EOS(rho)) / theta), p_EOS the
+ *        piecewise-linear equation of state of eq. EOS with slopes
+ *        eos[0..2] * theta (vapour, unstable, liquid) joined at rho_1 =
+ *        eos[3] and rho_2 = eos[4]; the paper uses it with G = -1 (D2Q21
+ *        only).  The 1/theta makes the bulk pressure equal p_EOS. */
+#define LBM_PSI_EXP 0
+#define LBM_PSI_EOS 1
+
 typedef struct {
-    int32_t nx, ny;          /* lattice size, both >= 1; 9*nx*ny*(bytes per
+    int32_t nx, ny;          /* lattice size, both >= 1; Q*nx*ny*(bytes per
                                 stored population) < 2^32                    */
     int32_t storage;         /* LBM_STORE_*                                   */
     int32_t wall_kind;       /* LBM_WALL_*                                    */
@@ -95,6 +110,11 @@ typedef struct {
     int32_t diag_interval;   /* K: a diagnostic pass after every K-th step;
                                 0 = only on request                          */
     int32_t seg_rows;        /* rows per wave segment of the diagnostic pass; 0 = library choice */
+    int32_t lattice;         /* LBM_D2Q9 (default) or LBM_D2Q21               */
+    int32_t psi_kind;        /* LBM_PSI_EXP (default) or LBM_PSI_EOS          */
+    double eos[5];           /* eq. EOS: theta_V/theta, theta_U/theta,
+                                theta_L/theta, rho_1, rho_2 (defaults: the
+                                paper's 0.25, -0.25, 1, 0.222, 0.869)        */
     int32_t reserved;        /* must be 0                                     */
 } lbm_params;
 
@@ -102,7 +122,8 @@ typedef struct lbm_ctx lbm_ctx;
 
 /* Fills *p with the defaults: tau = 1, G = -5, G_R = G_A = 0, eps = 1,
  * U_wall = F_ext = 0, wall_width = 2, core_range = 1, tail_range = 3,
- * rho_ref = 1, slab_rows = 8, storage F32, wall NONE, diag_interval 0. */
+ * rho_ref = 1, slab_rows = 8, storage F32, wall NONE, diag_interval 0,
+ * lattice D2Q9, psi EXP, eos = the paper's parameters. */
 lbm_status lbm_params_default(lbm_params *p);
 
 /* Last error message of the calling thread ("" if none).  Never NULL. */
@@ -168,7 +189,9 @@ lbm_status lbm_contact_angle(lbm_ctx *c, double iso, double y_ref, double out[4]
 lbm_status lbm_slip_length(lbm_ctx *c, double out[3]);
 
 /* Populations at the current time, post-streaming, as host float64
- * [9][ny][nx] (velocity order above).  Synchronises. */
+ * [Q][ny][nx] (Q = 9 or 21, velocity order of the oracle tables: D2Q9 as
+ * above; D2Q21 continues with (2,0) (0,2) (-2,0) (0,-2), (2,2) (-2,2)
+ * (-2,-2) (2,-2), (3,0) (0,3) (-3,0) (0,-3)).  Synchronises. */
 lbm_status lbm_get_state(lbm_ctx *c, double *f);
 
 /* Replaces the populations (same layout as lbm_get_state) and the step index;

@@ -88,8 +88,12 @@ uint32_t plane_stride(const lbm_params &p) {
     return uint32_t(N + LBM_PLANE_PAD_BYTES / s);
 }
 
+// Populations per node of the parameters' velocity set.
+int pop_count(const lbm_params &p) { return p.lattice == LBM_D2Q21 ? 21 : 9; }
+
 // Offsets (bytes) into one lattice's workspace.  fb and mom are adjacent: the
-// pair doubles as staging for host float64 arrays at creation.
+// pair doubles as staging for host float64 arrays at creation.  For D2Q21 the
+// diagnostic partial rows follow its own tiling (one per wave).
 Layout make_layout(const lbm_params &p) {
     Layout L{};
     const size_t N = size_t(p.nx) * p.ny, s = storage_bytes(p.storage), cb = compute_bytes(p.storage);
@@ -103,9 +107,10 @@ Layout make_layout(const lbm_params &p) {
     L.iso_blocks = isoline_blocks(uint32_t(N));
     size_t o = 0;
     L.pstride = plane_stride(p);
-    const size_t P = L.pstride;
-    L.fa = o; o = align_up(o + 9 * P * s);
-    L.fb = o; o = o + 9 * P * s;                       // no padding: fb+mom contiguous
+    const size_t P = L.pstride, nq = size_t(pop_count(p));
+    if (p.lattice == LBM_D2Q21) L.waves = q21_tiles(uint32_t(p.nx), uint32_t(p.ny)) * kQ21Waves;
+    L.fa = o; o = align_up(o + nq * P * s);
+    L.fb = o; o = o + nq * P * s;                      // no padding: fb+mom contiguous
     L.mom = o; o = align_up(o + 3 * N * cb);
     L.uprev = o; o = align_up(o + 2 * N * cb);
     const bool node = p.wall_kind == LBM_WALL_FIELDS;
@@ -126,8 +131,21 @@ lbm_status validate(const lbm_params *p) {
     if (p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_F16DEV && p->storage != LBM_STORE_F64 &&
         p->storage != LBM_STORE_F32X)
         return fail(LBM_EINVAL, "unknown storage %d", p->storage);
-    if ((int64_t(p->nx) * p->ny + LBM_PLANE_PAD_BYTES) * 9 * int64_t(storage_bytes(p->storage)) >= (int64_t(1) << 32))
-        return fail(LBM_EINVAL, "lattice too large: 9*(nx*ny + pad)*bytes must be < 2^32");
+    if (p->lattice != LBM_D2Q9 && p->lattice != LBM_D2Q21) return fail(LBM_EINVAL, "unknown lattice %d", p->lattice);
+    if ((int64_t(p->nx) * p->ny + LBM_PLANE_PAD_BYTES) * pop_count(*p) * int64_t(storage_bytes(p->storage)) >=
+        (int64_t(1) << 32))
+        return fail(LBM_EINVAL, "lattice too large: Q*(nx*ny + pad)*bytes must be < 2^32");
+    if (p->psi_kind != LBM_PSI_EXP && p->psi_kind != LBM_PSI_EOS)
+        return fail(LBM_EINVAL, "unknown psi_kind %d", p->psi_kind);
+    if (p->lattice == LBM_D2Q21 && p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_F64)
+        return fail(LBM_EINVAL, "D2Q21 takes storage F32 or F64");
+    if (p->psi_kind == LBM_PSI_EOS) {
+        if (p->lattice != LBM_D2Q21) return fail(LBM_EINVAL, "the EOS pseudo-potential is built for D2Q21");
+        for (double v : p->eos)
+            if (!isfinite(v)) return fail(LBM_EINVAL, "non-finite eos parameter");
+        if (!(p->eos[3] > 0) || !(p->eos[4] > p->eos[3]))
+            return fail(LBM_EINVAL, "eos needs 0 < rho_1 < rho_2");
+    }
     if (p->wall_kind < LBM_WALL_NONE || p->wall_kind > LBM_WALL_FIELDS)
         return fail(LBM_EINVAL, "unknown wall_kind %d", p->wall_kind);
     if (!(p->tau > 0.5) || !isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be > 0.5");
@@ -231,9 +249,14 @@ lbm_status launch_ok(hipError_t e, const char *what) {
 // Runs the diagnostic kernel over the current state and reduces it into
 // d_small[slot*8 .. +6].
 lbm_status run_diag(lbm_ctx *c, int write_mom, int compare, int update, int slot) {
-    TRY(launch_ok(launch_diag(kernel_storage(c->p.storage), nullptr, nullptr, 0, c->L, c->wall_mode, *c->cur,
-                              write_mom, compare, update, c->stream),
-                  "diag"));
+    if (c->p.lattice == LBM_D2Q21)
+        TRY(launch_ok(launch_diag_q21(kernel_storage(c->p.storage), c->L, c->wall_mode, *c->cur, write_mom, compare,
+                                      update, c->stream),
+                      "diag_q21"));
+    else
+        TRY(launch_ok(launch_diag(kernel_storage(c->p.storage), nullptr, nullptr, 0, c->L, c->wall_mode, *c->cur,
+                                  write_mom, compare, update, c->stream),
+                      "diag"));
     TRY(launch_ok(launch_reduce(c->L.partials, c->d_ranges, 1, 8, 6, c->d_small + 8 * slot, 8, c->stream),
                   "reduce"));
     return LBM_OK;
@@ -280,6 +303,19 @@ lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const d
     L.Ux = p->U_wall[0]; L.Uy = p->U_wall[1];
     L.Fx = p->F_ext[0]; L.Fy = p->F_ext[1];
     L.rho_ref = p->storage == LBM_STORE_F16DEV ? p->rho_ref : 1.0;
+    L.lattice = pop_count(*p);
+    L.psi_kind = p->psi_kind;
+    {
+        // eq. EOS in lattice units: slopes eos[0..2] * theta, pressures at rho_1, rho_2
+        const double th = p->lattice == LBM_D2Q21 ? 2.0 / 3.0 : 1.0 / 3.0;
+        L.eos_tV = p->eos[0] * th;
+        L.eos_tU = p->eos[1] * th;
+        L.eos_tL = p->eos[2] * th;
+        L.eos_r1 = p->eos[3];
+        L.eos_r2 = p->eos[4];
+        L.eos_p1 = L.eos_r1 * L.eos_tV;
+        L.eos_p2 = L.eos_p1 + (L.eos_r2 - L.eos_r1) * L.eos_tU;
+    }
 
     const uint32_t ranges[4] = {0, Y.waves, 0, Y.iso_blocks};
     HIPCHK(hipMemcpyAsync(c->d_ranges, ranges, sizeof ranges, hipMemcpyHostToDevice, stream));
@@ -289,12 +325,12 @@ lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const d
     double *phi_raw = (double *)(ws + Y.phi_raw);
     if (c->wall_mode == 0) {
         const int P = p->wall_kind == LBM_WALL_FLAT_SLAB ? p->slab_rows : 0;
-        TRY(launch_ok(launch_walls_row(f64, p->ny, P, p->wall_width, p->core_range, p->tail_range, p->eps,
+        TRY(launch_ok(launch_walls_row(f64, L.lattice, p->ny, P, p->wall_width, p->core_range, p->tail_range, p->eps,
                                        p->G_R, p->G_A, ws + Y.row_tab, phi_raw, stream),
                       "walls_row"));
     } else {
         HIPCHK(hipMemcpyAsync(stage, wall_fields, 3 * N * sizeof(double), hipMemcpyHostToDevice, stream));
-        TRY(launch_ok(launch_walls_node(f64, p->nx, p->ny, stage, p->eps, p->G_R, p->G_A, ws + Y.node_tab,
+        TRY(launch_ok(launch_walls_node(f64, L.lattice, p->nx, p->ny, stage, p->eps, p->G_R, p->G_A, ws + Y.node_tab,
                                         phi_raw, stream),
                       "walls_node"));
     }
@@ -307,7 +343,7 @@ lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const d
         dux = stage + N;
         duy = stage + 2 * N;
     }
-    TRY(launch_ok(launch_init(kernel_storage(p->storage), p->nx, p->ny, L.pstride, stage, dux, duy, L.fa, L.rho_ref, stream),
+    TRY(launch_ok(launch_init(kernel_storage(p->storage), L.lattice, p->nx, p->ny, L.pstride, stage, dux, duy, L.fa, L.rho_ref, stream),
                   "init"));
     HIPCHK(hipStreamSynchronize(stream));
     return LBM_OK;
@@ -352,6 +388,10 @@ lbm_status lbm_params_default(lbm_params *p) {
     p->tail_range = 3.0;
     p->rho_ref = 1.0;
     p->slab_rows = 8;
+    p->lattice = LBM_D2Q9;
+    p->psi_kind = LBM_PSI_EXP;
+    const double eos[5] = {0.25, -0.25, 1.0, 0.222, 0.869};
+    for (int i = 0; i < 5; ++i) p->eos[i] = eos[i];
     return LBM_OK;
 }
 
@@ -394,7 +434,10 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     const int ks = kernel_storage(c->p.storage);
     const int K = c->p.diag_interval;
     for (int64_t s = 0; s < nsteps; ++s) {
-        TRY(launch_ok(launch_step(ks, c->L, c->wall_mode, c->shape, *c->cur, c->stream), "step"));
+        if (c->p.lattice == LBM_D2Q21)
+            TRY(launch_ok(launch_step_q21(ks, c->L, c->wall_mode, *c->cur, c->stream), "step_q21"));
+        else
+            TRY(launch_ok(launch_step(ks, c->L, c->wall_mode, c->shape, *c->cur, c->stream), "step"));
         *c->cur ^= 1;
         ++*c->step;
         if (K > 0 && *c->step % K == 0) {
@@ -569,8 +612,8 @@ lbm_status lbm_get_state(lbm_ctx *c, double *f) {
     const size_t N = size_t(c->p.nx) * c->p.ny;
     void *pop = *c->cur ? c->L.fb : c->L.fa;
     double *stage = (double *)(*c->cur ? c->L.fa : c->L.fb);   // the other buffer is free between steps
-    for (int q = 0; q < 9; ++q) {
-        TRY(launch_ok(launch_plane(kernel_storage(c->p.storage), 0, c->p.nx, c->p.ny, c->L.pstride, q, pop, stage, c->L.rho_ref,
+    for (int q = 0; q < pop_count(c->p); ++q) {
+        TRY(launch_ok(launch_plane(kernel_storage(c->p.storage), c->L.lattice, 0, c->p.nx, c->p.ny, c->L.pstride, q, pop, stage, c->L.rho_ref,
                                    c->stream),
                       "get_plane"));
         HIPCHK(hipMemcpyAsync(f + q * N, stage, N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -586,9 +629,9 @@ lbm_status lbm_set_state(lbm_ctx *c, const double *f, int64_t step_index) {
     const size_t N = size_t(c->p.nx) * c->p.ny;
     void *pop = *c->cur ? c->L.fb : c->L.fa;
     double *stage = (double *)(*c->cur ? c->L.fa : c->L.fb);
-    for (int q = 0; q < 9; ++q) {
+    for (int q = 0; q < pop_count(c->p); ++q) {
         HIPCHK(hipMemcpyAsync(stage, f + q * N, N * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        TRY(launch_ok(launch_plane(kernel_storage(c->p.storage), 1, c->p.nx, c->p.ny, c->L.pstride, q, pop, stage, c->L.rho_ref,
+        TRY(launch_ok(launch_plane(kernel_storage(c->p.storage), c->L.lattice, 1, c->p.nx, c->p.ny, c->L.pstride, q, pop, stage, c->L.rho_ref,
                                    c->stream),
                       "set_plane"));
         TRY(sync(c));
@@ -617,6 +660,8 @@ static lbm_status batch_check(const lbm_params *ps, int32_t n) {
     for (int32_t k = 0; k < n; ++k) {
         TRY(validate(&ps[k]));
         if (ps[k].storage != LBM_STORE_F32) return fail(LBM_EINVAL, "lattice %d: batches take F32 storage only", k);
+        if (ps[k].lattice != LBM_D2Q9 || ps[k].psi_kind != LBM_PSI_EXP)
+            return fail(LBM_EINVAL, "lattice %d: batches take D2Q9 with the exponential pseudo-potential", k);
         if (ps[k].wall_kind == LBM_WALL_FIELDS)
             return fail(LBM_EINVAL, "lattice %d: batches take wall kinds NONE or FLAT_SLAB", k);
     }
@@ -827,8 +872,9 @@ static lbm_status attach_check(lbm_ctx *const *ctxs, int32_t n, uint32_t *nwork,
         const lbm_ctx *c = ctxs[k];
         if (!c) return fail(LBM_EINVAL, "context %d is NULL", k);
         if (c->view || c->attached) return fail(LBM_ESTATE, "context %d already belongs to a batch", k);
-        if (c->p.storage != LBM_STORE_F32 || c->wall_mode != 0)
-            return fail(LBM_EINVAL, "context %d: batches take F32 storage and wall kinds NONE or FLAT_SLAB", k);
+        if (c->p.storage != LBM_STORE_F32 || c->wall_mode != 0 || c->p.lattice != LBM_D2Q9 ||
+            c->p.psi_kind != LBM_PSI_EXP)
+            return fail(LBM_EINVAL, "context %d: batches take D2Q9, F32 storage and wall kinds NONE or FLAT_SLAB", k);
         for (int32_t j = 0; j < k; ++j)
             if (ctxs[j] == c) return fail(LBM_EINVAL, "context %d listed twice", k);
         w += c->lay.waves;
@@ -985,6 +1031,7 @@ lbm_status lbm_set_tile_shape(lbm_ctx *c, int32_t shape) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (c->view) return fail(LBM_ESTATE, "lattice belongs to a batch; use lbm_batch_set_tile_shapes");
     if (shape < 0 || shape >= kNumTileShapes) return fail(LBM_EINVAL, "tile shape %d out of range", shape);
+    if (c->p.lattice != LBM_D2Q9) return fail(LBM_EINVAL, "tile shapes apply to D2Q9 lattices");
     c->shape = shape;
     return LBM_OK;
 }
@@ -1034,6 +1081,7 @@ extern "C" {
 
 lbm_status lbm_tune(lbm_ctx *c, int32_t steps, int32_t *shape_out, double *ms_out) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (c->p.lattice != LBM_D2Q9) return fail(LBM_EINVAL, "tile shapes apply to D2Q9 lattices");
     if (c->view) return fail(LBM_ESTATE, "lattice belongs to a batch; use lbm_batch_tune");
     if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
     int best = c->shape;

@@ -15,34 +15,6 @@
 
 namespace lbmwet {
 
-// Wall terms of one row (WALL_ROW: per-row scalars) or node (WALL_NODE).
-template <class C> struct RowWall {
-    C phie, Sy;
-};
-
-template <class C, int WALL>
-__device__ inline RowWall<C> row_wall(const LatDev<C> &L, uint32_t y) {
-    RowWall<C> w{C(0), C(0)};
-    if (WALL == WALL_ROW) {
-        w.phie = L.row_tab[2 * y];
-        w.Sy = L.row_tab[2 * y + 1];
-    }
-    return w;
-}
-
-template <class C, int WALL>
-__device__ inline void wall_terms(const LatDev<C> &L, const RowWall<C> &rw, uint32_t n, C &phie, C &Sx, C &Sy) {
-    if (WALL == WALL_ROW) {
-        phie = rw.phie;
-        Sx = C(0);
-        Sy = rw.Sy;
-    } else {
-        phie = L.node_tab[n];
-        Sx = L.node_tab[L.plane + n];
-        Sy = L.node_tab[2 * L.plane + n];
-    }
-}
-
 // ---------------------------------------------------------------- marching
 // Walks one (strip, segment) tile and hands every row's node data to `act`.
 //
@@ -555,53 +527,61 @@ __global__ __launch_bounds__(256) void k_profile(uint32_t nx, const C *__restric
 }
 
 // ------------------------------------------------------------ state copies
-__device__ inline double feq_component(int q, double rho, double ux, double uy) {
-    const double cu = kCx[q] * ux + kCy[q] * uy;
-    return kW[q] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy));
+// Eq. f2 at equilibrium in FP64: w rho (1 + c.u/theta + ((c.u)^2 - theta u^2) / (2 theta^2)).
+template <int LQ> __device__ inline double feq_component(int q, double rho, double ux, double uy) {
+    using V = VelSet<LQ>;
+    const double cu = V::cx(q) * ux + V::cy(q) * uy;
+    if constexpr (LQ == 9)
+        return kW[q] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * (ux * ux + uy * uy));
+    const double th = V::theta;
+    return V::w(q) * rho * (1.0 + cu / th + (cu * cu - th * (ux * ux + uy * uy)) / (2.0 * th * th));
 }
 
 // Stored (pre-stream) populations such that pulling yields feq(rho0, u0):
 // stored_q(x) = feq_q at node x + c_q.
-template <class S, class C>
+template <class S, class C, int LQ>
 __global__ __launch_bounds__(256) void k_init(uint32_t nx, uint32_t ny, uint32_t P, const double *__restrict__ rho0,
                                               const double *__restrict__ ux0, const double *__restrict__ uy0,
                                               typename Codec<S>::Raw *__restrict__ dst, C rho_ref) {
+    using V = VelSet<LQ>;
     const uint32_t N = nx * ny;
     const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     const uint32_t y = n / nx, x = n - y * nx;
-    for (int q = 0; q < Q; ++q) {
-        const uint32_t xs = (x + nx + kCx[q]) % nx, ys = (y + ny + kCy[q]) % ny;
+    for (int q = 0; q < V::Q; ++q) {
+        const uint32_t xs = (x + 3 * nx + V::cx(q)) % nx, ys = (y + 3 * ny + V::cy(q)) % ny;
         const uint32_t m = ys * nx + xs;
-        const double v = feq_component(q, rho0[m], ux0 ? ux0[m] : 0.0, uy0 ? uy0[m] : 0.0);
+        const double v = feq_component<LQ>(q, rho0[m], ux0 ? ux0[m] : 0.0, uy0 ? uy0[m] : 0.0);
         dst[q * P + n] = Codec<S>::template encode<C>(C(v), q, rho_ref);
     }
 }
 
 // Post-streaming plane q as float64: out(x) = stored_q(x - c_q), decoded
 // exactly as the step kernel decodes it.
-template <class S, class C>
+template <class S, class C, int LQ>
 __global__ __launch_bounds__(256) void k_get_plane(uint32_t nx, uint32_t ny, uint32_t P, int q,
                                                    const typename Codec<S>::Raw *__restrict__ src,
                                                    double *__restrict__ out, C rho_ref) {
+    using V = VelSet<LQ>;
     const uint32_t N = nx * ny;
     const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     const uint32_t y = n / nx, x = n - y * nx;
-    const uint32_t xs = (x + nx - kCx[q]) % nx, ys = (y + ny - kCy[q]) % ny;
+    const uint32_t xs = (x + 3 * nx - V::cx(q)) % nx, ys = (y + 3 * ny - V::cy(q)) % ny;
     out[n] = double(Codec<S>::template decode<C>(src[q * P + ys * nx + xs], q, rho_ref));
 }
 
 // Inverse of k_get_plane: stored_q(x) = in(x + c_q).
-template <class S, class C>
+template <class S, class C, int LQ>
 __global__ __launch_bounds__(256) void k_set_plane(uint32_t nx, uint32_t ny, uint32_t P, int q,
                                                    const double *__restrict__ in,
                                                    typename Codec<S>::Raw *__restrict__ dst, C rho_ref) {
+    using V = VelSet<LQ>;
     const uint32_t N = nx * ny;
     const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     const uint32_t y = n / nx, x = n - y * nx;
-    const uint32_t xs = (x + nx + kCx[q]) % nx, ys = (y + ny + kCy[q]) % ny;
+    const uint32_t xs = (x + 3 * nx + V::cx(q)) % nx, ys = (y + 3 * ny + V::cy(q)) % ny;
     dst[q * P + n] = Codec<S>::template encode<C>(C(in[ys * nx + xs]), q, rho_ref);
 }
 
@@ -622,10 +602,11 @@ __device__ inline double slab_distance(int y, int ny, int P) {
 // Per-row tables for a flat slab (or all zeros when P == 0):
 //   tab[2y] = phi(y)^eps,  tab[2y+1] = S_y(y) = sum_i w_i psi_FS(y + c_iy) c_iy,
 //   psi_FS = G_A psiA - G_R psiR;  phi_raw[y] = phi(y) in float64.
-template <class C>
+template <class C, int LQ>
 __global__ __launch_bounds__(256) void k_walls_row(int ny, int P, double width, double core, double tail,
                                                    double eps, double GR, double GA, C *__restrict__ tab,
                                                    double *__restrict__ phi_raw) {
+    using V = VelSet<LQ>;
     const int y = blockIdx.x * blockDim.x + threadIdx.x;
     if (y >= ny) return;
     if (P <= 0) {
@@ -641,7 +622,7 @@ __global__ __launch_bounds__(256) void k_walls_row(int ny, int P, double width, 
         return GA * a - GR * r;
     };
     double sy = 0.0;
-    for (int q = 0; q < Q; ++q) sy += kW[q] * psi_fs(y + kCy[q]) * kCy[q];
+    for (int q = 0; q < V::Q; ++q) sy += V::w(q) * psi_fs(y + V::cy(q)) * V::cy(q);
     const double phi = step_profile(slab_distance(y, ny, P), width);
     tab[2 * y] = C(pow(phi, eps));
     tab[2 * y + 1] = C(sy);
@@ -650,20 +631,21 @@ __global__ __launch_bounds__(256) void k_walls_row(int ny, int P, double width, 
 
 // Per-node tables from caller fields (phi, psiR, psiA), each [ny][nx]:
 //   tab = [phi^eps | S_x | S_y], phi_raw = phi.
-template <class C>
+template <class C, int LQ>
 __global__ __launch_bounds__(256) void k_walls_node(uint32_t nx, uint32_t ny, const double *__restrict__ fields,
                                                     double eps, double GR, double GA, C *__restrict__ tab,
                                                     double *__restrict__ phi_raw) {
+    using V = VelSet<LQ>;
     const uint32_t N = nx * ny;
     const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     const uint32_t y = n / nx, x = n - y * nx;
     double sx = 0.0, sy = 0.0;
-    for (int q = 0; q < Q; ++q) {
-        const uint32_t m = ((y + ny + kCy[q]) % ny) * nx + (x + nx + kCx[q]) % nx;
+    for (int q = 0; q < V::Q; ++q) {
+        const uint32_t m = ((y + 3 * ny + V::cy(q)) % ny) * nx + (x + 3 * nx + V::cx(q)) % nx;
         const double fs = GA * fields[2 * size_t(N) + m] - GR * fields[size_t(N) + m];
-        sx += kW[q] * fs * kCx[q];
-        sy += kW[q] * fs * kCy[q];
+        sx += V::w(q) * fs * V::cx(q);
+        sy += V::w(q) * fs * V::cy(q);
     }
     const double phi = fields[n];
     tab[n] = C(pow(phi, eps));
@@ -783,57 +765,75 @@ hipError_t launch_profile(int f64, uint32_t nx, uint32_t ny, const void *ux, dou
     return hipGetLastError();
 }
 
-hipError_t launch_init(int storage, uint32_t nx, uint32_t ny, uint32_t pstride, const double *rho0,
+// Calls fn(integral_constant<int, LQ>) for a population count (9 or 21).
+template <class Fn> static hipError_t with_lattice(int lattice, Fn &&fn) {
+    if (lattice == 21) return fn(std::integral_constant<int, 21>{});
+    return fn(std::integral_constant<int, 9>{});
+}
+
+hipError_t launch_init(int storage, int lattice, uint32_t nx, uint32_t ny, uint32_t pstride, const double *rho0,
                        const double *ux0, const double *uy0, void *dst, double rho_ref, hipStream_t st) {
     const uint32_t nb = blocks_nodes(nx * ny);
     return dispatch(storage, [&](auto s, auto c) {
         using S = decltype(s);
         using C = decltype(c);
-        hipLaunchKernelGGL((k_init<S, C>), dim3(nb), dim3(256), 0, st, nx, ny, pstride, rho0, ux0, uy0,
-                           (typename Codec<S>::Raw *)dst, C(rho_ref));
-        return hipGetLastError();
+        return with_lattice(lattice, [&](auto lq) {
+            constexpr int LQ = decltype(lq)::value;
+            hipLaunchKernelGGL((k_init<S, C, LQ>), dim3(nb), dim3(256), 0, st, nx, ny, pstride, rho0, ux0, uy0,
+                               (typename Codec<S>::Raw *)dst, C(rho_ref));
+            return hipGetLastError();
+        });
     });
 }
 
-hipError_t launch_plane(int storage, int set, uint32_t nx, uint32_t ny, uint32_t pstride, int q, void *pop,
-                        double *buf, double rho_ref, hipStream_t st) {
+hipError_t launch_plane(int storage, int lattice, int set, uint32_t nx, uint32_t ny, uint32_t pstride, int q,
+                        void *pop, double *buf, double rho_ref, hipStream_t st) {
     const uint32_t nb = blocks_nodes(nx * ny);
     return dispatch(storage, [&](auto s, auto c) {
         using S = decltype(s);
         using C = decltype(c);
         using Raw = typename Codec<S>::Raw;
-        if (set)
-            hipLaunchKernelGGL((k_set_plane<S, C>), dim3(nb), dim3(256), 0, st, nx, ny, pstride, q, buf, (Raw *)pop,
-                               C(rho_ref));
+        return with_lattice(lattice, [&](auto lq) {
+            constexpr int LQ = decltype(lq)::value;
+            if (set)
+                hipLaunchKernelGGL((k_set_plane<S, C, LQ>), dim3(nb), dim3(256), 0, st, nx, ny, pstride, q, buf,
+                                   (Raw *)pop, C(rho_ref));
+            else
+                hipLaunchKernelGGL((k_get_plane<S, C, LQ>), dim3(nb), dim3(256), 0, st, nx, ny, pstride, q,
+                                   (const Raw *)pop, buf, C(rho_ref));
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t launch_walls_row(int f64, int lattice, int ny, int P, double width, double core, double tail, double eps,
+                            double GR, double GA, void *tab, double *phi_raw, hipStream_t st) {
+    const uint32_t nb = blocks_nodes(uint32_t(ny));
+    return with_lattice(lattice, [&](auto lq) {
+        constexpr int LQ = decltype(lq)::value;
+        if (f64)
+            hipLaunchKernelGGL((k_walls_row<double, LQ>), dim3(nb), dim3(256), 0, st, ny, P, width, core, tail, eps,
+                               GR, GA, (double *)tab, phi_raw);
         else
-            hipLaunchKernelGGL((k_get_plane<S, C>), dim3(nb), dim3(256), 0, st, nx, ny, pstride, q, (const Raw *)pop, buf,
-                               C(rho_ref));
+            hipLaunchKernelGGL((k_walls_row<float, LQ>), dim3(nb), dim3(256), 0, st, ny, P, width, core, tail, eps,
+                               GR, GA, (float *)tab, phi_raw);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_walls_row(int f64, int ny, int P, double width, double core, double tail, double eps,
-                            double GR, double GA, void *tab, double *phi_raw, hipStream_t st) {
-    const uint32_t nb = blocks_nodes(uint32_t(ny));
-    if (f64)
-        hipLaunchKernelGGL(k_walls_row<double>, dim3(nb), dim3(256), 0, st, ny, P, width, core, tail, eps, GR,
-                           GA, (double *)tab, phi_raw);
-    else
-        hipLaunchKernelGGL(k_walls_row<float>, dim3(nb), dim3(256), 0, st, ny, P, width, core, tail, eps, GR,
-                           GA, (float *)tab, phi_raw);
-    return hipGetLastError();
-}
-
-hipError_t launch_walls_node(int f64, uint32_t nx, uint32_t ny, const double *fields, double eps, double GR,
-                             double GA, void *tab, double *phi_raw, hipStream_t st) {
+hipError_t launch_walls_node(int f64, int lattice, uint32_t nx, uint32_t ny, const double *fields, double eps,
+                             double GR, double GA, void *tab, double *phi_raw, hipStream_t st) {
     const uint32_t nb = blocks_nodes(nx * ny);
-    if (f64)
-        hipLaunchKernelGGL(k_walls_node<double>, dim3(nb), dim3(256), 0, st, nx, ny, fields, eps, GR, GA,
-                           (double *)tab, phi_raw);
-    else
-        hipLaunchKernelGGL(k_walls_node<float>, dim3(nb), dim3(256), 0, st, nx, ny, fields, eps, GR, GA,
-                           (float *)tab, phi_raw);
-    return hipGetLastError();
+    return with_lattice(lattice, [&](auto lq) {
+        constexpr int LQ = decltype(lq)::value;
+        if (f64)
+            hipLaunchKernelGGL((k_walls_node<double, LQ>), dim3(nb), dim3(256), 0, st, nx, ny, fields, eps, GR, GA,
+                               (double *)tab, phi_raw);
+        else
+            hipLaunchKernelGGL((k_walls_node<float, LQ>), dim3(nb), dim3(256), 0, st, nx, ny, fields, eps, GR, GA,
+                               (float *)tab, phi_raw);
+        return hipGetLastError();
+    });
 }
 
 }  // namespace lbmwet

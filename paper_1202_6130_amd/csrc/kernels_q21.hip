@@ -1,0 +1,290 @@
+// D2Q21 kernels (gfx950): the paper's own lattice (Sec. II.A, Tab. I), each
+// node reaching three sites per step, with the exponential or the
+// equation-of-state pseudo-potential (eq. EOS).
+//
+// k_tile_q21: one workgroup of kQ21Waves waves owns a strip of 64 columns of
+// which the 3 on each side are halo columns (58 output columns) and
+// kQ21Waves * kQ21Rows consecutive rows of which the 3 on each side are halo
+// rows.  Every wave loads its rows at once (21 pulled loads per row, shifts up
+// to +-3 in both directions), computes density and pseudo-potential of all 64
+// columns, including the halo ones from their own loads, and publishes them
+// in LDS; after one barrier every output node sums w_i psi(x + c_i) c_i over
+// the 20 moving directions from LDS, forms the forces of eqs. force_SC,
+// force_SC_FS and wall_shift, and either collides and stores (step) or
+// accumulates the diagnostic sums (diagnostic pass).
+#include <type_traits>
+
+#include "launch.hpp"
+#include "lbm_device.hpp"
+
+namespace lbmwet {
+
+namespace {
+
+constexpr int kH = 3;   // halo width: the largest |c_i| of D2Q21
+
+// Pseudo-potential of the fluid-fluid force.  PSI 0: 1 - exp(-rho); PSI 1:
+// eq. EOS, psi^2 = 2 (rho theta - p_EOS) / theta (the 1/theta factor makes
+// the bulk pressure equal p_EOS for the force of eq. force_SC with G = -1).
+template <class C, int PSI> __device__ inline C psi21(const LatDev<C> &L, C rho) {
+    if constexpr (PSI == 0) {
+        return psi_of<C>(rho);
+    } else {
+        const C th = C(2.0 / 3.0);
+        C p;
+        if (rho <= L.eos_r1) p = rho * L.eos_tV;
+        else if (rho <= L.eos_r2) p = L.eos_p1 + (rho - L.eos_r1) * L.eos_tU;
+        else p = L.eos_p2 + (rho - L.eos_r2) * L.eos_tL;
+        const C a = C(2) * (rho * th - p) / th;
+        return sqrt(a > C(0) ? a : C(0));
+    }
+}
+
+// Eq. M0 in a fixed order (every tile computes a halo node's density with
+// the same additions as the tile that owns the node).
+template <class C> __device__ inline C density21(const C f[Q21]) {
+    C a = (f[1] + f[3]) + (f[2] + f[4]);
+    C b = (f[5] + f[7]) + (f[6] + f[8]);
+    C c = (f[9] + f[11]) + (f[10] + f[12]);
+    C d = (f[13] + f[15]) + (f[14] + f[16]);
+    C e = (f[17] + f[19]) + (f[18] + f[20]);
+    return f[0] + (((a + b) + (c + d)) + e);
+}
+
+// Eq. f2 at equilibrium on D2Q21 (theta = 2/3) from density and momentum
+// m = rho u: feq_i = w_i rho + w_i rho (1.125 (c_i.u)^2 - 0.75 u^2)
+// + 1.5 w_i c_i.m, the velocity terms added to w_i rho last.
+template <class C> __device__ inline void equilibrium21(C rho, C inv_rho, C mx, C my, C feq[Q21]) {
+    const C ux = mx * inv_rho, uy = my * inv_rho;
+    const C u2 = C(0.75) * (ux * ux + uy * uy);
+#pragma unroll
+    for (int q = 0; q < Q21; ++q) {
+        const C r = C(kW21[q]) * rho;
+        const C cu = C(kCx21[q]) * ux + C(kCy21[q]) * uy;
+        const C a = r * (C(1.125) * cu * cu - u2);
+        const C b = C(1.5 * kW21[q]) * (C(kCx21[q]) * mx + C(kCy21[q]) * my);
+        feq[q] = r + (a + b);
+    }
+}
+
+// The rest population closes the mass balance (the collision conserves mass
+// exactly in real arithmetic).
+template <class C> __device__ inline void close_mass21(C f[Q21], C rho) {
+    f[0] = C(0);
+    f[0] = rho - (density21<C>(f));
+}
+
+template <class C> struct Node21 {
+    C rho, inv_rho, jx, jy, ux, uy, Fx, Fy;
+};
+
+// Forces of one node (eqs. force_SC, force_SC_FS, wall_shift) given the
+// neighbour sums sx, sy = sum_i w_i psi(x + c_i) c_i.
+template <class C>
+__device__ inline Node21<C> node21(const C f[Q21], C rho, C psi_c, C sx, C sy, C phie, C Sx, C Sy,
+                                   const LatDev<C> &L) {
+    Node21<C> s;
+    s.rho = rho;
+    s.inv_rho = recip<C>(rho);
+    C jx = C(0), jy = C(0);
+#pragma unroll
+    for (int q = 1; q < Q21; ++q) {
+        if (kCx21[q] != 0) jx += C(kCx21[q]) * f[q];
+        if (kCy21[q] != 0) jy += C(kCy21[q]) * f[q];
+    }
+    s.jx = jx;
+    s.jy = jy;
+    s.ux = jx * s.inv_rho;
+    s.uy = jy * s.inv_rho;
+    const C ffx = -L.G * psi_c * sx, ffy = -L.G * psi_c * sy;
+    const C lrx = rho * Sx, lry = rho * Sy;
+    const C dsx = phie * (rho * (L.Ux - s.ux) - ffx);
+    const C dsy = phie * (rho * (L.Uy - s.uy) - ffy);
+    s.Fx = ((ffx + lrx) + dsx) + L.Fx;
+    s.Fy = ((ffy + lry) + dsy) + L.Fy;
+    return s;
+}
+
+// EDM-BGK collision (Sec. II.B): f' = (1 - 1/tau)(f - feq(u)) + feq(u*).
+template <class C> __device__ inline void collide21(C f[Q21], const Node21<C> &s, C omega) {
+    C fs[Q21];
+    equilibrium21<C>(s.rho, s.inv_rho, s.jx + s.Fx, s.jy + s.Fy, fs);
+    if (omega == C(1)) {
+#pragma unroll
+        for (int i = 0; i < Q21; ++i) f[i] = fs[i];
+    } else {
+        C fu[Q21];
+        equilibrium21<C>(s.rho, s.inv_rho, s.jx, s.jy, fu);
+        const C keep = C(1) - omega;
+#pragma unroll
+        for (int i = 0; i < Q21; ++i) f[i] = keep * (f[i] - fu[i]) + fs[i];
+    }
+    close_mass21<C>(f, s.rho);
+}
+
+template <class S, class C, int WALL, int PSI, int DIAG>
+__global__ __launch_bounds__(kQ21Waves * kWave) void k_tile_q21(LatDev<C> L, const void *__restrict__ src,
+                                                                void *__restrict__ dst, int write_mom, int compare,
+                                                                int update) {
+    using Raw = typename Codec<S>::Raw;
+    constexpr int R = kQ21Rows, ROWS = kQ21Waves * kQ21Rows;
+    constexpr uint32_t OUT = uint32_t(ROWS - 2 * kH);
+    __shared__ C psi_s[ROWS][kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kWave);
+    const uint32_t nx = L.nx, ny = L.ny, P = L.pstride;
+    const uint32_t strips = (nx + kQ21OutCols - 1) / kQ21OutCols;
+    const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const uint32_t trow = lb / strips, strip = lb - trow * strips;
+    const uint32_t x0 = strip * kQ21OutCols;                     // first output column (lane 3)
+    const uint32_t x = wrap_fast(x0 + uint32_t(lane) + 3 * nx - kH, nx);
+    const bool active = lane >= kH && lane < kWave - kH && x0 + uint32_t(lane) - kH < nx;
+    const uint32_t y0 = trow * OUT;
+    const uint32_t out_rows = min(OUT, ny - y0);
+
+    PopBuf<S> buf;
+    buf.init(src, 21u * P * uint32_t(sizeof(S)));
+    // column of the pulled population with c_x = c: x - c (wrapped)
+    uint32_t xs[2 * kH + 1];
+#pragma unroll
+    for (int c = -kH; c <= kH; ++c) xs[c + kH] = wrap_fast(x + 3 * nx - uint32_t(c + kH) + kH, nx);
+
+    C f[R][Q21], rho[R], psi[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const uint32_t k = uint32_t(w * R + j);
+        rho[j] = C(0);
+        psi[j] = C(0);
+        if (k < out_rows + 2 * kH) {
+            const uint32_t r = wrap_fast(y0 + 3 * ny - kH + k, ny);
+            uint32_t ro[2 * kH + 1];       // element offset of row r - c_y, c_y = -3..3
+#pragma unroll
+            for (int c = -kH; c <= kH; ++c) ro[c + kH] = wrap_fast(r + 3 * ny - uint32_t(c + kH) + kH, ny) * nx;
+            Raw raw[Q21];
+#pragma unroll
+            for (int q = 0; q < Q21; ++q) raw[q] = buf.load(xs[kCx21[q] + kH], uint32_t(q) * P + ro[kCy21[q] + kH]);
+#pragma unroll
+            for (int q = 0; q < Q21; ++q) f[j][q] = Codec<S>::template decode<C>(raw[q], q, L.rho_ref);
+            rho[j] = density21<C>(f[j]);
+            psi[j] = psi21<C, PSI>(L, rho[j]);
+            psi_s[k][lane] = psi[j];
+        }
+    }
+    __syncthreads();
+
+    // neighbour reads of the halo lanes stay inside the tile (their results
+    // are not used)
+    const int lc = lane < kH ? kH : (lane >= kWave - kH ? kWave - kH - 1 : lane);
+    PopBuf<S> out;
+    out.init(dst, 21u * P * uint32_t(sizeof(S)));
+    double s_rho = 0, s_jx = 0, s_jy = 0, s_du = 0, s_u = 0, s_bad = 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const uint32_t k = uint32_t(w * R + j);
+        if (k < uint32_t(kH) || k >= out_rows + kH) continue;
+        const uint32_t r = wrap_fast(y0 + 3 * ny - kH + k, ny);
+        C sx = C(0), sy = C(0);
+#pragma unroll
+        for (int q = 1; q < Q21; ++q) {
+            const C pn = psi_s[int(k) + kCy21[q]][lc + kCx21[q]];
+            if (kCx21[q] != 0) sx += C(kW21[q] * kCx21[q]) * pn;
+            if (kCy21[q] != 0) sy += C(kW21[q] * kCy21[q]) * pn;
+        }
+        const uint32_t n = r * nx + x;
+        C phie, Sx, Sy;
+        wall_terms<C, WALL>(L, row_wall<C, WALL>(L, r), n, phie, Sx, Sy);
+        const Node21<C> s = node21<C>(f[j], rho[j], psi[j], sx, sy, phie, Sx, Sy, L);
+        if constexpr (DIAG) {
+            const C vx = s.ux + C(0.5) * s.Fx * s.inv_rho;
+            const C vy = s.uy + C(0.5) * s.Fy * s.inv_rho;
+            if (active) {
+                if (write_mom) {
+                    L.mom[n] = rho[j];
+                    L.mom[L.plane + n] = vx;
+                    L.mom[2 * L.plane + n] = vy;
+                }
+                const bool ok = isfinite(double(rho[j])) && isfinite(double(vx)) && isfinite(double(vy));
+                s_bad += ok ? 0.0 : 1.0;
+                s_rho += double(rho[j]);
+                s_jx += double(s.jx);
+                s_jy += double(s.jy);
+                if (compare)
+                    s_du += fabs(double(vx) - double(L.uprev[n])) + fabs(double(vy) - double(L.uprev[L.plane + n]));
+                s_u += fabs(double(vx)) + fabs(double(vy));
+                if (update) {
+                    L.uprev[n] = vx;
+                    L.uprev[L.plane + n] = vy;
+                }
+            }
+        } else {
+            collide21<C>(f[j], s, L.omega);
+            if (active) {
+                const uint32_t row = r * nx;
+#pragma unroll
+                for (int q = 0; q < Q21; ++q)
+                    out.store(Codec<S>::template encode<C>(f[j][q], q, L.rho_ref), x, uint32_t(q) * P + row);
+            }
+        }
+    }
+    if constexpr (DIAG) {
+        const double v[6] = {s_rho, s_jx, s_jy, s_du, s_u, s_bad};
+        double *part = L.partials + 8 * (size_t(lb) * kQ21Waves + size_t(w));
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            double t = v[i];
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, kWave);
+            if (lane == 0) part[i] = t;
+        }
+    }
+}
+
+// Calls fn(S{}, C{}) for the storage modes of D2Q21 (binary32, binary64).
+template <class Fn> hipError_t dispatch21(int storage, Fn &&fn) {
+    switch (storage) {
+    case STORE_F32: return fn(float{}, float{});
+    case STORE_F64: return fn(double{}, double{});
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int DIAG>
+hipError_t launch_tile_q21(int storage, const LatDevAny &La, int wall, int parity, int write_mom, int compare,
+                           int update, int psi_kind, hipStream_t st) {
+    return dispatch21(storage, [&](auto s, auto c) {
+        using S = decltype(s);
+        using C = decltype(c);
+        LatDev<C> d = La.get<C>();
+        const void *src = parity ? d.fb : d.fa;
+        void *dst = parity ? d.fa : d.fb;
+        const dim3 grid(q21_tiles(d.nx, d.ny)), block(kQ21Waves * kWave);
+        auto go = [&](auto wallc, auto psic) {
+            constexpr int WL = decltype(wallc)::value, PS = decltype(psic)::value;
+            hipLaunchKernelGGL((k_tile_q21<S, C, WL, PS, DIAG>), grid, block, 0, st, d, src, dst, write_mom, compare,
+                               update);
+        };
+        using RowW = std::integral_constant<int, WALL_ROW>;
+        using NodeW = std::integral_constant<int, WALL_NODE>;
+        using PsiExp = std::integral_constant<int, 0>;
+        using PsiEos = std::integral_constant<int, 1>;
+        if (wall == WALL_ROW) {
+            if (psi_kind == 1) go(RowW{}, PsiEos{}); else go(RowW{}, PsiExp{});
+        } else {
+            if (psi_kind == 1) go(NodeW{}, PsiEos{}); else go(NodeW{}, PsiExp{});
+        }
+        return hipGetLastError();
+    });
+}
+
+}  // namespace
+
+hipError_t launch_step_q21(int storage, const LatDevAny &L, int wall, int parity, hipStream_t st) {
+    return launch_tile_q21<0>(storage, L, wall, parity, 0, 0, 0, L.psi_kind, st);
+}
+
+hipError_t launch_diag_q21(int storage, const LatDevAny &L, int wall, int parity, int write_mom, int compare,
+                           int update, hipStream_t st) {
+    return launch_tile_q21<1>(storage, L, wall, parity, write_mom, compare, update, L.psi_kind, st);
+}
+
+}  // namespace lbmwet

@@ -19,6 +19,8 @@ template <class C> struct LatDev;
 struct LatDevAny {
     uint32_t nx = 0, ny = 0, plane = 0;
     uint32_t pstride = 0;          // population plane stride (elements), >= plane
+    int lattice = 9;               // populations per node (9 or 21)
+    int psi_kind = 0;              // 0: 1 - exp(-rho), 1: eq. EOS
     uint32_t strips = 0, segs = 0, seg_rows = 0;
     uint32_t wave0 = 0;
     void *fa = nullptr, *fb = nullptr;
@@ -27,6 +29,9 @@ struct LatDevAny {
     void *uprev = nullptr;
     double *partials = nullptr;
     double G = 0, omega = 1, Ux = 0, Uy = 0, Fx = 0, Fy = 0, rho_ref = 1;
+    // equation-of-state pseudo-potential (eq. EOS): branch slopes, end points
+    // and pressures at the end points
+    double eos_tV = 0, eos_tU = 0, eos_tL = 0, eos_r1 = 0, eos_r2 = 0, eos_p1 = 0, eos_p2 = 0;
 
     template <class C> LatDev<C> get() const;
 };
@@ -43,6 +48,7 @@ template <class C> struct LatDev {
     C *uprev;
     double *partials;
     C G, omega, Ux, Uy, Fx, Fy, rho_ref;
+    C eos_tV, eos_tU, eos_tL, eos_r1, eos_r2, eos_p1, eos_p2;
 };
 
 template <class C> inline LatDev<C> LatDevAny::get() const {
@@ -58,6 +64,8 @@ template <class C> inline LatDev<C> LatDevAny::get() const {
     d.partials = partials;
     d.G = C(G); d.omega = C(omega); d.Ux = C(Ux); d.Uy = C(Uy);
     d.Fx = C(Fx); d.Fy = C(Fy); d.rho_ref = C(rho_ref);
+    d.eos_tV = C(eos_tV); d.eos_tU = C(eos_tU); d.eos_tL = C(eos_tL);
+    d.eos_r1 = C(eos_r1); d.eos_r2 = C(eos_r2); d.eos_p1 = C(eos_p1); d.eos_p2 = C(eos_p2);
     return d;
 }
 
@@ -109,13 +117,28 @@ hipError_t launch_isoline(int f64, const IsoParams &p, const void *rho, const do
                           hipStream_t st);
 uint32_t isoline_blocks(uint32_t nodes);
 hipError_t launch_profile(int f64, uint32_t nx, uint32_t ny, const void *ux, double *out, hipStream_t st);
-hipError_t launch_init(int storage, uint32_t nx, uint32_t ny, uint32_t pstride, const double *rho0,
+hipError_t launch_init(int storage, int lattice, uint32_t nx, uint32_t ny, uint32_t pstride, const double *rho0,
                        const double *ux0, const double *uy0, void *dst, double rho_ref, hipStream_t st);
-hipError_t launch_plane(int storage, int set, uint32_t nx, uint32_t ny, uint32_t pstride, int q, void *pop,
-                        double *buf, double rho_ref, hipStream_t st);
-hipError_t launch_walls_row(int f64, int ny, int P, double width, double core, double tail, double eps,
+hipError_t launch_plane(int storage, int lattice, int set, uint32_t nx, uint32_t ny, uint32_t pstride, int q,
+                        void *pop, double *buf, double rho_ref, hipStream_t st);
+hipError_t launch_walls_row(int f64, int lattice, int ny, int P, double width, double core, double tail, double eps,
                             double GR, double GA, void *tab, double *phi_raw, hipStream_t st);
-hipError_t launch_walls_node(int f64, uint32_t nx, uint32_t ny, const double *fields, double eps, double GR,
-                             double GA, void *tab, double *phi_raw, hipStream_t st);
+hipError_t launch_walls_node(int f64, int lattice, uint32_t nx, uint32_t ny, const double *fields, double eps,
+                             double GR, double GA, void *tab, double *phi_raw, hipStream_t st);
+
+// D2Q21 step (Tab. I): workgroups of kQ21Waves waves over strips of
+// kQ21OutCols output columns (64 lanes with 3 halo columns on each side) and
+// kQ21Waves * kQ21Rows loaded rows (3 halo rows above and below).
+constexpr int kQ21Waves = 16;
+constexpr int kQ21Rows = 2;
+constexpr uint32_t kQ21OutCols = 58;
+constexpr uint32_t kQ21OutRows = kQ21Waves * kQ21Rows - 6;
+inline uint32_t q21_strips(uint32_t nx) { return (nx + kQ21OutCols - 1) / kQ21OutCols; }
+inline uint32_t q21_tiles(uint32_t nx, uint32_t ny) { return q21_strips(nx) * ((ny + kQ21OutRows - 1) / kQ21OutRows); }
+hipError_t launch_step_q21(int storage, const LatDevAny &L, int wall, int parity, hipStream_t st);
+// The diagnostic pass of a D2Q21 lattice: one partial row per wave of the
+// same tiling (q21_tiles * kQ21Waves rows).
+hipError_t launch_diag_q21(int storage, const LatDevAny &L, int wall, int parity, int write_mom, int compare,
+                           int update, hipStream_t st);
 
 }  // namespace lbmwet

@@ -42,6 +42,35 @@ constexpr int kCy[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 constexpr double kW[Q] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
                           1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 
+// D2Q21 (Tab. I), indices 0..8 as D2Q9, then |c| = 2 axes, (+-2,+-2), |c| = 3
+// axes; theta = 2/3.
+constexpr int Q21 = 21;
+constexpr int kCx21[Q21] = {0, 1, 0, -1, 0, 1, -1, -1, 1, 2, 0, -2, 0, 2, -2, -2, 2, 3, 0, -3, 0};
+constexpr int kCy21[Q21] = {0, 0, 1, 0, -1, 1, 1, -1, -1, 0, 2, 0, -2, 2, 2, -2, -2, 0, 3, 0, -3};
+constexpr double kW21[Q21] = {91.0 / 324.0, 1.0 / 12.0, 1.0 / 12.0, 1.0 / 12.0, 1.0 / 12.0,
+                              2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0, 2.0 / 27.0,
+                              7.0 / 360.0, 7.0 / 360.0, 7.0 / 360.0, 7.0 / 360.0,
+                              1.0 / 432.0, 1.0 / 432.0, 1.0 / 432.0, 1.0 / 432.0,
+                              1.0 / 1620.0, 1.0 / 1620.0, 1.0 / 1620.0, 1.0 / 1620.0};
+
+// Velocity set by population count (set-up and copy kernels; the hot kernels
+// unroll their loops over constant tables).
+template <int LQ> struct VelSet;
+template <> struct VelSet<9> {
+    static constexpr int Q = 9;
+    static constexpr double theta = 1.0 / 3.0;
+    __device__ static inline int cx(int q) { return kCx[q]; }
+    __device__ static inline int cy(int q) { return kCy[q]; }
+    __device__ static inline double w(int q) { return kW[q]; }
+};
+template <> struct VelSet<21> {
+    static constexpr int Q = 21;
+    static constexpr double theta = 2.0 / 3.0;
+    __device__ static inline int cx(int q) { return kCx21[q]; }
+    __device__ static inline int cy(int q) { return kCy21[q]; }
+    __device__ static inline double w(int q) { return kW21[q]; }
+};
+
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kStripCols = 64;     // output columns per wave (one per lane, 64-aligned)
 constexpr int kBlockWaves = LBM_BLOCK_WAVES;   // waves per workgroup
@@ -384,6 +413,34 @@ template <class C> __device__ inline void collide(C f[Q], const NodeState<C> &s,
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[i] = keep * (f[i] - fu[i]) + fs[i];
     close_mass<C>(f, s.rho);
+}
+
+// Wall terms of one row (WALL_ROW: per-row scalars) or node (WALL_NODE).
+template <class C> struct RowWall {
+    C phie, Sy;
+};
+
+template <class C, int WALL>
+__device__ inline RowWall<C> row_wall(const LatDev<C> &L, uint32_t y) {
+    RowWall<C> w{C(0), C(0)};
+    if (WALL == WALL_ROW) {
+        w.phie = L.row_tab[2 * y];
+        w.Sy = L.row_tab[2 * y + 1];
+    }
+    return w;
+}
+
+template <class C, int WALL>
+__device__ inline void wall_terms(const LatDev<C> &L, const RowWall<C> &rw, uint32_t n, C &phie, C &Sx, C &Sy) {
+    if (WALL == WALL_ROW) {
+        phie = rw.phie;
+        Sx = C(0);
+        Sy = rw.Sy;
+    } else {
+        phie = L.node_tab[n];
+        Sx = L.node_tab[L.plane + n];
+        Sy = L.node_tab[2 * L.plane + n];
+    }
 }
 
 }  // namespace lbmwet

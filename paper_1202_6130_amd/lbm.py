@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(HERE, "_lib", "liblbmwet.so")
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ENOFIT, LBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
 STORE_F32, STORE_F16DEV, STORE_F64, STORE_F32X = 0, 1, 2, 3
 WALL_NONE, WALL_FLAT_SLAB, WALL_FIELDS = 0, 1, 2
+D2Q9, D2Q21 = 9, 21
+PSI_EXP, PSI_EOS = 0, 1
 
 _NAMES = {LBM_EINVAL: "EINVAL", LBM_ENOMEM: "ENOMEM", LBM_EDEVICE: "EDEVICE", LBM_EUNSTABLE: "EUNSTABLE",
           LBM_ENOFIT: "ENOFIT", LBM_ESTATE: "ESTATE"}
@@ -36,7 +38,9 @@ class lbm_params(ctypes.Structure):
                 ("wall_width", ctypes.c_double), ("core_range", ctypes.c_double),
                 ("tail_range", ctypes.c_double), ("rho_ref", ctypes.c_double),
                 ("slab_rows", ctypes.c_int32), ("diag_interval", ctypes.c_int32),
-                ("seg_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("seg_rows", ctypes.c_int32), ("lattice", ctypes.c_int32),
+                ("psi_kind", ctypes.c_int32), ("eos", ctypes.c_double * 5),
+                ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -129,11 +133,18 @@ def lbm_params_default(**kw):
     p = lbm_params()
     _check(lib().lbm_params_default(ctypes.byref(p)))
     for k, v in kw.items():
-        if k in ("U_wall", "F_ext"):
-            getattr(p, k)[0], getattr(p, k)[1] = v
+        if k in ("U_wall", "F_ext", "eos"):
+            arr = getattr(p, k)
+            for i, x in enumerate(v):
+                arr[i] = x
         else:
             setattr(p, k, v)
     return p
+
+
+def nq(p):
+    """Populations per node of the parameters' velocity set."""
+    return 21 if p.lattice == D2Q21 else 9
 
 
 def lbm_workspace_bytes(p):
@@ -183,8 +194,8 @@ def lbm_slip_length(ctx):
     return out
 
 
-def lbm_get_state(ctx, n):
-    f = np.zeros(9 * n)
+def lbm_get_state(ctx, n, q=9):
+    f = np.zeros(q * n)
     _check(lib().lbm_get_state(ctx, _ptr(f)))
     return f
 
@@ -359,10 +370,14 @@ class Lattice:
         return lbm_slip_length(self.ctx)
 
     def get_state(self):
-        """Populations as float64 [9, ny, nx] (post-streaming)."""
-        return lbm_get_state(self.ctx, self.n).reshape(9, self.ny, self.nx)
+        """Populations as float64 [Q, ny, nx] (post-streaming)."""
+        q = nq(self.p)
+        return lbm_get_state(self.ctx, self.n, q).reshape(q, self.ny, self.nx)
 
     def set_state(self, f, step_index=0):
+        f = np.asarray(f)
+        if f.size != nq(self.p) * self.n:
+            raise ValueError(f"state must hold {nq(self.p)} x {self.ny} x {self.nx} values")
         lbm_set_state(self.ctx, f, step_index)
 
     @property

@@ -45,7 +45,7 @@ def test_params_struct_matches_header():
     text = open(HEADER).read()
     body = text[text.index("typedef struct {"):text.index("} lbm_params;")]
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
-    fields = re.findall(r"\b([A-Za-z_]+)(?:\[2\])?\s*[,;]", body)
+    fields = re.findall(r"\b([A-Za-z_]+)(?:\[\d+\])?\s*[,;]", body)
     assert fields == [f for f, _ in lbm.lbm_params._fields_]
 
 
