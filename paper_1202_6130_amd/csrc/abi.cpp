@@ -306,15 +306,19 @@ lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const d
     L.lattice = pop_count(*p);
     L.psi_kind = p->psi_kind;
     {
-        // eq. EOS in lattice units: slopes eos[0..2] * theta, pressures at rho_1, rho_2
-        const double th = p->lattice == LBM_D2Q21 ? 2.0 / 3.0 : 1.0 / 3.0;
-        L.eos_tV = p->eos[0] * th;
-        L.eos_tU = p->eos[1] * th;
-        L.eos_tL = p->eos[2] * th;
-        L.eos_r1 = p->eos[3];
-        L.eos_r2 = p->eos[4];
-        L.eos_p1 = L.eos_r1 * L.eos_tV;
-        L.eos_p2 = L.eos_p1 + (L.eos_r2 - L.eos_r1) * L.eos_tU;
+        // eq. EOS with branch slopes s_b theta (s_b = eos[0..2]), pressure
+        // continuous at rho_1 = eos[3] and rho_2 = eos[4].  The pseudo-potential
+        // 2 (rho theta - p) / theta is linear on each branch; it is evaluated as
+        // k_b (rho - rho_b) + a_b so that a branch of slope theta (the paper's
+        // liquid) gives exactly the same psi at every density.
+        const double sV = p->eos[0], sU = p->eos[1], sL = p->eos[2], r1 = p->eos[3], r2 = p->eos[4];
+        L.eos_kV = 2.0 * (1.0 - sV);
+        L.eos_kU = 2.0 * (1.0 - sU);
+        L.eos_kL = 2.0 * (1.0 - sL);
+        L.eos_aU = 2.0 * r1 * (1.0 - sV);
+        L.eos_aL = L.eos_aU + 2.0 * (r2 - r1) * (1.0 - sU);
+        L.eos_r1 = r1;
+        L.eos_r2 = r2;
     }
 
     const uint32_t ranges[4] = {0, Y.waves, 0, Y.iso_blocks};

@@ -25,17 +25,16 @@ constexpr int kH = 3;   // halo width: the largest |c_i| of D2Q21
 
 // Pseudo-potential of the fluid-fluid force.  PSI 0: 1 - exp(-rho); PSI 1:
 // eq. EOS, psi^2 = 2 (rho theta - p_EOS) / theta (the 1/theta factor makes
-// the bulk pressure equal p_EOS for the force of eq. force_SC with G = -1).
+// the bulk pressure equal p_EOS for the force of eq. force_SC with G = -1),
+// linear in rho on each branch: k_b (rho - rho_b) + a_b.
 template <class C, int PSI> __device__ inline C psi21(const LatDev<C> &L, C rho) {
     if constexpr (PSI == 0) {
         return psi_of<C>(rho);
     } else {
-        const C th = C(2.0 / 3.0);
-        C p;
-        if (rho <= L.eos_r1) p = rho * L.eos_tV;
-        else if (rho <= L.eos_r2) p = L.eos_p1 + (rho - L.eos_r1) * L.eos_tU;
-        else p = L.eos_p2 + (rho - L.eos_r2) * L.eos_tL;
-        const C a = C(2) * (rho * th - p) / th;
+        C a;
+        if (rho <= L.eos_r1) a = L.eos_kV * rho;
+        else if (rho <= L.eos_r2) a = L.eos_kU * (rho - L.eos_r1) + L.eos_aU;
+        else a = L.eos_kL * (rho - L.eos_r2) + L.eos_aL;
         return sqrt(a > C(0) ? a : C(0));
     }
 }
@@ -51,9 +50,35 @@ template <class C> __device__ inline C density21(const C f[Q21]) {
     return f[0] + (((a + b) + (c + d)) + e);
 }
 
+// Momentum coefficient of each velocity class, B = 1.5 w |c|_inf: the
+// equilibrium's momentum term of population i is B_i (s_ix m_x + s_iy m_y),
+// s_i = sign(c_i).  Its first moment is (2 B_1 + 4 B_2 + 4 B_3 + 8 B_4 +
+// 6 B_5) m, and 1.5 sum_i w_i c_ix^2 = 1 makes the bracket 1.  In binary32 the
+// five constants are chosen (within 6e-7 relative of the exact values) so
+// that the bracket is exactly 1: the equilibrium then carries exactly the
+// momentum it is given, with no per-step gain or loss that would add up.
+template <class C> struct Mom21;
+template <> struct Mom21<float> {
+    static constexpr float b1 = 0x1.000000p-3f;      // 1.5 / 12
+    static constexpr float b2 = 0x1.c71c78p-4f;      // 1.5 * 2/27
+    static constexpr float b3 = 0x1.ddddd4p-5f;      // 2 * 1.5 * 7/360
+    static constexpr float b4 = 0x1.c71c62p-8f;      // 2 * 1.5 / 432
+    static constexpr float b5 = 0x1.6c16d0p-9f;      // 3 * 1.5 / 1620
+};
+template <> struct Mom21<double> {
+    static constexpr double b1 = 1.5 / 12.0, b2 = 1.5 * 2.0 / 27.0, b3 = 3.0 * 7.0 / 360.0;
+    static constexpr double b4 = 3.0 / 432.0, b5 = 4.5 / 1620.0;
+};
+template <class C> __device__ constexpr C mom21(int q) {
+    using M = Mom21<C>;
+    return q == 0 ? C(0) : q <= 4 ? M::b1 : q <= 8 ? M::b2 : q <= 12 ? M::b3 : q <= 16 ? M::b4 : M::b5;
+}
+constexpr int sgn(int v) { return (v > 0) - (v < 0); }
+
 // Eq. f2 at equilibrium on D2Q21 (theta = 2/3) from density and momentum
-// m = rho u: feq_i = w_i rho + w_i rho (1.125 (c_i.u)^2 - 0.75 u^2)
-// + 1.5 w_i c_i.m, the velocity terms added to w_i rho last.
+// m = rho u: feq_i = w_i rho + w_i rho (1.125 (c_i.u)^2 - 0.75 u^2) + B_i s_i.m,
+// the velocity terms added to w_i rho last.  Opposite populations get the
+// same first two terms and momentum terms of opposite sign.
 template <class C> __device__ inline void equilibrium21(C rho, C inv_rho, C mx, C my, C feq[Q21]) {
     const C ux = mx * inv_rho, uy = my * inv_rho;
     const C u2 = C(0.75) * (ux * ux + uy * uy);
@@ -62,7 +87,7 @@ template <class C> __device__ inline void equilibrium21(C rho, C inv_rho, C mx, 
         const C r = C(kW21[q]) * rho;
         const C cu = C(kCx21[q]) * ux + C(kCy21[q]) * uy;
         const C a = r * (C(1.125) * cu * cu - u2);
-        const C b = C(1.5 * kW21[q]) * (C(kCx21[q]) * mx + C(kCy21[q]) * my);
+        const C b = mom21<C>(q) * (C(sgn(kCx21[q])) * mx + C(sgn(kCy21[q])) * my);
         feq[q] = r + (a + b);
     }
 }
@@ -86,12 +111,12 @@ __device__ inline Node21<C> node21(const C f[Q21], C rho, C psi_c, C sx, C sy, C
     Node21<C> s;
     s.rho = rho;
     s.inv_rho = recip<C>(rho);
-    C jx = C(0), jy = C(0);
-#pragma unroll
-    for (int q = 1; q < Q21; ++q) {
-        if (kCx21[q] != 0) jx += C(kCx21[q]) * f[q];
-        if (kCy21[q] != 0) jy += C(kCy21[q]) * f[q];
-    }
+    // eq. M1 from differences of opposite populations (exact near rest)
+    const C d1 = f[1] - f[3], d2 = f[2] - f[4], d57 = f[5] - f[7], d68 = f[6] - f[8];
+    const C d9 = f[9] - f[11], d10 = f[10] - f[12], d13 = f[13] - f[15], d14 = f[14] - f[16];
+    const C d17 = f[17] - f[19], d18 = f[18] - f[20];
+    const C jx = ((d1 + (d57 - d68)) + C(2) * (d9 + (d13 - d14))) + C(3) * d17;
+    const C jy = ((d2 + (d57 + d68)) + C(2) * (d10 + (d13 + d14))) + C(3) * d18;
     s.jx = jx;
     s.jy = jy;
     s.ux = jx * s.inv_rho;
@@ -183,13 +208,18 @@ __global__ __launch_bounds__(kQ21Waves * kWave) void k_tile_q21(LatDev<C> L, con
         const uint32_t k = uint32_t(w * R + j);
         if (k < uint32_t(kH) || k >= out_rows + kH) continue;
         const uint32_t r = wrap_fast(y0 + 3 * ny - kH + k, ny);
-        C sx = C(0), sy = C(0);
-#pragma unroll
-        for (int q = 1; q < Q21; ++q) {
-            const C pn = psi_s[int(k) + kCy21[q]][lc + kCx21[q]];
-            if (kCx21[q] != 0) sx += C(kW21[q] * kCx21[q]) * pn;
-            if (kCy21[q] != 0) sy += C(kW21[q] * kCy21[q]) * pn;
-        }
+        // sum_i w_i psi(x + c_i) c_i from differences across the node, which
+        // vanish exactly where psi is uniform
+        auto ps = [&](int cx, int cy) { return psi_s[int(k) + cy][lc + cx]; };
+        const C x1 = ps(1, 0) - ps(-1, 0), y1 = ps(0, 1) - ps(0, -1);
+        const C a1 = ps(1, 1) - ps(-1, -1), b1 = ps(1, -1) - ps(-1, 1);
+        const C x2 = ps(2, 0) - ps(-2, 0), y2 = ps(0, 2) - ps(0, -2);
+        const C a2 = ps(2, 2) - ps(-2, -2), b2 = ps(2, -2) - ps(-2, 2);
+        const C x3 = ps(3, 0) - ps(-3, 0), y3 = ps(0, 3) - ps(0, -3);
+        const C sx = (((C(kW21[1]) * x1 + C(kW21[5]) * (a1 + b1)) + C(2 * kW21[9]) * x2) +
+                      C(2 * kW21[13]) * (a2 + b2)) + C(3 * kW21[17]) * x3;
+        const C sy = (((C(kW21[2]) * y1 + C(kW21[5]) * (a1 - b1)) + C(2 * kW21[10]) * y2) +
+                      C(2 * kW21[13]) * (a2 - b2)) + C(3 * kW21[18]) * y3;
         const uint32_t n = r * nx + x;
         C phie, Sx, Sy;
         wall_terms<C, WALL>(L, row_wall<C, WALL>(L, r), n, phie, Sx, Sy);

@@ -29,9 +29,9 @@ struct LatDevAny {
     void *uprev = nullptr;
     double *partials = nullptr;
     double G = 0, omega = 1, Ux = 0, Uy = 0, Fx = 0, Fy = 0, rho_ref = 1;
-    // equation-of-state pseudo-potential (eq. EOS): branch slopes, end points
-    // and pressures at the end points
-    double eos_tV = 0, eos_tU = 0, eos_tL = 0, eos_r1 = 0, eos_r2 = 0, eos_p1 = 0, eos_p2 = 0;
+    // equation-of-state pseudo-potential (eq. EOS) per branch b (vapour,
+    // unstable, liquid): psi^2 = k_b (rho - rho_b) + a_b with rho_b = 0, r1, r2
+    double eos_kV = 0, eos_kU = 0, eos_kL = 0, eos_aU = 0, eos_aL = 0, eos_r1 = 0, eos_r2 = 0;
 
     template <class C> LatDev<C> get() const;
 };
@@ -48,7 +48,7 @@ template <class C> struct LatDev {
     C *uprev;
     double *partials;
     C G, omega, Ux, Uy, Fx, Fy, rho_ref;
-    C eos_tV, eos_tU, eos_tL, eos_r1, eos_r2, eos_p1, eos_p2;
+    C eos_kV, eos_kU, eos_kL, eos_aU, eos_aL, eos_r1, eos_r2;
 };
 
 template <class C> inline LatDev<C> LatDevAny::get() const {
@@ -64,8 +64,8 @@ template <class C> inline LatDev<C> LatDevAny::get() const {
     d.partials = partials;
     d.G = C(G); d.omega = C(omega); d.Ux = C(Ux); d.Uy = C(Uy);
     d.Fx = C(Fx); d.Fy = C(Fy); d.rho_ref = C(rho_ref);
-    d.eos_tV = C(eos_tV); d.eos_tU = C(eos_tU); d.eos_tL = C(eos_tL);
-    d.eos_r1 = C(eos_r1); d.eos_r2 = C(eos_r2); d.eos_p1 = C(eos_p1); d.eos_p2 = C(eos_p2);
+    d.eos_kV = C(eos_kV); d.eos_kU = C(eos_kU); d.eos_kL = C(eos_kL);
+    d.eos_aU = C(eos_aU); d.eos_aL = C(eos_aL); d.eos_r1 = C(eos_r1); d.eos_r2 = C(eos_r2);
     return d;
 }
 
