@@ -24,19 +24,28 @@ HBM_PEAK_GBS = 8000.0
 DIAG_EVERY = 100
 
 
-KERNEL_SOURCES = ("paper_1202_6130_amd/csrc/kernels.hip", "paper_1202_6130_amd/csrc/lbm_device.hpp",
-                  "paper_1202_6130_amd/csrc/launch.hpp")
+KERNEL_SOURCES = {
+    9: ("paper_1202_6130_amd/csrc/kernels.hip", "paper_1202_6130_amd/csrc/lbm_device.hpp",
+        "paper_1202_6130_amd/csrc/launch.hpp"),
+    21: ("paper_1202_6130_amd/csrc/kernels_q21.hip", "paper_1202_6130_amd/csrc/lbm_device.hpp",
+         "paper_1202_6130_amd/csrc/launch.hpp"),
+}
 
 
-def kernel_sources_digest():
-    """SHA-256 over the device sources; a stored traffic figure is used only
-    while the kernels it was counted on are unchanged."""
+def kernel_sources_digest(q=9):
+    """SHA-256 over the device sources of the step kernel of D2Q<q>; a stored
+    traffic figure is used only while the kernel it was counted on is
+    unchanged."""
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in KERNEL_SOURCES[q]:
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def traffic_key(workload, storage, shape):
+    return f"{workload}:{storage}:" + (f"shape{shape}" if workload_q(workload) == 9 else "k_tile_q21")
 
 
 def stored_traffic(path, key):
@@ -47,14 +56,84 @@ def stored_traffic(path, key):
         return None
     with open(path) as fh:
         rec = json.load(fh).get(key)
-    if not rec or rec.get("kernel_sources_sha256") != kernel_sources_digest():
+    if not rec or rec.get("kernel_sources_sha256") != kernel_sources_digest(workload_q(key.split(":")[0])):
         return None
     return rec["bytes_per_launch"]
 
 
-def bytes_per_update(storage):
-    # 9 populations read + 9 written per lattice update
-    return {"f32": 72, "f16dev": 36, "f64": 144}[storage]
+def _counter_rows(run_dir):
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(run_dir, "**", "*_counter_collection.csv"), recursive=True))
+    if not files:
+        sys.exit(f"no *_counter_collection.csv under {run_dir}")
+    with open(files[-1]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def _step_dispatch_key(name):
+    """Tile shape (D2Q9) or "k_tile_q21" for a dispatch of a step kernel,
+    None for any other kernel (the diagnostic variant of k_tile_q21 included)."""
+    if "k_step_tiles<" in name and "k_step_tiles_batch" not in name:
+        return int(name.split("k_step_tiles<")[1].split(">")[0].split(",")[-1])
+    if "k_tile_q21<" in name and name.split("k_tile_q21<")[1].split(">")[0].split(",")[-1].strip() == "0":
+        return "k_tile_q21"
+    return None
+
+
+def ingest_counters(fetch_dir, write_dir, workload, storage, out_json):
+    """Per-launch HBM bytes of the step kernel from one rocprofv3 FETCH_SIZE
+    run and one WRITE_SIZE run of `bench.py --copy-ref` on the same workload:
+    each counter's KiB scaled by what it reads for the 1 GiB reference copy.
+    Updates out_json and prints a markdown table."""
+    import collections
+
+    def per_key(run_dir):
+        by = collections.defaultdict(list)
+        copy = None
+        for r in _counter_rows(run_dir):
+            k = _step_dispatch_key(r["Kernel_Name"])
+            if k is not None:
+                by[k].append(float(r["Counter_Value"]))
+            if r["Kernel_Name"] == "__amd_rocclr_copyBuffer" and int(r["Grid_Size"]) >= 65536:
+                copy = float(r["Counter_Value"])
+        if copy is None:
+            sys.exit(f"{run_dir}: no reference copy dispatch (run bench.py with --copy-ref)")
+        return by, copy
+
+    fb, fc = per_key(fetch_dir)
+    wb, wc = per_key(write_dir)
+    fs, ws = COPY_REF_BYTES / 1024 / fc, COPY_REF_BYTES / 1024 / wc
+    q = workload_q(workload)
+    nx, ny, _ = WORKLOADS[workload]
+    alg = bytes_per_update(storage, q) // 2 * nx * ny
+    data = {}
+    if os.path.exists(out_json):
+        with open(out_json) as fh:
+            data = json.load(fh)
+    print(f"FETCH_SIZE copy {fc:,.1f} KiB (scale {fs:.4f}), WRITE_SIZE copy {wc:,.1f} KiB (scale {ws:.4f}); "
+          f"algorithmic {alg:,} B each way per launch\n")
+    print("| Kernel / shape | dispatches | FETCH_SIZE KiB | read bytes (scaled) | read / algorithmic | "
+          "WRITE_SIZE KiB | write / algorithmic | total / algorithmic |")
+    print("|---|---|---|---|---|---|---|---|")
+    for k in sorted(fb, key=str):
+        f = sum(fb[k]) / len(fb[k])
+        w = sum(wb[k]) / len(wb[k])
+        rd, wr = f * fs * 1024, w * ws * 1024
+        shape = k if q == 9 else None
+        data[traffic_key(workload, storage, shape)] = {
+            "bytes_per_launch": round(rd + wr), "read_bytes": round(rd), "write_bytes": round(wr),
+            "fetch_kib": round(f, 2), "write_kib": round(w, 2), "fetch_scale": round(fs, 5),
+            "write_scale": round(ws, 5), "kernel_sources_sha256": kernel_sources_digest(q)}
+        print(f"| {k} | {len(fb[k])} | {f:,.0f} | {rd:,.0f} | {rd / alg:.3f} | {w:,.0f} | {wr / alg:.3f} | "
+              f"{(rd + wr) / (2 * alg):.3f} |")
+    with open(out_json, "w") as fh:
+        json.dump(data, fh, indent=1)
+
+
+def bytes_per_update(storage, q=9):
+    # q populations read + q written per lattice update
+    return 2 * q * {"f32": 4, "f16dev": 2, "f64": 8}[storage]
 
 
 def tile_desc(shape):
@@ -69,7 +148,18 @@ WORKLOADS = {
                                  "noise (sigma 4), 50% liquid, G=-5, tau=1, no solid"),
     "drop1024": (1024, 512, "sessile drop 1024x512, radius 160, flat solid band of 8 rows, "
                             "seeded wall amplitudes"),
+    # the paper's own lattice and fluid: D2Q21 (Tab. I) with the EOS pseudo-potential, G = -1
+    "spinodal4096_q21": (4096, 4096, "D2Q21, EOS pseudo-potential (G=-1, rho_1=0.222, rho_2=0.869): periodic "
+                                     "4096x4096 phase separation from seeded Gaussian-smoothed noise (sigma 4), "
+                                     "50% at rho 1.0 / 0.1, tau=1, no solid"),
+    "drop1024_q21": (1024, 512, "D2Q21, EOS pseudo-potential (G=-1): sessile drop 1024x512 at rho 1.0 / 0.1, "
+                                "radius 160, flat solid band of 8 rows, seeded wall amplitudes"),
 }
+Q21_TILE = "16 waves x 2 rows: 58 output columns x 26 output rows per workgroup (3 halo columns/rows each side)"
+
+
+def workload_q(name):
+    return 21 if name.endswith("_q21") else 9
 
 
 def make_lattice(name, storage, seg_rows):
@@ -77,16 +167,21 @@ def make_lattice(name, storage, seg_rows):
     from paper_1202_6130_amd import lbm
     st = {"f32": lbm.STORE_F32, "f16dev": lbm.STORE_F16DEV, "f64": lbm.STORE_F64}[storage]
     nx, ny, _ = WORKLOADS[name]
-    if name == "spinodal4096":
-        rho0 = I.spinodal_field(nx, seed=0)
+    if workload_q(name) == 21:
+        fluid = dict(lattice=lbm.D2Q21, psi_kind=lbm.PSI_EOS, G=-1.0)
+        dens = dict(rho_l=1.0, rho_g=0.1)
+    else:
+        fluid, dens = {}, {}
+    if name.startswith("spinodal"):
+        rho0 = I.spinodal_field(nx, seed=0, **dens)
         p = lbm.lbm_params_default(nx=nx, ny=ny, storage=st, diag_interval=DIAG_EVERY, seg_rows=seg_rows,
-                                   rho_ref=float(rho0.mean()))
+                                   rho_ref=float(rho0.mean()), **fluid)
     else:
         gr, ga = I.draw_wall_amplitudes(0)
-        rho0 = I.drop_field(nx, ny, 160.0)
+        rho0 = I.drop_field(nx, ny, 160.0, **dens)
         p = lbm.lbm_params_default(nx=nx, ny=ny, storage=st, wall_kind=lbm.WALL_FLAT_SLAB, G_R=float(gr[0]),
                                    G_A=float(ga[0]), diag_interval=DIAG_EVERY, seg_rows=seg_rows,
-                                   rho_ref=float(rho0.mean()))
+                                   rho_ref=float(rho0.mean()), **fluid)
     return lbm.Lattice(p, rho0), p
 
 
@@ -97,7 +192,9 @@ def time_gpu(name, storage, steps, warmup, seg_rows, tile=None):
     L, p = make_lattice(name, storage, seg_rows)
     nodes = p.nx * p.ny
     tune_ms = None
-    if tile is None:
+    if workload_q(name) == 21:
+        pass                      # one tile shape
+    elif tile is None:
         from paper_1202_6130_amd import lbm
         # 3 * tune_steps + 1 trial steps per shape, within the warm-up when it is long enough
         tune_steps = max(2, (warmup // len(lbm.lbm_tile_shapes()) - 1) // 3)
@@ -131,7 +228,7 @@ def time_gpu(name, storage, steps, warmup, seg_rows, tile=None):
     total_ms = t0.elapsed_time(t1)
     kern_ms = np.array([a.elapsed_time(b) for a, b in ev])
     d = L.diagnostics()
-    shape = L.tile_shape
+    shape = L.tile_shape if workload_q(name) == 9 else None
     L.close()
     return {
         "nodes": nodes, "ms_total": total_ms, "ms_per_step": total_ms / steps,
@@ -156,14 +253,21 @@ def copy_reference():
     del src, dst
 
 
-def cpu_baseline(seconds_hint=15.0):
+def cpu_baseline(seconds_hint=15.0, q=9):
     """The FP64 oracle (single thread, as it stands) on a bounded sample of the
-    same workload recipe: a 1024x1024 periodic spinodal lattice."""
+    same workload recipe: a 1024x1024 periodic spinodal lattice of the same
+    velocity set and pseudo-potential."""
     import oracle as O
     from paper_1202_6130_amd import inputs as I
     n = 1024
-    rho0 = I.spinodal_field(n, seed=0)
-    p = O.make_params(n, n, tau=1.0, G=-5.0)
+    if q == 21:
+        rho0 = I.spinodal_field(n, seed=0, rho_l=1.0, rho_g=0.1)
+        p = O.make_params(n, n, tau=1.0, G=-1.0, lattice=21, psi_kind=1)
+        what = "D2Q21 EOS"
+    else:
+        rho0 = I.spinodal_field(n, seed=0)
+        p = O.make_params(n, n, tau=1.0, G=-5.0)
+        what = "D2Q9"
     w = O.Walls.none(n, n)
     f = O.init(p, rho0)
     f = O.run(p, w, f, 1)            # page in
@@ -176,7 +280,7 @@ def cpu_baseline(seconds_hint=15.0):
             break
     dt = time.perf_counter() - t
     return {"value": n * n * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle, 1 thread, 1024x1024 periodic spinodal lattice (same recipe), "
+            "sample": f"FP64 oracle, 1 thread, 1024x1024 periodic {what} spinodal lattice (same recipe), "
                       f"{steps} steps in {dt:.1f} s"}
 
 
@@ -404,7 +508,14 @@ def main():
     ap.add_argument("--copy-ref", action="store_true",
                     help="after timing, run one plain device copy of 1 GiB (reference dispatch for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU work: read the rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE output directories of "
+                         "`bench.py --copy-ref` runs on --workload/--storage and record the step kernel's "
+                         "HBM bytes per launch in --traffic-json")
     args = ap.parse_args()
+    if args.ingest_counters:
+        ingest_counters(*args.ingest_counters, args.workload, args.storage, args.traffic_json)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the update is measured on a "
               "single MI355X and no multi-GPU path is built.", file=sys.stderr)
@@ -426,25 +537,30 @@ def main():
     if args.copy_ref:
         copy_reference()
     mlups = r["nodes"] * args.steps / (r["ms_total"] * 1e-3) / 1e6
-    bpu = bytes_per_update(args.storage)
+    q = workload_q(args.workload)
+    if q == 21 and args.storage == "f16dev":
+        sys.exit("D2Q21 runs with f32 or f64 storage")
+    bpu = bytes_per_update(args.storage, q)
     achieved = bpu * r["nodes"] / (r["kernel_ms_mean"] * 1e-3) / 1e9
-    traffic = stored_traffic(args.traffic_json, f"{args.workload}:{args.storage}:shape{r['tile_shape']}")
+    traffic = stored_traffic(args.traffic_json, traffic_key(args.workload, args.storage, r["tile_shape"]))
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.storage, "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload][2], "nx": WORKLOADS[args.workload][0],
                    "ny": WORKLOADS[args.workload][1], "storage": args.storage,
-                   "tile": tile_desc(r["tile_shape"]), "tile_tuned": args.tile is None,
+                   "lattice": f"D2Q{q}",
+                   "tile": tile_desc(r["tile_shape"]) if q == 9 else Q21_TILE,
+                   "tile_tuned": args.tile is None and q == 9,
                    "tune_ms_per_shape": r["tune_ms"], "diag_every": DIAG_EVERY},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": bpu * r["nodes"],
-                     "kernel": "k_step_tiles", "kernel_ms_mean": round(r["kernel_ms_mean"], 5),
+                     "kernel": "k_step_tiles" if q == 9 else "k_tile_q21", "kernel_ms_mean": round(r["kernel_ms_mean"], 5),
                      "bytes_per_update": bpu},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(q=q)
     print(json.dumps(out), flush=True)
 
 

@@ -93,7 +93,7 @@ int pop_count(const lbm_params &p) { return p.lattice == LBM_D2Q21 ? 21 : 9; }
 
 // Offsets (bytes) into one lattice's workspace.  fb and mom are adjacent: the
 // pair doubles as staging for host float64 arrays at creation.  For D2Q21 the
-// diagnostic partial rows follow its own tiling (one per wave).
+// diagnostic partial rows follow its own tiling (one per workgroup).
 Layout make_layout(const lbm_params &p) {
     Layout L{};
     const size_t N = size_t(p.nx) * p.ny, s = storage_bytes(p.storage), cb = compute_bytes(p.storage);
@@ -108,7 +108,8 @@ Layout make_layout(const lbm_params &p) {
     size_t o = 0;
     L.pstride = plane_stride(p);
     const size_t P = L.pstride, nq = size_t(pop_count(p));
-    if (p.lattice == LBM_D2Q21) L.waves = q21_tiles(uint32_t(p.nx), uint32_t(p.ny)) * kQ21Waves;
+    // D2Q21: one row of diagnostic partials per workgroup
+    if (p.lattice == LBM_D2Q21) L.waves = q21_tiles(uint32_t(p.nx), uint32_t(p.ny));
     L.fa = o; o = align_up(o + nq * P * s);
     L.fb = o; o = o + nq * P * s;                      // no padding: fb+mom contiguous
     L.mom = o; o = align_up(o + 3 * N * cb);

@@ -410,24 +410,33 @@ __global__ __launch_bounds__(kBlockThreads) void k_diag(const LatDev<C> *__restr
 // Deterministic reduction of partial rows: out[b*out_stride + j] = sum over
 // rows r in [ranges[2b], ranges[2b+1]) of part[r*stride + j], j < width, in a
 // fixed order.  One block per output row.
+constexpr uint32_t kReduceMaxWidth = 10;
+
 __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ part, const uint32_t *__restrict__ ranges,
                                                 uint32_t stride, uint32_t width, double *__restrict__ out,
                                                 uint32_t out_stride) {
-    __shared__ double sm[256];
-    const uint32_t b = blockIdx.x;
+    // one pass over the rows, every column at once; then a fixed-order tree
+    __shared__ double sm[kReduceMaxWidth][256];
+    const uint32_t b = blockIdx.x, t = threadIdx.x;
     const uint32_t beg = ranges[2 * b], end = ranges[2 * b + 1];
-    for (uint32_t j = 0; j < width; ++j) {
-        double acc = 0.0;
-        for (uint32_t r = beg + threadIdx.x; r < end; r += blockDim.x) acc += part[size_t(r) * stride + j];
-        sm[threadIdx.x] = acc;
-        __syncthreads();
-        for (uint32_t s = blockDim.x / 2; s > 0; s >>= 1) {
-            if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[size_t(b) * out_stride + j] = sm[0];
+    double acc[kReduceMaxWidth];
+#pragma unroll
+    for (uint32_t j = 0; j < kReduceMaxWidth; ++j) acc[j] = 0.0;
+    for (uint32_t r = beg + t; r < end; r += blockDim.x) {
+        const double *row = part + size_t(r) * stride;
+#pragma unroll
+        for (uint32_t j = 0; j < kReduceMaxWidth; ++j)
+            if (j < width) acc[j] += row[j];
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kReduceMaxWidth; ++j) sm[j][t] = acc[j];
+    __syncthreads();
+    for (uint32_t s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (t < s)
+            for (uint32_t j = 0; j < width; ++j) sm[j][t] += sm[j][t + s];
         __syncthreads();
     }
+    if (t < width) out[size_t(b) * out_stride + t] = sm[t][0];
 }
 
 // ------------------------------------------------ contact-angle isoline pass
@@ -740,6 +749,7 @@ hipError_t launch_diag(int storage, const void *lats, const uint4 *work, uint32_
 
 hipError_t launch_reduce(const double *part, const uint32_t *ranges, uint32_t nout, uint32_t stride,
                          uint32_t width, double *out, uint32_t out_stride, hipStream_t st) {
+    if (width > kReduceMaxWidth || width > stride) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_reduce, dim3(nout), dim3(256), 0, st, part, ranges, stride, width, out, out_stride);
     return hipGetLastError();
 }

@@ -6,12 +6,14 @@
 // which the 3 on each side are halo columns (58 output columns) and
 // kQ21Waves * kQ21Rows consecutive rows of which the 3 on each side are halo
 // rows.  Every wave loads its rows at once (21 pulled loads per row, shifts up
-// to +-3 in both directions), computes density and pseudo-potential of all 64
-// columns, including the halo ones from their own loads, and publishes them
-// in LDS; after one barrier every output node sums w_i psi(x + c_i) c_i over
-// the 20 moving directions from LDS, forms the forces of eqs. force_SC,
-// force_SC_FS and wall_shift, and either collides and stores (step) or
-// accumulates the diagnostic sums (diagnostic pass).
+// to +-3 in both directions), computes density, momentum and pseudo-potential
+// of all 64 columns, including the halo ones from their own loads, and
+// publishes the pseudo-potential in LDS; after one barrier every output node
+// sums w_i psi(x + c_i) c_i over the 20 moving directions from LDS, forms the
+// forces of eqs. force_SC, force_SC_FS and wall_shift, and either collides and
+// stores (step) or accumulates the diagnostic sums (diagnostic pass).  At
+// tau = 1 the collision needs only the moments, so the populations are not
+// kept across the barrier.
 #include <type_traits>
 
 #include "launch.hpp"
@@ -22,6 +24,7 @@ namespace lbmwet {
 namespace {
 
 constexpr int kH = 3;   // halo width: the largest |c_i| of D2Q21
+constexpr size_t kQ21LdsReserve = 96 * 1024;   // > half of the CU's 160 KB LDS
 
 // Pseudo-potential of the fluid-fluid force.  PSI 0: 1 - exp(-rho); PSI 1:
 // eq. EOS, psi^2 = 2 (rho theta - p_EOS) / theta (the 1/theta factor makes
@@ -103,20 +106,23 @@ template <class C> struct Node21 {
     C rho, inv_rho, jx, jy, ux, uy, Fx, Fy;
 };
 
-// Forces of one node (eqs. force_SC, force_SC_FS, wall_shift) given the
-// neighbour sums sx, sy = sum_i w_i psi(x + c_i) c_i.
+// Eq. M1 from differences of opposite populations (exact near rest).
+template <class C> __device__ inline void momentum21(const C f[Q21], C &jx, C &jy) {
+    const C d1 = f[1] - f[3], d2 = f[2] - f[4], d57 = f[5] - f[7], d68 = f[6] - f[8];
+    const C d9 = f[9] - f[11], d10 = f[10] - f[12], d13 = f[13] - f[15], d14 = f[14] - f[16];
+    const C d17 = f[17] - f[19], d18 = f[18] - f[20];
+    jx = ((d1 + (d57 - d68)) + C(2) * (d9 + (d13 - d14))) + C(3) * d17;
+    jy = ((d2 + (d57 + d68)) + C(2) * (d10 + (d13 + d14))) + C(3) * d18;
+}
+
+// Forces of one node (eqs. force_SC, force_SC_FS, wall_shift) given its
+// moments and the neighbour sums sx, sy = sum_i w_i psi(x + c_i) c_i.
 template <class C>
-__device__ inline Node21<C> node21(const C f[Q21], C rho, C psi_c, C sx, C sy, C phie, C Sx, C Sy,
+__device__ inline Node21<C> node21(C rho, C jx, C jy, C psi_c, C sx, C sy, C phie, C Sx, C Sy,
                                    const LatDev<C> &L) {
     Node21<C> s;
     s.rho = rho;
     s.inv_rho = recip<C>(rho);
-    // eq. M1 from differences of opposite populations (exact near rest)
-    const C d1 = f[1] - f[3], d2 = f[2] - f[4], d57 = f[5] - f[7], d68 = f[6] - f[8];
-    const C d9 = f[9] - f[11], d10 = f[10] - f[12], d13 = f[13] - f[15], d14 = f[14] - f[16];
-    const C d17 = f[17] - f[19], d18 = f[18] - f[20];
-    const C jx = ((d1 + (d57 - d68)) + C(2) * (d9 + (d13 - d14))) + C(3) * d17;
-    const C jy = ((d2 + (d57 + d68)) + C(2) * (d10 + (d13 + d14))) + C(3) * d18;
     s.jx = jx;
     s.jy = jy;
     s.ux = jx * s.inv_rho;
@@ -131,10 +137,11 @@ __device__ inline Node21<C> node21(const C f[Q21], C rho, C psi_c, C sx, C sy, C
 }
 
 // EDM-BGK collision (Sec. II.B): f' = (1 - 1/tau)(f - feq(u)) + feq(u*).
-template <class C> __device__ inline void collide21(C f[Q21], const Node21<C> &s, C omega) {
+// ONE: tau = 1, where f' = feq(u*) needs only the node's moments.
+template <class C, int ONE> __device__ inline void collide21(C f[Q21], const Node21<C> &s, C omega) {
     C fs[Q21];
     equilibrium21<C>(s.rho, s.inv_rho, s.jx + s.Fx, s.jy + s.Fy, fs);
-    if (omega == C(1)) {
+    if constexpr (ONE) {
 #pragma unroll
         for (int i = 0; i < Q21; ++i) f[i] = fs[i];
     } else {
@@ -147,7 +154,7 @@ template <class C> __device__ inline void collide21(C f[Q21], const Node21<C> &s
     close_mass21<C>(f, s.rho);
 }
 
-template <class S, class C, int WALL, int PSI, int DIAG>
+template <class S, class C, int WALL, int PSI, int DIAG, int ONE>
 __global__ __launch_bounds__(kQ21Waves * kWave) void k_tile_q21(LatDev<C> L, const void *__restrict__ src,
                                                                 void *__restrict__ dst, int write_mom, int compare,
                                                                 int update) {
@@ -174,11 +181,17 @@ __global__ __launch_bounds__(kQ21Waves * kWave) void k_tile_q21(LatDev<C> L, con
 #pragma unroll
     for (int c = -kH; c <= kH; ++c) xs[c + kH] = wrap_fast(x + 3 * nx - uint32_t(c + kH) + kH, nx);
 
-    C f[R][Q21], rho[R], psi[R];
+    // Populations stay in registers across the barrier only where the
+    // collision needs them (tau != 1); otherwise each row keeps its moments.
+    constexpr bool KEEP = !DIAG && !ONE;
+    C fk[KEEP ? R : 1][Q21], rho[R], jx[R], jy[R], psi[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const uint32_t k = uint32_t(w * R + j);
+        C *g = fk[KEEP ? j : 0];
         rho[j] = C(0);
+        jx[j] = C(0);
+        jy[j] = C(0);
         psi[j] = C(0);
         if (k < out_rows + 2 * kH) {
             const uint32_t r = wrap_fast(y0 + 3 * ny - kH + k, ny);
@@ -189,8 +202,9 @@ __global__ __launch_bounds__(kQ21Waves * kWave) void k_tile_q21(LatDev<C> L, con
 #pragma unroll
             for (int q = 0; q < Q21; ++q) raw[q] = buf.load(xs[kCx21[q] + kH], uint32_t(q) * P + ro[kCy21[q] + kH]);
 #pragma unroll
-            for (int q = 0; q < Q21; ++q) f[j][q] = Codec<S>::template decode<C>(raw[q], q, L.rho_ref);
-            rho[j] = density21<C>(f[j]);
+            for (int q = 0; q < Q21; ++q) g[q] = Codec<S>::template decode<C>(raw[q], q, L.rho_ref);
+            rho[j] = density21<C>(g);
+            momentum21<C>(g, jx[j], jy[j]);
             psi[j] = psi21<C, PSI>(L, rho[j]);
             psi_s[k][lane] = psi[j];
         }
@@ -223,7 +237,7 @@ __global__ __launch_bounds__(kQ21Waves * kWave) void k_tile_q21(LatDev<C> L, con
         const uint32_t n = r * nx + x;
         C phie, Sx, Sy;
         wall_terms<C, WALL>(L, row_wall<C, WALL>(L, r), n, phie, Sx, Sy);
-        const Node21<C> s = node21<C>(f[j], rho[j], psi[j], sx, sy, phie, Sx, Sy, L);
+        const Node21<C> s = node21<C>(rho[j], jx[j], jy[j], psi[j], sx, sy, phie, Sx, Sy, L);
         if constexpr (DIAG) {
             const C vx = s.ux + C(0.5) * s.Fx * s.inv_rho;
             const C vy = s.uy + C(0.5) * s.Fy * s.inv_rho;
@@ -247,24 +261,33 @@ __global__ __launch_bounds__(kQ21Waves * kWave) void k_tile_q21(LatDev<C> L, con
                 }
             }
         } else {
-            collide21<C>(f[j], s, L.omega);
+            C *g = fk[KEEP ? j : 0];
+            collide21<C, !KEEP>(g, s, L.omega);
             if (active) {
                 const uint32_t row = r * nx;
 #pragma unroll
                 for (int q = 0; q < Q21; ++q)
-                    out.store(Codec<S>::template encode<C>(f[j][q], q, L.rho_ref), x, uint32_t(q) * P + row);
+                    out.store(Codec<S>::template encode<C>(g[q], q, L.rho_ref), x, uint32_t(q) * P + row);
             }
         }
     }
     if constexpr (DIAG) {
+        // wave sums, then the workgroup's sum over its waves in a fixed order:
+        // one row of 8 partials per workgroup
+        __shared__ double red[kQ21Waves][6];
         const double v[6] = {s_rho, s_jx, s_jy, s_du, s_u, s_bad};
-        double *part = L.partials + 8 * (size_t(lb) * kQ21Waves + size_t(w));
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
             double t = v[i];
 #pragma unroll
             for (int o = kWave / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, kWave);
-            if (lane == 0) part[i] = t;
+            if (lane == 0) red[w][i] = t;
+        }
+        __syncthreads();
+        if (threadIdx.x < 6) {
+            double t = 0.0;
+            for (int v2 = 0; v2 < kQ21Waves; ++v2) t += red[v2][threadIdx.x];
+            L.partials[8 * size_t(lb) + threadIdx.x] = t;
         }
     }
 }
@@ -288,10 +311,22 @@ hipError_t launch_tile_q21(int storage, const LatDevAny &La, int wall, int parit
         const void *src = parity ? d.fb : d.fa;
         void *dst = parity ? d.fa : d.fb;
         const dim3 grid(q21_tiles(d.nx, d.ny)), block(kQ21Waves * kWave);
+        const bool one = DIAG || La.omega == 1.0;
+        // One workgroup per CU: its loads in flight (16 waves x 2 rows x 21
+        // planes x 256 B = 172 KB) from the 32 CUs of an XCD already exceed
+        // that XCD's 4 MB L2; a second resident workgroup evicts the halo lines
+        // neighbouring tiles share before they are read again (measured on the
+        // 4096^2 binary32 step: 0.94 ms with two workgroups per CU, 0.77 ms with
+        // one).  The unused dynamic LDS reservation is what caps residency.
+        const size_t lds_reserve = kQ21LdsReserve;
         auto go = [&](auto wallc, auto psic) {
             constexpr int WL = decltype(wallc)::value, PS = decltype(psic)::value;
-            hipLaunchKernelGGL((k_tile_q21<S, C, WL, PS, DIAG>), grid, block, 0, st, d, src, dst, write_mom, compare,
-                               update);
+            if (one)
+                hipLaunchKernelGGL((k_tile_q21<S, C, WL, PS, DIAG, 1>), grid, block, lds_reserve, st, d, src, dst, write_mom,
+                                   compare, update);
+            else if constexpr (!DIAG)
+                hipLaunchKernelGGL((k_tile_q21<S, C, WL, PS, 0, 0>), grid, block, lds_reserve, st, d, src, dst, write_mom,
+                                   compare, update);
         };
         using RowW = std::integral_constant<int, WALL_ROW>;
         using NodeW = std::integral_constant<int, WALL_NODE>;
