@@ -3,6 +3,7 @@
     python tests/golden/make_golden_full.py drop      # about an hour, one core
     python tests/golden/make_golden_full.py channel   # about half an hour
     python tests/golden/make_golden_full.py spinodal --threads 6   # about an hour on 6 cores
+    python tests/golden/make_golden_full.py laplace21 --threads 8  # under a minute
 
 drop: 1024x512 sessile drop of radius 160 on the lower face of a flat solid
 band of 8 rows (tanh wall functions of width 2, core range 1, tail range 3,
@@ -19,6 +20,13 @@ spinodal: 4096x4096 periodic lattice, no solid, G = -5, tau = 1, from the
 seeded phase-separation field (Gaussian-smoothed noise, sigma 4, 50% liquid);
 rho, u at 1024 seeded nodes and the totals after 100, 500, 1000, 2000 and
 5000 steps (OpenMP build of the oracle: bitwise the serial result).
+
+laplace21: the paper's own fluid (D2Q21, Tab. I; EOS pseudo-potential with
+G = -1, eq. EOS): free discs of radius 12, 16 and 24 in a periodic 96x96 box
+from rho 1.0 inside, 0.1 outside, tau = 1, 4000 steps.  Stores the bulk
+densities inside and outside, the pressure jump p_EOS(rho_in) -
+p_EOS(rho_out), the radius of the liquid area and the Laplace fit
+dp = gamma / R + b (Sec. II.B reports gamma of about 0.09).
 
 Only the oracle computes these values; a change to its arithmetic regenerates
 them in a commit that names the passage of the paper justifying it.
@@ -40,6 +48,18 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DROP = dict(nx=1024, ny=512, radius=160.0, steps=20000, seed=0)
 CHANNEL = dict(nx=32, ny=256, rho=2.0, force=1e-6, steps=600000, seed=0)
 SPINODAL = dict(n=4096, seed=0, checkpoints=(100, 500, 1000, 2000, 5000))
+LAPLACE21 = dict(n=96, radii=(12.0, 16.0, 24.0), steps=4000)
+
+
+def laplace_disc(p, w, rho, n):
+    """Bulk densities (4x4 nodes at the disc centre, 3x3 at the box corner),
+    pressure jump from the bulk pressure p_EOS, and the radius of the liquid
+    area (mass above the vapour level over the density contrast)."""
+    rin = float(rho[n // 2 - 2:n // 2 + 2, n // 2 - 2:n // 2 + 2].mean())
+    rout = float(rho[:3, :3].mean())
+    dp = O.p_eos(p, rin) - O.p_eos(p, rout)
+    req = float(np.sqrt(((rho - rout).sum() / (rin - rout)) / np.pi))
+    return {"rho_in": rin, "rho_out": rout, "dp": dp, "R": req}
 
 
 def sample_nodes(nx, ny, count, seed):
@@ -129,6 +149,30 @@ def spinodal():
         print("wrote", out, "through t =", tc, flush=True)
 
 
+def laplace21():
+    n = LAPLACE21["n"]
+    discs = []
+    for R in LAPLACE21["radii"]:
+        p = O.make_params(n, n, tau=1.0, G=-1.0, lattice=21, psi_kind=1)
+        w = O.Walls.none(n, n)
+        f = O.run(p, w, O.init(p, I.disc_field(n, n, R, rho_l=1.0, rho_g=0.1)), LAPLACE21["steps"])
+        rho, _, _, _ = O.macros(p, w, f)
+        d = laplace_disc(p, w, rho, n)
+        d["R0"] = R
+        discs.append(d)
+        print("laplace21", d, flush=True)
+    x = np.array([1.0 / d["R"] for d in discs])
+    y = np.array([d["dp"] for d in discs])
+    gamma, b = np.polyfit(x, y, 1)
+    data = {"config": {**LAPLACE21, "tau": 1.0, "G": -1.0, "lattice": 21, "psi": "eos", "eos": list(O.EOS_PAPER),
+                       "rho_l": 1.0, "rho_g": 0.1, "width": 2.0},
+            "discs": discs, "gamma": float(gamma), "intercept": float(b)}
+    out = os.path.join(HERE, "laplace21_fp64.json")
+    with open(out, "w") as fh:
+        json.dump(data, fh, indent=1)
+    print("wrote", out, "gamma", gamma, "intercept", b, flush=True)
+
+
 if __name__ == "__main__":
     args = sys.argv[1:]
     if "--threads" in args:
@@ -142,3 +186,5 @@ if __name__ == "__main__":
         drop()
     if "channel" in which:
         channel()
+    if "laplace21" in which:
+        laplace21()

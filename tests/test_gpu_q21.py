@@ -112,3 +112,35 @@ def test_q21_rejects_unsupported():
                                                        storage=lbm.STORE_F16DEV))
     with pytest.raises(lbm.LbmError):
         lbm.lbm_workspace_bytes(lbm.lbm_params_default(nx=8, ny=8, psi_kind=lbm.PSI_EOS))
+
+
+def test_q21_laplace_f32_against_oracle():
+    """Pressure jumps across D2Q21 EOS discs (the paper's surface tension
+    measurement) in binary32 against the oracle's values, written by
+    tests/golden/make_golden_full.py laplace21."""
+    import json, os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "laplace21_fp64.json")) as fh:
+        g = json.load(fh)
+    cfg = g["config"]
+    n = cfg["n"]
+    po = O.make_params(n, n, tau=1.0, G=-1.0, lattice=21, psi_kind=1)
+    pts = []
+    for d in g["discs"]:
+        rho0 = I.disc_field(n, n, d["R0"], rho_l=cfg["rho_l"], rho_g=cfg["rho_g"])
+        p = lbm.lbm_params_default(nx=n, ny=n, storage=lbm.STORE_F32, lattice=lbm.D2Q21, psi_kind=lbm.PSI_EOS,
+                                   G=-1.0)
+        L = lbm.Lattice(p, rho0)
+        L.step(cfg["steps"])
+        rho = L.moments()[0]
+        L.close()
+        rin = rho[n // 2 - 2:n // 2 + 2, n // 2 - 2:n // 2 + 2].mean()
+        rout = rho[:3, :3].mean()
+        dp = O.p_eos(po, rin) - O.p_eos(po, rout)
+        req = np.sqrt(((rho - rout).sum() / (rin - rout)) / np.pi)
+        assert abs(rin - d["rho_in"]) < 1e-5 and abs(rout - d["rho_out"]) < 1e-5
+        assert abs(dp - d["dp"]) < 2e-3 * d["dp"]
+        pts.append((1.0 / req, dp))
+    x, y = np.array(pts).T
+    gamma, _ = np.polyfit(x, y, 1)
+    print(f"D2Q21 EOS Laplace FP32: gamma {gamma:.5f} (oracle {g['gamma']:.5f})")
+    assert abs(gamma - g["gamma"]) < 2e-3 * g["gamma"]
