@@ -27,7 +27,7 @@ class Params(ctypes.Structure):
                 ("eps", ctypes.c_double),
                 ("U_wall", ctypes.c_double * 2), ("F_ext", ctypes.c_double * 2),
                 ("lattice", ctypes.c_int), ("psi_kind", ctypes.c_int),
-                ("eos", ctypes.c_double * 5)]
+                ("eos", ctypes.c_double * 5), ("collision", ctypes.c_int)]
 
 
 # eq. EOS parameters of the paper: theta_V/theta, theta_U/theta, theta_L/theta,
@@ -60,6 +60,7 @@ def lib():
         P = ctypes.POINTER(Params)
         L.orc_equilibrium.argtypes = [ctypes.c_double] * 3 + [dp]
         L.orc_equilibrium_q.argtypes = [ctypes.c_int] + [ctypes.c_double] * 3 + [dp]
+        L.orc_project_q.argtypes = [ctypes.c_int, dp, dp]
         L.orc_psi.argtypes = [P, ctypes.c_double]
         L.orc_psi.restype = ctypes.c_double
         L.orc_p_eos.argtypes = [P, ctypes.c_double]
@@ -102,13 +103,14 @@ def _p(a):
 
 
 def make_params(nx, ny, tau=1.0, G=-5.0, G_R=0.0, G_A=0.0, eps=1.0,
-                U_wall=(0.0, 0.0), F_ext=(0.0, 0.0), lattice=9, psi_kind=0, eos=EOS_PAPER):
+                U_wall=(0.0, 0.0), F_ext=(0.0, 0.0), lattice=9, psi_kind=0, eos=EOS_PAPER, collision=0):
     p = Params()
     p.nx, p.ny = int(nx), int(ny)
     p.tau, p.G, p.G_R, p.G_A, p.eps = tau, G, G_R, G_A, eps
     p.U_wall[0], p.U_wall[1] = U_wall
     p.F_ext[0], p.F_ext[1] = F_ext
     p.lattice, p.psi_kind = int(lattice), int(psi_kind)
+    p.collision = int(collision)
     for k, v in enumerate(eos):
         p.eos[k] = v
     return p
@@ -157,6 +159,14 @@ class Walls:
         phi = np.zeros((ny, nx)); psiR = np.zeros((ny, nx)); psiA = np.zeros((ny, nx))
         lib().orc_flat_slab_walls(nx, ny, P, width, core, tail, _p(phi), _p(psiR), _p(psiA))
         return Walls(phi, psiR, psiA)
+
+
+def project(f, lattice=9):
+    """Projection of one node's populations onto eq. f2 (Sec. II.A)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.zeros_like(f)
+    lib().orc_project_q(lattice, _p(f), _p(out))
+    return out
 
 
 def equilibrium(rho, ux, uy, lattice=9):

@@ -258,6 +258,32 @@ void orc_forces(const orc_params *p, const double *phi, const double *psiR,
     free(psiFS);
 }
 
+/* Projection (Sec. II.A, after eq. f2): the populations are replaced by the
+ * truncated Hermite form of eq. f2 built from their own M0, M1 and M2
+ * (eqs. M0-M2), which keeps those three moments and drops every component of
+ * higher order. */
+void orc_project_q(int lattice, const double *f, double *fp)
+{
+    const orc_lattice L = lattice_of(lattice);
+    const double th = L.theta;
+    double M0 = 0, M1x = 0, M1y = 0, Mxx = 0, Mxy = 0, Myy = 0;
+    for (int i = 0; i < L.Q; ++i) {
+        double cx = L.cx[i], cy = L.cy[i];
+        M0 += f[i];
+        M1x += f[i] * cx;
+        M1y += f[i] * cy;
+        Mxx += f[i] * cx * cx;
+        Mxy += f[i] * cx * cy;
+        Myy += f[i] * cy * cy;
+    }
+    for (int i = 0; i < L.Q; ++i) {
+        double cx = L.cx[i], cy = L.cy[i];
+        /* (M2 - M0 theta I) : (c c - theta I) */
+        double h2 = (Mxx - M0 * th) * (cx * cx - th) + 2.0 * Mxy * cx * cy + (Myy - M0 * th) * (cy * cy - th);
+        fp[i] = L.w[i] * (M0 + (M1x * cx + M1y * cy) / th + h2 / (2.0 * th * th));
+    }
+}
+
 void orc_collide(const orc_params *p, const double *phi, const double *psiR,
                  const double *psiA, const double *f, double *fpost)
 {
@@ -271,11 +297,17 @@ void orc_collide(const orc_params *p, const double *phi, const double *psiR,
     orc_forces(p, phi, psiR, psiA, f, rho, ux, uy, NULL, NULL, NULL, NULL, usx, usy);
 #pragma omp parallel for schedule(static)
     for (long n = 0; n < N; ++n) {
-        double feq_u[21], feq_s[21];
+        double feq_u[21], feq_s[21], fproj[21];
+        const double *fn = &f[n * Q];
         orc_equilibrium_q(p->lattice, rho[n], ux[n], uy[n], feq_u);
         orc_equilibrium_q(p->lattice, rho[n], usx[n], usy[n], feq_s);
+        if (p->collision == 1) {
+            /* the projection step enforces eq. f2 before the collision */
+            orc_project_q(p->lattice, fn, fproj);
+            fn = fproj;
+        }
         for (int i = 0; i < Q; ++i) {
-            double fi = f[n * Q + i];
+            double fi = fn[i];
             /* BGK relaxation (eq. BE-BGK) plus the EDM force term */
             fpost[n * Q + i] = fi - (fi - feq_u[i]) / p->tau + (feq_s[i] - feq_u[i]);
         }

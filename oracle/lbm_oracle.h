@@ -43,6 +43,7 @@ typedef struct {
     int psi_kind;      /* 0: psi = 1 - exp(-rho); 1: EOS, eq. EOS            */
     double eos[5];     /* EOS: theta_V/theta, theta_U/theta, theta_L/theta,
                           rho_1, rho_2 (eq. EOS)                              */
+    int collision;     /* 0: BGK; 1: projection onto eq. f2 before BGK       */
 } orc_params;
 
 /* D2Q9 tables (the oracle's own copy). */
@@ -91,8 +92,13 @@ void orc_forces(const orc_params *p, const double *phi, const double *psiR,
                 double *uy, double *Fff, double *Flr, double *dFs,
                 double *Ftot, double *usx, double *usy);
 
+/* Projection of one node's Q populations onto the truncated Hermite form of
+ * eq. f2 with their own M0, M1, M2 (Sec. II.A). */
+void orc_project_q(int lattice, const double *f, double *fp);
+
 /* Collision at every node (no streaming): fpost = f - (f - feq(u))/tau
- * + feq(u*) - feq(u).  Exposed separately so the tests can check the
+ * + feq(u*) - feq(u), with f first replaced by its projection when
+ * p->collision == 1.  Exposed separately so the tests can check the
  * conservation laws of the collision alone. */
 void orc_collide(const orc_params *p, const double *phi, const double *psiR,
                  const double *psiA, const double *f, double *fpost);
