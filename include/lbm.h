@@ -91,6 +91,16 @@ typedef int lbm_status;
 #define LBM_PSI_EXP 0
 #define LBM_PSI_EOS 1
 
+/* Collision (Sec. II.A-B):
+ *  BGK       : f' = (1 - 1/tau)(f - feq(u)) + feq(u*)   (EDM forcing)
+ *  PROJECTED : the projection step the paper adds after eq. f2: f is first
+ *              replaced by the truncated Hermite form of eq. f2 with its own
+ *              M0, M1, M2, then BGK as above; equivalently the non-equilibrium
+ *              part f - feq(u) is reduced to w_i (c_i c_i - theta I):Pi / (2
+ *              theta^2), Pi its second moment.  Identical to BGK at tau = 1. */
+#define LBM_COLL_BGK       0
+#define LBM_COLL_PROJECTED 1
+
 typedef struct {
     int32_t nx, ny;          /* lattice size, both >= 1; Q*nx*ny*(bytes per
                                 stored population) < 2^32                    */
@@ -115,6 +125,7 @@ typedef struct {
     double eos[5];           /* eq. EOS: theta_V/theta, theta_U/theta,
                                 theta_L/theta, rho_1, rho_2 (defaults: the
                                 paper's 0.25, -0.25, 1, 0.222, 0.869)        */
+    int32_t collision;       /* LBM_COLL_BGK (default) or LBM_COLL_PROJECTED  */
     int32_t reserved;        /* must be 0                                     */
 } lbm_params;
 
@@ -123,7 +134,7 @@ typedef struct lbm_ctx lbm_ctx;
 /* Fills *p with the defaults: tau = 1, G = -5, G_R = G_A = 0, eps = 1,
  * U_wall = F_ext = 0, wall_width = 2, core_range = 1, tail_range = 3,
  * rho_ref = 1, slab_rows = 8, storage F32, wall NONE, diag_interval 0,
- * lattice D2Q9, psi EXP, eos = the paper's parameters. */
+ * lattice D2Q9, psi EXP, eos = the paper's parameters, collision BGK. */
 lbm_status lbm_params_default(lbm_params *p);
 
 /* Last error message of the calling thread ("" if none).  Never NULL. */

@@ -138,6 +138,8 @@ lbm_status validate(const lbm_params *p) {
         return fail(LBM_EINVAL, "lattice too large: Q*(nx*ny + pad)*bytes must be < 2^32");
     if (p->psi_kind != LBM_PSI_EXP && p->psi_kind != LBM_PSI_EOS)
         return fail(LBM_EINVAL, "unknown psi_kind %d", p->psi_kind);
+    if (p->collision != LBM_COLL_BGK && p->collision != LBM_COLL_PROJECTED)
+        return fail(LBM_EINVAL, "unknown collision %d", p->collision);
     if (p->lattice == LBM_D2Q21 && p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_F64)
         return fail(LBM_EINVAL, "D2Q21 takes storage F32 or F64");
     if (p->psi_kind == LBM_PSI_EOS) {
@@ -306,6 +308,7 @@ lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const d
     L.rho_ref = p->storage == LBM_STORE_F16DEV ? p->rho_ref : 1.0;
     L.lattice = pop_count(*p);
     L.psi_kind = p->psi_kind;
+    L.collision = p->collision;
     {
         // eq. EOS with branch slopes s_b theta (s_b = eos[0..2]), pressure
         // continuous at rho_1 = eos[3] and rho_2 = eos[4].  The pseudo-potential
@@ -395,6 +398,7 @@ lbm_status lbm_params_default(lbm_params *p) {
     p->slab_rows = 8;
     p->lattice = LBM_D2Q9;
     p->psi_kind = LBM_PSI_EXP;
+    p->collision = LBM_COLL_BGK;
     const double eos[5] = {0.25, -0.25, 1.0, 0.222, 0.869};
     for (int i = 0; i < 5; ++i) p->eos[i] = eos[i];
     return LBM_OK;

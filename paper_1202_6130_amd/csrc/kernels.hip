@@ -176,7 +176,7 @@ template <class S, class C, int WALL> struct StepAct {
         C phie, Sx, Sy;
         wall_terms<C, WALL>(L, rw, n, phie, Sx, Sy);
         NodeState<C> s = node_forces<C>(f, rho, psi_c, sx, sy, phie, Sx, Sy, L.G, L.Ux, L.Uy, L.Fx, L.Fy);
-        collide<C>(f, s, L.omega);
+        collide<C>(f, s, L.omega, L.collision);
         if (active) {
             const uint32_t row = y * L.nx;
 #pragma unroll

@@ -102,9 +102,7 @@ template <class C> __device__ inline void close_mass21(C f[Q21], C rho) {
     f[0] = rho - (density21<C>(f));
 }
 
-template <class C> struct Node21 {
-    C rho, inv_rho, jx, jy, ux, uy, Fx, Fy;
-};
+template <class C> using Node21 = NodeState<C>;
 
 // Eq. M1 from differences of opposite populations (exact near rest).
 template <class C> __device__ inline void momentum21(const C f[Q21], C &jx, C &jy) {
@@ -127,20 +125,15 @@ __device__ inline Node21<C> node21(C rho, C jx, C jy, C psi_c, C sx, C sy, C phi
     s.jy = jy;
     s.ux = jx * s.inv_rho;
     s.uy = jy * s.inv_rho;
-    const C ffx = -L.G * psi_c * sx, ffy = -L.G * psi_c * sy;
-    const C lrx = rho * Sx, lry = rho * Sy;
-    const C dsx = phie * (rho * (L.Ux - s.ux) - ffx);
-    const C dsy = phie * (rho * (L.Uy - s.uy) - ffy);
-    s.Fx = ((ffx + lrx) + dsx) + L.Fx;
-    s.Fy = ((ffy + lry) + dsy) + L.Fy;
+    momentum_after_force<C>(s, psi_c, sx, sy, phie, Sx, Sy, L.G, L.Ux, L.Uy, L.Fx, L.Fy);
     return s;
 }
 
 // EDM-BGK collision (Sec. II.B): f' = (1 - 1/tau)(f - feq(u)) + feq(u*).
 // ONE: tau = 1, where f' = feq(u*) needs only the node's moments.
-template <class C, int ONE> __device__ inline void collide21(C f[Q21], const Node21<C> &s, C omega) {
+template <class C, int ONE> __device__ inline void collide21(C f[Q21], const Node21<C> &s, C omega, int projected) {
     C fs[Q21];
-    equilibrium21<C>(s.rho, s.inv_rho, s.jx + s.Fx, s.jy + s.Fy, fs);
+    equilibrium21<C>(s.rho, s.inv_rho, s.jsx, s.jsy, fs);
     if constexpr (ONE) {
 #pragma unroll
         for (int i = 0; i < Q21; ++i) f[i] = fs[i];
@@ -149,7 +142,10 @@ template <class C, int ONE> __device__ inline void collide21(C f[Q21], const Nod
         equilibrium21<C>(s.rho, s.inv_rho, s.jx, s.jy, fu);
         const C keep = C(1) - omega;
 #pragma unroll
-        for (int i = 0; i < Q21; ++i) f[i] = keep * (f[i] - fu[i]) + fs[i];
+        for (int i = 0; i < Q21; ++i) fu[i] = f[i] - fu[i];
+        if (projected) project_neq<C, VelSet<21>>(fu);
+#pragma unroll
+        for (int i = 0; i < Q21; ++i) f[i] = keep * fu[i] + fs[i];
     }
     close_mass21<C>(f, s.rho);
 }
@@ -262,7 +258,7 @@ __global__ __launch_bounds__(kQ21Waves * kWave) void k_tile_q21(LatDev<C> L, con
             }
         } else {
             C *g = fk[KEEP ? j : 0];
-            collide21<C, !KEEP>(g, s, L.omega);
+            collide21<C, !KEEP>(g, s, L.omega, L.collision);
             if (active) {
                 const uint32_t row = r * nx;
 #pragma unroll

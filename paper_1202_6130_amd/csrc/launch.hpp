@@ -32,6 +32,7 @@ struct LatDevAny {
     // equation-of-state pseudo-potential (eq. EOS) per branch b (vapour,
     // unstable, liquid): psi^2 = k_b (rho - rho_b) + a_b with rho_b = 0, r1, r2
     double eos_kV = 0, eos_kU = 0, eos_kL = 0, eos_aU = 0, eos_aL = 0, eos_r1 = 0, eos_r2 = 0;
+    int collision = 0;             // 1: non-equilibrium part projected onto eq. f2
 
     template <class C> LatDev<C> get() const;
 };
@@ -49,6 +50,7 @@ template <class C> struct LatDev {
     double *partials;
     C G, omega, Ux, Uy, Fx, Fy, rho_ref;
     C eos_kV, eos_kU, eos_kL, eos_aU, eos_aL, eos_r1, eos_r2;
+    int collision;
 };
 
 template <class C> inline LatDev<C> LatDevAny::get() const {
@@ -66,6 +68,7 @@ template <class C> inline LatDev<C> LatDevAny::get() const {
     d.Fx = C(Fx); d.Fy = C(Fy); d.rho_ref = C(rho_ref);
     d.eos_kV = C(eos_kV); d.eos_kU = C(eos_kU); d.eos_kL = C(eos_kL);
     d.eos_aU = C(eos_aU); d.eos_aL = C(eos_aL); d.eos_r1 = C(eos_r1); d.eos_r2 = C(eos_r2);
+    d.collision = collision;
     return d;
 }
 

@@ -62,6 +62,9 @@ template <> struct VelSet<9> {
     __device__ static inline int cx(int q) { return kCx[q]; }
     __device__ static inline int cy(int q) { return kCy[q]; }
     __device__ static inline double w(int q) { return kW[q]; }
+    __host__ __device__ static constexpr int cxc(int q) { return kCx[q]; }
+    __host__ __device__ static constexpr int cyc(int q) { return kCy[q]; }
+    __host__ __device__ static constexpr double wc(int q) { return kW[q]; }
 };
 template <> struct VelSet<21> {
     static constexpr int Q = 21;
@@ -69,6 +72,9 @@ template <> struct VelSet<21> {
     __device__ static inline int cx(int q) { return kCx21[q]; }
     __device__ static inline int cy(int q) { return kCy21[q]; }
     __device__ static inline double w(int q) { return kW21[q]; }
+    __host__ __device__ static constexpr int cxc(int q) { return kCx21[q]; }
+    __host__ __device__ static constexpr int cyc(int q) { return kCy21[q]; }
+    __host__ __device__ static constexpr double wc(int q) { return kW21[q]; }
 };
 
 constexpr int kWave = 64;          // CDNA wavefront width
@@ -330,7 +336,29 @@ template <class C> struct NodeState {
     C jx, jy;                      // momentum j = sum_i f_i c_i (pre-force)
     C ux, uy;                      // u = j / rho
     C Fx, Fy;                      // total force density
+    C jsx, jsy;                    // rho u* = j + F, rounded once
 };
+
+// rho u* = j + F with F = F_FF + F_LR + phi^eps [rho (U - u) - F_FF] + F_ext
+// (eqs. force_SC, force_SC_FS, wall_shift), rearranged without cancellation
+// as (1 - phi^eps)(j + F_FF) + phi^eps rho U + F_LR + F_ext and formed in
+// binary64 whatever the storage: near a wall F_FF and F_LR reach 0.1-0.2
+// while a driving force is ~1e-6, and binary32 sums of those terms lose the
+// driving force to a rounding that repeats every step.
+template <class C>
+__device__ inline void momentum_after_force(NodeState<C> &s, C psi_c, C sx, C sy, C phie, C Sx, C Sy, C G,
+                                            C Ux, C Uy, C Fxe, C Fye) {
+    const double r = double(s.rho), ph = double(phie), om = 1.0 - ph;
+    const double gp = -double(G) * double(psi_c);
+    const double ffx = gp * double(sx), ffy = gp * double(sy);
+    const double jx = double(s.jx), jy = double(s.jy);
+    const double jsx = om * (jx + ffx) + ((ph * (r * double(Ux)) + r * double(Sx)) + double(Fxe));
+    const double jsy = om * (jy + ffy) + ((ph * (r * double(Uy)) + r * double(Sy)) + double(Fye));
+    s.jsx = C(jsx);
+    s.jsy = C(jsy);
+    s.Fx = C(jsx - jx);
+    s.Fy = C(jsy - jy);
+}
 
 // Forces of one node (eqs. force_SC, force_SC_FS, wall_shift) given the
 // neighbour sums of psi.
@@ -345,15 +373,9 @@ __device__ inline NodeState<C> node_forces(const C f[Q], C rho, C psi_c, C sx, C
     s.jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
     s.ux = s.jx * s.inv_rho;
     s.uy = s.jy * s.inv_rho;
-    C ffx = -G * psi_c * sx;
-    C ffy = -G * psi_c * sy;
-    // long-range wall force: rho * S (S precomputed from the static psi_FS)
-    C lrx = rho * Sx, lry = rho * Sy;
-    // short-range exchange: phi^eps [rho (U - u) - F_FF]
-    C dsx = phie * (rho * (Ux - s.ux) - ffx);
-    C dsy = phie * (rho * (Uy - s.uy) - ffy);
-    s.Fx = ((ffx + lrx) + dsx) + Fxe;
-    s.Fy = ((ffy + lry) + dsy) + Fye;
+    // long-range wall force rho S (S precomputed from the static psi_FS);
+    // short-range exchange phi^eps [rho (U - u) - F_FF]
+    momentum_after_force<C>(s, psi_c, sx, sy, phie, Sx, Sy, G, Ux, Uy, Fxe, Fye);
     return s;
 }
 
@@ -397,9 +419,31 @@ template <class C> __device__ inline void close_mass(C f[Q], C rho) {
 // EDM-BGK collision: f' = f - (f - feq(u))/tau + feq(u*) - feq(u)
 //                       = (1 - 1/tau) (f - feq(u)) + feq(u*),
 // with rho u* = j + F.
-template <class C> __device__ inline void collide(C f[Q], const NodeState<C> &s, C omega) {
+// The non-equilibrium part g = f - feq(u) reduced to its component in the
+// truncated Hermite form of eq. f2 (the projection step of Sec. II.A applied
+// to f; the equilibrium is already of that form): with Pi = sum_i g_i c_i c_i,
+// g_i <- w_i (c_i c_i - theta I) : Pi / (2 theta^2).  Used by both lattices.
+template <class C, class VS> __device__ inline void project_neq(C g[VS::Q]) {
+    constexpr double th = VS::theta;
+    C pxx = C(0), pxy = C(0), pyy = C(0);
+#pragma unroll
+    for (int i = 1; i < VS::Q; ++i) {
+        const int cx = VS::cxc(i), cy = VS::cyc(i);
+        if (cx != 0) pxx += C(cx * cx) * g[i];
+        if (cx * cy != 0) pxy += C(cx * cy) * g[i];
+        if (cy != 0) pyy += C(cy * cy) * g[i];
+    }
+#pragma unroll
+    for (int i = 0; i < VS::Q; ++i) {
+        const int cx = VS::cxc(i), cy = VS::cyc(i);
+        const C k = C(VS::wc(i) / (2.0 * th * th));
+        g[i] = k * ((C(cx * cx - th) * pxx + C(2 * cx * cy) * pxy) + C(cy * cy - th) * pyy);
+    }
+}
+
+template <class C> __device__ inline void collide(C f[Q], const NodeState<C> &s, C omega, int projected) {
     C fs[Q];
-    equilibrium<C>(s.rho, s.inv_rho, s.jx + s.Fx, s.jy + s.Fy, fs);
+    equilibrium<C>(s.rho, s.inv_rho, s.jsx, s.jsy, fs);
     if (omega == C(1)) {
         // tau = 1: the factor (1 - 1/tau) is exactly zero, f' = feq(u*)
 #pragma unroll
@@ -411,7 +455,10 @@ template <class C> __device__ inline void collide(C f[Q], const NodeState<C> &s,
     equilibrium<C>(s.rho, s.inv_rho, s.jx, s.jy, fu);
     const C keep = C(1) - omega;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = keep * (f[i] - fu[i]) + fs[i];
+    for (int i = 0; i < Q; ++i) fu[i] = f[i] - fu[i];
+    if (projected) project_neq<C, VelSet<9>>(fu);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = keep * fu[i] + fs[i];
     close_mass<C>(f, s.rho);
 }
 

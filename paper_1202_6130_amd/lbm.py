@@ -18,6 +18,7 @@ STORE_F32, STORE_F16DEV, STORE_F64, STORE_F32X = 0, 1, 2, 3
 WALL_NONE, WALL_FLAT_SLAB, WALL_FIELDS = 0, 1, 2
 D2Q9, D2Q21 = 9, 21
 PSI_EXP, PSI_EOS = 0, 1
+COLL_BGK, COLL_PROJECTED = 0, 1
 
 _NAMES = {LBM_EINVAL: "EINVAL", LBM_ENOMEM: "ENOMEM", LBM_EDEVICE: "EDEVICE", LBM_EUNSTABLE: "EUNSTABLE",
           LBM_ENOFIT: "ENOFIT", LBM_ESTATE: "ESTATE"}
@@ -40,7 +41,7 @@ class lbm_params(ctypes.Structure):
                 ("slab_rows", ctypes.c_int32), ("diag_interval", ctypes.c_int32),
                 ("seg_rows", ctypes.c_int32), ("lattice", ctypes.c_int32),
                 ("psi_kind", ctypes.c_int32), ("eos", ctypes.c_double * 5),
-                ("reserved", ctypes.c_int32)]
+                ("collision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
