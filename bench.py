@@ -162,7 +162,7 @@ def workload_q(name):
     return 21 if name.endswith("_q21") else 9
 
 
-def make_lattice(name, storage, seg_rows):
+def make_lattice(name, storage, seg_rows, tau=1.0, collision=0):
     from paper_1202_6130_amd import inputs as I
     from paper_1202_6130_amd import lbm
     st = {"f32": lbm.STORE_F32, "f16dev": lbm.STORE_F16DEV, "f64": lbm.STORE_F64}[storage]
@@ -175,21 +175,21 @@ def make_lattice(name, storage, seg_rows):
     if name.startswith("spinodal"):
         rho0 = I.spinodal_field(nx, seed=0, **dens)
         p = lbm.lbm_params_default(nx=nx, ny=ny, storage=st, diag_interval=DIAG_EVERY, seg_rows=seg_rows,
-                                   rho_ref=float(rho0.mean()), **fluid)
+                                   rho_ref=float(rho0.mean()), tau=tau, collision=collision, **fluid)
     else:
         gr, ga = I.draw_wall_amplitudes(0)
         rho0 = I.drop_field(nx, ny, 160.0, **dens)
         p = lbm.lbm_params_default(nx=nx, ny=ny, storage=st, wall_kind=lbm.WALL_FLAT_SLAB, G_R=float(gr[0]),
                                    G_A=float(ga[0]), diag_interval=DIAG_EVERY, seg_rows=seg_rows,
-                                   rho_ref=float(rho0.mean()), **fluid)
+                                   rho_ref=float(rho0.mean()), tau=tau, collision=collision, **fluid)
     return lbm.Lattice(p, rho0), p
 
 
-def time_gpu(name, storage, steps, warmup, seg_rows, tile=None):
+def time_gpu(name, storage, steps, warmup, seg_rows, tile=None, tau=1.0, collision=0):
     """tile None: the autotuner picks the tile shape during the warm-up
     (its steps count as warm-up); else the given shape."""
     import torch
-    L, p = make_lattice(name, storage, seg_rows)
+    L, p = make_lattice(name, storage, seg_rows, tau, collision)
     nodes = p.nx * p.ny
     tune_ms = None
     if workload_q(name) == 21:
@@ -503,6 +503,9 @@ def main():
     ap.add_argument("--serve-max-nodes", type=int, default=16 << 20, help="serve: resident lattice nodes cap")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16dev", "f64"])
     ap.add_argument("--seg-rows", type=int, default=0)
+    ap.add_argument("--tau", type=float, default=1.0, help="relaxation time (the workloads are defined at 1)")
+    ap.add_argument("--collision", default="bgk", choices=["bgk", "projected"],
+                    help="projected: the projection step onto eq. f2 before the collision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--copy-ref", action="store_true",
@@ -533,7 +536,8 @@ def main():
     if args.workload == "wetting1024":
         print(json.dumps(wetting()), flush=True)
         return
-    r = time_gpu(args.workload, args.storage, args.steps, args.warmup, args.seg_rows, args.tile)
+    coll = 1 if args.collision == "projected" else 0
+    r = time_gpu(args.workload, args.storage, args.steps, args.warmup, args.seg_rows, args.tile, args.tau, coll)
     if args.copy_ref:
         copy_reference()
     mlups = r["nodes"] * args.steps / (r["ms_total"] * 1e-3) / 1e6
@@ -549,7 +553,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": args.storage, "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload][2], "nx": WORKLOADS[args.workload][0],
                    "ny": WORKLOADS[args.workload][1], "storage": args.storage,
-                   "lattice": f"D2Q{q}",
+                   "lattice": f"D2Q{q}", "tau": args.tau, "collision": args.collision,
                    "tile": tile_desc(r["tile_shape"]) if q == 9 else Q21_TILE,
                    "tile_tuned": args.tile is None and q == 9,
                    "tune_ms_per_shape": r["tune_ms"], "diag_every": DIAG_EVERY},
