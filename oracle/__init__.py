@@ -61,6 +61,7 @@ def lib():
         L.orc_equilibrium.argtypes = [ctypes.c_double] * 3 + [dp]
         L.orc_equilibrium_q.argtypes = [ctypes.c_int] + [ctypes.c_double] * 3 + [dp]
         L.orc_project_q.argtypes = [ctypes.c_int, dp, dp]
+        L.orc_filter_walls.argtypes = [ctypes.c_int] * 3 + [dp, dp] + [ctypes.c_int] * 2 + [dp] * 3
         L.orc_psi.argtypes = [P, ctypes.c_double]
         L.orc_psi.restype = ctypes.c_double
         L.orc_p_eos.argtypes = [P, ctypes.c_double]
@@ -153,6 +154,16 @@ class Walls:
     def none(nx, ny):
         z = np.zeros((ny, nx))
         return Walls(z, z.copy(), z.copy())
+
+    @staticmethod
+    def filtered(solid, bnd, lattice=9, n_core=5, n_wall=22):
+        """Appendix A: recursive filter of the solid indicator (orc_filter_walls)."""
+        solid = np.ascontiguousarray(solid, dtype=np.float64)
+        bnd = np.ascontiguousarray(bnd, dtype=np.float64)
+        ny, nx = solid.shape
+        phi = np.zeros((ny, nx)); psiR = np.zeros((ny, nx)); psiA = np.zeros((ny, nx))
+        lib().orc_filter_walls(lattice, nx, ny, _p(solid), _p(bnd), n_core, n_wall, _p(phi), _p(psiR), _p(psiA))
+        return Walls(phi, psiR, psiA)
 
     @staticmethod
     def flat_slab(nx, ny, P=8, width=2.0, core=1.0, tail=3.0):

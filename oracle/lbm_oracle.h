@@ -92,6 +92,13 @@ void orc_forces(const orc_params *p, const double *phi, const double *psiR,
                 double *uy, double *Fff, double *Flr, double *dFs,
                 double *Ftot, double *usx, double *usy);
 
+/* Wall functions of arbitrary geometry by the recursive filter of Appendix A
+ * (eq. iteration): solid and bnd are [ny*nx] indicators (0 or 1) of the solid
+ * region and of its outer-boundary nodes, reset to 1 after every pass;
+ * psiR = G^(n_core), phi = G^(n_wall), psiA = phi - psiR. */
+void orc_filter_walls(int lattice, int nx, int ny, const double *solid, const double *bnd,
+                      int n_core, int n_wall, double *phi, double *psiR, double *psiA);
+
 /* Projection of one node's Q populations onto the truncated Hermite form of
  * eq. f2 with their own M0, M1, M2 (Sec. II.A). */
 void orc_project_q(int lattice, const double *f, double *fp);
