@@ -71,10 +71,18 @@ typedef int lbm_status;
  *              T(s; w) = (1 - tanh(s / w)) / 2:
  *              phi = T(s; wall_width), psiR = T(s; core_range),
  *              psiA = T(s; tail_range) - T(s; core_range).
- *  FIELDS    : per-node (phi, psiR, psiA) given by the caller at creation. */
+ *  FIELDS    : per-node (phi, psiR, psiA) given by the caller at creation.
+ *  MASK      : arbitrary geometry (Appendix A, eq. iteration): the caller
+ *              gives two per-node indicators (0 or 1), the solid region H and
+ *              the outer-boundary nodes B held at 1; at creation the library
+ *              filters G^0 = H recursively, G^n = sum_i w_i G^(n-1)(x + c_i)
+ *              with the lattice's own weights and B reset to 1 after each
+ *              pass, and takes psiR = G^filter_core, phi = G^filter_wall,
+ *              psiA = phi - psiR (the paper: 5 and 22). */
 #define LBM_WALL_NONE      0
 #define LBM_WALL_FLAT_SLAB 1
 #define LBM_WALL_FIELDS    2
+#define LBM_WALL_MASK      3
 
 /* Velocity sets (Sec. II.A): D2Q9, and D2Q21 of Tab. I (theta = 2/3, each
  * node reaching three sites per step; storage F32 or F64, no batches). */
@@ -126,6 +134,8 @@ typedef struct {
                                 theta_L/theta, rho_1, rho_2 (defaults: the
                                 paper's 0.25, -0.25, 1, 0.222, 0.869)        */
     int32_t collision;       /* LBM_COLL_BGK (default) or LBM_COLL_PROJECTED  */
+    int32_t filter_core;     /* MASK: passes for psiR, 0 <= . <= filter_wall (5) */
+    int32_t filter_wall;     /* MASK: passes for phi, 1 <= . <= 1000       (22) */
     int32_t reserved;        /* must be 0                                     */
 } lbm_params;
 
@@ -134,7 +144,8 @@ typedef struct lbm_ctx lbm_ctx;
 /* Fills *p with the defaults: tau = 1, G = -5, G_R = G_A = 0, eps = 1,
  * U_wall = F_ext = 0, wall_width = 2, core_range = 1, tail_range = 3,
  * rho_ref = 1, slab_rows = 8, storage F32, wall NONE, diag_interval 0,
- * lattice D2Q9, psi EXP, eos = the paper's parameters, collision BGK. */
+ * lattice D2Q9, psi EXP, eos = the paper's parameters, collision BGK,
+ * filter_core 5, filter_wall 22. */
 lbm_status lbm_params_default(lbm_params *p);
 
 /* Last error message of the calling thread ("" if none).  Never NULL. */

@@ -114,7 +114,7 @@ Layout make_layout(const lbm_params &p) {
     L.fb = o; o = o + nq * P * s;                      // no padding: fb+mom contiguous
     L.mom = o; o = align_up(o + 3 * N * cb);
     L.uprev = o; o = align_up(o + 2 * N * cb);
-    const bool node = p.wall_kind == LBM_WALL_FIELDS;
+    const bool node = p.wall_kind == LBM_WALL_FIELDS || p.wall_kind == LBM_WALL_MASK;
     L.row_tab = o; o = align_up(o + 2 * size_t(p.ny) * cb);
     L.node_tab = o; o = align_up(o + (node ? 3 * N * cb : 0));
     L.phi_raw = o; o = align_up(o + (node ? N : size_t(p.ny)) * sizeof(double));
@@ -149,7 +149,11 @@ lbm_status validate(const lbm_params *p) {
         if (!(p->eos[3] > 0) || !(p->eos[4] > p->eos[3]))
             return fail(LBM_EINVAL, "eos needs 0 < rho_1 < rho_2");
     }
-    if (p->wall_kind < LBM_WALL_NONE || p->wall_kind > LBM_WALL_FIELDS)
+    if (p->wall_kind == LBM_WALL_MASK &&
+        !(p->filter_wall >= 1 && p->filter_wall <= 1000 && p->filter_core >= 0 && p->filter_core <= p->filter_wall))
+        return fail(LBM_EINVAL, "mask walls need 0 <= filter_core <= filter_wall <= 1000, filter_wall >= 1 (got %d, %d)",
+                    p->filter_core, p->filter_wall);
+    if (p->wall_kind < LBM_WALL_NONE || p->wall_kind > LBM_WALL_MASK)
         return fail(LBM_EINVAL, "unknown wall_kind %d", p->wall_kind);
     if (!(p->tau > 0.5) || !isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be > 0.5");
     if (!(p->eps >= 1.0) || !isfinite(p->eps)) return fail(LBM_EINVAL, "eps must be >= 1");
@@ -287,7 +291,7 @@ lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const d
     c->have_prev = false;
     c->last_diag_step = -1;
     c->last_diag_compared = false;
-    c->wall_mode = p->wall_kind == LBM_WALL_FIELDS ? 1 : 0;
+    c->wall_mode = (p->wall_kind == LBM_WALL_FIELDS || p->wall_kind == LBM_WALL_MASK) ? 1 : 0;
     const Layout &Y = c->lay;
     const size_t N = size_t(p->nx) * p->ny;
     c->d_small = (double *)(ws + Y.small);
@@ -337,7 +341,18 @@ lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const d
                                        p->G_R, p->G_A, ws + Y.row_tab, phi_raw, stream),
                       "walls_row"));
     } else {
-        HIPCHK(hipMemcpyAsync(stage, wall_fields, 3 * N * sizeof(double), hipMemcpyHostToDevice, stream));
+        if (p->wall_kind == LBM_WALL_MASK) {
+            // solid indicator into the first field slot, held nodes into
+            // population buffer A (free until the initial state is written)
+            double *bnd = (double *)(ws + Y.fa);
+            HIPCHK(hipMemcpyAsync(stage, wall_fields, N * sizeof(double), hipMemcpyHostToDevice, stream));
+            HIPCHK(hipMemcpyAsync(bnd, wall_fields + N, N * sizeof(double), hipMemcpyHostToDevice, stream));
+            TRY(launch_ok(launch_filter_walls(L.lattice, uint32_t(p->nx), uint32_t(p->ny), stage, bnd, p->filter_core,
+                                              p->filter_wall, stream),
+                          "filter_walls"));
+        } else {
+            HIPCHK(hipMemcpyAsync(stage, wall_fields, 3 * N * sizeof(double), hipMemcpyHostToDevice, stream));
+        }
         TRY(launch_ok(launch_walls_node(f64, L.lattice, p->nx, p->ny, stage, p->eps, p->G_R, p->G_A, ws + Y.node_tab,
                                         phi_raw, stream),
                       "walls_node"));
@@ -373,8 +388,13 @@ lbm_status check_host_fields(const lbm_params *p, const double *rho0, const doub
             if (!isfinite(wall_fields[i])) return fail(LBM_EINVAL, "non-finite wall field at %zu", i);
         for (size_t i = 0; i < N; ++i)
             if (wall_fields[i] < 0 || wall_fields[i] > 1) return fail(LBM_EINVAL, "phi must be in [0,1]");
+    } else if (p->wall_kind == LBM_WALL_MASK) {
+        if (!wall_fields) return fail(LBM_EINVAL, "wall_fields (solid, boundary indicators) required for LBM_WALL_MASK");
+        for (size_t i = 0; i < 2 * N; ++i)
+            if (wall_fields[i] != 0.0 && wall_fields[i] != 1.0)
+                return fail(LBM_EINVAL, "mask indicator at %zu must be 0 or 1", i);
     } else if (wall_fields) {
-        return fail(LBM_EINVAL, "wall_fields must be NULL unless wall_kind is LBM_WALL_FIELDS");
+        return fail(LBM_EINVAL, "wall_fields must be NULL unless wall_kind is LBM_WALL_FIELDS or LBM_WALL_MASK");
     }
     return LBM_OK;
 }
@@ -399,6 +419,8 @@ lbm_status lbm_params_default(lbm_params *p) {
     p->lattice = LBM_D2Q9;
     p->psi_kind = LBM_PSI_EXP;
     p->collision = LBM_COLL_BGK;
+    p->filter_core = 5;
+    p->filter_wall = 22;
     const double eos[5] = {0.25, -0.25, 1.0, 0.222, 0.869};
     for (int i = 0; i < 5; ++i) p->eos[i] = eos[i];
     return LBM_OK;
@@ -671,7 +693,7 @@ static lbm_status batch_check(const lbm_params *ps, int32_t n) {
         if (ps[k].storage != LBM_STORE_F32) return fail(LBM_EINVAL, "lattice %d: batches take F32 storage only", k);
         if (ps[k].lattice != LBM_D2Q9 || ps[k].psi_kind != LBM_PSI_EXP)
             return fail(LBM_EINVAL, "lattice %d: batches take D2Q9 with the exponential pseudo-potential", k);
-        if (ps[k].wall_kind == LBM_WALL_FIELDS)
+        if (ps[k].wall_kind == LBM_WALL_FIELDS || ps[k].wall_kind == LBM_WALL_MASK)
             return fail(LBM_EINVAL, "lattice %d: batches take wall kinds NONE or FLAT_SLAB", k);
     }
     return LBM_OK;

@@ -10,6 +10,8 @@
 // padded plane stride.  The marching walk (march) serves the diagnostic pass.
 #include <type_traits>
 
+#include <utility>
+
 #include "launch.hpp"
 #include "lbm_device.hpp"
 
@@ -663,6 +665,31 @@ __global__ __launch_bounds__(256) void k_walls_node(uint32_t nx, uint32_t ny, co
     phi_raw[n] = phi;
 }
 
+// Wall functions of arbitrary geometry (Appendix A, eq. iteration): one pass
+// of the recursive filter, out = sum_i w_i in(x + r_i) over the lattice's
+// velocity set (periodic), held at 1 where bnd != 0.  Set-up only.
+template <int LQ>
+__global__ __launch_bounds__(256) void k_filter_pass(uint32_t nx, uint32_t ny, const double *__restrict__ in,
+                                                     const double *__restrict__ bnd, double *__restrict__ out) {
+    using V = VelSet<LQ>;
+    const uint32_t N = nx * ny;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    const uint32_t y = n / nx, x = n - y * nx;
+    double acc = 0.0;
+    for (int q = 0; q < V::Q; ++q) {
+        const uint32_t m = ((y + 3 * ny + V::cy(q)) % ny) * nx + (x + 3 * nx + V::cx(q)) % nx;
+        acc += V::w(q) * in[m];
+    }
+    out[n] = bnd[n] != 0.0 ? 1.0 : acc;
+}
+
+// psiA = phi - psiR, fields laid out [phi | psiR | psiA].
+__global__ __launch_bounds__(256) void k_filter_finish(uint32_t N, double *__restrict__ fields) {
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < N) fields[2 * size_t(N) + n] = fields[n] - fields[size_t(N) + n];
+}
+
 // ================================================================ launchers
 static inline uint32_t blocks_for(uint32_t waves) { return (waves + kBlockWaves - 1) / kBlockWaves; }
 static inline uint32_t blocks_nodes(uint32_t n) { return (n + 255) / 256; }
@@ -844,6 +871,37 @@ hipError_t launch_walls_node(int f64, int lattice, uint32_t nx, uint32_t ny, con
                                (float *)tab, phi_raw);
         return hipGetLastError();
     });
+}
+
+hipError_t launch_filter_walls(int lattice, uint32_t nx, uint32_t ny, double *fields, const double *bnd,
+                               int n_core, int n_wall, hipStream_t st) {
+    const size_t N = size_t(nx) * ny;
+    double *slot[3] = {fields, fields + N, fields + 2 * N};   // phi, psiR, psiA
+    const uint32_t nb = blocks_nodes(uint32_t(N));
+    double *cur = slot[0], *nxt = slot[2];
+    if (n_core == 0) {
+        const hipError_t e = hipMemcpyAsync(slot[1], cur, N * sizeof(double), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+    }
+    for (int pass = 1; pass <= n_wall; ++pass) {
+        if (lattice == 21)
+            hipLaunchKernelGGL(k_filter_pass<21>, dim3(nb), dim3(256), 0, st, nx, ny, cur, bnd, nxt);
+        else
+            hipLaunchKernelGGL(k_filter_pass<9>, dim3(nb), dim3(256), 0, st, nx, ny, cur, bnd, nxt);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        std::swap(cur, nxt);
+        if (pass == n_core) {
+            e = hipMemcpyAsync(slot[1], cur, N * sizeof(double), hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return e;
+        }
+    }
+    if (cur != slot[0]) {
+        const hipError_t e = hipMemcpyAsync(slot[0], cur, N * sizeof(double), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_filter_finish, dim3(nb), dim3(256), 0, st, uint32_t(N), fields);
+    return hipGetLastError();
 }
 
 }  // namespace lbmwet

@@ -114,6 +114,11 @@ hipError_t launch_step_batch(const void *lats, const uint4 *twork, uint32_t ntil
                              hipStream_t st);
 hipError_t launch_diag(int storage, const void *lats, const uint4 *work, uint32_t nwork, const LatDevAny &single,
                        int wall, int parity, int write_mom, int compare, int update, hipStream_t st);
+// Recursive-filter wall functions (Appendix A): fields[0..N) holds the solid
+// indicator on entry; on return [phi | psiR | psiA] (3N doubles).  bnd: N
+// doubles, nonzero on the nodes held at 1.
+hipError_t launch_filter_walls(int lattice, uint32_t nx, uint32_t ny, double *fields, const double *bnd,
+                               int n_core, int n_wall, hipStream_t st);
 hipError_t launch_reduce(const double *part, const uint32_t *ranges, uint32_t nout, uint32_t stride,
                          uint32_t width, double *out, uint32_t out_stride, hipStream_t st);
 hipError_t launch_isoline(int f64, const IsoParams &p, const void *rho, const double *phi, double *part,

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "liblbmwet.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ENOFIT, LBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
 STORE_F32, STORE_F16DEV, STORE_F64, STORE_F32X = 0, 1, 2, 3
-WALL_NONE, WALL_FLAT_SLAB, WALL_FIELDS = 0, 1, 2
+WALL_NONE, WALL_FLAT_SLAB, WALL_FIELDS, WALL_MASK = 0, 1, 2, 3
 D2Q9, D2Q21 = 9, 21
 PSI_EXP, PSI_EOS = 0, 1
 COLL_BGK, COLL_PROJECTED = 0, 1
@@ -41,7 +41,8 @@ class lbm_params(ctypes.Structure):
                 ("slab_rows", ctypes.c_int32), ("diag_interval", ctypes.c_int32),
                 ("seg_rows", ctypes.c_int32), ("lattice", ctypes.c_int32),
                 ("psi_kind", ctypes.c_int32), ("eos", ctypes.c_double * 5),
-                ("collision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("collision", ctypes.c_int32), ("filter_core", ctypes.c_int32), ("filter_wall", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _lib = None

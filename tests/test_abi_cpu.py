@@ -126,3 +126,14 @@ def test_batch_validation():
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_batch_workspace_bytes(ps)
     assert "F32" in str(e.value)
+
+
+def test_mask_wall_parameters_validated():
+    from paper_1202_6130_amd import lbm
+    ok = lbm.lbm_params_default(nx=16, ny=16, wall_kind=lbm.WALL_MASK)
+    assert ok.filter_core == 5 and ok.filter_wall == 22
+    assert lbm.lbm_workspace_bytes(ok) > 0
+    for core, wall in ((6, 5), (-1, 22), (0, 0), (5, 1001)):
+        bad = lbm.lbm_params_default(nx=16, ny=16, wall_kind=lbm.WALL_MASK, filter_core=core, filter_wall=wall)
+        with pytest.raises(lbm.LbmError):
+            lbm.lbm_workspace_bytes(bad)
