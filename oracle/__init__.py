@@ -87,6 +87,8 @@ def lib():
         L.orc_contact_angle.argtypes = [P, dp, dp, dp, dp, ctypes.c_double,
                                         ctypes.c_double, dp]
         L.orc_contact_angle.restype = ctypes.c_int
+        L.orc_dynamic_angles.argtypes = [P, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_dynamic_angles.restype = ctypes.c_int
         L.orc_slip_length.argtypes = [P, dp, dp, dp, dp, ctypes.c_int,
                                       ctypes.c_double, dp]
         L.orc_slip_length.restype = ctypes.c_int
@@ -266,6 +268,13 @@ def contact_angle(p, walls, f, iso=1.07, y_ref=0.0):
     out = np.zeros(4)
     rc = lib().orc_contact_angle(ctypes.byref(p), _p(walls.phi), _p(walls.psiR),
                                  _p(walls.psiA), _p(f), iso, y_ref, _p(out))
+    return None if rc != 0 else out
+
+
+def dynamic_angles(p, walls, f, iso=1.07, y_ref=0.0):
+    out = np.zeros(8)
+    rc = lib().orc_dynamic_angles(ctypes.byref(p), _p(walls.phi), _p(walls.psiR),
+                                  _p(walls.psiA), _p(f), iso, y_ref, _p(out))
     return None if rc != 0 else out
 
 

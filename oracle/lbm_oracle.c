@@ -576,6 +576,84 @@ int orc_contact_angle(const orc_params *p, const double *phi,
     return rc;
 }
 
+/* Sec. III.C: advancing and receding angles of a moving drop from two
+ * circles fitted to the rear and front parts of its region-III isoline, both
+ * ending at the apex, and the drop's mean speed U.  x is taken periodic about
+ * the circular mean of the crossings so that a drop across x = 0 stays whole;
+ * the apex is the highest crossing (the smaller x on a tie); U is the
+ * rho-weighted mean u_x of the region-III nodes with rho >= iso (u the
+ * reported velocity); the advancing side is the one U points to. */
+int orc_dynamic_angles(const orc_params *p, const double *phi, const double *psiR,
+                       const double *psiA, const double *f, double iso, double y_ref,
+                       double out[8])
+{
+    const int nx = p->nx, ny = p->ny;
+    const long N = (long)nx * ny;
+    double *rho = (double *)malloc(sizeof(double) * N);
+    double *ux = (double *)malloc(sizeof(double) * N);
+    double *uy = (double *)malloc(sizeof(double) * N);
+    orc_macros(p, phi, psiR, psiA, f, rho, ux, uy, NULL);
+    long cap = 2 * N;
+    double *px = (double *)malloc(sizeof(double) * cap);
+    double *py = (double *)malloc(sizeof(double) * cap);
+    double *sx = (double *)malloc(sizeof(double) * cap);
+    double *sy = (double *)malloc(sizeof(double) * cap);
+    long n = orc_isoline_points(nx, ny, rho, phi, iso, 0.01, px, py, cap);
+    int rc = -1;
+    if (n >= 16) {
+        double ss = 0, sc = 0;
+        for (long k = 0; k < n; ++k) {
+            ss += sin(2.0 * M_PI * px[k] / nx);
+            sc += cos(2.0 * M_PI * px[k] / nx);
+        }
+        double xmid = atan2(ss, sc) * nx / (2.0 * M_PI);
+        if (xmid < 0) xmid += nx;
+        long top = -1;
+        for (long k = 0; k < n; ++k) {
+            px[k] -= nx * floor((px[k] - xmid) / nx + 0.5);
+            if (top < 0 || py[k] > py[top] || (py[k] == py[top] && px[k] < px[top])) top = k;
+        }
+        double c[2][3];
+        int ok = 1;
+        for (int side = 0; side < 2 && ok; ++side) {
+            long m = 0;
+            for (long k = 0; k < n; ++k)
+                if (side == 0 ? px[k] <= px[top] : px[k] >= px[top]) {
+                    sx[m] = px[k];
+                    sy[m] = py[k];
+                    ++m;
+                }
+            ok = m >= 8 && orc_circle_fit(m, sx, sy, c[side]) == 0;
+        }
+        double mass = 0, mom = 0, cnt = 0;
+        for (long a = 0; a < N; ++a)
+            if (phi[a] < 0.01 && rho[a] >= iso) {
+                mass += rho[a];
+                mom += rho[a] * ux[a];
+                cnt += 1;
+            }
+        if (ok && mass > 0) {
+            double U = mom / mass;
+            int adv = U >= 0 ? 1 : 0;
+            for (int k = 0; k < 2; ++k) {
+                int sdx = k == 0 ? adv : 1 - adv;
+                double cs = (y_ref - c[sdx][1]) / c[sdx][2];
+                if (cs > 1.0) cs = 1.0;
+                if (cs < -1.0) cs = -1.0;
+                out[k] = acos(cs) * 180.0 / M_PI;
+                out[3 + k] = c[sdx][2];
+            }
+            out[2] = U;
+            out[5] = px[top] - nx * floor(px[top] / nx);
+            out[6] = py[top];
+            out[7] = mass / cnt;
+            rc = 0;
+        }
+    }
+    free(rho); free(ux); free(uy); free(px); free(py); free(sx); free(sy);
+    return rc;
+}
+
 int orc_slip_length(const orc_params *p, const double *phi, const double *psiR,
                     const double *psiA, const double *f, int P, double width,
                     double out[3])

@@ -151,6 +151,12 @@ int orc_contact_angle(const orc_params *p, const double *phi,
                       const double *psiR, const double *psiA, const double *f,
                       double iso, double y_ref, double out[4]);
 
+/* Sec. III.C: out = (theta_A, theta_R [deg], U, R_A, R_R, x_apex, y_apex,
+ * mean liquid rho); returns 0, or -1 if a fit is impossible. */
+int orc_dynamic_angles(const orc_params *p, const double *phi, const double *psiR,
+                       const double *psiA, const double *f, double iso, double y_ref,
+                       double out[8]);
+
 /* Slip in a flat channel (Sec. III.A): x-averaged u_out,x(y), a parabola
  * fitted over region-III rows of the fluid gap [0, ny-P], evaluated at the
  * hydrodynamic boundary y_w where phi(y_w) = 0.01.  out = (b, u_s, c2) with
