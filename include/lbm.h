@@ -202,6 +202,23 @@ lbm_status lbm_moments(lbm_ctx *c, double *rho, double *ux, double *uy,
  * the fit is degenerate.  Synchronises. */
 lbm_status lbm_contact_angle(lbm_ctx *c, double iso, double y_ref, double out[4]);
 
+/* Dynamic contact angles of a moving drop (Sec. III.C): the rho = iso
+ * crossings of region III (phi < 0.01, as lbm_contact_angle) are taken along
+ * the periodic x about their circular mean (so a drop across x = 0 stays
+ * whole); the highest crossing is the apex; one least-squares circle is
+ * fitted to the crossings with x <= x_apex (rear) and one to those with
+ * x >= x_apex (front), each needing >= 8 points.  U is the mass-weighted mean
+ * u_x (reported velocity) of the liquid nodes (rho >= iso) of region III; the
+ * advancing side is the one U points to (the front when U = 0).
+ *  out[0] theta_A (degrees)   out[1] theta_R        out[2] U
+ *  out[3] R of the advancing circle   out[4] R of the receding circle
+ *  out[5] x_apex in [0, nx)   out[6] y_apex   out[7] mean rho of those liquid nodes
+ * The capillary number of the paper is Ca = U mu_L / gamma with mu_L =
+ * out[7] * theta * (tau - 1/2) and the caller's surface tension gamma.
+ * Returns LBM_ENOFIT when a fit has too few points or degenerates.
+ * Synchronises. */
+lbm_status lbm_dynamic_angles(lbm_ctx *c, double iso, double y_ref, double out[8]);
+
 /* Slip in a FLAT_SLAB channel (Sec. III.A): the x-averaged reported u_x(y)
  * over region-III rows of the gap [0, ny - slab_rows] is fitted by a parabola
  * and evaluated at the hydrodynamic boundary y_w, phi(y_w) = 0.01, of both

@@ -550,19 +550,15 @@ lbm_status iso_pass(lbm_ctx *c, IsoParams ip, double sums[10]) {
     return sync(c);
 }
 
-}  // namespace
-
-extern "C" {
-
-lbm_status lbm_contact_angle(lbm_ctx *c, double iso, double y_ref, double out[4]) {
-    if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
-    if (!isfinite(iso) || !isfinite(y_ref)) return fail(LBM_EINVAL, "iso and y_ref must be finite");
-    TRY(run_diag(c, 1, 0, 0, 1));
-    IsoParams ip{uint32_t(c->p.nx), uint32_t(c->p.ny), c->wall_mode, 0, iso, 0.01, 0, 0, 0, 0, 0};
+// Least-squares circle through the region-III crossings selected by ip
+// (side, unwrap): algebraic (Kasa) fit about the centroid, then up to 20
+// Gauss-Newton steps of the geometric fit (Sec. III.B).
+lbm_status fit_circle(lbm_ctx *c, IsoParams ip, double min_points, double &xc_out, double &yc_out, double &R_out) {
     double s[10];
+    ip.mode = 0;
     TRY(iso_pass(c, ip, s));
     const double n = s[0];
-    if (n < 16) return fail(LBM_ENOFIT, "only %.0f isoline points in region III", n);
+    if (n < min_points) return fail(LBM_ENOFIT, "only %.0f isoline points in region III", n);
     ip.mx = s[1] / n;
     ip.my = s[2] / n;
     // algebraic fit about the centroid: x^2 + y^2 + D x + E y + F = 0
@@ -586,14 +582,97 @@ lbm_status lbm_contact_angle(lbm_ctx *c, double iso, double y_ref, double out[4]
         if (fabs(d[0]) + fabs(d[1]) + fabs(d[2]) < 1e-13 * (1.0 + fabs(R))) break;
     }
     if (!(R > 0) || !isfinite(R) || !isfinite(xc) || !isfinite(yc)) return fail(LBM_ENOFIT, "circle fit diverged");
-    xc += ip.mx;
-    yc += ip.my;
+    xc_out = xc + ip.mx;
+    yc_out = yc + ip.my;
+    R_out = R;
+    return LBM_OK;
+}
+
+// theta = acos((y_ref - yc) / R), clamped, in degrees (Sec. III.B: h = yc + R - y_ref).
+double contact_angle_deg(double xc, double yc, double R, double y_ref) {
+    (void)xc;
     double cs = (y_ref - yc) / R;
     cs = cs > 1 ? 1 : (cs < -1 ? -1 : cs);
-    out[0] = acos(cs) * (180.0 / M_PI);
+    return acos(cs) * (180.0 / M_PI);
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_contact_angle(lbm_ctx *c, double iso, double y_ref, double out[4]) {
+    if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
+    if (!isfinite(iso) || !isfinite(y_ref)) return fail(LBM_EINVAL, "iso and y_ref must be finite");
+    TRY(run_diag(c, 1, 0, 0, 1));
+    IsoParams ip{uint32_t(c->p.nx), uint32_t(c->p.ny), c->wall_mode, 0, iso, 0.01, 0, 0, 0, 0, 0};
+    double xc, yc, R;
+    TRY(fit_circle(c, ip, 16, xc, yc, R));
+    out[0] = contact_angle_deg(xc, yc, R, y_ref);
     out[1] = R;
     out[2] = xc;
     out[3] = yc;
+    return LBM_OK;
+}
+
+lbm_status lbm_dynamic_angles(lbm_ctx *c, double iso, double y_ref, double out[8]) {
+    if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
+    if (!isfinite(iso) || !isfinite(y_ref)) return fail(LBM_EINVAL, "iso and y_ref must be finite");
+    TRY(run_diag(c, 1, 0, 0, 1));
+    const uint32_t nx = uint32_t(c->p.nx), ny = uint32_t(c->p.ny);
+    IsoParams ip{nx, ny, c->wall_mode, 5, iso, 0.01, 0, 0, 0, 0, 0};
+    double s[10];
+    // the drop's position along the periodic x: circular mean of its crossings
+    TRY(iso_pass(c, ip, s));
+    if (s[0] < 16) return fail(LBM_ENOFIT, "only %.0f isoline points in region III", s[0]);
+    if (!(fabs(s[1]) + fabs(s[2]) > 1e-9 * s[0]))
+        return fail(LBM_ENOFIT, "isoline points spread evenly over the periodic x range");
+    double xmid = atan2(s[1], s[2]) * (double(nx) / (2.0 * M_PI));
+    if (xmid < 0) xmid += double(nx);
+    ip.unwrap = 1;
+    ip.xmid = xmid;
+    // apex: the highest crossing
+    ip.mode = 3;
+    const int f64 = compute_is_f64(c->p.storage);
+    double *part = (double *)(c->ws + c->lay.iso_part);
+    TRY(launch_ok(launch_isoline(f64, ip, c->L.mom, (const double *)(c->ws + c->lay.phi_raw), part, c->stream),
+                  "isoline top"));
+    std::vector<double> top(size_t(c->lay.iso_blocks) * 10);
+    HIPCHK(hipMemcpyAsync(top.data(), part, top.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    TRY(sync(c));
+    bool found = false;
+    double ax = 0, ay = -1;
+    for (uint32_t b = 0; b < c->lay.iso_blocks; ++b) {
+        const double f = top[10 * b], x = top[10 * b + 1], y = top[10 * b + 2];
+        if (f != 0.0 && (!found || y > ay || (y == ay && x < ax))) {
+            found = true;
+            ax = x;
+            ay = y;
+        }
+    }
+    if (!found) return fail(LBM_ENOFIT, "no isoline points");
+    // rear (x <= apex) and front (x >= apex) circles, each through the apex
+    double cx[2], cy[2], cr[2];
+    for (int k = 0; k < 2; ++k) {
+        IsoParams sp = ip;
+        sp.side = k == 0 ? -1 : 1;
+        sp.xs = ax;
+        TRY(fit_circle(c, sp, 8, cx[k], cy[k], cr[k]));
+    }
+    // mean velocity and density of the liquid in region III
+    ip.mode = 4;
+    ip.unwrap = 0;
+    TRY(iso_pass(c, ip, s));
+    if (!(s[1] > 0)) return fail(LBM_ENOFIT, "no liquid nodes in region III");
+    const double U = s[2] / s[1];
+    const int adv = U >= 0 ? 1 : 0;          // the side the drop moves towards
+    out[0] = contact_angle_deg(cx[adv], cy[adv], cr[adv], y_ref);
+    out[1] = contact_angle_deg(cx[1 - adv], cy[1 - adv], cr[1 - adv], y_ref);
+    out[2] = U;
+    out[3] = cr[adv];
+    out[4] = cr[1 - adv];
+    out[5] = ax - double(nx) * floor(ax / double(nx));
+    out[6] = ay;
+    out[7] = s[1] / s[0];
     return LBM_OK;
 }
 

@@ -452,6 +452,9 @@ struct IsoArgs {
     int per_node;          // phi indexed per node (else per row)
     int mode;
     double iso, phi_max, mx, my, xc, yc, R;
+    int side;              // 0: every point; -1: x <= xs; +1: x >= xs
+    int unwrap;            // x taken in [xmid - nx/2, xmid + nx/2)
+    double xs, xmid;
 };
 
 __device__ inline void iso_accumulate(const IsoArgs &a, double px, double py, double acc[10]) {
@@ -464,13 +467,54 @@ __device__ inline void iso_accumulate(const IsoArgs &a, double px, double py, do
         const double q = x * x + y * y;
         acc[1] += x; acc[2] += y; acc[3] += x * x; acc[4] += x * y; acc[5] += y * y;
         acc[6] += x * q; acc[7] += y * q; acc[8] += q;
-    } else {
+    } else if (a.mode == 2) {
         const double dx = x - a.xc, dy = y - a.yc;
         const double d = sqrt(dx * dx + dy * dy);
         const double j0 = -dx / d, j1 = -dy / d, j2 = -1.0, r = d - a.R;
         acc[1] += j0 * j0; acc[2] += j0 * j1; acc[3] += j0 * j2;
         acc[4] += j1 * j1; acc[5] += j1 * j2; acc[6] += j2 * j2;
         acc[7] -= j0 * r; acc[8] -= j1 * r; acc[9] -= j2 * r;
+    } else if (a.mode == 5) {
+        // circular mean of x over the periodic direction
+        const double t = 6.283185307179586 * px / double(a.nx);
+        acc[1] += sin(t);
+        acc[2] += cos(t);
+    }
+}
+
+// x of a crossing in the window [xmid - nx/2, xmid + nx/2) when unwrapping.
+__device__ inline double iso_unwrap(const IsoArgs &a, double px) {
+    if (!a.unwrap) return px;
+    const double n = double(a.nx);
+    return px - n * floor((px - a.xmid) / n + 0.5);
+}
+
+// Calls emit(x, y) for every rho = iso crossing on the edges from node n to
+// its right (periodic) and upper neighbours, both ends in region phi < phi_max.
+template <class C, class Emit>
+__device__ inline void iso_crossings(const IsoArgs &a, const C *__restrict__ rho, const double *__restrict__ phi,
+                                     uint32_t n, Emit &&emit) {
+    const uint32_t y = n / a.nx, x = n - y * a.nx;
+    const double pa = a.per_node ? phi[n] : phi[y];
+    if (!(pa < a.phi_max)) return;
+    const double ra = double(rho[n]);
+    const bool ia = ra >= a.iso;
+    const uint32_t xr = x + 1 == a.nx ? 0 : x + 1;
+    const uint32_t nr = y * a.nx + xr;
+    const double pr = a.per_node ? phi[nr] : phi[y];
+    const double rr = double(rho[nr]);
+    if (pr < a.phi_max && ia != (rr >= a.iso)) {
+        const double t = (a.iso - ra) / (rr - ra);
+        emit(double(x) + t, double(y));
+    }
+    if (y + 1 < a.ny) {
+        const uint32_t nu = n + a.nx;
+        const double pu = a.per_node ? phi[nu] : phi[y + 1];
+        const double ru = double(rho[nu]);
+        if (pu < a.phi_max && ia != (ru >= a.iso)) {
+            const double t = (a.iso - ra) / (ru - ra);
+            emit(double(x), double(y) + t);
+        }
     }
 }
 
@@ -483,28 +527,24 @@ __global__ __launch_bounds__(256) void k_isoline(IsoArgs a, const C *__restrict_
     const uint32_t N = a.nx * a.ny;
     const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n < N) {
-        const uint32_t y = n / a.nx, x = n - y * a.nx;
-        const double pa = a.per_node ? phi[n] : phi[y];
-        if (pa < a.phi_max) {
-            const double ra = double(rho[n]);
-            const bool ia = ra >= a.iso;
-            const uint32_t xr = x + 1 == a.nx ? 0 : x + 1;
-            const uint32_t nr = y * a.nx + xr;
-            const double pr = a.per_node ? phi[nr] : phi[y];
-            const double rr = double(rho[nr]);
-            if (pr < a.phi_max && ia != (rr >= a.iso)) {
-                const double t = (a.iso - ra) / (rr - ra);
-                iso_accumulate(a, double(x) + t, double(y), acc);
+        if (a.mode == 4) {
+            // liquid nodes of region III: (count, sum rho, sum rho u_x, sum rho u_y);
+            // rho points at the moment planes (rho | u_x | u_y)
+            const uint32_t y = n / a.nx;
+            const double pa = a.per_node ? phi[n] : phi[y];
+            const double r = double(rho[n]);
+            if (pa < a.phi_max && r >= a.iso) {
+                acc[0] += 1.0;
+                acc[1] += r;
+                acc[2] += r * double(rho[N + n]);
+                acc[3] += r * double(rho[2 * size_t(N) + n]);
             }
-            if (y + 1 < a.ny) {
-                const uint32_t nu = n + a.nx;
-                const double pu = a.per_node ? phi[nu] : phi[y + 1];
-                const double ru = double(rho[nu]);
-                if (pu < a.phi_max && ia != (ru >= a.iso)) {
-                    const double t = (a.iso - ra) / (ru - ra);
-                    iso_accumulate(a, double(x), double(y) + t, acc);
-                }
-            }
+        } else {
+            iso_crossings(a, rho, phi, n, [&](double px, double py) {
+                px = iso_unwrap(a, px);
+                if ((a.side < 0 && px > a.xs) || (a.side > 0 && px < a.xs)) return;
+                iso_accumulate(a, px, py, acc);
+            });
         }
     }
     const uint32_t w = threadIdx.x / kWave;
@@ -518,6 +558,56 @@ __global__ __launch_bounds__(256) void k_isoline(IsoArgs a, const C *__restrict_
         double s = 0.0;
         for (int i = 0; i < kIsoWaves; ++i) s += sm[i][threadIdx.x];
         part[size_t(blockIdx.x) * 10 + threadIdx.x] = s;
+    }
+}
+
+// Highest crossing (largest y, then smallest unwrapped x) of each block:
+// part[10 b] = found (0/1), part[10 b + 1] = x, part[10 b + 2] = y.
+template <class C>
+__global__ __launch_bounds__(256) void k_isoline_top(IsoArgs a, const C *__restrict__ rho,
+                                                     const double *__restrict__ phi, double *__restrict__ part) {
+    constexpr int kIsoWaves = 256 / kWave;
+    __shared__ double sm[kIsoWaves][3];
+    double found = 0.0, bx = 0.0, by = -1.0;
+    const uint32_t N = a.nx * a.ny;
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    auto better = [](double x1, double y1, double x2, double y2) { return y1 > y2 || (y1 == y2 && x1 < x2); };
+    if (n < N)
+        iso_crossings(a, rho, phi, n, [&](double px, double py) {
+            px = iso_unwrap(a, px);
+            if (found == 0.0 || better(px, py, bx, by)) {
+                found = 1.0;
+                bx = px;
+                by = py;
+            }
+        });
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const double f2 = __shfl_xor(found, o, kWave), x2 = __shfl_xor(bx, o, kWave), y2 = __shfl_xor(by, o, kWave);
+        if (f2 != 0.0 && (found == 0.0 || better(x2, y2, bx, by))) {
+            found = 1.0;
+            bx = x2;
+            by = y2;
+        }
+    }
+    const uint32_t w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        sm[w][0] = found;
+        sm[w][1] = bx;
+        sm[w][2] = by;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double f = 0.0, x = 0.0, y = -1.0;
+        for (int i = 0; i < kIsoWaves; ++i)
+            if (sm[i][0] != 0.0 && (f == 0.0 || better(sm[i][1], sm[i][2], x, y))) {
+                f = 1.0;
+                x = sm[i][1];
+                y = sm[i][2];
+            }
+        part[size_t(blockIdx.x) * 10] = f;
+        part[size_t(blockIdx.x) * 10 + 1] = x;
+        part[size_t(blockIdx.x) * 10 + 2] = y;
     }
 }
 
@@ -783,8 +873,16 @@ hipError_t launch_reduce(const double *part, const uint32_t *ranges, uint32_t no
 
 hipError_t launch_isoline(int f64, const IsoParams &p, const void *rho, const double *phi, double *part,
                           hipStream_t st) {
-    IsoArgs a{p.nx, p.ny, p.per_node, p.mode, p.iso, p.phi_max, p.mx, p.my, p.xc, p.yc, p.R};
+    IsoArgs a{p.nx, p.ny, p.per_node, p.mode, p.iso, p.phi_max, p.mx, p.my, p.xc, p.yc, p.R,
+              p.side, p.unwrap, p.xs, p.xmid};
     const uint32_t nb = blocks_nodes(p.nx * p.ny);
+    if (p.mode == 3) {
+        if (f64)
+            hipLaunchKernelGGL(k_isoline_top<double>, dim3(nb), dim3(256), 0, st, a, (const double *)rho, phi, part);
+        else
+            hipLaunchKernelGGL(k_isoline_top<float>, dim3(nb), dim3(256), 0, st, a, (const float *)rho, phi, part);
+        return hipGetLastError();
+    }
     if (f64)
         hipLaunchKernelGGL(k_isoline<double>, dim3(nb), dim3(256), 0, st, a, (const double *)rho, phi, part);
     else

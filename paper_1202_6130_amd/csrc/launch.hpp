@@ -72,10 +72,18 @@ template <class C> inline LatDev<C> LatDevAny::get() const {
     return d;
 }
 
+// Isoline passes over region III (phi < phi_max).  mode 0: (n, sum x,
+// sum y); 1: algebraic circle sums about (mx, my); 2: Gauss-Newton normal
+// equations of the geometric circle fit; 3: highest crossing per block;
+// 4: liquid nodes (rho >= iso): (n, sum rho, sum rho u_x, sum rho u_y) with
+// rho pointing at the moment planes; 5: (n, sum sin, sum cos) of 2 pi x / nx.
+// side/xs keep one side of x = xs; unwrap/xmid take x periodic about xmid.
 struct IsoParams {
     uint32_t nx, ny;
     int per_node, mode;
     double iso, phi_max, mx, my, xc, yc, R;
+    int side = 0, unwrap = 0;
+    double xs = 0, xmid = 0;
 };
 
 constexpr uint32_t kStripColsHost = 64;

@@ -77,6 +77,7 @@ def lib():
         "lbm_moments": ([_vp, _dp, _dp, _dp, _dp], ctypes.c_int),
         "lbm_contact_angle": ([_vp, ctypes.c_double, ctypes.c_double, _dp], ctypes.c_int),
         "lbm_slip_length": ([_vp, _dp], ctypes.c_int),
+        "lbm_dynamic_angles": ([_vp, ctypes.c_double, ctypes.c_double, _dp], ctypes.c_int),
         "lbm_get_state": ([_vp, _dp], ctypes.c_int),
         "lbm_set_state": ([_vp, _dp, i64], ctypes.c_int),
         "lbm_step_index": ([_vp], i64),
@@ -184,6 +185,17 @@ def lbm_moments(ctx, n, want=(True, True, True)):
 def lbm_contact_angle(ctx, iso, y_ref):
     out = np.zeros(4)
     code = lib().lbm_contact_angle(ctx, float(iso), float(y_ref), _ptr(out))
+    if code == LBM_ENOFIT:
+        return None
+    _check(code)
+    return out
+
+
+def lbm_dynamic_angles(ctx, iso, y_ref):
+    """(theta_A, theta_R, U, R_A, R_R, x_apex, y_apex, rho_L), or None when a
+    fit has too few points; see lbm.h."""
+    out = np.zeros(8)
+    code = lib().lbm_dynamic_angles(ctx, float(iso), float(y_ref), _ptr(out))
     if code == LBM_ENOFIT:
         return None
     _check(code)
@@ -367,6 +379,9 @@ class Lattice:
 
     def contact_angle(self, iso=1.07, y_ref=0.0):
         return lbm_contact_angle(self.ctx, iso, y_ref)
+
+    def dynamic_angles(self, iso=1.07, y_ref=0.0):
+        return lbm_dynamic_angles(self.ctx, iso, y_ref)
 
     def slip_length(self):
         return lbm_slip_length(self.ctx)
