@@ -489,13 +489,96 @@ def serving(count, max_steps, seed=0, rate=20.0, max_nodes=16 << 20):
     }
 
 
+def laplace_gamma_q21(storage, n=96, radii=(12.0, 16.0, 24.0), steps=4000):
+    """Surface tension of the D2Q21 EOS fluid from pressure jumps across free
+    discs (Sec. II.B's measurement): dp = p_EOS(rho_in) - p_EOS(rho_out)
+    against 1/R (R from the liquid area), least-squares slope."""
+    from paper_1202_6130_amd import inputs as I
+    from paper_1202_6130_amd import lbm
+    th = 2.0 / 3.0
+    tV, tU, tL, r1, r2 = 0.25 * th, -0.25 * th, th, 0.222, 0.869     # eq. EOS, the paper's parameters
+
+    def p_eos(r):
+        p1 = r1 * tV
+        return r * tV if r <= r1 else (p1 + (r - r1) * tU if r <= r2 else p1 + (r2 - r1) * tU + (r - r2) * tL)
+    pts = []
+    for R in radii:
+        p = lbm.lbm_params_default(nx=n, ny=n, storage=storage, lattice=lbm.D2Q21, psi_kind=lbm.PSI_EOS, G=-1.0)
+        L = lbm.Lattice(p, I.disc_field(n, n, R, rho_l=1.0, rho_g=0.1))
+        L.step(steps)
+        rho = L.moments()[0]
+        L.close()
+        rin = rho[n // 2 - 2:n // 2 + 2, n // 2 - 2:n // 2 + 2].mean()
+        rout = rho[:3, :3].mean()
+        req = np.sqrt(((rho - rout).sum() / (rin - rout)) / np.pi)
+        pts.append((1.0 / req, p_eos(rin) - p_eos(rout)))
+    x, y = np.array(pts).T
+    return float(np.polyfit(x, y, 1)[0])
+
+
+def paper_dynamic(steps=50000, dp=5.25e-4):
+    """The paper's own model and geometry (Sec. III.B-C): D2Q21 (Tab. I), EOS
+    pseudo-potential with G = -1, wall functions from the recursive filter of
+    Appendix A with the domain's top and bottom rows as solid outer boundary,
+    G_R = 1.33, G_A = 0.5, eps = 1, tau = 1, on 650x150 with a drop of radius
+    50 on the lower wall.  A static run (no force) gives the equilibrium angle;
+    a run driven by the largest pressure difference of Sec. III.C, applied
+    across the domain length as a uniform force density dp / L_x, gives the
+    advancing and receding angles, the mean drop speed U and Ca = U mu_L /
+    gamma, with gamma measured in the same process from Laplace pressure
+    jumps.  The step rate is the
+    binary32 rate of the static run."""
+    import torch
+    from paper_1202_6130_amd import inputs as I
+    from paper_1202_6130_amd import lbm
+    nx, ny = 650, 150
+    H = np.zeros((ny, nx))
+    H[0, :] = 1.0
+    H[ny - 1, :] = 1.0
+    rho0 = I.drop_field(nx, ny, 50.0, rho_l=1.0, rho_g=0.1, slab_rows=1)
+    iso = 0.55
+    force = dp / nx
+    res = {"metric": "MLUPS and contact angles (paper's model)", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "650x150, D2Q21, EOS psi (G=-1), recursive-filter walls (psiR=G^5, phi=G^22, "
+                                  "outer rows solid), G_R=1.33, G_A=0.5, eps=1, tau=1, drop radius 50, binary32",
+                      "steps": steps, "dp": dp, "force_density": force, "iso": iso, "y_ref": 0.0}}
+    gamma = laplace_gamma_q21(lbm.STORE_F32)
+    res["gamma"] = gamma
+    for name, F in (("static", 0.0), ("driven", force)):
+        p = lbm.lbm_params_default(nx=nx, ny=ny, storage=lbm.STORE_F32, wall_kind=lbm.WALL_MASK, lattice=lbm.D2Q21,
+                                   psi_kind=lbm.PSI_EOS, G=-1.0, G_R=1.33, G_A=0.5, eps=1.0, tau=1.0,
+                                   F_ext=(F, 0.0))
+        L = lbm.Lattice(p, rho0, wall_fields=np.stack([H, H]))
+        L.step(100)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        L.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        d = {"mlups": round(nx * ny * steps / dt / 1e6, 1), "seconds": round(dt, 3)}
+        if name == "static":
+            ang = L.contact_angle(iso, 0.0)
+            d["theta_deg"] = None if ang is None else float(ang[0])
+        else:
+            dyn = L.dynamic_angles(iso, 0.0)
+            d["dynamic_fit"] = dyn is not None
+            if dyn is not None:
+                mu_l = dyn[7] * (2.0 / 3.0) * (1.0 - 0.5)
+                d.update({"theta_A_deg": float(dyn[0]), "theta_R_deg": float(dyn[1]), "U": float(dyn[2]),
+                          "Ca": float(dyn[2] * mu_l / gamma)})
+        res[name] = d
+        L.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="spinodal4096",
-                    choices=sorted(WORKLOADS) + ["ensemble256", "serve", "precision4096", "wetting1024"])
+                    choices=sorted(WORKLOADS) + ["ensemble256", "serve", "precision4096", "wetting1024",
+                                                 "paper650x150"])
     ap.add_argument("--tile", type=int, default=None, help="tile shape index (default: autotuned in the warm-up)")
     ap.add_argument("--seq-steps", type=int, default=500, help="ensemble: steps per lattice of the sequential leg")
     ap.add_argument("--requests", type=int, default=60, help="serve: number of requests")
@@ -532,6 +615,9 @@ def main():
         return
     if args.workload == "precision4096":
         print(json.dumps(precision_study()), flush=True)
+        return
+    if args.workload == "paper650x150":
+        print(json.dumps(paper_dynamic()), flush=True)
         return
     if args.workload == "wetting1024":
         print(json.dumps(wetting()), flush=True)
