@@ -259,7 +259,13 @@ lbm_status lbm_destroy(lbm_ctx *c);
 int32_t lbm_tile_shapes(int32_t *waves, int32_t *rows, int32_t *strips, int32_t cap);
 
 /* Sets / returns the tile shape of a context (not one inside a batch:
- * LBM_ESTATE).  lbm_get_tile_shape returns -1 for NULL. */
+ * LBM_ESTATE).  lbm_get_tile_shape returns -1 for NULL.
+ * D2Q21 contexts have two step variants instead, bitwise the same update:
+ *  0  tiles of 16 waves x 2 rows (58 x 26 output nodes), any storage and tau;
+ *  1  marching workgroups of 256 aligned columns over segments of 128 rows
+ *     (F32 storage at tau = 1 only, else LBM_EINVAL).
+ * A new D2Q21 context starts with 1 where it applies and the lattice holds at
+ * least 256 such segments, else 0. */
 lbm_status lbm_set_tile_shape(lbm_ctx *c, int32_t shape);
 int32_t lbm_get_tile_shape(const lbm_ctx *c);
 
@@ -268,7 +274,8 @@ int32_t lbm_get_tile_shape(const lbm_ctx *c);
  * around each block), and keeps the shape of smallest median per-step time.
  * shape_out (nullable) gets the choice, ms_out (nullable, one entry per
  * shape) the medians.  The lattice advances by (3 steps + 1) *
- * lbm_tile_shapes(...) steps.  Synchronises. */
+ * lbm_tile_shapes(...) steps.  For D2Q21 the candidates are the step
+ * variants above that apply.  Synchronises. */
 lbm_status lbm_tune(lbm_ctx *c, int32_t steps, int32_t *shape_out, double *ms_out);
 
 /* ------------------------------------------------------------------------

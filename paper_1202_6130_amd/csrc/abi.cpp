@@ -313,6 +313,10 @@ lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const d
     L.lattice = pop_count(*p);
     L.psi_kind = p->psi_kind;
     L.collision = p->collision;
+    // D2Q21: marching step where it applies and the lattice fills the chip
+    if (p->lattice == LBM_D2Q21)
+        c->shape = (q21_march_ok(kernel_storage(p->storage), L.omega) &&
+                    q21_march_blocks(uint32_t(p->nx), uint32_t(p->ny)) >= 256) ? 1 : 0;
     {
         // eq. EOS with branch slopes s_b theta (s_b = eos[0..2]), pressure
         // continuous at rho_1 = eos[3] and rho_2 = eos[4].  The pseudo-potential
@@ -466,7 +470,7 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     const int K = c->p.diag_interval;
     for (int64_t s = 0; s < nsteps; ++s) {
         if (c->p.lattice == LBM_D2Q21)
-            TRY(launch_ok(launch_step_q21(ks, c->L, c->wall_mode, *c->cur, c->stream), "step_q21"));
+            TRY(launch_ok(launch_step_q21(ks, c->L, c->wall_mode, *c->cur, c->shape, c->stream), "step_q21"));
         else
             TRY(launch_ok(launch_step(ks, c->L, c->wall_mode, c->shape, *c->cur, c->stream), "step"));
         *c->cur ^= 1;
@@ -1140,8 +1144,14 @@ int32_t lbm_tile_shapes(int32_t *waves, int32_t *rows, int32_t *strips, int32_t 
 lbm_status lbm_set_tile_shape(lbm_ctx *c, int32_t shape) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (c->view) return fail(LBM_ESTATE, "lattice belongs to a batch; use lbm_batch_set_tile_shapes");
+    if (c->p.lattice == LBM_D2Q21) {
+        if (shape < 0 || shape >= kQ21Variants) return fail(LBM_EINVAL, "D2Q21 step variant %d out of range", shape);
+        if (shape == 1 && !q21_march_ok(kernel_storage(c->p.storage), c->L.omega))
+            return fail(LBM_EINVAL, "the marching D2Q21 step needs F32 storage and tau = 1");
+        c->shape = shape;
+        return LBM_OK;
+    }
     if (shape < 0 || shape >= kNumTileShapes) return fail(LBM_EINVAL, "tile shape %d out of range", shape);
-    if (c->p.lattice != LBM_D2Q9) return fail(LBM_EINVAL, "tile shapes apply to D2Q9 lattices");
     c->shape = shape;
     return LBM_OK;
 }
@@ -1191,12 +1201,13 @@ extern "C" {
 
 lbm_status lbm_tune(lbm_ctx *c, int32_t steps, int32_t *shape_out, double *ms_out) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
-    if (c->p.lattice != LBM_D2Q9) return fail(LBM_EINVAL, "tile shapes apply to D2Q9 lattices");
     if (c->view) return fail(LBM_ESTATE, "lattice belongs to a batch; use lbm_batch_tune");
     if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
     int best = c->shape;
     double best_ms = INFINITY;
-    for (int s = 0; s < kNumTileShapes; ++s) {
+    int count = kNumTileShapes;
+    if (c->p.lattice == LBM_D2Q21) count = q21_march_ok(kernel_storage(c->p.storage), c->L.omega) ? kQ21Variants : 1;
+    for (int s = 0; s < count; ++s) {
         c->shape = s;
         TRY(lbm_step(c, 1));                      // first launch of this shape: not timed
         double ms = 0;

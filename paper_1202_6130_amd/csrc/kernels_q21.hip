@@ -288,6 +288,132 @@ __global__ __launch_bounds__(kQ21Waves * kWave) void k_tile_q21(LatDev<C> L, con
     }
 }
 
+// ---------------------------------------------------------------------------
+// k_march_q21: the binary32 step at tau = 1 on large lattices.  A workgroup of
+// kMarchCols threads owns kMarchCols aligned columns (every lane an output, so
+// every population row is stored as whole 256-byte rows) and marches down a
+// segment of rows, one row per iteration: it loads the row 3 below the next
+// output row (issuing the following row's loads first), forms density,
+// momentum and pseudo-potential, keeps the pseudo-potential in an LDS ring of
+// kRing rows and the moments in an LDS ring of 4 rows, and once the row 3 below
+// an output row is in the ring forms that row's forces, collision and stores.
+// The 3 columns left and right of the workgroup: threads 0..125 load one
+// population of one of those 6 nodes each; the 6 densities are summed from LDS
+// in the order of density21, so they equal the owning workgroup's bit for bit.
+// Each segment reloads 6 rows; the tile kernel reloads 6 of every 32.
+constexpr int kMarchCols = kQ21MarchCols, kRing = 8, kHaloNodes = 2 * kH;
+
+// c_x + 3, c_y + 3 of D2Q21 velocity q packed 3 bits per q (lane-dependent q
+// without a memory table)
+constexpr uint64_t pack21(const int *c) {
+    uint64_t v = 0;
+    for (int q = 0; q < Q21; ++q) v |= uint64_t(c[q] + 3) << (3 * q);
+    return v;
+}
+constexpr uint64_t kCx21Code = pack21(kCx21), kCy21Code = pack21(kCy21);
+__device__ inline int cx21_dyn(int q) { return int((kCx21Code >> (3 * q)) & 7u) - 3; }
+__device__ inline int cy21_dyn(int q) { return int((kCy21Code >> (3 * q)) & 7u) - 3; }
+
+template <int WALL, int PSI>
+__global__ __launch_bounds__(kMarchCols) void k_march_q21(LatDev<float> L, const float *__restrict__ src,
+                                                          float *__restrict__ dst, uint32_t seg_rows) {
+    using C = float;
+    __shared__ C psi_r[kRing][kMarchCols + 2 * kH];   // column offset c at index c + 3
+    __shared__ C mom_r[4][3][kMarchCols];              // rho, j_x, j_y of rows waiting for output
+    __shared__ C halo_raw[kHaloNodes][Q21];
+    const uint32_t t = threadIdx.x;
+    const uint32_t nx = L.nx, ny = L.ny, P = L.pstride;
+    const uint32_t bxs = (nx + kMarchCols - 1) / kMarchCols;
+    const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const uint32_t by = lb / bxs, bx = lb - by * bxs;
+    const uint32_t x0 = bx * kMarchCols, y0 = by * seg_rows;
+    const uint32_t out_rows = min(seg_rows, ny - y0);
+    const uint32_t x = wrap_fast(x0 + t, nx);
+    const bool active = x0 + t < nx;
+    uint32_t xs[2 * kH + 1];                           // column of the pull with c_x = c: x - c
+#pragma unroll
+    for (int c = -kH; c <= kH; ++c) xs[c + kH] = wrap_fast(x + 3 * nx - uint32_t(c + kH) + kH, nx);
+    // halo loader: node e (0..2 left of x0, 3..5 right of x0 + kMarchCols - 1), population hq
+    const bool hl = t < uint32_t(kHaloNodes * Q21);
+    const uint32_t he = hl ? t / Q21 : 0, hq = hl ? t - he * Q21 : 0;
+    const uint32_t hcol = he < uint32_t(kH) ? wrap_fast(x0 + 3 * nx - kH + he, nx)
+                                            : wrap_fast(x0 + kMarchCols + (he - kH), nx);
+    const int hcx = cx21_dyn(int(hq)), hcy = cy21_dyn(int(hq));
+    const uint32_t hx = wrap_fast(hcol + 3 * nx - uint32_t(hcx), nx);
+
+    const uint32_t total = out_rows + 2 * kH;          // rows loaded: y0 - 3 .. y0 + out_rows + 2
+    auto row_of = [&](uint32_t i) { return wrap_fast(y0 + 3 * ny - kH + i, ny); };
+    auto load_row = [&](uint32_t r, C v[Q21]) {
+        uint32_t ro[2 * kH + 1];
+#pragma unroll
+        for (int c = -kH; c <= kH; ++c) ro[c + kH] = wrap_fast(r + 3 * ny - uint32_t(c + kH) + kH, ny) * nx;
+#pragma unroll
+        for (int q = 0; q < Q21; ++q) v[q] = src[size_t(q) * P + ro[kCy21[q] + kH] + xs[kCx21[q] + kH]];
+    };
+    auto load_halo = [&](uint32_t r) -> C {
+        if (!hl) return C(0);
+        const uint32_t rr = wrap_fast(r + 3 * ny - uint32_t(hcy), ny);
+        return src[size_t(hq) * P + rr * nx + hx];
+    };
+    C nxt[Q21];
+    load_row(row_of(0), nxt);
+    C hnxt = load_halo(row_of(0));
+    for (uint32_t i = 0; i < total; ++i) {
+        C g[Q21];
+#pragma unroll
+        for (int q = 0; q < Q21; ++q) g[q] = nxt[q];
+        const C hcur = hnxt;
+        if (i + 1 < total) {
+            load_row(row_of(i + 1), nxt);
+            hnxt = load_halo(row_of(i + 1));
+        }
+        const C rho = density21<C>(g);
+        C jx, jy;
+        momentum21<C>(g, jx, jy);
+        const uint32_t slot = i % kRing;
+        psi_r[slot][t + kH] = psi21<C, PSI>(L, rho);
+        mom_r[i % 4][0][t] = rho;
+        mom_r[i % 4][1][t] = jx;
+        mom_r[i % 4][2][t] = jy;
+        if (hl) halo_raw[he][hq] = hcur;
+        __syncthreads();
+        if (t < uint32_t(kHaloNodes)) {
+            C h[Q21];
+#pragma unroll
+            for (int q = 0; q < Q21; ++q) h[q] = halo_raw[t][q];
+            const C hp = psi21<C, PSI>(L, density21<C>(h));
+            psi_r[slot][t < uint32_t(kH) ? t : kMarchCols + t] = hp;
+        }
+        __syncthreads();
+        if (i >= uint32_t(2 * kH)) {
+            const uint32_t o = i - 2 * kH, ci = i - kH;    // output row y0 + o, loaded as row ci
+            const uint32_t y = y0 + o;
+            auto ps = [&](int cx, int cy) { return psi_r[(ci + kRing + uint32_t(cy)) % kRing][int(t) + kH + cx]; };
+            const C x1 = ps(1, 0) - ps(-1, 0), y1 = ps(0, 1) - ps(0, -1);
+            const C a1 = ps(1, 1) - ps(-1, -1), b1 = ps(1, -1) - ps(-1, 1);
+            const C x2 = ps(2, 0) - ps(-2, 0), y2 = ps(0, 2) - ps(0, -2);
+            const C a2 = ps(2, 2) - ps(-2, -2), b2 = ps(2, -2) - ps(-2, 2);
+            const C x3 = ps(3, 0) - ps(-3, 0), y3 = ps(0, 3) - ps(0, -3);
+            const C sx = (((C(kW21[1]) * x1 + C(kW21[5]) * (a1 + b1)) + C(2 * kW21[9]) * x2) +
+                          C(2 * kW21[13]) * (a2 + b2)) + C(3 * kW21[17]) * x3;
+            const C sy = (((C(kW21[2]) * y1 + C(kW21[5]) * (a1 - b1)) + C(2 * kW21[10]) * y2) +
+                          C(2 * kW21[13]) * (a2 - b2)) + C(3 * kW21[18]) * y3;
+            const uint32_t ms = ci % 4;
+            const C r0 = mom_r[ms][0][t], jx0 = mom_r[ms][1][t], jy0 = mom_r[ms][2][t];
+            const uint32_t n = y * nx + x;
+            C phie, Sx, Sy;
+            wall_terms<C, WALL>(L, row_wall<C, WALL>(L, y), n, phie, Sx, Sy);
+            const Node21<C> st = node21<C>(r0, jx0, jy0, ps(0, 0), sx, sy, phie, Sx, Sy, L);
+            C f[Q21];
+            collide21<C, 1>(f, st, L.omega, 0);
+            if (active) {
+#pragma unroll
+                for (int q = 0; q < Q21; ++q) __builtin_nontemporal_store(f[q], dst + size_t(q) * P + n);
+            }
+        }
+    }
+}
+
 // Calls fn(S{}, C{}) for the storage modes of D2Q21 (binary32, binary64).
 template <class Fn> hipError_t dispatch21(int storage, Fn &&fn) {
     switch (storage) {
@@ -339,8 +465,25 @@ hipError_t launch_tile_q21(int storage, const LatDevAny &La, int wall, int parit
 
 }  // namespace
 
-hipError_t launch_step_q21(int storage, const LatDevAny &L, int wall, int parity, hipStream_t st) {
-    return launch_tile_q21<0>(storage, L, wall, parity, 0, 0, 0, L.psi_kind, st);
+hipError_t launch_step_q21(int storage, const LatDevAny &L, int wall, int parity, int variant, hipStream_t st) {
+    if (variant == 0) return launch_tile_q21<0>(storage, L, wall, parity, 0, 0, 0, L.psi_kind, st);
+    if (!q21_march_ok(storage, L.omega)) return hipErrorInvalidValue;
+    const LatDev<float> d = L.get<float>();
+    const float *src = (const float *)(parity ? d.fb : d.fa);
+    float *dst = (float *)(parity ? d.fa : d.fb);
+    const dim3 grid(q21_march_blocks(d.nx, d.ny)), block(kMarchCols);
+    if (wall == WALL_ROW) {
+        if (L.psi_kind == 1)
+            hipLaunchKernelGGL((k_march_q21<WALL_ROW, 1>), grid, block, 0, st, d, src, dst, kQ21MarchRows);
+        else
+            hipLaunchKernelGGL((k_march_q21<WALL_ROW, 0>), grid, block, 0, st, d, src, dst, kQ21MarchRows);
+    } else {
+        if (L.psi_kind == 1)
+            hipLaunchKernelGGL((k_march_q21<WALL_NODE, 1>), grid, block, 0, st, d, src, dst, kQ21MarchRows);
+        else
+            hipLaunchKernelGGL((k_march_q21<WALL_NODE, 0>), grid, block, 0, st, d, src, dst, kQ21MarchRows);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_diag_q21(int storage, const LatDevAny &L, int wall, int parity, int write_mom, int compare,

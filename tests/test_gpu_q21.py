@@ -151,3 +151,71 @@ def test_q21_laplace_against_oracle():
         print(f"D2Q21 EOS Laplace storage {storage}: gamma {gamma:.6f} (oracle {g['gamma']:.6f})")
         tol = 1e-8 if storage == lbm.STORE_F64 else 5e-3
         assert abs(gamma - g["gamma"]) < tol * g["gamma"]
+
+
+@pytest.mark.parametrize("psi_kind", [lbm.PSI_EOS, lbm.PSI_EXP])
+@pytest.mark.parametrize("nx,ny,walls", [(300, 200, 1), (257, 131, 2), (64, 40, 1), (5, 3, 0), (1, 1, 0),
+                                         (700, 300, 0), (513, 129, 2)])
+def test_q21_march_matches_tiles_bitwise(nx, ny, walls, psi_kind):
+    """The marching variant computes bitwise the tile variant's update
+    (binary32, tau = 1; ragged and tiny lattices, row and node walls)."""
+    G = -1.0 if psi_kind == lbm.PSI_EOS else -6.0
+    kw = dict(nx=nx, ny=ny, storage=lbm.STORE_F32, lattice=lbm.D2Q21, psi_kind=psi_kind, G=G, G_R=0.4, G_A=0.2,
+              eps=1.3, F_ext=(1e-5, 0.0))
+    fields = None
+    if walls == 1:
+        kw["wall_kind"] = lbm.WALL_FLAT_SLAB
+        kw["slab_rows"] = min(8, ny - 1) if ny > 1 else 1
+        if ny < 3:
+            kw["wall_kind"] = lbm.WALL_NONE
+    elif walls == 2:
+        kw["wall_kind"] = lbm.WALL_FIELDS
+        rng = np.random.Generator(np.random.PCG64(nx))
+        fields = np.stack([rng.uniform(0, 1, (ny, nx)), rng.uniform(0, 1, (ny, nx)), rng.uniform(0, 0.4, (ny, nx))])
+    rng = np.random.Generator(np.random.PCG64(ny + 7))
+    rho0 = rng.uniform(0.1, 1.0, (ny, nx)) if psi_kind == lbm.PSI_EOS else rng.uniform(0.3, 1.8, (ny, nx))
+    out = []
+    for variant in (0, 1):
+        L = lbm.Lattice(lbm.lbm_params_default(**kw), rho0, wall_fields=fields)
+        L.tile_shape = variant
+        L.step(7)
+        out.append(L.get_state())
+        L.close()
+    assert np.array_equal(out[0], out[1])
+
+
+def test_q21_variants_selection():
+    p = lbm.lbm_params_default(nx=4096, ny=4096, lattice=lbm.D2Q21, psi_kind=lbm.PSI_EOS, G=-1.0)
+    L = lbm.Lattice(p, np.full((4096, 4096), 0.5))
+    assert L.tile_shape == 1
+    L.close()
+    p = lbm.lbm_params_default(nx=1024, ny=512, lattice=lbm.D2Q21, psi_kind=lbm.PSI_EOS, G=-1.0)
+    L = lbm.Lattice(p, np.full((512, 1024), 0.5))
+    assert L.tile_shape == 0
+    L.tile_shape = 1
+    L.close()
+    for kw in (dict(storage=lbm.STORE_F64), dict(tau=0.8)):
+        p = lbm.lbm_params_default(nx=64, ny=64, lattice=lbm.D2Q21, psi_kind=lbm.PSI_EOS, G=-1.0, **kw)
+        L = lbm.Lattice(p, np.full((64, 64), 0.5))
+        with pytest.raises(lbm.LbmError):
+            L.tile_shape = 1
+        L.close()
+
+
+def test_q21_march_drop_against_oracle():
+    """The EOS drop of test_q21_f32_eos_drop_tolerance stepped by the marching
+    variant: same bar against the oracle."""
+    nx, ny, steps = 80, 48, 1000
+    po = O.make_params(nx, ny, tau=1.0, G=-1.0, G_R=0.4, G_A=0.2, eps=1.0, lattice=21, psi_kind=1)
+    w = O.Walls.flat_slab(nx, ny, 8, 2.0, 1.0, 3.0)
+    rho0 = I.drop_field(nx, ny, 14.0, rho_l=1.0, rho_g=0.1)
+    p = lbm.lbm_params_default(nx=nx, ny=ny, storage=lbm.STORE_F32, wall_kind=lbm.WALL_FLAT_SLAB, tau=1.0, G=-1.0,
+                               G_R=0.4, G_A=0.2, eps=1.0, lattice=lbm.D2Q21, psi_kind=lbm.PSI_EOS)
+    L = lbm.Lattice(p, rho0)
+    L.tile_shape = 1
+    L.step(steps)
+    rho, ux, uy, _ = L.moments()
+    L.close()
+    r_o, ux_o, uy_o, _ = O.macros(po, w, O.run(po, w, O.init(po, rho0), steps))
+    assert np.abs(rho - r_o).max() / np.abs(r_o).max() < 1e-5
+    assert np.hypot(ux - ux_o, uy - uy_o).max() / CS21 < 1e-5
