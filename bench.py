@@ -44,8 +44,13 @@ def kernel_sources_digest(q=9):
     return h.hexdigest()
 
 
+def q21_kernel(variant):
+    return "k_march_q21" if variant == 1 else "k_tile_q21"
+
+
 def traffic_key(workload, storage, shape):
-    return f"{workload}:{storage}:" + (f"shape{shape}" if workload_q(workload) == 9 else "k_tile_q21")
+    """shape: the D2Q9 tile shape, or the D2Q21 step variant."""
+    return f"{workload}:{storage}:" + (f"shape{shape}" if workload_q(workload) == 9 else q21_kernel(shape))
 
 
 def stored_traffic(path, key):
@@ -72,12 +77,15 @@ def _counter_rows(run_dir):
 
 
 def _step_dispatch_key(name):
-    """Tile shape (D2Q9) or "k_tile_q21" for a dispatch of a step kernel,
-    None for any other kernel (the diagnostic variant of k_tile_q21 included)."""
+    """Tile shape (D2Q9), or the D2Q21 step variant (0 tiles, 1 marching), of
+    a dispatch of a step kernel; None for any other kernel (the diagnostic
+    variant of k_tile_q21 included)."""
     if "k_step_tiles<" in name and "k_step_tiles_batch" not in name:
         return int(name.split("k_step_tiles<")[1].split(">")[0].split(",")[-1])
-    if "k_tile_q21<" in name and name.split("k_tile_q21<")[1].split(">")[0].split(",")[-1].strip() == "0":
-        return "k_tile_q21"
+    if "k_march_q21<" in name:
+        return 1
+    if "k_tile_q21<" in name and name.split("k_tile_q21<")[1].split(">")[0].split(",")[-2].strip() == "0":
+        return 0
     return None
 
 
@@ -120,12 +128,11 @@ def ingest_counters(fetch_dir, write_dir, workload, storage, out_json):
         f = sum(fb[k]) / len(fb[k])
         w = sum(wb[k]) / len(wb[k])
         rd, wr = f * fs * 1024, w * ws * 1024
-        shape = k if q == 9 else None
-        data[traffic_key(workload, storage, shape)] = {
+        data[traffic_key(workload, storage, k)] = {
             "bytes_per_launch": round(rd + wr), "read_bytes": round(rd), "write_bytes": round(wr),
             "fetch_kib": round(f, 2), "write_kib": round(w, 2), "fetch_scale": round(fs, 5),
             "write_scale": round(ws, 5), "kernel_sources_sha256": kernel_sources_digest(q)}
-        print(f"| {k} | {len(fb[k])} | {f:,.0f} | {rd:,.0f} | {rd / alg:.3f} | {w:,.0f} | {wr / alg:.3f} | "
+        print(f"| {k if q == 9 else q21_kernel(k)} | {len(fb[k])} | {f:,.0f} | {rd:,.0f} | {rd / alg:.3f} | {w:,.0f} | {wr / alg:.3f} | "
               f"{(rd + wr) / (2 * alg):.3f} |")
     with open(out_json, "w") as fh:
         json.dump(data, fh, indent=1)
@@ -155,7 +162,9 @@ WORKLOADS = {
     "drop1024_q21": (1024, 512, "D2Q21, EOS pseudo-potential (G=-1): sessile drop 1024x512 at rho 1.0 / 0.1, "
                                 "radius 160, flat solid band of 8 rows, seeded wall amplitudes"),
 }
-Q21_TILE = "16 waves x 2 rows: 58 output columns x 26 output rows per workgroup (3 halo columns/rows each side)"
+Q21_TILE = {0: "tiles of 16 waves x 2 rows: 58 output columns x 26 output rows per workgroup (3 halo columns/rows "
+               "each side)",
+            1: "marching: 256 aligned output columns per workgroup over 128-row segments (6 halo rows per segment)"}
 
 
 def workload_q(name):
@@ -228,7 +237,7 @@ def time_gpu(name, storage, steps, warmup, seg_rows, tile=None, tau=1.0, collisi
     total_ms = t0.elapsed_time(t1)
     kern_ms = np.array([a.elapsed_time(b) for a, b in ev])
     d = L.diagnostics()
-    shape = L.tile_shape if workload_q(name) == 9 else None
+    shape = L.tile_shape
     L.close()
     return {
         "nodes": nodes, "ms_total": total_ms, "ms_per_step": total_ms / steps,
@@ -640,13 +649,13 @@ def main():
         "config": {"workload": WORKLOADS[args.workload][2], "nx": WORKLOADS[args.workload][0],
                    "ny": WORKLOADS[args.workload][1], "storage": args.storage,
                    "lattice": f"D2Q{q}", "tau": args.tau, "collision": args.collision,
-                   "tile": tile_desc(r["tile_shape"]) if q == 9 else Q21_TILE,
+                   "tile": tile_desc(r["tile_shape"]) if q == 9 else Q21_TILE[r["tile_shape"]],
                    "tile_tuned": args.tile is None and q == 9,
                    "tune_ms_per_shape": r["tune_ms"], "diag_every": DIAG_EVERY},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": bpu * r["nodes"],
-                     "kernel": "k_step_tiles" if q == 9 else "k_tile_q21", "kernel_ms_mean": round(r["kernel_ms_mean"], 5),
+                     "kernel": "k_step_tiles" if q == 9 else q21_kernel(r["tile_shape"]), "kernel_ms_mean": round(r["kernel_ms_mean"], 5),
                      "bytes_per_update": bpu},
     }
     if not args.no_cpu_baseline:
