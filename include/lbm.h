@@ -263,7 +263,7 @@ int32_t lbm_tile_shapes(int32_t *waves, int32_t *rows, int32_t *strips, int32_t 
  * D2Q21 contexts have two step variants instead, bitwise the same update:
  *  0  tiles of 16 waves x 2 rows (58 x 26 output nodes), any storage and tau;
  *  1  marching workgroups of 256 aligned columns over segments of 128 rows
- *     (F32 storage at tau = 1 only, else LBM_EINVAL).
+ *     (F32 storage only, else LBM_EINVAL).
  * A new D2Q21 context starts with 1 where it applies and the lattice holds at
  * least 256 such segments, else 0. */
 lbm_status lbm_set_tile_shape(lbm_ctx *c, int32_t shape);

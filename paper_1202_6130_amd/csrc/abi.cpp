@@ -1147,7 +1147,7 @@ lbm_status lbm_set_tile_shape(lbm_ctx *c, int32_t shape) {
     if (c->p.lattice == LBM_D2Q21) {
         if (shape < 0 || shape >= kQ21Variants) return fail(LBM_EINVAL, "D2Q21 step variant %d out of range", shape);
         if (shape == 1 && !q21_march_ok(kernel_storage(c->p.storage), c->L.omega))
-            return fail(LBM_EINVAL, "the marching D2Q21 step needs F32 storage and tau = 1");
+            return fail(LBM_EINVAL, "the marching D2Q21 step needs F32 storage");
         c->shape = shape;
         return LBM_OK;
     }

@@ -289,7 +289,7 @@ __global__ __launch_bounds__(kQ21Waves * kWave) void k_tile_q21(LatDev<C> L, con
 }
 
 // ---------------------------------------------------------------------------
-// k_march_q21: the binary32 step at tau = 1 on large lattices.  A workgroup of
+// k_march_q21: the binary32 step on large lattices.  A workgroup of
 // kMarchCols threads owns kMarchCols aligned columns (every lane an output, so
 // every population row is stored as whole 256-byte rows) and marches down a
 // segment of rows, one row per iteration: it loads the row 3 below the next
@@ -297,6 +297,8 @@ __global__ __launch_bounds__(kQ21Waves * kWave) void k_tile_q21(LatDev<C> L, con
 // momentum and pseudo-potential, keeps the pseudo-potential in an LDS ring of
 // kRing rows and the moments in an LDS ring of 4 rows, and once the row 3 below
 // an output row is in the ring forms that row's forces, collision and stores.
+// At tau != 1 the collision also needs the output row's populations: they
+// are loaded again (three iterations after their first load, from L2).
 // The 3 columns left and right of the workgroup: threads 0..125 load one
 // population of one of those 6 nodes each; the 6 densities are summed from LDS
 // in the order of density21, so they equal the owning workgroup's bit for bit.
@@ -314,7 +316,7 @@ constexpr uint64_t kCx21Code = pack21(kCx21), kCy21Code = pack21(kCy21);
 __device__ inline int cx21_dyn(int q) { return int((kCx21Code >> (3 * q)) & 7u) - 3; }
 __device__ inline int cy21_dyn(int q) { return int((kCy21Code >> (3 * q)) & 7u) - 3; }
 
-template <int WALL, int PSI>
+template <int WALL, int PSI, int ONE>
 __global__ __launch_bounds__(kMarchCols) void k_march_q21(LatDev<float> L, const float *__restrict__ src,
                                                           float *__restrict__ dst, uint32_t seg_rows) {
     using C = float;
@@ -405,7 +407,8 @@ __global__ __launch_bounds__(kMarchCols) void k_march_q21(LatDev<float> L, const
             wall_terms<C, WALL>(L, row_wall<C, WALL>(L, y), n, phie, Sx, Sy);
             const Node21<C> st = node21<C>(r0, jx0, jy0, ps(0, 0), sx, sy, phie, Sx, Sy, L);
             C f[Q21];
-            collide21<C, 1>(f, st, L.omega, 0);
+            if constexpr (!ONE) load_row(row_of(ci), f);
+            collide21<C, ONE>(f, st, L.omega, L.collision);
             if (active) {
 #pragma unroll
                 for (int q = 0; q < Q21; ++q) __builtin_nontemporal_store(f[q], dst + size_t(q) * P + n);
@@ -472,17 +475,20 @@ hipError_t launch_step_q21(int storage, const LatDevAny &L, int wall, int parity
     const float *src = (const float *)(parity ? d.fb : d.fa);
     float *dst = (float *)(parity ? d.fa : d.fb);
     const dim3 grid(q21_march_blocks(d.nx, d.ny)), block(kMarchCols);
-    if (wall == WALL_ROW) {
-        if (L.psi_kind == 1)
-            hipLaunchKernelGGL((k_march_q21<WALL_ROW, 1>), grid, block, 0, st, d, src, dst, kQ21MarchRows);
-        else
-            hipLaunchKernelGGL((k_march_q21<WALL_ROW, 0>), grid, block, 0, st, d, src, dst, kQ21MarchRows);
-    } else {
-        if (L.psi_kind == 1)
-            hipLaunchKernelGGL((k_march_q21<WALL_NODE, 1>), grid, block, 0, st, d, src, dst, kQ21MarchRows);
-        else
-            hipLaunchKernelGGL((k_march_q21<WALL_NODE, 0>), grid, block, 0, st, d, src, dst, kQ21MarchRows);
-    }
+    auto go = [&](auto wallc, auto psic, auto onec) {
+        constexpr int WL = decltype(wallc)::value, PS = decltype(psic)::value, ON = decltype(onec)::value;
+        hipLaunchKernelGGL((k_march_q21<WL, PS, ON>), grid, block, 0, st, d, src, dst, kQ21MarchRows);
+    };
+    auto with_one = [&](auto wallc, auto psic) {
+        if (L.omega == 1.0) go(wallc, psic, std::integral_constant<int, 1>{});
+        else go(wallc, psic, std::integral_constant<int, 0>{});
+    };
+    auto with_psi = [&](auto wallc) {
+        if (L.psi_kind == 1) with_one(wallc, std::integral_constant<int, 1>{});
+        else with_one(wallc, std::integral_constant<int, 0>{});
+    };
+    if (wall == WALL_ROW) with_psi(std::integral_constant<int, WALL_ROW>{});
+    else with_psi(std::integral_constant<int, WALL_NODE>{});
     return hipGetLastError();
 }
 

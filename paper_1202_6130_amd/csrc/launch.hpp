@@ -151,12 +151,12 @@ constexpr uint32_t kQ21OutCols = 58;
 constexpr uint32_t kQ21OutRows = kQ21Waves * kQ21Rows - 6;
 inline uint32_t q21_strips(uint32_t nx) { return (nx + kQ21OutCols - 1) / kQ21OutCols; }
 inline uint32_t q21_tiles(uint32_t nx, uint32_t ny) { return q21_strips(nx) * ((ny + kQ21OutRows - 1) / kQ21OutRows); }
-// D2Q21 step variants: 0 tiles (any storage and tau), 1 marching workgroups of
+// D2Q21 step variants: 0 tiles (any storage), 1 marching workgroups of
 // kQ21MarchCols aligned columns over segments of kQ21MarchRows rows (binary32
-// storage at tau = 1 only).
+// storage only).
 constexpr int kQ21Variants = 2;
 constexpr uint32_t kQ21MarchCols = 256, kQ21MarchRows = 128;
-inline bool q21_march_ok(int storage, double omega) { return storage == STORE_F32 && omega == 1.0; }
+inline bool q21_march_ok(int storage, double omega) { return storage == STORE_F32 && omega > 0.0; }
 inline uint32_t q21_march_blocks(uint32_t nx, uint32_t ny) {
     return ((nx + kQ21MarchCols - 1) / kQ21MarchCols) * ((ny + kQ21MarchRows - 1) / kQ21MarchRows);
 }

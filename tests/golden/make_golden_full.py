@@ -4,6 +4,7 @@
     python tests/golden/make_golden_full.py channel   # about half an hour
     python tests/golden/make_golden_full.py spinodal --threads 6   # about an hour on 6 cores
     python tests/golden/make_golden_full.py laplace21 --threads 8  # under a minute
+    python tests/golden/make_golden_full.py spinodal21 --threads 8 # about 15 minutes on 8 cores
 
 drop: 1024x512 sessile drop of radius 160 on the lower face of a flat solid
 band of 8 rows (tanh wall functions of width 2, core range 1, tail range 3,
@@ -28,6 +29,10 @@ densities inside and outside, the pressure jump p_EOS(rho_in) -
 p_EOS(rho_out), the radius of the liquid area and the Laplace fit
 dp = gamma / R + b (Sec. II.B reports gamma of about 0.09).
 
+spinodal21: the same phase-separation recipe for the paper's fluid (D2Q21,
+EOS, G = -1, rho 1.0 / 0.1), rho and u at 1024 seeded nodes and the totals
+after 100 and 300 steps.
+
 Only the oracle computes these values; a change to its arithmetic regenerates
 them in a commit that names the passage of the paper justifying it.
 """
@@ -49,6 +54,7 @@ DROP = dict(nx=1024, ny=512, radius=160.0, steps=20000, seed=0)
 CHANNEL = dict(nx=32, ny=256, rho=2.0, force=1e-6, steps=600000, seed=0)
 SPINODAL = dict(n=4096, seed=0, checkpoints=(100, 500, 1000, 2000, 5000))
 LAPLACE21 = dict(n=96, radii=(12.0, 16.0, 24.0), steps=4000)
+SPINODAL21 = dict(n=4096, seed=0, checkpoints=(100, 300))
 
 
 def laplace_disc(p, w, rho, n):
@@ -125,17 +131,26 @@ def channel():
     print("wrote", out)
 
 
-def spinodal():
-    c = SPINODAL
+def spinodal(q21=False):
+    c = SPINODAL21 if q21 else SPINODAL
     n = c["n"]
-    p = O.make_params(n, n, tau=1.0, G=-5.0)
+    if q21:
+        p = O.make_params(n, n, tau=1.0, G=-1.0, lattice=21, psi_kind=1)
+        rho0 = I.spinodal_field(n, seed=c["seed"], rho_l=1.0, rho_g=0.1)
+        name, what = "spinodal21_4096_fp64.json", ("periodic 4096x4096 phase separation, sigma 4, 50% at rho 1.0 / "
+                                                    "0.1, D2Q21, EOS pseudo-potential, G=-1, tau=1, FP64 oracle")
+    else:
+        p = O.make_params(n, n, tau=1.0, G=-5.0)
+        rho0 = I.spinodal_field(n, seed=c["seed"])
+        name, what = "spinodal_4096_fp64.json", "periodic 4096x4096 phase separation, sigma 4, 50% liquid, G=-5, tau=1, FP64 oracle"
     w = O.Walls.none(n, n)
-    f = O.init(p, I.spinodal_field(n, seed=c["seed"]))
+    f = O.init(p, rho0)
+    del rho0
     nodes = sample_nodes(n, n, 1024, 12)
     ys = np.array([y for y, _ in nodes])
     xs = np.array([x for _, x in nodes])
-    data = {"workload": "periodic 4096x4096 phase separation, sigma 4, 50% liquid, G=-5, tau=1, FP64 oracle",
-            "params": dict(c, G=-5.0), "nodes_y": ys.tolist(), "nodes_x": xs.tolist(), "checkpoints": []}
+    data = {"workload": what, "params": dict(c, G=float(p.G)), "nodes_y": ys.tolist(), "nodes_x": xs.tolist(),
+            "checkpoints": []}
     t = 0
     for tc in c["checkpoints"]:
         f = run_chunks(p, w, f, tc - t, 50, f"spinodal to {tc}")
@@ -143,7 +158,7 @@ def spinodal():
         rho, ux, uy, tot = O.macros(p, w, f)
         data["checkpoints"].append({"t": tc, "totals": tot.tolist(), "rho": rho[ys, xs].tolist(),
                                     "ux": ux[ys, xs].tolist(), "uy": uy[ys, xs].tolist()})
-        out = os.path.join(HERE, "spinodal_4096_fp64.json")
+        out = os.path.join(HERE, name)
         with open(out, "w") as fh:
             json.dump(data, fh)
         print("wrote", out, "through t =", tc, flush=True)
@@ -188,3 +203,5 @@ if __name__ == "__main__":
         channel()
     if "laplace21" in which:
         laplace21()
+    if "spinodal21" in which:
+        spinodal(q21=True)

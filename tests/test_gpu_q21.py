@@ -194,12 +194,31 @@ def test_q21_variants_selection():
     assert L.tile_shape == 0
     L.tile_shape = 1
     L.close()
-    for kw in (dict(storage=lbm.STORE_F64), dict(tau=0.8)):
-        p = lbm.lbm_params_default(nx=64, ny=64, lattice=lbm.D2Q21, psi_kind=lbm.PSI_EOS, G=-1.0, **kw)
-        L = lbm.Lattice(p, np.full((64, 64), 0.5))
-        with pytest.raises(lbm.LbmError):
-            L.tile_shape = 1
+    p = lbm.lbm_params_default(nx=64, ny=64, lattice=lbm.D2Q21, psi_kind=lbm.PSI_EOS, G=-1.0, storage=lbm.STORE_F64)
+    L = lbm.Lattice(p, np.full((64, 64), 0.5))
+    with pytest.raises(lbm.LbmError):
+        L.tile_shape = 1
+    L.close()
+
+
+@pytest.mark.parametrize("coll", [lbm.COLL_BGK, lbm.COLL_PROJECTED])
+@pytest.mark.parametrize("nx,ny", [(300, 200), (257, 131), (5, 3)])
+def test_q21_march_matches_tiles_bitwise_tau(nx, ny, coll):
+    """At tau != 1 (BGK and projected) the marching variant reloads the output
+    row's populations: still bitwise the tile variant's update."""
+    kw = dict(nx=nx, ny=ny, storage=lbm.STORE_F32, lattice=lbm.D2Q21, psi_kind=lbm.PSI_EOS, G=-1.0, tau=0.8,
+              collision=coll, G_R=0.4, G_A=0.2, wall_kind=lbm.WALL_FLAT_SLAB if ny > 8 else lbm.WALL_NONE,
+              F_ext=(1e-5, 0.0))
+    rng = np.random.Generator(np.random.PCG64(nx + ny))
+    rho0 = rng.uniform(0.1, 1.0, (ny, nx))
+    out = []
+    for variant in (0, 1):
+        L = lbm.Lattice(lbm.lbm_params_default(**kw), rho0)
+        L.tile_shape = variant
+        L.step(7)
+        out.append(L.get_state())
         L.close()
+    assert np.array_equal(out[0], out[1])
 
 
 def test_q21_march_drop_against_oracle():
