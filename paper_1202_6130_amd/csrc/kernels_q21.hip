@@ -14,6 +14,12 @@
 // stores (step) or accumulates the diagnostic sums (diagnostic pass).  At
 // tau = 1 the collision needs only the moments, so the populations are not
 // kept across the barrier.
+//
+// k_march_q21 (further down): the binary32 step on large lattices, marching
+// workgroups of 256 aligned columns down 128-row segments; it reloads only 6
+// rows per segment and stores whole 256-byte rows.  Both kernels build every
+// node's update from the same functions in the same order, so they produce
+// bitwise the same populations.
 #include <type_traits>
 
 #include "launch.hpp"

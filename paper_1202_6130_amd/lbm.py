@@ -403,6 +403,9 @@ class Lattice:
 
     @property
     def tile_shape(self):
+        """D2Q9: index into lbm_tile_shapes(); D2Q21: step variant (0 tiles,
+        1 marching, binary32 only).  Every choice computes bitwise the same
+        update."""
         return lbm_get_tile_shape(self.ctx)
 
     @tile_shape.setter
