@@ -1,0 +1,78 @@
+"""Host logic of bench.py (no GPU): bytes per update, the step-kernel
+dispatch names, counter ingestion from rocprofv3 CSV files, and the refusal
+of more than one GPU."""
+import csv
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+FIELDS = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id", "Thread_Id", "Grid_Size",
+          "Kernel_Id", "Kernel_Name", "Workgroup_Size", "LDS_Block_Size", "Scratch_Size", "VGPR_Count",
+          "Accum_VGPR_Count", "SGPR_Count", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+
+
+def test_bytes_per_update():
+    assert bench.bytes_per_update("f32") == 72 and bench.bytes_per_update("f16dev") == 36
+    assert bench.bytes_per_update("f64") == 144 and bench.bytes_per_update("f32", 21) == 168
+
+
+def test_step_dispatch_names():
+    k = bench._step_dispatch_key
+    assert k("void lbmwet::k_step_tiles<float, float, 0, 8>(lbmwet::LatDev<float>, void const*, void*)") == 8
+    assert k("void lbmwet::k_step_tiles_batch<float, float, 0, 5>(lbmwet::LatDev<float> const*, uint4 const*, int)") \
+        is None
+    assert k("void lbmwet::(anonymous namespace)::k_march_q21<0, 1, 1>(lbmwet::LatDev<float>, float const*, "
+             "float*, unsigned int)") == 1
+    assert k("void lbmwet::(anonymous namespace)::k_tile_q21<float, float, 0, 1, 0, 1>(lbmwet::LatDev<float>, "
+             "void const*, void*, int, int, int)") == 0
+    assert k("void lbmwet::(anonymous namespace)::k_tile_q21<float, float, 0, 1, 1, 1>(lbmwet::LatDev<float>, "
+             "void const*, void*, int, int, int)") is None          # the diagnostic pass
+    assert k("void lbmwet::k_diag<float, float, 0>(...)") is None
+    assert bench.traffic_key("spinodal4096", "f32", 8) == "spinodal4096:f32:shape8"
+    assert bench.traffic_key("spinodal4096_q21", "f32", 1) == "spinodal4096_q21:f32:k_march_q21"
+
+
+def _write_run(path, counter, copy_kib, steps):
+    os.makedirs(path)
+    with open(os.path.join(path, "1_counter_collection.csv"), "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        rows = [("__amd_rocclr_copyBuffer", 131072, copy_kib)]
+        rows += [(name, 1024, v) for name, v in steps]
+        for i, (name, grid, v) in enumerate(rows):
+            w.writerow({"Correlation_Id": i, "Dispatch_Id": i, "Grid_Size": grid, "Kernel_Name": name,
+                        "Counter_Name": counter, "Counter_Value": v})
+
+
+def test_ingest_counters(tmp_path):
+    name = "void lbmwet::k_step_tiles<float, float, 0, 8>(lbmwet::LatDev<float>, void const*, void*)"
+    diag = "void lbmwet::k_diag<float, float, 0>(x)"
+    # FETCH_SIZE books 128-byte requests as 64 bytes: the 1 GiB copy reads as 524288 KiB
+    _write_run(str(tmp_path / "f"), "FETCH_SIZE", 524288.0, [(name, 300000.0), (name, 310000.0), (diag, 9e9)])
+    _write_run(str(tmp_path / "w"), "WRITE_SIZE", 1048576.0, [(name, 589824.0), (name, 589824.0), (diag, 9e9)])
+    out = tmp_path / "traffic.json"
+    bench.ingest_counters(str(tmp_path / "f"), str(tmp_path / "w"), "spinodal4096", "f32", str(out))
+    rec = json.loads(out.read_text())["spinodal4096:f32:shape8"]
+    assert rec["fetch_scale"] == pytest.approx(2.0) and rec["write_scale"] == pytest.approx(1.0)
+    assert rec["read_bytes"] == round(305000.0 * 2.0 * 1024)
+    assert rec["write_bytes"] == 589824 * 1024 == 72 // 2 * 4096 * 4096
+    assert rec["bytes_per_launch"] == rec["read_bytes"] + rec["write_bytes"]
+    assert rec["kernel_sources_sha256"] == bench.kernel_sources_digest(9)
+    assert bench.stored_traffic(str(out), "spinodal4096:f32:shape8") == rec["bytes_per_launch"]
+    data = json.loads(out.read_text())
+    data["spinodal4096:f32:shape8"]["kernel_sources_sha256"] = "0" * 64
+    out.write_text(json.dumps(data))
+    assert bench.stored_traffic(str(out), "spinodal4096:f32:shape8") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
