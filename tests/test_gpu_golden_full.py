@@ -105,7 +105,7 @@ def test_spinodal_4096_vs_oracle():
     runs = {}
     for name, st in (("f64", lbm.STORE_F64), ("f32", lbm.STORE_F32)):
         runs[name] = lbm.Lattice(lbm.lbm_params_default(nx=n, ny=n, storage=st, diag_interval=0), rho0)
-    runs["f32"].tile_shape = 8          # the shape the benchmark's autotuner keeps on this lattice
+    runs["f32"].tile_shape = 8          # one of the two shapes the benchmark's autotuner keeps here (7, 8)
     t0 = 0
     for cp in g["checkpoints"]:
         for L in runs.values():
