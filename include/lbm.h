@@ -46,7 +46,7 @@ extern "C" {
 typedef int lbm_status;
 #define LBM_OK         0
 #define LBM_EINVAL    (-1)  /* invalid argument or parameter                  */
-#define LBM_ENOMEM    (-2)  /* workspace too small                            */
+#define LBM_ENOMEM    (-2)  /* workspace too small, or host allocation failed  */
 #define LBM_EDEVICE   (-3)  /* a HIP runtime call or kernel launch failed     */
 #define LBM_EUNSTABLE (-4)  /* non-finite density or velocity detected        */
 #define LBM_ENOFIT    (-5)  /* contact angle: < 16 points or degenerate fit   */

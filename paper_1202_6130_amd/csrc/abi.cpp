@@ -452,7 +452,7 @@ lbm_status lbm_create(const lbm_params *p, const double *rho0, const double *ux0
     if (workspace_bytes < Y.total)
         return fail(LBM_ENOMEM, "workspace too small: %zu < %zu bytes", workspace_bytes, Y.total);
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
-    if (!c) return fail(LBM_EINVAL, "host allocation failed");
+    if (!c) return fail(LBM_ENOMEM, "host allocation failed");
     lbm_status st = init_ctx(c, p, rho0, ux0, uy0, wall_fields, (char *)workspace, (hipStream_t)stream);
     if (st != LBM_OK) {
         delete c;
@@ -954,7 +954,7 @@ lbm_status lbm_batch_create(const lbm_params *ps, int32_t n, const double *const
     hipStream_t st = (hipStream_t)stream;
     TablesLayout T = tables_layout(B.lats, n, B.nwork, B.ntiles);
     lbm_batch *b = new_batch(ws, T, B.nwork, B.ntiles, st, true);
-    if (!b) return fail(LBM_EINVAL, "host allocation failed");
+    if (!b) return fail(LBM_ENOMEM, "host allocation failed");
     lbm_status stt = LBM_OK;
     for (int32_t k = 0; k < n && stt == LBM_OK; ++k) {
         lbm_params p = ps[k];
@@ -962,7 +962,7 @@ lbm_status lbm_batch_create(const lbm_params *ps, int32_t n, const double *const
         stt = check_host_fields(&p, rho0s[k], ux0s ? ux0s[k] : nullptr, uy0s ? uy0s[k] : nullptr, nullptr);
         if (stt != LBM_OK) break;
         lbm_ctx *c = new (std::nothrow) lbm_ctx();
-        if (!c) { stt = fail(LBM_EINVAL, "host allocation failed"); break; }
+        if (!c) { stt = fail(LBM_ENOMEM, "host allocation failed"); break; }
         stt = init_ctx(c, &p, rho0s[k], ux0s ? ux0s[k] : nullptr, uy0s ? uy0s[k] : nullptr, nullptr,
                        ws + B.off[k], st);
         if (stt != LBM_OK) { delete c; break; }
@@ -1020,7 +1020,7 @@ lbm_status lbm_batch_attach(lbm_ctx *const *ctxs, int32_t n, void *workspace, si
     TablesLayout T = tables_layout(0, n, nwork, ntiles);
     if (workspace_bytes < T.total) return fail(LBM_ENOMEM, "workspace too small: %zu < %zu", workspace_bytes, T.total);
     lbm_batch *b = new_batch((char *)workspace, T, nwork, ntiles, st, false);
-    if (!b) return fail(LBM_EINVAL, "host allocation failed");
+    if (!b) return fail(LBM_ENOMEM, "host allocation failed");
     for (int32_t k = 0; k < n; ++k) {
         lbm_ctx *c = ctxs[k];
         // make every context's current state its buffer fa: batch parity 0
