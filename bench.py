@@ -262,6 +262,30 @@ def copy_reference():
     del src, dst
 
 
+def copy_ceiling(reps=20):
+    """HBM rate of a plain 1 GiB device-to-device copy (read + write bytes over
+    time), timed with events in this process: the practical ceiling the step
+    kernel's roofline fraction is compared against."""
+    import torch
+    n = COPY_REF_BYTES // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return {"value": round(2 * COPY_REF_BYTES / (ms * 1e-3) / 1e9, 1), "unit": "GB/s",
+            "kind": "1 GiB device-to-device copy (torch), read + write bytes"}
+
+
 def cpu_baseline(seconds_hint=15.0, q=9):
     """The FP64 oracle (single thread, as it stands) on a bounded sample of the
     same workload recipe: a 1024x1024 periodic spinodal lattice of the same
@@ -658,6 +682,7 @@ def main():
                      "kernel": "k_step_tiles" if q == 9 else q21_kernel(r["tile_shape"]), "kernel_ms_mean": round(r["kernel_ms_mean"], 5),
                      "bytes_per_update": bpu},
     }
+    out["copy_ceiling"] = copy_ceiling()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(q=q)
     print(json.dumps(out), flush=True)
