@@ -22,6 +22,7 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS + % peak HBM GB/s (1 GPU); batched solves/s, p50/p99 latency vs plain"
 HBM_PEAK_GBS = 8000.0
 DIAG_EVERY = 100
+SAMPLE_EVERY = 10          # timed launches per per-launch event pair
 
 
 KERNEL_SOURCES = {
@@ -48,9 +49,15 @@ def q21_kernel(variant):
     return "k_march_q21" if variant == 1 else "k_tile_q21"
 
 
+def q21_label(variant):
+    """Kernel and tiling of a D2Q21 step variant (variants 0 and 2 are the
+    two-row and one-row instances of k_tile_q21)."""
+    return {0: "k_tile_q21", 1: "k_march_q21", 2: "k_tile_q21_r1"}[variant]
+
+
 def traffic_key(workload, storage, shape):
     """shape: the D2Q9 tile shape, or the D2Q21 step variant."""
-    return f"{workload}:{storage}:" + (f"shape{shape}" if workload_q(workload) == 9 else q21_kernel(shape))
+    return f"{workload}:{storage}:" + (f"shape{shape}" if workload_q(workload) == 9 else q21_label(shape))
 
 
 def stored_traffic(path, key):
@@ -77,15 +84,17 @@ def _counter_rows(run_dir):
 
 
 def _step_dispatch_key(name):
-    """Tile shape (D2Q9), or the D2Q21 step variant (0 tiles, 1 marching), of
-    a dispatch of a step kernel; None for any other kernel (the diagnostic
-    variant of k_tile_q21 included)."""
+    """Tile shape (D2Q9), or the D2Q21 step variant (0 two-row tiles, 1
+    marching, 2 one-row tiles), of a dispatch of a step kernel; None for any
+    other kernel (the diagnostic variant of k_tile_q21 included)."""
     if "k_step_tiles<" in name and "k_step_tiles_batch" not in name:
         return int(name.split("k_step_tiles<")[1].split(">")[0].split(",")[-1])
     if "k_march_q21<" in name:
         return 1
-    if "k_tile_q21<" in name and name.split("k_tile_q21<")[1].split(">")[0].split(",")[-2].strip() == "0":
-        return 0
+    if "k_tile_q21<" in name:
+        args = [a.strip() for a in name.split("k_tile_q21<")[1].split(">")[0].split(",")]
+        if args[-3] == "0":                           # <S, C, WALL, PSI, DIAG, ONE, rows per wave>
+            return 0 if args[-1] == "2" else 2
     return None
 
 
@@ -132,7 +141,7 @@ def ingest_counters(fetch_dir, write_dir, workload, storage, out_json):
             "bytes_per_launch": round(rd + wr), "read_bytes": round(rd), "write_bytes": round(wr),
             "fetch_kib": round(f, 2), "write_kib": round(w, 2), "fetch_scale": round(fs, 5),
             "write_scale": round(ws, 5), "kernel_sources_sha256": kernel_sources_digest(q)}
-        print(f"| {k if q == 9 else q21_kernel(k)} | {len(fb[k])} | {f:,.0f} | {rd:,.0f} | {rd / alg:.3f} | {w:,.0f} | {wr / alg:.3f} | "
+        print(f"| {k if q == 9 else q21_label(k)} | {len(fb[k])} | {f:,.0f} | {rd:,.0f} | {rd / alg:.3f} | {w:,.0f} | {wr / alg:.3f} | "
               f"{(rd + wr) / (2 * alg):.3f} |")
     with open(out_json, "w") as fh:
         json.dump(data, fh, indent=1)
@@ -161,10 +170,15 @@ WORKLOADS = {
                                      "50% at rho 1.0 / 0.1, tau=1, no solid"),
     "drop1024_q21": (1024, 512, "D2Q21, EOS pseudo-potential (G=-1): sessile drop 1024x512 at rho 1.0 / 0.1, "
                                 "radius 160, flat solid band of 8 rows, seeded wall amplitudes"),
+    "paper650x150_q21": (650, 150, "D2Q21, EOS pseudo-potential (G=-1): the paper's 650x150 domain, drop of "
+                                   "radius 50 at rho 1.0 / 0.1 on the lower wall, recursive-filter walls with the "
+                                   "outer rows solid, G_R=1.33, G_A=0.5, eps=1"),
 }
 Q21_TILE = {0: "tiles of 16 waves x 2 rows: 58 output columns x 26 output rows per workgroup (3 halo columns/rows "
                "each side)",
-            1: "marching: 256 aligned output columns per workgroup over 128-row segments (6 halo rows per segment)"}
+            1: "marching: 256 aligned output columns per workgroup over 128-row segments (6 halo rows per segment)",
+            2: "tiles of 16 waves x 1 row: 58 output columns x 10 output rows per workgroup (3 halo columns/rows "
+               "each side)"}
 
 
 def workload_q(name):
@@ -185,6 +199,15 @@ def make_lattice(name, storage, seg_rows, tau=1.0, collision=0):
         rho0 = I.spinodal_field(nx, seed=0, **dens)
         p = lbm.lbm_params_default(nx=nx, ny=ny, storage=st, diag_interval=DIAG_EVERY, seg_rows=seg_rows,
                                    rho_ref=float(rho0.mean()), tau=tau, collision=collision, **fluid)
+    elif name.startswith("paper650x150"):
+        H = np.zeros((ny, nx))
+        H[0, :] = 1.0
+        H[ny - 1, :] = 1.0
+        rho0 = I.drop_field(nx, ny, 50.0, slab_rows=1, **dens)
+        p = lbm.lbm_params_default(nx=nx, ny=ny, storage=st, wall_kind=lbm.WALL_MASK, G_R=1.33, G_A=0.5, eps=1.0,
+                                   diag_interval=DIAG_EVERY, seg_rows=seg_rows, rho_ref=float(rho0.mean()), tau=tau,
+                                   collision=collision, **fluid)
+        return lbm.Lattice(p, rho0, wall_fields=np.stack([H, H])), p
     else:
         gr, ga = I.draw_wall_amplitudes(0)
         rho0 = I.drop_field(nx, ny, 160.0, **dens)
@@ -195,43 +218,52 @@ def make_lattice(name, storage, seg_rows, tau=1.0, collision=0):
 
 
 def time_gpu(name, storage, steps, warmup, seg_rows, tile=None, tau=1.0, collision=0):
-    """tile None: the autotuner picks the tile shape during the warm-up
-    (its steps count as warm-up); else the given shape."""
+    """tile None: the autotuner picks the D2Q9 tile shape during the
+    warm-up (its steps count as warm-up), and a D2Q21 lattice keeps the step
+    variant a new context starts with; else the given shape or variant."""
     import torch
     L, p = make_lattice(name, storage, seg_rows, tau, collision)
     nodes = p.nx * p.ny
     tune_ms = None
-    if workload_q(name) == 21:
-        pass                      # one tile shape
-    elif tile is None:
+    if tile is not None:
+        L.tile_shape = tile
+    elif workload_q(name) == 21:
+        pass                      # the context's default step variant
+    else:
         from paper_1202_6130_amd import lbm
         # 3 * tune_steps + 1 trial steps per shape, within the warm-up when it is long enough
         tune_steps = max(2, (warmup // len(lbm.lbm_tile_shapes()) - 1) // 3)
         shape, tune_ms = L.tune(tune_steps)
         tune_ms = [round(float(v), 5) for v in tune_ms]
-    else:
-        L.tile_shape = tile
     L.step(max(0, warmup - L.step_index))
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    # per-launch events on the launch stream for steps without a diagnostic pass
+    # The timed steps run in blocks of SAMPLE_EVERY: the first step of a block
+    # (unless it runs the diagnostic pass) between a pair of events on the
+    # launch stream, the rest in one lbm_step call, so that host work per step
+    # never starves the GPU on small lattices.
+    pool = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in range((steps + SAMPLE_EVERY - 1) // SAMPLE_EVERY)]
     ev = []
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record(stream)
     start_idx = L.step_index
-    for s in range(steps):
-        diag_here = (start_idx + s + 1) % DIAG_EVERY == 0
-        if not diag_here:
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
+    s = 0
+    while s < steps:
+        n = min(SAMPLE_EVERY, steps - s)
+        if (start_idx + s + 1) % DIAG_EVERY != 0:
+            a, b = pool[len(ev)]
             a.record(stream)
             L.step(1)
             b.record(stream)
             ev.append((a, b))
+            if n > 1:
+                L.step(n - 1)
         else:
-            L.step(1)
+            L.step(n)
+        s += n
     t1.record(stream)
     torch.cuda.synchronize()
     total_ms = t0.elapsed_time(t1)
@@ -242,6 +274,7 @@ def time_gpu(name, storage, steps, warmup, seg_rows, tile=None, tau=1.0, collisi
     return {
         "nodes": nodes, "ms_total": total_ms, "ms_per_step": total_ms / steps,
         "kernel_ms_mean": float(kern_ms.mean()), "kernel_ms_median": float(np.median(kern_ms)),
+        "kernel_samples": len(ev),
         "mass": float(d[1]), "nonfinite": float(d[5]), "seg_rows": p.seg_rows, "tile_shape": shape,
         "tune_ms": tune_ms,
     }
@@ -583,6 +616,7 @@ def paper_dynamic(steps=50000, dp=5.25e-4):
                                    psi_kind=lbm.PSI_EOS, G=-1.0, G_R=1.33, G_A=0.5, eps=1.0, tau=1.0,
                                    F_ext=(F, 0.0))
         L = lbm.Lattice(p, rho0, wall_fields=np.stack([H, H]))
+        res["config"]["step_variant"] = Q21_TILE[L.tile_shape]
         L.step(100)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -613,7 +647,9 @@ def main():
     ap.add_argument("--workload", default="spinodal4096",
                     choices=sorted(WORKLOADS) + ["ensemble256", "serve", "precision4096", "wetting1024",
                                                  "paper650x150"])
-    ap.add_argument("--tile", type=int, default=None, help="tile shape index (default: autotuned in the warm-up)")
+    ap.add_argument("--tile", type=int, default=None,
+                    help="D2Q9 tile shape index (default: autotuned in the warm-up), or D2Q21 step variant "
+                         "(default: the one a new context starts with)")
     ap.add_argument("--seq-steps", type=int, default=500, help="ensemble: steps per lattice of the sequential leg")
     ap.add_argument("--requests", type=int, default=60, help="serve: number of requests")
     ap.add_argument("--max-steps", type=int, default=20000, help="serve: step cap per request")
@@ -681,6 +717,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": bpu * r["nodes"],
                      "kernel": "k_step_tiles" if q == 9 else q21_kernel(r["tile_shape"]), "kernel_ms_mean": round(r["kernel_ms_mean"], 5),
+                     "kernel_timing": f"HIP events around {r['kernel_samples']} of the timed launches (every "
+                                      f"{SAMPLE_EVERY}th, none with a diagnostic pass), on the launch stream",
                      "bytes_per_update": bpu},
     }
     out["device_copy"] = device_copy()

@@ -260,12 +260,13 @@ int32_t lbm_tile_shapes(int32_t *waves, int32_t *rows, int32_t *strips, int32_t 
 
 /* Sets / returns the tile shape of a context (not one inside a batch:
  * LBM_ESTATE).  lbm_get_tile_shape returns -1 for NULL.
- * D2Q21 contexts have two step variants instead, bitwise the same update:
+ * D2Q21 contexts have three step variants instead, bitwise the same update:
  *  0  tiles of 16 waves x 2 rows (58 x 26 output nodes), any storage and tau;
  *  1  marching workgroups of 256 aligned columns over segments of 128 rows
- *     (F32 storage only, else LBM_EINVAL).
+ *     (F32 storage only, else LBM_EINVAL);
+ *  2  tiles of 16 waves x 1 row (58 x 10 output nodes), any storage and tau.
  * A new D2Q21 context starts with 1 where it applies and the lattice holds at
- * least 256 such segments, else 0. */
+ * least 256 such segments, else with 2. */
 lbm_status lbm_set_tile_shape(lbm_ctx *c, int32_t shape);
 int32_t lbm_get_tile_shape(const lbm_ctx *c);
 
@@ -273,9 +274,11 @@ int32_t lbm_get_tile_shape(const lbm_ctx *c);
  * three timed blocks of `steps` consecutive ordinary time steps (events
  * around each block), and keeps the shape of smallest median per-step time.
  * shape_out (nullable) gets the choice, ms_out (nullable, one entry per
- * shape) the medians.  The lattice advances by (3 steps + 1) *
- * lbm_tile_shapes(...) steps.  For D2Q21 the candidates are the step
- * variants above that apply.  Synchronises. */
+ * shape) the medians.  The lattice advances by 3 * steps + 1 steps per
+ * candidate.
+ * The candidates are the lbm_tile_shapes(...) shapes, for D2Q21 the three
+ * step variants above (ms_out gets INFINITY for variant 1 where it does not
+ * apply).  Synchronises. */
 lbm_status lbm_tune(lbm_ctx *c, int32_t steps, int32_t *shape_out, double *ms_out);
 
 /* ------------------------------------------------------------------------

@@ -314,9 +314,13 @@ lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const d
     L.psi_kind = p->psi_kind;
     L.collision = p->collision;
     // D2Q21: marching step where it applies and the lattice fills the chip
+    // with marching workgroups, else one-row tiles (measured on MI355X: never
+    // slower than two-row tiles except binary32 at tau != 1 on lattices that
+    // march; faster on lattices of few tiles, and in binary64, where the
+    // two-row tile at tau != 1 spills registers)
     if (p->lattice == LBM_D2Q21)
         c->shape = (q21_march_ok(kernel_storage(p->storage), L.omega) &&
-                    q21_march_blocks(uint32_t(p->nx), uint32_t(p->ny)) >= 256) ? 1 : 0;
+                    q21_march_blocks(uint32_t(p->nx), uint32_t(p->ny)) >= kQ21FillBlocks) ? 1 : 2;
     {
         // eq. EOS with branch slopes s_b theta (s_b = eos[0..2]), pressure
         // continuous at rho_1 = eos[3] and rho_2 = eos[4].  The pseudo-potential
@@ -1205,9 +1209,13 @@ lbm_status lbm_tune(lbm_ctx *c, int32_t steps, int32_t *shape_out, double *ms_ou
     if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
     int best = c->shape;
     double best_ms = INFINITY;
-    int count = kNumTileShapes;
-    if (c->p.lattice == LBM_D2Q21) count = q21_march_ok(kernel_storage(c->p.storage), c->L.omega) ? kQ21Variants : 1;
+    const bool q21 = c->p.lattice == LBM_D2Q21;
+    const int count = q21 ? kQ21Variants : kNumTileShapes;
     for (int s = 0; s < count; ++s) {
+        if (q21 && s == 1 && !q21_march_ok(kernel_storage(c->p.storage), c->L.omega)) {
+            if (ms_out) ms_out[s] = INFINITY;   // marching step does not apply
+            continue;
+        }
         c->shape = s;
         TRY(lbm_step(c, 1));                      // first launch of this shape: not timed
         double ms = 0;

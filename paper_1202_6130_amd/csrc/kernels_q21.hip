@@ -4,8 +4,8 @@
 //
 // k_tile_q21: one workgroup of kQ21Waves waves owns a strip of 64 columns of
 // which the 3 on each side are halo columns (58 output columns) and
-// kQ21Waves * kQ21Rows consecutive rows of which the 3 on each side are halo
-// rows.  Every wave loads its rows at once (21 pulled loads per row, shifts up
+// kQ21Waves * R consecutive rows (R = 2, or 1 on lattices too small to fill
+// the chip with two-row tiles) of which the 3 on each side are halo rows.  Every wave loads its rows at once (21 pulled loads per row, shifts up
 // to +-3 in both directions), computes density, momentum and pseudo-potential
 // of all 64 columns, including the halo ones from their own loads, and
 // publishes the pseudo-potential in LDS; after one barrier every output node
@@ -156,12 +156,29 @@ template <class C, int ONE> __device__ inline void collide21(C f[Q21], const Nod
     close_mass21<C>(f, s.rho);
 }
 
-template <class S, class C, int WALL, int PSI, int DIAG, int ONE>
+// sum_i w_i psi(x + c_i) c_i over the 20 moving directions, from differences
+// across the node, which vanish exactly where psi is uniform; ps(c_x, c_y)
+// returns psi(x + c).  Both step kernels take this one order of operations.
+template <class C, class Ps> __device__ inline void psi_sum21(const Ps &ps, C &sx, C &sy) {
+    const C x1 = ps(1, 0) - ps(-1, 0), y1 = ps(0, 1) - ps(0, -1);
+    const C a1 = ps(1, 1) - ps(-1, -1), b1 = ps(1, -1) - ps(-1, 1);
+    const C x2 = ps(2, 0) - ps(-2, 0), y2 = ps(0, 2) - ps(0, -2);
+    const C a2 = ps(2, 2) - ps(-2, -2), b2 = ps(2, -2) - ps(-2, 2);
+    const C x3 = ps(3, 0) - ps(-3, 0), y3 = ps(0, 3) - ps(0, -3);
+    sx = (((C(kW21[1]) * x1 + C(kW21[5]) * (a1 + b1)) + C(2 * kW21[9]) * x2) + C(2 * kW21[13]) * (a2 + b2)) +
+         C(3 * kW21[17]) * x3;
+    sy = (((C(kW21[2]) * y1 + C(kW21[5]) * (a1 - b1)) + C(2 * kW21[10]) * y2) + C(2 * kW21[13]) * (a2 - b2)) +
+         C(3 * kW21[18]) * y3;
+}
+
+template <class S, class C, int WALL, int PSI, int DIAG, int ONE, int R>
 __global__ __launch_bounds__(kQ21Waves * kWave) void k_tile_q21(LatDev<C> L, const void *__restrict__ src,
                                                                 void *__restrict__ dst, int write_mom, int compare,
                                                                 int update) {
+    // the diagnostic partials are sized for the default tiling
+    static_assert(!DIAG || R == kQ21Rows, "diagnostic pass uses kQ21Rows rows per wave");
     using Raw = typename Codec<S>::Raw;
-    constexpr int R = kQ21Rows, ROWS = kQ21Waves * kQ21Rows;
+    constexpr int ROWS = kQ21Waves * R;
     constexpr uint32_t OUT = uint32_t(ROWS - 2 * kH);
     __shared__ C psi_s[ROWS][kWave];
     const int lane = threadIdx.x & (kWave - 1);
@@ -224,18 +241,8 @@ __global__ __launch_bounds__(kQ21Waves * kWave) void k_tile_q21(LatDev<C> L, con
         const uint32_t k = uint32_t(w * R + j);
         if (k < uint32_t(kH) || k >= out_rows + kH) continue;
         const uint32_t r = wrap_fast(y0 + 3 * ny - kH + k, ny);
-        // sum_i w_i psi(x + c_i) c_i from differences across the node, which
-        // vanish exactly where psi is uniform
-        auto ps = [&](int cx, int cy) { return psi_s[int(k) + cy][lc + cx]; };
-        const C x1 = ps(1, 0) - ps(-1, 0), y1 = ps(0, 1) - ps(0, -1);
-        const C a1 = ps(1, 1) - ps(-1, -1), b1 = ps(1, -1) - ps(-1, 1);
-        const C x2 = ps(2, 0) - ps(-2, 0), y2 = ps(0, 2) - ps(0, -2);
-        const C a2 = ps(2, 2) - ps(-2, -2), b2 = ps(2, -2) - ps(-2, 2);
-        const C x3 = ps(3, 0) - ps(-3, 0), y3 = ps(0, 3) - ps(0, -3);
-        const C sx = (((C(kW21[1]) * x1 + C(kW21[5]) * (a1 + b1)) + C(2 * kW21[9]) * x2) +
-                      C(2 * kW21[13]) * (a2 + b2)) + C(3 * kW21[17]) * x3;
-        const C sy = (((C(kW21[2]) * y1 + C(kW21[5]) * (a1 - b1)) + C(2 * kW21[10]) * y2) +
-                      C(2 * kW21[13]) * (a2 - b2)) + C(3 * kW21[18]) * y3;
+        C sx, sy;
+        psi_sum21<C>([&](int cx, int cy) { return psi_s[int(k) + cy][lc + cx]; }, sx, sy);
         const uint32_t n = r * nx + x;
         C phie, Sx, Sy;
         wall_terms<C, WALL>(L, row_wall<C, WALL>(L, r), n, phie, Sx, Sy);
@@ -397,15 +404,8 @@ __global__ __launch_bounds__(kMarchCols) void k_march_q21(LatDev<float> L, const
             const uint32_t o = i - 2 * kH, ci = i - kH;    // output row y0 + o, loaded as row ci
             const uint32_t y = y0 + o;
             auto ps = [&](int cx, int cy) { return psi_r[(ci + kRing + uint32_t(cy)) % kRing][int(t) + kH + cx]; };
-            const C x1 = ps(1, 0) - ps(-1, 0), y1 = ps(0, 1) - ps(0, -1);
-            const C a1 = ps(1, 1) - ps(-1, -1), b1 = ps(1, -1) - ps(-1, 1);
-            const C x2 = ps(2, 0) - ps(-2, 0), y2 = ps(0, 2) - ps(0, -2);
-            const C a2 = ps(2, 2) - ps(-2, -2), b2 = ps(2, -2) - ps(-2, 2);
-            const C x3 = ps(3, 0) - ps(-3, 0), y3 = ps(0, 3) - ps(0, -3);
-            const C sx = (((C(kW21[1]) * x1 + C(kW21[5]) * (a1 + b1)) + C(2 * kW21[9]) * x2) +
-                          C(2 * kW21[13]) * (a2 + b2)) + C(3 * kW21[17]) * x3;
-            const C sy = (((C(kW21[2]) * y1 + C(kW21[5]) * (a1 - b1)) + C(2 * kW21[10]) * y2) +
-                          C(2 * kW21[13]) * (a2 - b2)) + C(3 * kW21[18]) * y3;
+            C sx, sy;
+            psi_sum21<C>(ps, sx, sy);
             const uint32_t ms = ci % 4;
             const C r0 = mom_r[ms][0][t], jx0 = mom_r[ms][1][t], jy0 = mom_r[ms][2][t];
             const uint32_t n = y * nx + x;
@@ -432,7 +432,7 @@ template <class Fn> hipError_t dispatch21(int storage, Fn &&fn) {
     }
 }
 
-template <int DIAG>
+template <int DIAG, int R>
 hipError_t launch_tile_q21(int storage, const LatDevAny &La, int wall, int parity, int write_mom, int compare,
                            int update, int psi_kind, hipStream_t st) {
     return dispatch21(storage, [&](auto s, auto c) {
@@ -441,7 +441,7 @@ hipError_t launch_tile_q21(int storage, const LatDevAny &La, int wall, int parit
         LatDev<C> d = La.get<C>();
         const void *src = parity ? d.fb : d.fa;
         void *dst = parity ? d.fa : d.fb;
-        const dim3 grid(q21_tiles(d.nx, d.ny)), block(kQ21Waves * kWave);
+        const dim3 grid(q21_tiles(d.nx, d.ny, R)), block(kQ21Waves * kWave);
         const bool one = DIAG || La.omega == 1.0;
         // One workgroup per CU: its loads in flight (16 waves x 2 rows x 21
         // planes x 256 B = 172 KB) from the 32 CUs of an XCD already exceed
@@ -449,14 +449,15 @@ hipError_t launch_tile_q21(int storage, const LatDevAny &La, int wall, int parit
         // neighbouring tiles share before they are read again (measured on the
         // 4096^2 binary32 step: 0.94 ms with two workgroups per CU, 0.77 ms with
         // one).  The unused dynamic LDS reservation is what caps residency.
-        const size_t lds_reserve = kQ21LdsReserve;
+        // One-row tiles (half the loads in flight) are left two per CU.
+        const size_t lds_reserve = R == kQ21Rows ? kQ21LdsReserve : 0;
         auto go = [&](auto wallc, auto psic) {
             constexpr int WL = decltype(wallc)::value, PS = decltype(psic)::value;
             if (one)
-                hipLaunchKernelGGL((k_tile_q21<S, C, WL, PS, DIAG, 1>), grid, block, lds_reserve, st, d, src, dst, write_mom,
+                hipLaunchKernelGGL((k_tile_q21<S, C, WL, PS, DIAG, 1, R>), grid, block, lds_reserve, st, d, src, dst, write_mom,
                                    compare, update);
             else if constexpr (!DIAG)
-                hipLaunchKernelGGL((k_tile_q21<S, C, WL, PS, 0, 0>), grid, block, lds_reserve, st, d, src, dst, write_mom,
+                hipLaunchKernelGGL((k_tile_q21<S, C, WL, PS, 0, 0, R>), grid, block, lds_reserve, st, d, src, dst, write_mom,
                                    compare, update);
         };
         using RowW = std::integral_constant<int, WALL_ROW>;
@@ -475,7 +476,9 @@ hipError_t launch_tile_q21(int storage, const LatDevAny &La, int wall, int parit
 }  // namespace
 
 hipError_t launch_step_q21(int storage, const LatDevAny &L, int wall, int parity, int variant, hipStream_t st) {
-    if (variant == 0) return launch_tile_q21<0>(storage, L, wall, parity, 0, 0, 0, L.psi_kind, st);
+    if (variant == 0) return launch_tile_q21<0, kQ21Rows>(storage, L, wall, parity, 0, 0, 0, L.psi_kind, st);
+    if (variant == 2) return launch_tile_q21<0, 1>(storage, L, wall, parity, 0, 0, 0, L.psi_kind, st);
+    if (variant != 1) return hipErrorInvalidValue;
     if (!q21_march_ok(storage, L.omega)) return hipErrorInvalidValue;
     const LatDev<float> d = L.get<float>();
     const float *src = (const float *)(parity ? d.fb : d.fa);
@@ -500,7 +503,7 @@ hipError_t launch_step_q21(int storage, const LatDevAny &L, int wall, int parity
 
 hipError_t launch_diag_q21(int storage, const LatDevAny &L, int wall, int parity, int write_mom, int compare,
                            int update, hipStream_t st) {
-    return launch_tile_q21<1>(storage, L, wall, parity, write_mom, compare, update, L.psi_kind, st);
+    return launch_tile_q21<1, kQ21Rows>(storage, L, wall, parity, write_mom, compare, update, L.psi_kind, st);
 }
 
 }  // namespace lbmwet

@@ -144,25 +144,30 @@ hipError_t launch_walls_node(int f64, int lattice, uint32_t nx, uint32_t ny, con
 
 // D2Q21 step (Tab. I): workgroups of kQ21Waves waves over strips of
 // kQ21OutCols output columns (64 lanes with 3 halo columns on each side) and
-// kQ21Waves * kQ21Rows loaded rows (3 halo rows above and below).
+// kQ21Waves * rows_per_wave loaded rows (3 halo rows above and below);
+// kQ21Rows rows per wave unless stated.
 constexpr int kQ21Waves = 16;
 constexpr int kQ21Rows = 2;
 constexpr uint32_t kQ21OutCols = 58;
-constexpr uint32_t kQ21OutRows = kQ21Waves * kQ21Rows - 6;
 inline uint32_t q21_strips(uint32_t nx) { return (nx + kQ21OutCols - 1) / kQ21OutCols; }
-inline uint32_t q21_tiles(uint32_t nx, uint32_t ny) { return q21_strips(nx) * ((ny + kQ21OutRows - 1) / kQ21OutRows); }
-// D2Q21 step variants: 0 tiles (any storage), 1 marching workgroups of
-// kQ21MarchCols aligned columns over segments of kQ21MarchRows rows (binary32
-// storage only).
-constexpr int kQ21Variants = 2;
+inline uint32_t q21_tiles(uint32_t nx, uint32_t ny, int rows_per_wave = kQ21Rows) {
+    const uint32_t out_rows = uint32_t(kQ21Waves * rows_per_wave - 6);
+    return q21_strips(nx) * ((ny + out_rows - 1) / out_rows);
+}
+// D2Q21 step variants: 0 tiles of kQ21Rows rows per wave (any storage), 1
+// marching workgroups of kQ21MarchCols aligned columns over segments of
+// kQ21MarchRows rows (binary32 storage only), 2 tiles of one row per wave (any
+// storage; twice the workgroups of variant 0 on small lattices).
+constexpr int kQ21Variants = 3;
 constexpr uint32_t kQ21MarchCols = 256, kQ21MarchRows = 128;
+constexpr uint32_t kQ21FillBlocks = 256;   // one workgroup per CU of the chip
 inline bool q21_march_ok(int storage, double omega) { return storage == STORE_F32 && omega > 0.0; }
 inline uint32_t q21_march_blocks(uint32_t nx, uint32_t ny) {
     return ((nx + kQ21MarchCols - 1) / kQ21MarchCols) * ((ny + kQ21MarchRows - 1) / kQ21MarchRows);
 }
 hipError_t launch_step_q21(int storage, const LatDevAny &L, int wall, int parity, int variant, hipStream_t st);
-// The diagnostic pass of a D2Q21 lattice: one partial row per wave of the
-// same tiling (q21_tiles * kQ21Waves rows).
+// The diagnostic pass of a D2Q21 lattice: one row of 8 partials per workgroup
+// of the kQ21Rows tiling (q21_tiles rows).
 hipError_t launch_diag_q21(int storage, const LatDevAny &L, int wall, int parity, int write_mom, int compare,
                            int update, hipStream_t st);
 

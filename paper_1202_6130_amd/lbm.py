@@ -403,9 +403,9 @@ class Lattice:
 
     @property
     def tile_shape(self):
-        """D2Q9: index into lbm_tile_shapes(); D2Q21: step variant (0 tiles,
-        1 marching, binary32 only).  Every choice computes bitwise the same
-        update."""
+        """D2Q9: index into lbm_tile_shapes(); D2Q21: step variant (0 two-row
+        tiles, 1 marching, binary32 only, 2 one-row tiles).  Every choice
+        computes bitwise the same update."""
         return lbm_get_tile_shape(self.ctx)
 
     @tile_shape.setter

@@ -30,13 +30,16 @@ def test_step_dispatch_names():
         is None
     assert k("void lbmwet::(anonymous namespace)::k_march_q21<0, 1, 1>(lbmwet::LatDev<float>, float const*, "
              "float*, unsigned int)") == 1
-    assert k("void lbmwet::(anonymous namespace)::k_tile_q21<float, float, 0, 1, 0, 1>(lbmwet::LatDev<float>, "
+    assert k("void lbmwet::(anonymous namespace)::k_tile_q21<float, float, 0, 1, 0, 1, 2>(lbmwet::LatDev<float>, "
              "void const*, void*, int, int, int)") == 0
-    assert k("void lbmwet::(anonymous namespace)::k_tile_q21<float, float, 0, 1, 1, 1>(lbmwet::LatDev<float>, "
+    assert k("void lbmwet::(anonymous namespace)::k_tile_q21<float, float, 1, 1, 0, 0, 1>(lbmwet::LatDev<float>, "
+             "void const*, void*, int, int, int)") == 2             # one-row tiles
+    assert k("void lbmwet::(anonymous namespace)::k_tile_q21<float, float, 0, 1, 1, 1, 2>(lbmwet::LatDev<float>, "
              "void const*, void*, int, int, int)") is None          # the diagnostic pass
     assert k("void lbmwet::k_diag<float, float, 0>(...)") is None
     assert bench.traffic_key("spinodal4096", "f32", 8) == "spinodal4096:f32:shape8"
     assert bench.traffic_key("spinodal4096_q21", "f32", 1) == "spinodal4096_q21:f32:k_march_q21"
+    assert bench.traffic_key("drop1024_q21", "f32", 2) == "drop1024_q21:f32:k_tile_q21_r1"
 
 
 def _write_run(path, counter, copy_kib, steps):

@@ -157,8 +157,9 @@ def test_q21_laplace_against_oracle():
 @pytest.mark.parametrize("nx,ny,walls", [(300, 200, 1), (257, 131, 2), (64, 40, 1), (5, 3, 0), (1, 1, 0),
                                          (700, 300, 0), (513, 129, 2)])
 def test_q21_march_matches_tiles_bitwise(nx, ny, walls, psi_kind):
-    """The marching variant computes bitwise the tile variant's update
-    (binary32, tau = 1; ragged and tiny lattices, row and node walls)."""
+    """The marching and one-row tile variants compute bitwise the two-row tile
+    variant's update (binary32, tau = 1; ragged and tiny lattices, row and
+    node walls)."""
     G = -1.0 if psi_kind == lbm.PSI_EOS else -6.0
     kw = dict(nx=nx, ny=ny, storage=lbm.STORE_F32, lattice=lbm.D2Q21, psi_kind=psi_kind, G=G, G_R=0.4, G_A=0.2,
               eps=1.3, F_ext=(1e-5, 0.0))
@@ -175,8 +176,26 @@ def test_q21_march_matches_tiles_bitwise(nx, ny, walls, psi_kind):
     rng = np.random.Generator(np.random.PCG64(ny + 7))
     rho0 = rng.uniform(0.1, 1.0, (ny, nx)) if psi_kind == lbm.PSI_EOS else rng.uniform(0.3, 1.8, (ny, nx))
     out = []
-    for variant in (0, 1):
+    for variant in (0, 1, 2):
         L = lbm.Lattice(lbm.lbm_params_default(**kw), rho0, wall_fields=fields)
+        L.tile_shape = variant
+        L.step(7)
+        out.append(L.get_state())
+        L.close()
+    assert np.array_equal(out[0], out[1])
+    assert np.array_equal(out[0], out[2])
+
+
+@pytest.mark.parametrize("nx,ny", [(650, 150), (131, 37), (5, 3)])
+def test_q21_row_tiles_match_f64_bitwise(nx, ny):
+    """Binary64 storage at tau != 1: the one-row tiles give bitwise the
+    two-row tiles' update."""
+    kw = dict(nx=nx, ny=ny, storage=lbm.STORE_F64, lattice=lbm.D2Q21, psi_kind=lbm.PSI_EOS, G=-1.0, tau=0.8,
+              G_R=0.4, G_A=0.2, wall_kind=lbm.WALL_FLAT_SLAB if ny > 8 else lbm.WALL_NONE, F_ext=(1e-5, 0.0))
+    rho0 = np.random.Generator(np.random.PCG64(nx * ny)).uniform(0.1, 1.0, (ny, nx))
+    out = []
+    for variant in (0, 2):
+        L = lbm.Lattice(lbm.lbm_params_default(**kw), rho0)
         L.tile_shape = variant
         L.step(7)
         out.append(L.get_state())
@@ -191,13 +210,23 @@ def test_q21_variants_selection():
     L.close()
     p = lbm.lbm_params_default(nx=1024, ny=512, lattice=lbm.D2Q21, psi_kind=lbm.PSI_EOS, G=-1.0)
     L = lbm.Lattice(p, np.full((512, 1024), 0.5))
-    assert L.tile_shape == 0
+    assert L.tile_shape == 2          # 16 marching segments do not fill the chip
     L.tile_shape = 1
+    L.tile_shape = 0
+    with pytest.raises(lbm.LbmError):
+        L.tile_shape = 3
+    L.close()
+    p = lbm.lbm_params_default(nx=650, ny=150, lattice=lbm.D2Q21, psi_kind=lbm.PSI_EOS, G=-1.0)
+    L = lbm.Lattice(p, np.full((150, 650), 0.5))
+    assert L.tile_shape == 2
     L.close()
     p = lbm.lbm_params_default(nx=64, ny=64, lattice=lbm.D2Q21, psi_kind=lbm.PSI_EOS, G=-1.0, storage=lbm.STORE_F64)
     L = lbm.Lattice(p, np.full((64, 64), 0.5))
+    assert L.tile_shape == 2
     with pytest.raises(lbm.LbmError):
         L.tile_shape = 1
+    shape, ms = L.tune(2)
+    assert shape in (0, 2) and np.isinf(ms[1]) and np.isfinite(ms[0]) and np.isfinite(ms[2])
     L.close()
 
 
@@ -212,13 +241,14 @@ def test_q21_march_matches_tiles_bitwise_tau(nx, ny, coll):
     rng = np.random.Generator(np.random.PCG64(nx + ny))
     rho0 = rng.uniform(0.1, 1.0, (ny, nx))
     out = []
-    for variant in (0, 1):
+    for variant in (0, 1, 2):
         L = lbm.Lattice(lbm.lbm_params_default(**kw), rho0)
         L.tile_shape = variant
         L.step(7)
         out.append(L.get_state())
         L.close()
     assert np.array_equal(out[0], out[1])
+    assert np.array_equal(out[0], out[2])
 
 
 def test_q21_march_drop_against_oracle():
