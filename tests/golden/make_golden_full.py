@@ -5,6 +5,7 @@
     python tests/golden/make_golden_full.py spinodal --threads 6   # about an hour on 6 cores
     python tests/golden/make_golden_full.py laplace21 --threads 8  # under a minute
     python tests/golden/make_golden_full.py spinodal21 --threads 8 # about 15 minutes on 8 cores
+    python tests/golden/make_golden_full.py paper650 --threads 8   # under a minute
 
 drop: 1024x512 sessile drop of radius 160 on the lower face of a flat solid
 band of 8 rows (tanh wall functions of width 2, core range 1, tail range 3,
@@ -33,6 +34,14 @@ spinodal21: the same phase-separation recipe for the paper's fluid (D2Q21,
 EOS, G = -1, rho 1.0 / 0.1), rho and u at 1024 seeded nodes and the totals
 after 100 and 300 steps.
 
+paper650: the paper's own domain and model (Sec. III.B): 650x150, D2Q21 with
+the EOS pseudo-potential (G = -1), wall functions from the recursive filter of
+Appendix A with the top and bottom rows as solid outer boundary (psi_R =
+G^(5), phi = G^(22), psi_A = G^(22) - G^(5)), G_R = 1.33, G_A = 0.5, eps = 1,
+tau = 1, a drop of radius 50 at rho 1.0 / 0.1 on the lower wall.  rho and u at
+1024 seeded nodes, the totals and the contact angle of the rho = 0.55
+isoline after 200 and 2000 steps.
+
 Only the oracle computes these values; a change to its arithmetic regenerates
 them in a commit that names the passage of the paper justifying it.
 """
@@ -55,6 +64,7 @@ CHANNEL = dict(nx=32, ny=256, rho=2.0, force=1e-6, steps=600000, seed=0)
 SPINODAL = dict(n=4096, seed=0, checkpoints=(100, 500, 1000, 2000, 5000))
 LAPLACE21 = dict(n=96, radii=(12.0, 16.0, 24.0), steps=4000)
 SPINODAL21 = dict(n=4096, seed=0, checkpoints=(100, 300))
+PAPER650 = dict(nx=650, ny=150, radius=50.0, G_R=1.33, G_A=0.5, eps=1.0, iso=0.55, checkpoints=(200, 2000))
 
 
 def laplace_disc(p, w, rho, n):
@@ -188,6 +198,38 @@ def laplace21():
     print("wrote", out, "gamma", gamma, "intercept", b, flush=True)
 
 
+def paper650():
+    c = PAPER650
+    nx, ny = c["nx"], c["ny"]
+    H = np.zeros((ny, nx))
+    H[0, :] = 1.0
+    H[ny - 1, :] = 1.0
+    w = O.Walls.filtered(H, H, 21, 5, 22)
+    p = O.make_params(nx, ny, tau=1.0, G=-1.0, G_R=c["G_R"], G_A=c["G_A"], eps=c["eps"], lattice=21, psi_kind=1)
+    f = O.init(p, I.drop_field(nx, ny, c["radius"], rho_l=1.0, rho_g=0.1, slab_rows=1))
+    nodes = sample_nodes(nx, ny, 1024, 13)
+    ys = np.array([y for y, _ in nodes])
+    xs = np.array([x for _, x in nodes])
+    data = {"workload": "the paper's 650x150 domain: D2Q21, EOS pseudo-potential (G=-1), recursive-filter walls "
+                        "with the outer rows solid, G_R=1.33, G_A=0.5, eps=1, tau=1, drop of radius 50 at rho 1.0 / "
+                        "0.1, FP64 oracle",
+            "params": c, "nodes_y": ys.tolist(), "nodes_x": xs.tolist(), "checkpoints": []}
+    t = 0
+    for tc in c["checkpoints"]:
+        f = run_chunks(p, w, f, tc - t, 200, f"paper650 to {tc}")
+        t = tc
+        rho, ux, uy, tot = O.macros(p, w, f)
+        ang = O.contact_angle(p, w, f, c["iso"], 0.0)
+        data["checkpoints"].append({"t": tc, "totals": tot.tolist(),
+                                    "contact_angle": None if ang is None else ang.tolist(),
+                                    "rho": rho[ys, xs].tolist(), "ux": ux[ys, xs].tolist(),
+                                    "uy": uy[ys, xs].tolist()})
+    out = os.path.join(HERE, "paper650x150_fp64.json")
+    with open(out, "w") as fh:
+        json.dump(data, fh)
+    print("wrote", out, [cp["contact_angle"] for cp in data["checkpoints"]], flush=True)
+
+
 if __name__ == "__main__":
     args = sys.argv[1:]
     if "--threads" in args:
@@ -205,3 +247,5 @@ if __name__ == "__main__":
         laplace21()
     if "spinodal21" in which:
         spinodal(q21=True)
+    if "paper650" in which:
+        paper650()

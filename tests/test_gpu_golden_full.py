@@ -9,7 +9,10 @@ FP64 oracle wrote (tests/golden/make_golden_full.py):
     totals at t = 100 ... 5000;
   - the same for the paper's fluid (D2Q21, EOS pseudo-potential) at t = 100
     and 300, stepped by the marching variant the benchmark uses (binary32)
-    and the tile variant (FP64 storage).
+    and the one-row tiles (FP64 storage);
+  - the paper's own 650x150 domain (D2Q21, EOS, recursive-filter walls, drop
+    of radius 50): rho, u at 1024 seeded nodes, totals and contact angle at
+    t = 200 and 2000, one-row tiles in both storages.
 
 Bars: FP64 storage agrees to 1e-9 relative (summation order only).  FP32
 storage: fields within 1e-5 (rho relative to its maximum, |u| relative to
@@ -165,5 +168,48 @@ def test_spinodal21_4096_vs_oracle():
                 assert r_max < 1e-5 and u_max < 1e-5
             else:
                 assert r_rms < 1e-3 and mass < 1e-5
+    for L in runs.values():
+        L.close()
+
+
+def test_paper650_vs_oracle():
+    """The paper's own domain and model (650x150, D2Q21, EOS, recursive-filter
+    walls), stepped in the launch configuration a new context picks (one-row
+    tiles, binary32 and binary64) against the FP64 oracle: sampled fields,
+    totals and the contact angle after 200 and 2000 steps."""
+    g = _golden("paper650x150_fp64.json")
+    c = g["params"]
+    nx, ny = c["nx"], c["ny"]
+    ys, xs = np.array(g["nodes_y"]), np.array(g["nodes_x"])
+    H = np.zeros((ny, nx))
+    H[0, :] = 1.0
+    H[ny - 1, :] = 1.0
+    rho0 = I.drop_field(nx, ny, c["radius"], rho_l=1.0, rho_g=0.1, slab_rows=1)
+    cs = np.sqrt(2.0 / 3.0)
+    runs = {}
+    for name, st in (("f64", lbm.STORE_F64), ("f32", lbm.STORE_F32)):
+        p = lbm.lbm_params_default(nx=nx, ny=ny, storage=st, wall_kind=lbm.WALL_MASK, lattice=lbm.D2Q21,
+                                   psi_kind=lbm.PSI_EOS, G=-1.0, G_R=c["G_R"], G_A=c["G_A"], eps=c["eps"])
+        runs[name] = lbm.Lattice(p, rho0, wall_fields=np.stack([H, H]))
+        assert runs[name].tile_shape == 2
+    t0 = 0
+    for cp in g["checkpoints"]:
+        for L in runs.values():
+            L.step(cp["t"] - t0)
+        t0 = cp["t"]
+        want_r, want_x, want_y = (np.array(cp[k]) for k in ("rho", "ux", "uy"))
+        for name, L in runs.items():
+            rho, ux, uy, tot = L.moments()
+            r_max = np.abs(rho[ys, xs] - want_r).max() / np.abs(want_r).max()
+            u_max = np.hypot(ux[ys, xs] - want_x, uy[ys, xs] - want_y).max() / cs
+            mass = abs(tot[0] - cp["totals"][0]) / cp["totals"][0]
+            ang = L.contact_angle(c["iso"], 0.0)
+            d_ang = abs(ang[0] - cp["contact_angle"][0])
+            print(f"paper650 t={cp['t']} {name}: rho max rel {r_max:.2e}, u/c_s {u_max:.2e}, mass {mass:.2e}, "
+                  f"theta {ang[0]:.6f} (oracle {cp['contact_angle'][0]:.6f})")
+            if name == "f64":
+                assert r_max < 1e-9 and u_max < 1e-9 and mass < 1e-12 and d_ang < 1e-6
+            else:
+                assert r_max < 1e-5 and u_max < 1e-5 and mass < 1e-6 and d_ang < 1e-2
     for L in runs.values():
         L.close()
