@@ -8,6 +8,7 @@ import re
 import numpy as np
 import pytest
 
+from max_lattices import MAX_LATTICES, STORAGE_BYTES, buffer_bytes
 from paper_1202_6130_amd import lbm
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -81,6 +82,20 @@ def test_too_large_lattice_rejected():
     p = lbm.lbm_params_default(nx=65536, ny=65536)
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_workspace_bytes(p)
+    assert "too large" in str(e.value)
+
+
+@pytest.mark.parametrize("case", sorted(MAX_LATTICES))
+def test_largest_lattice_accepted_one_more_row_rejected(case):
+    q, st, nx, ny = MAX_LATTICES[case]
+    assert buffer_bytes(q, st, nx, ny) < 1 << 32 <= buffer_bytes(q, st, nx, ny + 1)
+    kw = dict(storage={"f32": lbm.STORE_F32, "f16dev": lbm.STORE_F16DEV, "f64": lbm.STORE_F64}[st],
+              lattice=lbm.D2Q21 if q == 21 else lbm.D2Q9)
+    if q == 21:
+        kw.update(psi_kind=lbm.PSI_EOS, G=-1.0)
+    assert lbm.lbm_workspace_bytes(lbm.lbm_params_default(nx=nx, ny=ny, **kw)) > 2 * q * nx * ny * STORAGE_BYTES[st]
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_workspace_bytes(lbm.lbm_params_default(nx=nx, ny=ny + 1, **kw))
     assert "too large" in str(e.value)
 
 
