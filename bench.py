@@ -295,6 +295,33 @@ def copy_reference():
     del src, dst
 
 
+def copy_ceiling(reps=20):
+    """HBM rate of lbm_device_copy (16-byte non-temporal loads and stores) on
+    COPY_REF_BYTES, read + write bytes over time, events on the launch stream:
+    the measured plain-copy ceiling next to the nominal peak."""
+    import torch
+    from paper_1202_6130_amd import lbm
+    src = torch.ones(COPY_REF_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        lbm.lbm_device_copy(src.data_ptr(), dst.data_ptr(), COPY_REF_BYTES, stream.cuda_stream)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        lbm.lbm_device_copy(src.data_ptr(), dst.data_ptr(), COPY_REF_BYTES, stream.cuda_stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    ok = bool(torch.equal(src, dst))
+    del src, dst
+    return {"value": round(2 * COPY_REF_BYTES / (ms * 1e-3) / 1e9, 1), "unit": "GB/s", "copied_exactly": ok,
+            "kind": "lbm_device_copy: 1 GiB device-to-device copy with 16-byte non-temporal loads and stores, "
+                    "read + write bytes"}
+
+
 def device_copy(reps=20):
     """HBM rate of a plain 1 GiB device-to-device copy with torch's copy kernel
     (read + write bytes over time), timed with events in this process: a
@@ -721,6 +748,8 @@ def main():
                                       f"{SAMPLE_EVERY}th, none with a diagnostic pass), on the launch stream",
                      "bytes_per_update": bpu},
     }
+    out["copy_ceiling"] = copy_ceiling()
+    out["copy_ceiling"]["step_fraction"] = round(achieved / out["copy_ceiling"]["value"], 4)
     out["device_copy"] = device_copy()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(q=q)

@@ -151,6 +151,16 @@ lbm_status lbm_params_default(lbm_params *p);
 /* Last error message of the calling thread ("" if none).  Never NULL. */
 const char *lbm_last_error(void);
 
+/* Measurement utility, no lattice involved: copies `bytes` from device
+ * memory src to device memory dst on `stream` (a hipStream_t, NULL for the
+ * default stream) with 16-byte non-temporal loads and stores, as fast as a
+ * plain copy runs on this GPU.  It is the bandwidth reference next to the
+ * step kernels' HBM roofline (each of them reads and writes every stored
+ * population once per step, as a copy does).  src, dst and bytes must be
+ * multiples of 16 and the ranges must not overlap (else LBM_EINVAL); the
+ * caller owns both buffers.  Asynchronous: returns after the launch. */
+lbm_status lbm_device_copy(const void *src, void *dst, size_t bytes, void *stream);
+
 /* Device bytes a context with these parameters needs (written to *bytes). */
 lbm_status lbm_workspace_bytes(const lbm_params *p, size_t *bytes);
 

@@ -2,7 +2,7 @@
 
     python -m paper_1202_6130_amd.build
 
-Compiles csrc/kernels.hip, csrc/kernels_q21.hip and csrc/abi.cpp with hipcc into
+Compiles csrc/kernels.hip, csrc/kernels_q21.hip, csrc/copy.hip and csrc/abi.cpp with hipcc into
 paper_1202_6130_amd/_lib/liblbmwet.so.  Packed FP32 instructions are disabled
 for device code (-packed-fp32-ops).
 """
@@ -27,7 +27,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 def build(verbose=False, extra=()):
     os.makedirs(LIBDIR, exist_ok=True)
     objs = []
-    for src in ("kernels.hip", "kernels_q21.hip", "abi.cpp"):
+    for src in ("kernels.hip", "kernels_q21.hip", "copy.hip", "abi.cpp"):
         obj = os.path.join(LIBDIR, src + ".o")
         cmd = [HIPCC, *FLAGS, *extra, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:

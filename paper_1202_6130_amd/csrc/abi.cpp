@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "lbm.h"
+#include "copy.hpp"
 #include "launch.hpp"
 
 using namespace lbmwet;
@@ -435,6 +436,16 @@ lbm_status lbm_params_default(lbm_params *p) {
 }
 
 const char *lbm_last_error(void) { return g_err.c_str(); }
+
+lbm_status lbm_device_copy(const void *src, void *dst, size_t bytes, void *stream) {
+    if (!src || !dst) return fail(LBM_EINVAL, "NULL pointer");
+    if (uintptr_t(src) % 16 || uintptr_t(dst) % 16 || bytes % 16)
+        return fail(LBM_EINVAL, "src, dst and bytes must be multiples of 16");
+    const uintptr_t s = uintptr_t(src), d = uintptr_t(dst);
+    if (bytes && s < d + bytes && d < s + bytes) return fail(LBM_EINVAL, "src and dst overlap");
+    HIPCHK(launch_copy16(src, dst, bytes, (hipStream_t)stream));
+    return LBM_OK;
+}
 
 lbm_status lbm_workspace_bytes(const lbm_params *p, size_t *bytes) {
     TRY(validate(p));

@@ -71,6 +71,7 @@ def lib():
         "lbm_params_default": ([P], ctypes.c_int),
         "lbm_last_error": ([], ctypes.c_char_p),
         "lbm_workspace_bytes": ([P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "lbm_device_copy": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
         "lbm_create": ([P, _dp, _dp, _dp, _dp, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
         "lbm_step": ([_vp, i64], ctypes.c_int),
         "lbm_diagnostics": ([_vp, _dp], ctypes.c_int),
@@ -148,6 +149,12 @@ def lbm_params_default(**kw):
 def nq(p):
     """Populations per node of the parameters' velocity set."""
     return 21 if p.lattice == D2Q21 else 9
+
+
+def lbm_device_copy(src_ptr, dst_ptr, nbytes, stream_ptr):
+    """Plain 16-byte non-temporal device copy (the bandwidth reference);
+    device pointers and the stream as integers."""
+    _check(lib().lbm_device_copy(_vp(src_ptr), _vp(dst_ptr), ctypes.c_size_t(nbytes), _vp(stream_ptr)))
 
 
 def lbm_workspace_bytes(p):

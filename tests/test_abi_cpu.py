@@ -152,3 +152,15 @@ def test_mask_wall_parameters_validated():
         bad = lbm.lbm_params_default(nx=16, ny=16, wall_kind=lbm.WALL_MASK, filter_core=core, filter_wall=wall)
         with pytest.raises(lbm.LbmError):
             lbm.lbm_workspace_bytes(bad)
+
+
+@pytest.mark.parametrize("src,dst,nbytes,msg", [
+    (0, 4096, 16, "NULL"), (4096, 0, 16, "NULL"), (4100, 8192, 16, "multiples of 16"),
+    (4096, 8200, 16, "multiples of 16"), (4096, 8192, 24, "multiples of 16"), (4096, 4112, 32, "overlap"),
+    (4112, 4096, 32, "overlap"),
+])
+def test_device_copy_rejects_bad_arguments(src, dst, nbytes, msg):
+    # validated on the host before any launch: the addresses are never touched
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_device_copy(src, dst, nbytes, 0)
+    assert e.value.code == lbm.LBM_EINVAL and msg in str(e.value)
