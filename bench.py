@@ -1,12 +1,15 @@
 """Benchmark of the fused lattice-Boltzmann step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps 500] [--warmup 50] [--workload spinodal4096]
+    python bench.py [--gpus 1] [--steps 500] [--warmup 300] [--workload spinodal4096]
 
 A "step" is one time step of the whole update (pull-stream, moments,
 pseudo-potential forces, wall forces, EDM-BGK collision, store) on the
 workload lattice, with the diagnostic pass (FP64 totals, residual, non-finite
 check) every 100 steps inside the timed region.  Inputs are resident in HBM
-before timing starts.  Prints one JSON line.
+before timing starts.  On D2Q9 lattices with F32 or F16DEV storage the
+warm-up autotunes the tile shape and then the choice between one step per
+launch and two steps per launch (temporal blocking: the populations between
+the two steps stay in LDS; bitwise the same fields).  Prints one JSON line.
 """
 import argparse
 import json
@@ -56,8 +59,22 @@ def q21_label(variant):
 
 
 def traffic_key(workload, storage, shape):
-    """shape: the D2Q9 tile shape, or the D2Q21 step variant."""
+    """shape: the D2Q9 tile shape, "pass2v<V>" for two steps per pass with
+    variant V, or the D2Q21 step variant."""
+    if isinstance(shape, str):
+        return f"{workload}:{storage}:{shape}"
     return f"{workload}:{storage}:" + (f"shape{shape}" if workload_q(workload) == 9 else q21_label(shape))
+
+
+# (strips, output rows, waves per strip) of the two-steps-per-pass variants, as
+# in lbm_two_step_variants (strips, rows, waves per workgroup)
+PASS2_GEOMETRY = [(1, 8, 4), (1, 16, 4), (2, 8, 4), (1, 16, 8), (1, 32, 8)]
+
+
+def pass2_desc(v):
+    ts, oh, wps = PASS2_GEOMETRY[v]
+    return (f"two steps per pass, variant {v}: {64 * ts} x {oh} output nodes per workgroup "
+            f"({ts * wps} waves), populations between the steps in LDS")
 
 
 def stored_traffic(path, key):
@@ -89,6 +106,9 @@ def _step_dispatch_key(name):
     other kernel (the diagnostic variant of k_tile_q21 included)."""
     if "k_step_tiles<" in name and "k_step_tiles_batch" not in name:
         return int(name.split("k_step_tiles<")[1].split(">")[0].split(",")[-1])
+    if "k_step_pass2<" in name:
+        args = [a.strip() for a in name.split("k_step_pass2<")[1].split(">")[0].split(",")]
+        return f"pass2v{PASS2_GEOMETRY.index((int(args[-3]), int(args[-2]), int(args[-1])))}"
     if "k_march_q21<" in name:
         return 1
     if "k_tile_q21<" in name:
@@ -141,8 +161,9 @@ def ingest_counters(fetch_dir, write_dir, workload, storage, out_json):
             "bytes_per_launch": round(rd + wr), "read_bytes": round(rd), "write_bytes": round(wr),
             "fetch_kib": round(f, 2), "write_kib": round(w, 2), "fetch_scale": round(fs, 5),
             "write_scale": round(ws, 5), "kernel_sources_sha256": kernel_sources_digest(q)}
-        print(f"| {k if q == 9 else q21_label(k)} | {len(fb[k])} | {f:,.0f} | {rd:,.0f} | {rd / alg:.3f} | {w:,.0f} | {wr / alg:.3f} | "
-              f"{(rd + wr) / (2 * alg):.3f} |")
+        a = alg * (2 if isinstance(k, str) else 1)    # two updates per launch
+        print(f"| {k if q == 9 else q21_label(k)} | {len(fb[k])} | {f:,.0f} | {rd:,.0f} | {rd / a:.3f} | {w:,.0f} | {wr / a:.3f} | "
+              f"{(rd + wr) / (2 * a):.3f} |")
     with open(out_json, "w") as fh:
         json.dump(data, fh, indent=1)
 
@@ -217,31 +238,15 @@ def make_lattice(name, storage, seg_rows, tau=1.0, collision=0):
     return lbm.Lattice(p, rho0), p
 
 
-def time_gpu(name, storage, steps, warmup, seg_rows, tile=None, tau=1.0, collision=0):
-    """tile None: the autotuner picks the D2Q9 tile shape during the
-    warm-up (its steps count as warm-up), and a D2Q21 lattice keeps the step
-    variant a new context starts with; else the given shape or variant."""
+def _timed(L, steps, upl):
+    """Times `steps` steps in blocks of SAMPLE_EVERY: the first launch of a
+    block (unless a diagnostic pass follows its first step) between a pair of
+    events on the launch stream, the rest in one lbm_step call, so that host
+    work per step never starves the GPU on small lattices.  upl: time steps
+    per launch (2 with two steps per pass).  Returns (total ms, per-launch ms
+    of the sampled launches)."""
     import torch
-    L, p = make_lattice(name, storage, seg_rows, tau, collision)
-    nodes = p.nx * p.ny
-    tune_ms = None
-    if tile is not None:
-        L.tile_shape = tile
-    elif workload_q(name) == 21:
-        pass                      # the context's default step variant
-    else:
-        from paper_1202_6130_amd import lbm
-        # 3 * tune_steps + 1 trial steps per shape, within the warm-up when it is long enough
-        tune_steps = max(2, (warmup // len(lbm.lbm_tile_shapes()) - 1) // 3)
-        shape, tune_ms = L.tune(tune_steps)
-        tune_ms = [round(float(v), 5) for v in tune_ms]
-    L.step(max(0, warmup - L.step_index))
-    torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    # The timed steps run in blocks of SAMPLE_EVERY: the first step of a block
-    # (unless it runs the diagnostic pass) between a pair of events on the
-    # launch stream, the rest in one lbm_step call, so that host work per step
-    # never starves the GPU on small lattices.
     pool = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             for _ in range((steps + SAMPLE_EVERY - 1) // SAMPLE_EVERY)]
     ev = []
@@ -253,30 +258,74 @@ def time_gpu(name, storage, steps, warmup, seg_rows, tile=None, tau=1.0, collisi
     s = 0
     while s < steps:
         n = min(SAMPLE_EVERY, steps - s)
-        if (start_idx + s + 1) % DIAG_EVERY != 0:
+        if (start_idx + s + 1) % DIAG_EVERY != 0 and n >= upl:
             a, b = pool[len(ev)]
             a.record(stream)
-            L.step(1)
+            L.step(upl)
             b.record(stream)
             ev.append((a, b))
-            if n > 1:
-                L.step(n - 1)
+            if n > upl:
+                L.step(n - upl)
         else:
             L.step(n)
         s += n
     t1.record(stream)
     torch.cuda.synchronize()
-    total_ms = t0.elapsed_time(t1)
-    kern_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    return t0.elapsed_time(t1), np.array([a.elapsed_time(b) for a, b in ev])
+
+
+def time_gpu(name, storage, steps, warmup, seg_rows, tile=None, tau=1.0, collision=0, two_step=None):
+    """tile None: the autotuner picks the D2Q9 tile shape during the
+    warm-up (its steps count as warm-up), and a D2Q21 lattice keeps the step
+    variant a new context starts with; else the given shape or variant.
+    two_step None: for D2Q9 with F32 or F16DEV storage, a second autotuner
+    chooses between single steps and two steps per pass; -1: single steps;
+    V >= 0: that two-step variant.  With two steps per pass, the same number
+    of single steps is timed afterwards as well (the "single" entry)."""
+    import torch
+    from paper_1202_6130_amd import lbm
+    L, p = make_lattice(name, storage, seg_rows, tau, collision)
+    nodes = p.nx * p.ny
+    q = workload_q(name)
+    tune_ms = two_ms = None
+    pass2_ok = q == 9 and storage in ("f32", "f16dev")
+    budget = warmup // 2 if (two_step is None and pass2_ok) else warmup
+    if tile is not None:
+        L.tile_shape = tile
+    elif q == 21:
+        pass                      # the context's default step variant
+    else:
+        # 3 * tune_steps + 1 trial steps per shape, within the warm-up when it is long enough
+        tune_steps = max(2, (budget // len(lbm.lbm_tile_shapes()) - 1) // 3)
+        shape, tune_ms = L.tune(tune_steps)
+        tune_ms = [round(float(v), 5) for v in tune_ms]
+    if pass2_ok and two_step is None:
+        # 6 * steps + 2 trial steps per candidate (the variants and single steps)
+        cand = len(lbm.lbm_two_step_variants()) + 1
+        steps2 = max(1, ((warmup - budget) // cand - 2) // 6)
+        _, two_ms = L.tune_two_step(steps2)
+        two_ms = [round(float(v), 5) for v in two_ms]
+    elif two_step is not None and two_step >= 0:
+        L.two_step = two_step
+    variant = L.two_step if q == 9 else -1
+    upl = 2 if variant >= 0 else 1
+    L.step(max(0, warmup - L.step_index))
+    total_ms, kern_ms = _timed(L, steps, upl)
+    single = None
+    if upl == 2:
+        L.two_step = -1
+        s_total, s_kern = _timed(L, steps, 1)
+        single = {"ms_total": s_total, "kernel_ms_mean": float(s_kern.mean()), "kernel_samples": len(s_kern)}
     d = L.diagnostics()
     shape = L.tile_shape
     L.close()
     return {
         "nodes": nodes, "ms_total": total_ms, "ms_per_step": total_ms / steps,
         "kernel_ms_mean": float(kern_ms.mean()), "kernel_ms_median": float(np.median(kern_ms)),
-        "kernel_samples": len(ev),
+        "kernel_samples": len(kern_ms),
         "mass": float(d[1]), "nonfinite": float(d[5]), "seg_rows": p.seg_rows, "tile_shape": shape,
-        "tune_ms": tune_ms,
+        "tune_ms": tune_ms, "two_step_ms": two_ms, "updates_per_launch": upl, "two_step": variant,
+        "single": single,
     }
 
 
@@ -670,13 +719,16 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--workload", default="spinodal4096",
                     choices=sorted(WORKLOADS) + ["ensemble256", "serve", "precision4096", "wetting1024",
                                                  "paper650x150"])
     ap.add_argument("--tile", type=int, default=None,
                     help="D2Q9 tile shape index (default: autotuned in the warm-up), or D2Q21 step variant "
                          "(default: the one a new context starts with)")
+    ap.add_argument("--two-step", type=int, default=None,
+                    help="D2Q9 F32/F16DEV: two time steps per launch with this variant (lbm_two_step_variants), "
+                         "-1 for single steps (default: autotuned in the warm-up)")
     ap.add_argument("--seq-steps", type=int, default=500, help="ensemble: steps per lattice of the sequential leg")
     ap.add_argument("--requests", type=int, default=60, help="serve: number of requests")
     ap.add_argument("--max-steps", type=int, default=20000, help="serve: step cap per request")
@@ -720,7 +772,8 @@ def main():
         print(json.dumps(wetting()), flush=True)
         return
     coll = 1 if args.collision == "projected" else 0
-    r = time_gpu(args.workload, args.storage, args.steps, args.warmup, args.seg_rows, args.tile, args.tau, coll)
+    r = time_gpu(args.workload, args.storage, args.steps, args.warmup, args.seg_rows, args.tile, args.tau, coll,
+                 args.two_step)
     if args.copy_ref:
         copy_reference()
     mlups = r["nodes"] * args.steps / (r["ms_total"] * 1e-3) / 1e6
@@ -728,8 +781,16 @@ def main():
     if q == 21 and args.storage == "f16dev":
         sys.exit("D2Q21 runs with f32 or f64 storage")
     bpu = bytes_per_update(args.storage, q)
-    achieved = bpu * r["nodes"] / (r["kernel_ms_mean"] * 1e-3) / 1e9
-    traffic = stored_traffic(args.traffic_json, traffic_key(args.workload, args.storage, r["tile_shape"]))
+    upl = r["updates_per_launch"]
+    achieved = bpu * upl * r["nodes"] / (r["kernel_ms_mean"] * 1e-3) / 1e9
+    key = f"pass2v{r['two_step']}" if upl == 2 else r["tile_shape"]
+    traffic = stored_traffic(args.traffic_json, traffic_key(args.workload, args.storage, key))
+    if upl == 2:
+        kernel, tile = "k_step_pass2", pass2_desc(r["two_step"])
+    elif q == 9:
+        kernel, tile = "k_step_tiles", tile_desc(r["tile_shape"])
+    else:
+        kernel, tile = q21_kernel(r["tile_shape"]), Q21_TILE[r["tile_shape"]]
     out = {
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 4), "higher_is_better": True,
@@ -737,17 +798,30 @@ def main():
         "config": {"workload": WORKLOADS[args.workload][2], "nx": WORKLOADS[args.workload][0],
                    "ny": WORKLOADS[args.workload][1], "storage": args.storage,
                    "lattice": f"D2Q{q}", "tau": args.tau, "collision": args.collision,
-                   "tile": tile_desc(r["tile_shape"]) if q == 9 else Q21_TILE[r["tile_shape"]],
-                   "tile_tuned": args.tile is None and q == 9,
-                   "tune_ms_per_shape": r["tune_ms"], "diag_every": DIAG_EVERY},
+                   "tile": tile, "tile_tuned": args.tile is None and q == 9,
+                   "tune_ms_per_shape": r["tune_ms"], "two_step_tuned": args.two_step is None and q == 9,
+                   "tune_ms_per_two_step_variant_then_single": r["two_step_ms"], "diag_every": DIAG_EVERY},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": bpu * r["nodes"],
-                     "kernel": "k_step_tiles" if q == 9 else q21_kernel(r["tile_shape"]), "kernel_ms_mean": round(r["kernel_ms_mean"], 5),
+                     "traffic_unit": "bytes per launch", "algorithmic_bytes_per_launch": bpu * upl * r["nodes"],
+                     "updates_per_launch": upl,
+                     "kernel": kernel, "kernel_ms_mean": round(r["kernel_ms_mean"], 5),
                      "kernel_timing": f"HIP events around {r['kernel_samples']} of the timed launches (every "
                                       f"{SAMPLE_EVERY}th, none with a diagnostic pass), on the launch stream",
                      "bytes_per_update": bpu},
     }
+    if traffic is not None:
+        # bytes that actually crossed to memory per second (counters), beside the algorithmic rate
+        out["roofline"]["hbm_gbs_from_traffic"] = round(traffic / (r["kernel_ms_mean"] * 1e-3) / 1e9, 1)
+    if r["single"] is not None:
+        sg = r["single"]
+        s_ach = bpu * r["nodes"] / (sg["kernel_ms_mean"] * 1e-3) / 1e9
+        out["single_step"] = {
+            "value": round(r["nodes"] * args.steps / (sg["ms_total"] * 1e-3) / 1e6, 1), "unit": "MLUPS",
+            "kernel": "k_step_tiles", "tile": tile_desc(r["tile_shape"]), "kernel_ms_mean": round(sg["kernel_ms_mean"], 5),
+            "achieved": round(s_ach, 1), "frac": round(s_ach / HBM_PEAK_GBS, 4),
+            "traffic": stored_traffic(args.traffic_json, traffic_key(args.workload, args.storage, r["tile_shape"])),
+            "note": "the same lattice stepped one step per launch right after the timed region, same step count"}
     out["copy_ceiling"] = copy_ceiling()
     out["copy_ceiling"]["step_fraction"] = round(achieved / out["copy_ceiling"]["value"], 4)
     out["device_copy"] = device_copy()

@@ -280,6 +280,25 @@ int32_t lbm_tile_shapes(int32_t *waves, int32_t *rows, int32_t *strips, int32_t 
 lbm_status lbm_set_tile_shape(lbm_ctx *c, int32_t shape);
 int32_t lbm_get_tile_shape(const lbm_ctx *c);
 
+/* Two time steps per pass (temporal blocking; Sec. II.A streaming and the
+ * collision of eq. BE-BGK applied twice).  With a variant v >= 0 set,
+ * lbm_step advances D2Q9 lattices with F32 or F16DEV storage two steps per
+ * kernel launch: each workgroup reads a block of 64 * strips[v] columns x
+ * rows[v] rows plus a halo of four nodes, computes the first step on the
+ * block grown by two nodes with the populations kept in on-chip memory, and
+ * writes the second step of the block.  The result equals two single steps
+ * bit for bit (tile shapes do not matter); only the traffic to memory is
+ * halved.  A single step is taken where one step is left, or where a
+ * diagnostic pass (diag_interval) falls after the first step of a pair.
+ * lbm_two_step_variants writes up to cap (strips, rows, waves per
+ * workgroup) triples (any array may be NULL) and returns the number of
+ * variants.  lbm_set_two_step(c, -1) returns to single steps (the default);
+ * another lattice or storage gives LBM_EINVAL, a batch lattice LBM_ESTATE.
+ * lbm_get_two_step returns the variant, -1 when off, -2 for NULL. */
+int32_t lbm_two_step_variants(int32_t *strips, int32_t *rows, int32_t *waves, int32_t cap);
+lbm_status lbm_set_two_step(lbm_ctx *c, int32_t variant);
+int32_t lbm_get_two_step(const lbm_ctx *c);
+
 /* Autotuner for one lattice: for every shape runs one untimed step, then
  * three timed blocks of `steps` consecutive ordinary time steps (events
  * around each block), and keeps the shape of smallest median per-step time.
@@ -290,6 +309,17 @@ int32_t lbm_get_tile_shape(const lbm_ctx *c);
  * step variants above (ms_out gets INFINITY for variant 1 where it does not
  * apply).  Synchronises. */
 lbm_status lbm_tune(lbm_ctx *c, int32_t steps, int32_t *shape_out, double *ms_out);
+
+/* Autotuner between single steps (with the context's tile shape, so call
+ * lbm_tune first) and the two-steps-per-pass variants: for every candidate
+ * runs one untimed pair of steps, then three timed blocks of `steps` pairs,
+ * and keeps the candidate of smallest median time per step (the variant, or
+ * -1 for single steps; variant_out, nullable).  ms_out (nullable) gets
+ * lbm_two_step_variants(...) + 1 entries: per-step medians of the variants,
+ * then of single steps; INFINITY for variants that do not apply to the
+ * lattice (then only single steps are timed).  The lattice advances by
+ * 6 * steps + 2 steps per timed candidate.  Synchronises. */
+lbm_status lbm_tune_two_step(lbm_ctx *c, int32_t steps, int32_t *variant_out, double *ms_out);
 
 /* ------------------------------------------------------------------------
  * Batched ensembles: many independent lattices (each with its own size and

@@ -215,6 +215,7 @@ struct lbm_ctx {
     int *cur;                      // which buffer holds the state (0: fa, 1: fb)
     int64_t *step;
     int shape;                     // step tile shape (index into kShapeWaves/kShapeRows)
+    int pass2;                     // two-steps-per-pass variant, -1: single steps
     bool view;                     // lives inside a batch (lbm_step/lbm_set_state refused)
     bool attached;                 // an lbm_ctx of the caller grouped by lbm_batch_attach
     // diagnostics bookkeeping
@@ -287,6 +288,7 @@ lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const d
     c->cur = &c->own_cur;
     c->step = &c->own_step;
     c->shape = 0;
+    c->pass2 = -1;
     c->view = false;
     c->attached = false;
     c->have_prev = false;
@@ -483,13 +485,18 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
     if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
     const int ks = kernel_storage(c->p.storage);
     const int K = c->p.diag_interval;
-    for (int64_t s = 0; s < nsteps; ++s) {
+    for (int64_t s = 0; s < nsteps;) {
+        // two steps in one pass unless a diagnostic falls after the first
+        const bool pair = c->pass2 >= 0 && nsteps - s >= 2 && !(K > 0 && (*c->step + 1) % K == 0);
         if (c->p.lattice == LBM_D2Q21)
             TRY(launch_ok(launch_step_q21(ks, c->L, c->wall_mode, *c->cur, c->shape, c->stream), "step_q21"));
+        else if (pair)
+            TRY(launch_ok(launch_step_pass2(ks, c->L, c->wall_mode, c->pass2, *c->cur, c->stream), "step_pass2"));
         else
             TRY(launch_ok(launch_step(ks, c->L, c->wall_mode, c->shape, *c->cur, c->stream), "step"));
         *c->cur ^= 1;
-        ++*c->step;
+        *c->step += pair ? 2 : 1;
+        s += pair ? 2 : 1;
         if (K > 0 && *c->step % K == 0) {
             TRY(run_diag(c, 0, c->have_prev ? 1 : 0, 1, 0));
             c->last_diag_compared = c->have_prev;
@@ -1173,6 +1180,27 @@ lbm_status lbm_set_tile_shape(lbm_ctx *c, int32_t shape) {
 
 int32_t lbm_get_tile_shape(const lbm_ctx *c) { return c ? c->shape : -1; }
 
+int32_t lbm_two_step_variants(int32_t *strips, int32_t *rows, int32_t *waves, int32_t cap) {
+    for (int v = 0; v < kPass2Variants && v < cap; ++v) {
+        if (strips) strips[v] = kPass2Strips[v];
+        if (rows) rows[v] = kPass2Rows[v];
+        if (waves) waves[v] = kPass2Strips[v] * kPass2WavesPerStrip[v];
+    }
+    return kPass2Variants;
+}
+
+lbm_status lbm_set_two_step(lbm_ctx *c, int32_t variant) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (c->view) return fail(LBM_ESTATE, "lattice belongs to a batch");
+    if (variant < -1 || variant >= kPass2Variants) return fail(LBM_EINVAL, "two-step variant %d out of range", variant);
+    if (variant >= 0 && (c->p.lattice != LBM_D2Q9 || !pass2_ok(kernel_storage(c->p.storage))))
+        return fail(LBM_EINVAL, "two steps per pass need a D2Q9 lattice with F32 or F16DEV storage");
+    c->pass2 = variant;
+    return LBM_OK;
+}
+
+int32_t lbm_get_two_step(const lbm_ctx *c) { return c ? c->pass2 : -2; }
+
 }  // extern "C"
 
 namespace {
@@ -1239,6 +1267,36 @@ lbm_status lbm_tune(lbm_ctx *c, int32_t steps, int32_t *shape_out, double *ms_ou
     }
     c->shape = best;
     if (shape_out) *shape_out = best;
+    return LBM_OK;
+}
+
+lbm_status lbm_tune_two_step(lbm_ctx *c, int32_t steps, int32_t *variant_out, double *ms_out) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (c->view) return fail(LBM_ESTATE, "lattice belongs to a batch");
+    if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
+    const bool ok = c->p.lattice == LBM_D2Q9 && pass2_ok(kernel_storage(c->p.storage));
+    int best = -1;
+    double best_ms = INFINITY;
+    // candidate -1 (single steps with the context's tile shape), then every variant
+    for (int v = -1; v < kPass2Variants; ++v) {
+        double *slot = ms_out ? (v < 0 ? ms_out + kPass2Variants : ms_out + v) : nullptr;
+        if (v >= 0 && !ok) {
+            if (slot) *slot = INFINITY;
+            continue;
+        }
+        c->pass2 = v;
+        TRY(lbm_step(c, 2));                      // first pass of this candidate: not timed
+        double ms = 0;
+        TRY(time_steps(c->stream, steps, [&]() { return lbm_step(c, 2); }, &ms));
+        ms *= 0.5;                                // per time step
+        if (slot) *slot = ms;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    c->pass2 = best;
+    if (variant_out) *variant_out = best;
     return LBM_OK;
 }
 

@@ -375,6 +375,169 @@ __global__ __launch_bounds__(kShapeWaves[SHAPE] * kWave) void k_step_tiles_batch
     tile_step<S, C, WALL, TW, TR, TS>(L, parity ? L.fb : L.fa, parity ? L.fa : L.fb, wk.y, wk.z, sm);
 }
 
+// ---------------------------------------------------------------- two steps per pass
+// Temporal blocking: one workgroup advances an output block of OW = 64 TS
+// columns x OH rows by two time steps with one read and one write of the
+// populations.  The first step is computed on the block grown by two nodes on
+// every side (region R2), which needs the pseudo-potential on the block grown
+// by three (R1) and populations pulled from one node further out; its
+// populations stay in LDS.  The second step pulls from LDS, forms the
+// pseudo-potential on the block grown by one (R3), and writes the block with
+// the aligned row stores of k_step_tiles.  Every node of either step goes
+// through the device functions of the single step (density, psi, the
+// neighbour sums grouped by column, wall terms, node_forces, collide, the
+// storage round trip), so a pass equals two single steps bit for bit.
+template <int TS, int OH, int WPS> struct Pass2Geo {
+    static constexpr int OW = TS * kStripCols;
+    static constexpr int NT = TS * WPS * kWave;                    // threads
+    static constexpr int W1 = OW + 6, H1 = OH + 6, N1 = W1 * H1;   // psi, step one
+    static constexpr int W2 = OW + 4, H2 = OH + 4, N2 = W2 * H2;   // populations after step one
+    static constexpr int W3 = OW + 2, H3 = OH + 2, N3 = W3 * H3;   // psi, step two
+    static constexpr int K1 = (N1 + NT - 1) / NT, K2 = (N2 + NT - 1) / NT, K3 = (N3 + NT - 1) / NT;
+    static_assert(OH % WPS == 0, "output rows must split evenly over the waves of a strip");
+};
+
+template <class S, class C, int WALL, int TS, int OH, int WPS>
+__global__ __launch_bounds__(TS * WPS * kWave) void k_step_pass2(LatDev<C> L, const void *__restrict__ src,
+                                                                         void *__restrict__ dst) {
+    using G = Pass2Geo<TS, OH, WPS>;
+    using Raw = typename Codec<S>::Raw;
+    constexpr int NT = G::NT, W1 = G::W1, W2 = G::W2, W3 = G::W3, N2 = G::N2;
+    extern __shared__ __align__(16) unsigned char pass2_lds[];
+    C *sf = reinterpret_cast<C *>(pass2_lds);   // [Q][N2] populations of step one
+    C *sp = sf + Q * N2;                         // [N1] psi of step one, then [N3] psi of step two
+    const uint32_t nx = L.nx, ny = L.ny, P = L.pstride;
+    const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const uint32_t groups = (nx + uint32_t(G::OW) - 1) / uint32_t(G::OW);
+    const uint32_t trow = lb / groups, group = lb - trow * groups;
+    const uint32_t X0 = group * uint32_t(G::OW), Y0 = trow * uint32_t(OH);
+    // multiples of nx and ny of at least 3, so that X0 - 3 + c never goes negative
+    const uint32_t kx = nx >= 3 ? nx : (nx == 2 ? 4u : 3u), ky = ny >= 3 ? ny : (ny == 2 ? 4u : 3u);
+    const int tid = int(threadIdx.x);
+    const C rref = L.rho_ref;
+
+    // R1: pulled populations, density and psi of step one; populations of R2 to LDS
+    {
+        PopBuf<S> in;
+        in.init(src, 9u * P * uint32_t(sizeof(S)));
+        Raw raw[G::K1][Q];
+#pragma unroll
+        for (int k = 0; k < G::K1; ++k) {
+            const int i = tid + k * NT;
+            if ((k + 1) * NT <= G::N1 || i < G::N1) {
+                const int r = i / W1, c = i - r * W1;
+                const uint32_t x = wrap_fast(X0 + kx - 3u + uint32_t(c), nx);
+                const uint32_t y = wrap_fast(Y0 + ky - 3u + uint32_t(r), ny);
+                const uint32_t xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
+                const uint32_t r0 = y * nx, rm = wrap_dec(y, ny) * nx, rp = wrap_inc(y, ny) * nx;
+                raw[k][0] = in.load(r0 + x, 0);
+                raw[k][1] = in.load(r0 + xm, P);
+                raw[k][2] = in.load(rm + x, 2 * P);
+                raw[k][3] = in.load(r0 + xp, 3 * P);
+                raw[k][4] = in.load(rp + x, 4 * P);
+                raw[k][5] = in.load(rm + xm, 5 * P);
+                raw[k][6] = in.load(rm + xp, 6 * P);
+                raw[k][7] = in.load(rp + xp, 7 * P);
+                raw[k][8] = in.load(rp + xm, 8 * P);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < G::K1; ++k) {
+            const int i = tid + k * NT;
+            if ((k + 1) * NT <= G::N1 || i < G::N1) {
+                C f[Q];
+                decode_row<S, C>(raw[k], f, rref);
+                sp[i] = psi_of<C>(density<C>(f));
+                const int r = i / W1, c = i - r * W1;
+                if (r >= 1 && r < G::H1 - 1 && c >= 1 && c < W1 - 1) {
+                    const int j = (r - 1) * W2 + (c - 1);
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) sf[q * N2 + j] = f[q];
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    const C w1 = C(1.0 / 9.0), w2 = C(1.0 / 36.0);
+    // R2: forces and collision of step one, in place in LDS (each node reads only its own populations)
+#pragma unroll
+    for (int k = 0; k < G::K2; ++k) {
+        const int i = tid + k * NT;
+        if (!((k + 1) * NT <= N2 || i < N2)) continue;
+        const int r2 = i / W2, c2 = i - r2 * W2;
+        const C *p = sp + (r2 + 1) * W1 + (c2 + 1);
+        const C pm = p[-W1], pp = p[W1];
+        const C lm = p[-W1 - 1], lc = p[-1], lp = p[W1 - 1];
+        const C rm = p[-W1 + 1], rc = p[1], rp = p[W1 + 1];
+        // sum_i w_i psi(x + c_i) c_i, grouped by column as in tile_step
+        const C al = w1 * lc + w2 * (lp + lm), ar = w1 * rc + w2 * (rp + rm);
+        const C b = pp - pm, bl = lp - lm, br = rp - rm;
+        const C sx = ar - al;
+        const C sy = w1 * b + w2 * (br + bl);
+        C f[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) f[q] = sf[q * N2 + i];
+        const C rho = density<C>(f);
+        const uint32_t x = wrap_fast(X0 + kx - 2u + uint32_t(c2), nx);
+        const uint32_t y = wrap_fast(Y0 + ky - 2u + uint32_t(r2), ny);
+        const RowWall<C> rw = row_wall<C, WALL>(L, y);
+        C phie, Sx, Sy;
+        wall_terms<C, WALL>(L, rw, y * nx + x, phie, Sx, Sy);
+        NodeState<C> s = node_forces<C>(f, rho, p[0], sx, sy, phie, Sx, Sy, L.G, L.Ux, L.Uy, L.Fx, L.Fy);
+        collide<C>(f, s, L.omega, L.collision);
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            sf[q * N2 + i] = Codec<S>::template decode<C>(Codec<S>::template encode<C>(f[q], q, rref), q, rref);
+    }
+    __syncthreads();
+
+    // R3: pulled populations, density and psi of step two
+#pragma unroll
+    for (int k = 0; k < G::K3; ++k) {
+        const int i = tid + k * NT;
+        if (!((k + 1) * NT <= G::N3 || i < G::N3)) continue;
+        const int r3 = i / W3, c3 = i - r3 * W3;
+        const int j = (r3 + 1) * W2 + (c3 + 1);
+        C f[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) f[q] = sf[q * N2 + j - kCy[q] * W2 - kCx[q]];
+        sp[i] = psi_of<C>(density<C>(f));
+    }
+    __syncthreads();
+
+    // output block: lane = column, WPS waves per 64-column strip, OH / WPS rows each
+    const int lane = tid & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int sj = w / WPS, wr = w - sj * WPS;
+    const int c4 = sj * kStripCols + lane;
+    const uint32_t gx = X0 + uint32_t(c4);
+    const bool active = gx < nx;
+    const uint32_t x = wrap_fast(gx, nx);
+    StepAct<S, C, WALL> act;
+    act.dst.init(dst, 9u * P * uint32_t(sizeof(S)));
+#pragma unroll
+    for (int jr = 0; jr < OH / WPS; ++jr) {
+        const int r4 = wr * (OH / WPS) + jr;
+        const uint32_t y = Y0 + uint32_t(r4);
+        if (y >= ny) break;
+        const int j = (r4 + 2) * W2 + (c4 + 2);
+        C f[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) f[q] = sf[q * N2 + j - kCy[q] * W2 - kCx[q]];
+        const C rho = density<C>(f);
+        const C *p = sp + (r4 + 1) * W3 + (c4 + 1);
+        const C pm = p[-W3], pp = p[W3];
+        const C lm = p[-W3 - 1], lc = p[-1], lp = p[W3 - 1];
+        const C rm = p[-W3 + 1], rc = p[1], rp = p[W3 + 1];
+        const C al = w1 * lc + w2 * (lp + lm), ar = w1 * rc + w2 * (rp + rm);
+        const C b = pp - pm, bl = lp - lm, br = rp - rm;
+        const C sx = ar - al;
+        const C sy = w1 * b + w2 * (br + bl);
+        act.row(L, row_wall<C, WALL>(L, y), y, x, active, f, rho, p[0], sx, sy);
+    }
+}
+
 template <class S, class C, int WALL>
 __global__ __launch_bounds__(kBlockThreads) void k_diag(const LatDev<C> *__restrict__ lats, const uint4 *__restrict__ work,
                                               uint32_t nwork, LatDev<C> single, int parity, int write_mom,
@@ -834,6 +997,46 @@ hipError_t launch_step(int storage, const LatDevAny &L, int wall, int shape, int
             return hipGetLastError();
         });
     });
+}
+
+template <int V> struct Pass2Var {
+    static constexpr int TS = kPass2Strips[V], OH = kPass2Rows[V], WPS = kPass2WavesPerStrip[V];
+    using G = Pass2Geo<TS, OH, WPS>;
+};
+
+hipError_t launch_step_pass2(int storage, const LatDevAny &L, int wall, int variant, int parity, hipStream_t st) {
+    if (!pass2_ok(storage) || L.lattice != 9) return hipErrorInvalidValue;
+    auto go = [&](auto s, auto vc) -> hipError_t {
+        using S = decltype(s);
+        constexpr int V = decltype(vc)::value;
+        using PV = Pass2Var<V>;
+        using G = typename PV::G;
+        LatDev<float> d = L.get<float>();
+        const void *src = parity ? d.fb : d.fa;
+        void *dst = parity ? d.fa : d.fb;
+        const uint32_t nb = ((d.nx + G::OW - 1) / G::OW) * ((d.ny + PV::OH - 1) / PV::OH);
+        const size_t lds = sizeof(float) * (size_t(Q) * G::N2 + G::N1);
+        if (wall == WALL_ROW)
+            hipLaunchKernelGGL((k_step_pass2<S, float, WALL_ROW, PV::TS, PV::OH, PV::WPS>), dim3(nb), dim3(G::NT), lds,
+                               st, d, src, dst);
+        else
+            hipLaunchKernelGGL((k_step_pass2<S, float, WALL_NODE, PV::TS, PV::OH, PV::WPS>), dim3(nb), dim3(G::NT),
+                               lds, st, d, src, dst);
+        return hipGetLastError();
+    };
+    auto with_var = [&](auto s) -> hipError_t {
+        switch (variant) {
+        case 0: return go(s, std::integral_constant<int, 0>{});
+        case 1: return go(s, std::integral_constant<int, 1>{});
+        case 2: return go(s, std::integral_constant<int, 2>{});
+        case 3: return go(s, std::integral_constant<int, 3>{});
+        case 4: return go(s, std::integral_constant<int, 4>{});
+        default: return hipErrorInvalidValue;
+        }
+    };
+    static_assert(kPass2Variants == 5, "launch_step_pass2 lists every variant");
+    if (storage == STORE_F32) return with_var(float{});
+    return with_var(__half{});
 }
 
 hipError_t launch_step_batch(const void *lats, const uint4 *twork, uint32_t ntiles, int shape, int parity,

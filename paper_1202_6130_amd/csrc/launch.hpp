@@ -118,6 +118,16 @@ constexpr uint32_t tile_rows(uint32_t ny, int s) { return (ny + shape_out_rows(s
 
 uint32_t step_tiles(uint32_t nx, uint32_t ny, int shape);
 hipError_t launch_step(int storage, const LatDevAny &L, int wall, int shape, int parity, hipStream_t st);
+// Two time steps per pass (k_step_pass2, D2Q9, F32 and F16 storage): variant
+// v updates blocks of 64 * kPass2Strips[v] columns x kPass2Rows[v] rows, one
+// workgroup of kPass2Strips[v] * kPass2WavesPerStrip[v] waves each, with the
+// populations between the two steps in LDS.  Bitwise two single steps.
+constexpr int kPass2Variants = 5;
+constexpr int kPass2Strips[kPass2Variants] = {1, 1, 2, 1, 1};
+constexpr int kPass2Rows[kPass2Variants] = {8, 16, 8, 16, 32};
+constexpr int kPass2WavesPerStrip[kPass2Variants] = {4, 4, 4, 8, 8};
+inline bool pass2_ok(int storage) { return storage == STORE_F32 || storage == STORE_F16; }
+hipError_t launch_step_pass2(int storage, const LatDevAny &L, int wall, int variant, int parity, hipStream_t st);
 hipError_t launch_step_batch(const void *lats, const uint4 *twork, uint32_t ntiles, int shape, int parity,
                              hipStream_t st);
 hipError_t launch_diag(int storage, const void *lats, const uint4 *work, uint32_t nwork, const LatDevAny &single,

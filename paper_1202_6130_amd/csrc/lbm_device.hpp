@@ -104,7 +104,12 @@ template <> struct Codec<__half> {
     using Raw = uint16_t;
     __device__ static inline float w(int q) { return q == 0 ? 4.0f / 9.0f : (q < 5 ? 1.0f / 9.0f : 1.0f / 36.0f); }
     __device__ static inline float winv(int q) { return q == 0 ? 2.25f : (q < 5 ? 9.0f : 36.0f); }
+    // The decoded population is a rounded product: contracted into the sums
+    // that consume it (density, momentum), it would round differently where
+    // it is consumed from registers than where it went through memory, and
+    // the kernels' updates would depend on their data paths.
     template <class C> __device__ static inline C decode(Raw r, int q, C rho_ref) {
+#pragma clang fp contract(off)
         return C(w(q) * (float(rho_ref) + __half2float(__builtin_bit_cast(__half, r))));
     }
     template <class C> __device__ static inline Raw encode(C v, int q, C rho_ref) {

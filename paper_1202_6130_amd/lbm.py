@@ -97,6 +97,10 @@ def lib():
         "lbm_tile_shapes": ([_ip, _ip, _ip, ctypes.c_int32], ctypes.c_int32),
         "lbm_set_tile_shape": ([_vp, ctypes.c_int32], ctypes.c_int),
         "lbm_get_tile_shape": ([_vp], ctypes.c_int32),
+        "lbm_two_step_variants": ([_ip, _ip, _ip, ctypes.c_int32], ctypes.c_int32),
+        "lbm_set_two_step": ([_vp, ctypes.c_int32], ctypes.c_int),
+        "lbm_get_two_step": ([_vp], ctypes.c_int32),
+        "lbm_tune_two_step": ([_vp, ctypes.c_int32, _ip, _dp], ctypes.c_int),
         "lbm_tune": ([_vp, ctypes.c_int32, _ip, _dp], ctypes.c_int),
         "lbm_batch_set_tile_shapes": ([_vp, _ip], ctypes.c_int),
         "lbm_batch_get_tile_shapes": ([_vp, _ip], ctypes.c_int),
@@ -314,6 +318,33 @@ def lbm_get_tile_shape(ctx):
     return int(lib().lbm_get_tile_shape(ctx))
 
 
+def lbm_two_step_variants():
+    """[(strips, rows, waves), ...] of the two-steps-per-pass variants."""
+    n = lib().lbm_two_step_variants(None, None, None, 0)
+    s = np.zeros(n, dtype=np.int32)
+    r = np.zeros(n, dtype=np.int32)
+    w = np.zeros(n, dtype=np.int32)
+    lib().lbm_two_step_variants(_iptr(s), _iptr(r), _iptr(w), n)
+    return [(int(a), int(b), int(c)) for a, b, c in zip(s, r, w)]
+
+
+def lbm_set_two_step(ctx, variant):
+    _check(lib().lbm_set_two_step(ctx, int(variant)))
+
+
+def lbm_get_two_step(ctx):
+    return int(lib().lbm_get_two_step(ctx))
+
+
+def lbm_tune_two_step(ctx, steps):
+    """Returns (chosen variant or -1 for single steps, median ms per step of
+    every variant followed by that of single steps)."""
+    v = np.zeros(1, dtype=np.int32)
+    ms = np.zeros(len(lbm_two_step_variants()) + 1)
+    _check(lib().lbm_tune_two_step(ctx, int(steps), _iptr(v), _ptr(ms)))
+    return int(v[0]), ms
+
+
 def lbm_tune(ctx, steps):
     """Returns (chosen shape, median ms per step of every shape)."""
     shape = np.zeros(1, dtype=np.int32)
@@ -419,9 +450,24 @@ class Lattice:
     def tile_shape(self, shape):
         lbm_set_tile_shape(self.ctx, shape)
 
+    @property
+    def two_step(self):
+        """Two-steps-per-pass variant (index into lbm_two_step_variants()),
+        -1 for single steps.  Bitwise the same fields either way."""
+        return lbm_get_two_step(self.ctx)
+
+    @two_step.setter
+    def two_step(self, variant):
+        lbm_set_two_step(self.ctx, variant)
+
     def tune(self, steps=10):
         """Autotune the tile shape (advances the lattice; see lbm_tune)."""
         return lbm_tune(self.ctx, steps)
+
+    def tune_two_step(self, steps=10):
+        """Choose between single steps and two steps per pass (advances the
+        lattice; see lbm_tune_two_step)."""
+        return lbm_tune_two_step(self.ctx, steps)
 
     def close(self):
         if self.ctx:
