@@ -149,7 +149,7 @@ def ingest_counters(fetch_dir, write_dir, workload, storage, out_json):
         with open(out_json) as fh:
             data = json.load(fh)
     print(f"FETCH_SIZE copy {fc:,.1f} KiB (scale {fs:.4f}), WRITE_SIZE copy {wc:,.1f} KiB (scale {ws:.4f}); "
-          f"algorithmic {alg:,} B each way per launch\n")
+          f"algorithmic {alg:,} B each way per launch of one time step (twice that for a two-step pass)\n")
     print("| Kernel / shape | dispatches | FETCH_SIZE KiB | read bytes (scaled) | read / algorithmic | "
           "WRITE_SIZE KiB | write / algorithmic | total / algorithmic |")
     print("|---|---|---|---|---|---|---|---|")
