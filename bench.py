@@ -68,7 +68,8 @@ def traffic_key(workload, storage, shape):
 
 # (strips, output rows, waves per strip) of the two-steps-per-pass variants, as
 # in lbm_two_step_variants (strips, rows, waves per workgroup)
-PASS2_GEOMETRY = [(1, 8, 4), (1, 16, 4), (2, 8, 4), (1, 16, 8), (1, 32, 8)]
+PASS2_GEOMETRY = [(1, 8, 4), (1, 8, 8), (2, 8, 4), (1, 12, 6), (1, 12, 12), (1, 16, 8), (1, 16, 16), (1, 24, 8),
+                  (1, 24, 12)]
 
 
 def pass2_desc(v):

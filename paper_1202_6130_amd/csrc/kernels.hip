@@ -406,6 +406,7 @@ __global__ __launch_bounds__(TS * WPS * kWave) void k_step_pass2(LatDev<C> L, co
     extern __shared__ __align__(16) unsigned char pass2_lds[];
     C *sf = reinterpret_cast<C *>(pass2_lds);   // [Q][N2] populations of step one
     C *sp = sf + Q * N2;                         // [N1] psi of step one, then [N3] psi of step two
+    C *sw = sp + G::N1;                          // [H2][2] row wall terms of step one (WALL_ROW)
     const uint32_t nx = L.nx, ny = L.ny, P = L.pstride;
     const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const uint32_t groups = (nx + uint32_t(G::OW) - 1) / uint32_t(G::OW);
@@ -415,6 +416,21 @@ __global__ __launch_bounds__(TS * WPS * kWave) void k_step_pass2(LatDev<C> L, co
     const uint32_t kx = nx >= 3 ? nx : (nx == 2 ? 4u : 3u), ky = ny >= 3 ? ny : (ny == 2 ? 4u : 3u);
     const int tid = int(threadIdx.x);
     const C rref = L.rho_ref;
+    // On lattices at least one grown block wide and high every coordinate
+    // formed below is < 3 nx (3 ny): two conditional subtractions wrap it.
+    const bool big = nx >= uint32_t(W1) && ny >= uint32_t(G::H1);
+    auto wrap = [big](uint32_t v, uint32_t n) {
+        if (big) {
+            v = v >= n ? v - n : v;
+            return v >= n ? v - n : v;
+        }
+        return wrap_fast(v, n);
+    };
+    if (WALL == WALL_ROW && tid < G::H2) {
+        const RowWall<C> rw = row_wall<C, WALL>(L, wrap(Y0 + ky - 2u + uint32_t(tid), ny));
+        sw[2 * tid] = rw.phie;
+        sw[2 * tid + 1] = rw.Sy;
+    }
 
     // R1: pulled populations, density and psi of step one; populations of R2 to LDS
     {
@@ -426,8 +442,8 @@ __global__ __launch_bounds__(TS * WPS * kWave) void k_step_pass2(LatDev<C> L, co
             const int i = tid + k * NT;
             if ((k + 1) * NT <= G::N1 || i < G::N1) {
                 const int r = i / W1, c = i - r * W1;
-                const uint32_t x = wrap_fast(X0 + kx - 3u + uint32_t(c), nx);
-                const uint32_t y = wrap_fast(Y0 + ky - 3u + uint32_t(r), ny);
+                const uint32_t x = wrap(X0 + kx - 3u + uint32_t(c), nx);
+                const uint32_t y = wrap(Y0 + ky - 3u + uint32_t(r), ny);
                 const uint32_t xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
                 const uint32_t r0 = y * nx, rm = wrap_dec(y, ny) * nx, rp = wrap_inc(y, ny) * nx;
                 raw[k][0] = in.load(r0 + x, 0);
@@ -479,11 +495,16 @@ __global__ __launch_bounds__(TS * WPS * kWave) void k_step_pass2(LatDev<C> L, co
 #pragma unroll
         for (int q = 0; q < Q; ++q) f[q] = sf[q * N2 + i];
         const C rho = density<C>(f);
-        const uint32_t x = wrap_fast(X0 + kx - 2u + uint32_t(c2), nx);
-        const uint32_t y = wrap_fast(Y0 + ky - 2u + uint32_t(r2), ny);
-        const RowWall<C> rw = row_wall<C, WALL>(L, y);
         C phie, Sx, Sy;
-        wall_terms<C, WALL>(L, rw, y * nx + x, phie, Sx, Sy);
+        if (WALL == WALL_ROW) {
+            phie = sw[2 * r2];
+            Sx = C(0);
+            Sy = sw[2 * r2 + 1];
+        } else {
+            const uint32_t x = wrap(X0 + kx - 2u + uint32_t(c2), nx);
+            const uint32_t y = wrap(Y0 + ky - 2u + uint32_t(r2), ny);
+            wall_terms<C, WALL>(L, RowWall<C>{C(0), C(0)}, y * nx + x, phie, Sx, Sy);
+        }
         NodeState<C> s = node_forces<C>(f, rho, p[0], sx, sy, phie, Sx, Sy, L.G, L.Ux, L.Uy, L.Fx, L.Fy);
         collide<C>(f, s, L.omega, L.collision);
 #pragma unroll
@@ -1015,7 +1036,7 @@ hipError_t launch_step_pass2(int storage, const LatDevAny &L, int wall, int vari
         const void *src = parity ? d.fb : d.fa;
         void *dst = parity ? d.fa : d.fb;
         const uint32_t nb = ((d.nx + G::OW - 1) / G::OW) * ((d.ny + PV::OH - 1) / PV::OH);
-        const size_t lds = sizeof(float) * (size_t(Q) * G::N2 + G::N1);
+        const size_t lds = sizeof(float) * (size_t(Q) * G::N2 + G::N1 + 2 * G::H2);
         if (wall == WALL_ROW)
             hipLaunchKernelGGL((k_step_pass2<S, float, WALL_ROW, PV::TS, PV::OH, PV::WPS>), dim3(nb), dim3(G::NT), lds,
                                st, d, src, dst);
@@ -1031,10 +1052,14 @@ hipError_t launch_step_pass2(int storage, const LatDevAny &L, int wall, int vari
         case 2: return go(s, std::integral_constant<int, 2>{});
         case 3: return go(s, std::integral_constant<int, 3>{});
         case 4: return go(s, std::integral_constant<int, 4>{});
+        case 5: return go(s, std::integral_constant<int, 5>{});
+        case 6: return go(s, std::integral_constant<int, 6>{});
+        case 7: return go(s, std::integral_constant<int, 7>{});
+        case 8: return go(s, std::integral_constant<int, 8>{});
         default: return hipErrorInvalidValue;
         }
     };
-    static_assert(kPass2Variants == 5, "launch_step_pass2 lists every variant");
+    static_assert(kPass2Variants == 9, "launch_step_pass2 lists every variant");
     if (storage == STORE_F32) return with_var(float{});
     return with_var(__half{});
 }

@@ -122,10 +122,10 @@ hipError_t launch_step(int storage, const LatDevAny &L, int wall, int shape, int
 // v updates blocks of 64 * kPass2Strips[v] columns x kPass2Rows[v] rows, one
 // workgroup of kPass2Strips[v] * kPass2WavesPerStrip[v] waves each, with the
 // populations between the two steps in LDS.  Bitwise two single steps.
-constexpr int kPass2Variants = 5;
-constexpr int kPass2Strips[kPass2Variants] = {1, 1, 2, 1, 1};
-constexpr int kPass2Rows[kPass2Variants] = {8, 16, 8, 16, 32};
-constexpr int kPass2WavesPerStrip[kPass2Variants] = {4, 4, 4, 8, 8};
+constexpr int kPass2Variants = 9;
+constexpr int kPass2Strips[kPass2Variants] = {1, 1, 2, 1, 1, 1, 1, 1, 1};
+constexpr int kPass2Rows[kPass2Variants] = {8, 8, 8, 12, 12, 16, 16, 24, 24};
+constexpr int kPass2WavesPerStrip[kPass2Variants] = {4, 8, 4, 6, 12, 8, 16, 8, 12};
 inline bool pass2_ok(int storage) { return storage == STORE_F32 || storage == STORE_F16; }
 hipError_t launch_step_pass2(int storage, const LatDevAny &L, int wall, int variant, int parity, hipStream_t st);
 hipError_t launch_step_batch(const void *lats, const uint4 *twork, uint32_t ntiles, int shape, int parity,

@@ -10,7 +10,8 @@ from paper_1202_6130_amd import inputs as I
 from paper_1202_6130_amd import lbm
 
 pytestmark = pytest.mark.gpu
-VARIANTS = [(1, 8, 4), (1, 16, 4), (2, 8, 8), (1, 16, 8), (1, 32, 8)]
+VARIANTS = [(1, 8, 4), (1, 8, 8), (2, 8, 8), (1, 12, 6), (1, 12, 12), (1, 16, 8), (1, 16, 16), (1, 24, 8),
+            (1, 24, 12)]
 
 
 def _fields(nx, ny, seed):
@@ -68,7 +69,7 @@ def test_diagnostic_schedule_kept():
     nx, ny = 256, 96
     rho0 = I.drop_field(nx, ny, 30.0)
     ref_s, ref_d = _run(nx, ny, lbm.STORE_F32, lbm.WALL_FLAT_SLAB, -1, 71, rho0, diag_interval=7)
-    for v in (1, 4):
+    for v in (1, 7):
         s, d = _run(nx, ny, lbm.STORE_F32, lbm.WALL_FLAT_SLAB, v, 71, rho0, diag_interval=7)
         assert np.array_equal(s, ref_s)
         assert np.array_equal(d, ref_d)
