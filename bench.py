@@ -428,7 +428,7 @@ def cpu_baseline(seconds_hint=15.0, q=9):
                       f"{steps} steps in {dt:.1f} s"}
 
 
-def ensemble(steps, seq_steps, seed=0, count=256, chunk=100, tune_steps=5):
+def ensemble(steps, seq_steps, seed=0, count=256, chunk=100, tune_steps=5, two_step=None):
     """Batched ensemble of `count` sessile drops of uneven size and wall
     parameters: one launch per time step over all lattices, replayed from a
     HIP graph, against the same lattices stepped one after another alone."""
@@ -443,6 +443,11 @@ def ensemble(steps, seq_steps, seed=0, count=256, chunk=100, tune_steps=5):
     B = lbm.Batch(ps, rhos)
     stream = B._stream_obj
     shapes, tune_ms = B.tune(tune_steps)
+    two_ms = None
+    if two_step is None:
+        variant, two_ms = B.tune_two_step(2)
+    else:
+        B.two_step = variant = two_step
     B.step(chunk, chunk=chunk)
     torch.cuda.synchronize()
     a = torch.cuda.Event(enable_timing=True); b = torch.cuda.Event(enable_timing=True)
@@ -458,7 +463,8 @@ def ensemble(steps, seq_steps, seed=0, count=256, chunk=100, tune_steps=5):
     seq_ms = 0.0
     for p, rho, shape in zip(ps, rhos, shapes):
         L = lbm.Lattice(p, rho)
-        L.tile_shape = int(shape)      # same tile shape as in the batch: the speedup is batching alone
+        L.tile_shape = int(shape)      # same tile shape and step variant as in the batch:
+        L.two_step = variant           # the speedup is batching alone
         L.step(2)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -473,10 +479,16 @@ def ensemble(steps, seq_steps, seed=0, count=256, chunk=100, tune_steps=5):
         "data": "synthetic",
         "config": {"workload": f"{count} sessile drops, nx in 128..1024, ny in 64..512 (multiples of 32), "
                                "radius 0.3*min(nx,ny), G~U[-5.5,-4.5], G_R~U[0,1], G_A~U[0,0.6], "
-                               f"{steps} steps each, one launch per step over all lattices, graph chunks of {chunk}",
-                   "lattices": count, "nodes": nodes},
+                               f"{steps} steps each, one launch per step (or per two steps) over all lattices, "
+                               f"graph chunks of {chunk}",
+                   "lattices": count, "nodes": nodes,
+                   "two_step": variant if variant < 0 else pass2_desc(variant),
+                   "two_step_tuner_ms_per_step_variants_then_single":
+                       None if two_ms is None else [round(float(v), 4) for v in two_ms]},
         "mlups": round(nodes * steps / (ms_batch * 1e-3) / 1e6, 1),
         "hbm_frac": round(72 * nodes * steps / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "hbm_frac_note": "algorithmic bytes (72 B per update) over the whole batched run; with two steps "
+                         "per launch about half of them cross to HBM",
         "batched_s": round(ms_batch * 1e-3, 3),
         "sequential": {"solves_per_s": round(count / (seq_ms_full * 1e-3), 2), "s": round(seq_ms_full * 1e-3, 2),
                        "measured_steps_per_lattice": seq_steps, "extrapolated_to": steps},
@@ -619,6 +631,7 @@ def serving(count, max_steps, seed=0, rate=20.0, max_nodes=16 << 20):
         srv = serve.Server(max_steps=max_steps, **kw)
         res = srv.run(reqs, realtime=True)
         out[name] = serve.summarize(res, srv.elapsed)
+        out[name]["two_step"] = srv.two_step
     c, q = out["continuous"], out["sequential"]
     return {
         "metric": "served solves/s and p50/p99 latency (contact angle + slip queries)",
@@ -758,7 +771,7 @@ def main():
         sys.exit(2)
 
     if args.workload == "ensemble256":
-        print(json.dumps(ensemble(args.steps, args.seq_steps)), flush=True)
+        print(json.dumps(ensemble(args.steps, args.seq_steps, two_step=args.two_step)), flush=True)
         return
     if args.workload == "serve":
         print(json.dumps(serving(args.requests, args.max_steps, max_nodes=args.serve_max_nodes)), flush=True)

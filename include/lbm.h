@@ -391,6 +391,22 @@ lbm_status lbm_batch_get_tile_shapes(const lbm_batch *b, int32_t *shapes);
  * not timed).  The tuning steps are ordinary time steps.  Synchronises. */
 lbm_status lbm_batch_tune(lbm_batch *b, int32_t steps, int32_t *shapes_out, double *ms_out);
 
+/* Two time steps per launch for a whole batch (the single-lattice
+ * lbm_set_two_step, applied to every lattice of the batch with one variant):
+ * lbm_batch_step then advances every lattice two steps per launch (per graph
+ * replay, chunk / 2 launches), single steps only for an odd remainder.
+ * Bitwise the same fields as single steps.  -1 returns to single steps.
+ * lbm_batch_get_two_step returns the variant, -1 when off, -2 for NULL.
+ * lbm_batch_tune_two_step times single steps (with the batch's tile shapes)
+ * and every variant on the whole batch (one untimed pair, then three timed
+ * blocks of `steps` pairs each), keeps the fastest (variant_out, nullable)
+ * and writes lbm_two_step_variants(...) + 1 per-step medians to ms_out
+ * (nullable): the variants, then single steps.  Every lattice advances by
+ * 6 * steps + 2 steps per candidate.  Synchronises. */
+lbm_status lbm_batch_set_two_step(lbm_batch *b, int32_t variant);
+int32_t lbm_batch_get_two_step(const lbm_batch *b);
+lbm_status lbm_batch_tune_two_step(lbm_batch *b, int32_t steps, int32_t *variant_out, double *ms_out);
+
 /* Frees the host-side batch (waits for its stream).  A batch from
  * lbm_batch_create frees its contexts; an attached batch hands its contexts
  * back with their state, step index and tile shape.  NULL is accepted. */

@@ -103,8 +103,12 @@ Layout make_layout(const lbm_params &p) {
     L.strips = (uint32_t(p.nx) + kStripColsHost - 1) / kStripColsHost;
     L.segs = (uint32_t(p.ny) + L.seg_rows - 1) / L.seg_rows;
     L.waves = L.strips * L.segs;
-    L.tiles = 0;                       // largest tile count over the shapes
-    for (int s = 0; s < kNumTileShapes; ++s) L.tiles = std::max(L.tiles, step_tiles(uint32_t(p.nx), uint32_t(p.ny), s));
+    // batch work-list capacity: the largest tile count over the shapes plus
+    // the largest block count over the two-step variants (both lists are kept)
+    uint32_t t1 = 0, t2 = 0;
+    for (int s = 0; s < kNumTileShapes; ++s) t1 = std::max(t1, step_tiles(uint32_t(p.nx), uint32_t(p.ny), s));
+    for (int v = 0; v < kPass2Variants; ++v) t2 = std::max(t2, pass2_blocks(uint32_t(p.nx), uint32_t(p.ny), v));
+    L.tiles = t1 + t2;
     L.iso_blocks = isoline_blocks(uint32_t(N));
     size_t o = 0;
     L.pstride = plane_stride(p);
@@ -240,6 +244,8 @@ struct lbm_batch {
     uint32_t ntiles;               // capacity of d_twork (largest tile count of every lattice)
     std::vector<int> shapes;       // tile shape of each lattice
     uint32_t toff[kNumTileShapes + 1];   // d_twork[toff[s], toff[s+1]): tiles of shape s
+    int pass2;                     // two-steps-per-pass variant, -1: single steps
+    uint32_t poff, pcnt;           // d_twork[poff, poff + pcnt): blocks of that variant
     std::vector<uint4> h_twork;    // host image of d_twork (kept until the next upload)
     double *d_part;
     uint32_t *d_ranges;
@@ -873,6 +879,8 @@ static lbm_batch *new_batch(char *ws, const TablesLayout &T, uint32_t nwork, uin
     b->nwork = nwork;
     b->ntiles = ntiles;
     for (int s = 0; s <= kNumTileShapes; ++s) b->toff[s] = 0;
+    b->pass2 = -1;
+    b->poff = b->pcnt = 0;
     b->d_lats = ws + T.lats;
     b->d_work = (uint4 *)(ws + T.work);
     b->d_twork = (uint4 *)(ws + T.twork);
@@ -908,6 +916,18 @@ static lbm_status upload_twork(lbm_batch *b) {
         }
     }
     b->toff[kNumTileShapes] = uint32_t(tw.size());
+    b->poff = uint32_t(tw.size());
+    if (b->pass2 >= 0) {
+        const int v = b->pass2;
+        for (int32_t k = 0; k < n; ++k) {
+            const lbm_ctx *c = b->lat[k];
+            const uint32_t bands = (uint32_t(c->p.ny) + uint32_t(kPass2Rows[v]) - 1) / uint32_t(kPass2Rows[v]);
+            const uint32_t groups = pass2_blocks(uint32_t(c->p.nx), uint32_t(c->p.ny), v) / bands;
+            for (uint32_t tr = 0; tr < bands; ++tr)
+                for (uint32_t gp = 0; gp < groups; ++gp) tw.push_back(make_uint4(uint32_t(k), gp, tr, 0));
+        }
+    }
+    b->pcnt = uint32_t(tw.size()) - b->poff;
     if (tw.size() > b->ntiles) return fail(LBM_EINVAL, "internal: tile list exceeds its capacity");
     HIPCHK(hipMemcpyAsync(b->d_twork, tw.data(), tw.size() * sizeof(uint4), hipMemcpyHostToDevice, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
@@ -1075,7 +1095,19 @@ static void batch_advance(lbm_batch *b, int64_t n) {
     for (lbm_ctx *c : b->lat) *c->step += n;
 }
 
+// Two time steps of every lattice of the batch: one launch of the batch's
+// two-step variant.
+static hipError_t batch_launch_pass2(lbm_batch *b, int parity) {
+    return launch_step_pass2_batch(b->d_lats, b->d_twork + b->poff, b->pcnt, b->pass2, parity, b->stream);
+}
+
 static lbm_status batch_plain(lbm_batch *b, int64_t n) {
+    while (b->pass2 >= 0 && n >= 2) {
+        TRY(launch_ok(batch_launch_pass2(b, b->cur), "step_pass2_batch"));
+        b->cur ^= 1;
+        batch_advance(b, 2);
+        n -= 2;
+    }
     for (int64_t s = 0; s < n; ++s) {
         TRY(launch_ok(batch_launch(b, b->cur), "step_batch"));
         b->cur ^= 1;
@@ -1099,8 +1131,11 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps, int32_t chunk) {
             hipGraph_t g;
             HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
             hipError_t e = hipSuccess;
-            for (int s = 0; s < chunk && e == hipSuccess; ++s)
-                e = batch_launch(b, par ^ (s & 1));
+            if (b->pass2 >= 0) {
+                for (int s = 0; s < chunk / 2 && e == hipSuccess; ++s) e = batch_launch_pass2(b, par ^ (s & 1));
+            } else {
+                for (int s = 0; s < chunk && e == hipSuccess; ++s) e = batch_launch(b, par ^ (s & 1));
+            }
             hipError_t e2 = hipStreamEndCapture(b->stream, &g);
             if (e != hipSuccess) return fail(LBM_EDEVICE, "capture launch: %s", hipGetErrorString(e));
             if (e2 != hipSuccess) return fail(LBM_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e2));
@@ -1110,7 +1145,10 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps, int32_t chunk) {
             b->graph_chunk[par] = chunk;
         }
         HIPCHK(hipGraphLaunch(b->graph[par], b->stream));
-        batch_advance(b, chunk);   // chunk is even: the parity is unchanged
+        // chunk is even: one-step launches leave the parity unchanged, chunk / 2
+        // two-step launches flip it when chunk / 2 is odd
+        if (b->pass2 >= 0) b->cur ^= (chunk / 2) & 1;
+        batch_advance(b, chunk);
         nsteps -= chunk;
     }
     return batch_plain(b, nsteps);
@@ -1376,6 +1414,37 @@ lbm_status lbm_batch_tune(lbm_batch *b, int32_t steps, int32_t *shapes_out, doub
         TRY(lbm_batch_set_tile_shapes(b, cand.data()));
     }
     if (shapes_out) TRY(lbm_batch_get_tile_shapes(b, shapes_out));
+    return LBM_OK;
+}
+
+lbm_status lbm_batch_set_two_step(lbm_batch *b, int32_t variant) {
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (variant < -1 || variant >= kPass2Variants) return fail(LBM_EINVAL, "two-step variant %d out of range", variant);
+    b->pass2 = variant;
+    return upload_twork(b);
+}
+
+int32_t lbm_batch_get_two_step(const lbm_batch *b) { return b ? b->pass2 : -2; }
+
+lbm_status lbm_batch_tune_two_step(lbm_batch *b, int32_t steps, int32_t *variant_out, double *ms_out) {
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
+    int best = -1;
+    double best_ms = INFINITY;
+    for (int v = -1; v < kPass2Variants; ++v) {
+        TRY(lbm_batch_set_two_step(b, v));
+        TRY(batch_plain(b, 2));                   // first launch of this candidate: not timed
+        double ms = 0;
+        TRY(time_steps(b->stream, steps, [&]() { return batch_plain(b, 2); }, &ms));
+        ms *= 0.5;                                // per time step
+        if (ms_out) ms_out[v < 0 ? kPass2Variants : v] = ms;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    TRY(lbm_batch_set_two_step(b, best));
+    if (variant_out) *variant_out = best;
     return LBM_OK;
 }
 

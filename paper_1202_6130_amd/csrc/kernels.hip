@@ -394,23 +394,22 @@ template <int TS, int OH, int WPS> struct Pass2Geo {
     static constexpr int W2 = OW + 4, H2 = OH + 4, N2 = W2 * H2;   // populations after step one
     static constexpr int W3 = OW + 2, H3 = OH + 2, N3 = W3 * H3;   // psi, step two
     static constexpr int K1 = (N1 + NT - 1) / NT, K2 = (N2 + NT - 1) / NT, K3 = (N3 + NT - 1) / NT;
+    static constexpr size_t lds_bytes = sizeof(float) * (size_t(Q) * N2 + N1 + 2 * H2);
     static_assert(OH % WPS == 0, "output rows must split evenly over the waves of a strip");
 };
 
+// One block (column group `group`, row band `trow`) of lattice L; lds holds
+// Pass2Geo::lds_bytes of dynamic LDS.
 template <class S, class C, int WALL, int TS, int OH, int WPS>
-__global__ __launch_bounds__(TS * WPS * kWave) void k_step_pass2(LatDev<C> L, const void *__restrict__ src,
-                                                                         void *__restrict__ dst) {
+__device__ inline void pass2_block(const LatDev<C> &L, const void *src, void *dst, uint32_t group, uint32_t trow,
+                                   unsigned char *lds) {
     using G = Pass2Geo<TS, OH, WPS>;
     using Raw = typename Codec<S>::Raw;
     constexpr int NT = G::NT, W1 = G::W1, W2 = G::W2, W3 = G::W3, N2 = G::N2;
-    extern __shared__ __align__(16) unsigned char pass2_lds[];
-    C *sf = reinterpret_cast<C *>(pass2_lds);   // [Q][N2] populations of step one
+    C *sf = reinterpret_cast<C *>(lds);          // [Q][N2] populations of step one
     C *sp = sf + Q * N2;                         // [N1] psi of step one, then [N3] psi of step two
     C *sw = sp + G::N1;                          // [H2][2] row wall terms of step one (WALL_ROW)
     const uint32_t nx = L.nx, ny = L.ny, P = L.pstride;
-    const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
-    const uint32_t groups = (nx + uint32_t(G::OW) - 1) / uint32_t(G::OW);
-    const uint32_t trow = lb / groups, group = lb - trow * groups;
     const uint32_t X0 = group * uint32_t(G::OW), Y0 = trow * uint32_t(OH);
     // multiples of nx and ny of at least 3, so that X0 - 3 + c never goes negative
     const uint32_t kx = nx >= 3 ? nx : (nx == 2 ? 4u : 3u), ky = ny >= 3 ? ny : (ny == 2 ? 4u : 3u);
@@ -557,6 +556,29 @@ __global__ __launch_bounds__(TS * WPS * kWave) void k_step_pass2(LatDev<C> L, co
         const C sy = w1 * b + w2 * (br + bl);
         act.row(L, row_wall<C, WALL>(L, y), y, x, active, f, rho, p[0], sx, sy);
     }
+}
+
+template <class S, class C, int WALL, int TS, int OH, int WPS>
+__global__ __launch_bounds__(TS * WPS * kWave) void k_step_pass2(LatDev<C> L, const void *__restrict__ src,
+                                                                 void *__restrict__ dst) {
+    extern __shared__ __align__(16) unsigned char pass2_lds[];
+    const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const uint32_t groups = (L.nx + uint32_t(TS * kStripCols) - 1) / uint32_t(TS * kStripCols);
+    const uint32_t trow = lb / groups, group = lb - trow * groups;
+    pass2_block<S, C, WALL, TS, OH, WPS>(L, src, dst, group, trow, pass2_lds);
+}
+
+// Two-step passes over the blocks of many lattices: pwork[b] = (lattice,
+// column group, row band) of logical workgroup b.
+template <int TS, int OH, int WPS>
+__global__ __launch_bounds__(TS * WPS * kWave) void k_step_pass2_batch(const LatDev<float> *__restrict__ lats,
+                                                                       const uint4 *__restrict__ pwork, int parity) {
+    extern __shared__ __align__(16) unsigned char pass2_lds[];
+    const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const uint4 wk = pwork[lb];
+    const LatDev<float> L = lats[wk.x];
+    pass2_block<float, float, WALL_ROW, TS, OH, WPS>(L, parity ? L.fb : L.fa, parity ? L.fa : L.fb, wk.y, wk.z,
+                                                     pass2_lds);
 }
 
 template <class S, class C, int WALL>
@@ -1035,8 +1057,8 @@ hipError_t launch_step_pass2(int storage, const LatDevAny &L, int wall, int vari
         LatDev<float> d = L.get<float>();
         const void *src = parity ? d.fb : d.fa;
         void *dst = parity ? d.fa : d.fb;
-        const uint32_t nb = ((d.nx + G::OW - 1) / G::OW) * ((d.ny + PV::OH - 1) / PV::OH);
-        const size_t lds = sizeof(float) * (size_t(Q) * G::N2 + G::N1 + 2 * G::H2);
+        const uint32_t nb = pass2_blocks(d.nx, d.ny, V);
+        const size_t lds = G::lds_bytes;
         if (wall == WALL_ROW)
             hipLaunchKernelGGL((k_step_pass2<S, float, WALL_ROW, PV::TS, PV::OH, PV::WPS>), dim3(nb), dim3(G::NT), lds,
                                st, d, src, dst);
@@ -1062,6 +1084,30 @@ hipError_t launch_step_pass2(int storage, const LatDevAny &L, int wall, int vari
     static_assert(kPass2Variants == 9, "launch_step_pass2 lists every variant");
     if (storage == STORE_F32) return with_var(float{});
     return with_var(__half{});
+}
+
+hipError_t launch_step_pass2_batch(const void *lats, const uint4 *pwork, uint32_t nblocks, int variant, int parity,
+                                   hipStream_t st) {
+    if (nblocks == 0) return hipSuccess;
+    auto go = [&](auto vc) -> hipError_t {
+        constexpr int V = decltype(vc)::value;
+        using PV = Pass2Var<V>;
+        hipLaunchKernelGGL((k_step_pass2_batch<PV::TS, PV::OH, PV::WPS>), dim3(nblocks), dim3(PV::G::NT),
+                           PV::G::lds_bytes, st, (const LatDev<float> *)lats, pwork, parity);
+        return hipGetLastError();
+    };
+    switch (variant) {
+    case 0: return go(std::integral_constant<int, 0>{});
+    case 1: return go(std::integral_constant<int, 1>{});
+    case 2: return go(std::integral_constant<int, 2>{});
+    case 3: return go(std::integral_constant<int, 3>{});
+    case 4: return go(std::integral_constant<int, 4>{});
+    case 5: return go(std::integral_constant<int, 5>{});
+    case 6: return go(std::integral_constant<int, 6>{});
+    case 7: return go(std::integral_constant<int, 7>{});
+    case 8: return go(std::integral_constant<int, 8>{});
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_step_batch(const void *lats, const uint4 *twork, uint32_t ntiles, int shape, int parity,

@@ -127,7 +127,15 @@ constexpr int kPass2Strips[kPass2Variants] = {1, 1, 2, 1, 1, 1, 1, 1, 1};
 constexpr int kPass2Rows[kPass2Variants] = {8, 8, 8, 12, 12, 16, 16, 24, 24};
 constexpr int kPass2WavesPerStrip[kPass2Variants] = {4, 8, 4, 6, 12, 8, 16, 8, 12};
 inline bool pass2_ok(int storage) { return storage == STORE_F32 || storage == STORE_F16; }
+constexpr uint32_t pass2_blocks(uint32_t nx, uint32_t ny, int v) {
+    return ((nx + 64u * uint32_t(kPass2Strips[v]) - 1) / (64u * uint32_t(kPass2Strips[v]))) *
+           ((ny + uint32_t(kPass2Rows[v]) - 1) / uint32_t(kPass2Rows[v]));
+}
 hipError_t launch_step_pass2(int storage, const LatDevAny &L, int wall, int variant, int parity, hipStream_t st);
+// The same over the blocks of many F32 flat-wall lattices: pwork[b] = (lattice,
+// column group, row band) for variant `variant`.
+hipError_t launch_step_pass2_batch(const void *lats, const uint4 *pwork, uint32_t nblocks, int variant, int parity,
+                                   hipStream_t st);
 hipError_t launch_step_batch(const void *lats, const uint4 *twork, uint32_t ntiles, int shape, int parity,
                              hipStream_t st);
 hipError_t launch_diag(int storage, const void *lats, const uint4 *work, uint32_t nwork, const LatDevAny &single,

@@ -105,6 +105,9 @@ def lib():
         "lbm_batch_set_tile_shapes": ([_vp, _ip], ctypes.c_int),
         "lbm_batch_get_tile_shapes": ([_vp, _ip], ctypes.c_int),
         "lbm_batch_tune": ([_vp, ctypes.c_int32, _ip, _dp], ctypes.c_int),
+        "lbm_batch_set_two_step": ([_vp, ctypes.c_int32], ctypes.c_int),
+        "lbm_batch_get_two_step": ([_vp], ctypes.c_int32),
+        "lbm_batch_tune_two_step": ([_vp, ctypes.c_int32, _ip, _dp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -373,6 +376,23 @@ def lbm_batch_tune(b, n, steps):
     return shapes, ms
 
 
+def lbm_batch_set_two_step(b, variant):
+    _check(lib().lbm_batch_set_two_step(b, int(variant)))
+
+
+def lbm_batch_get_two_step(b):
+    return int(lib().lbm_batch_get_two_step(b))
+
+
+def lbm_batch_tune_two_step(b, steps):
+    """Returns (chosen variant or -1 for single steps, median ms per step of
+    every variant followed by that of single steps), over the whole batch."""
+    v = np.zeros(1, dtype=np.int32)
+    ms = np.zeros(len(lbm_two_step_variants()) + 1)
+    _check(lib().lbm_batch_tune_two_step(b, int(steps), _iptr(v), _ptr(ms)))
+    return int(v[0]), ms
+
+
 # ------------------------------------------------------------ conveniences
 def _workspace(nbytes, device):
     import torch
@@ -515,6 +535,20 @@ class Attached:
     def tune(self, steps=10):
         return lbm_batch_tune(self.b, self.n, steps)
 
+    @property
+    def two_step(self):
+        """Two-steps-per-pass variant of the batch, -1 for single steps."""
+        return lbm_batch_get_two_step(self.b)
+
+    @two_step.setter
+    def two_step(self, variant):
+        lbm_batch_set_two_step(self.b, variant)
+
+    def tune_two_step(self, steps=5):
+        """Choose between single steps and two steps per pass for the whole
+        batch (advances every lattice; see lbm_batch_tune_two_step)."""
+        return lbm_batch_tune_two_step(self.b, steps)
+
     def close(self):
         if self.b:
             lbm_batch_destroy(self.b)
@@ -575,6 +609,8 @@ class Batch:
 
     tile_shapes = Attached.tile_shapes
     tune = Attached.tune
+    two_step = Attached.two_step
+    tune_two_step = Attached.tune_two_step
 
     def lattice(self, k):
         return View(self, k, self.ps[k])

@@ -16,7 +16,10 @@ state across rebuilds.  A request whose lattice turns non-finite fails alone.
 Tile shapes: at start-up the batch autotuner measures a per-tile step cost
 for every tile shape on a small calibration ensemble; each admitted lattice
 then gets the shape of least predicted cost (tile count x per-tile cost).
-Shapes change speed only, never results.
+Two steps per launch: on the same calibration ensemble the batch's two-step
+autotuner chooses between single steps and the two-step variants, and every
+batch (and, in the sequential baseline, every lattice) uses that choice.
+Shapes and step variants change speed only, never results.
 
 `Server(batched=False, max_resident=1)` is the plain sequential baseline.
 """
@@ -73,6 +76,19 @@ def calibrate_tile_costs(seed=0, count=16, steps=3, device="cuda:0"):
     return [float(ms[s]) / sum(tile_count(c.nx, c.ny, s) for c in cases) for s in range(nshape)]
 
 
+def calibrate_two_step(seed=0, count=16, steps=2, device="cuda:0"):
+    """Two-step variant (or -1 for single steps) the batch two-step autotuner
+    keeps on the calibration ensemble of calibrate_tile_costs."""
+    cases = I.ensemble_cases(seed=seed, count=count)
+    ps = [lbm.lbm_params_default(nx=c.nx, ny=c.ny, wall_kind=lbm.WALL_FLAT_SLAB, G=c.G, G_R=c.G_R, G_A=c.G_A)
+          for c in cases]
+    B = lbm.Batch(ps, [I.drop_field(c.nx, c.ny, c.radius) for c in cases], device=device)
+    B.tune(3)
+    v, _ = B.tune_two_step(steps)
+    B.close()
+    return v
+
+
 def pick_tile_shape(nx, ny, costs):
     return min(range(len(costs)), key=lambda s: tile_count(nx, ny, s) * costs[s])
 
@@ -98,7 +114,7 @@ def request_params(req, seg_rows=0):
 class Server:
     def __init__(self, budget_bytes=96 << 30, max_resident=64, diag_every=100, max_steps=20000, tol=1e-8,
                  batched=True, device="cuda:0", seg_rows=0, on_admit=None, tile_costs="calibrate",
-                 max_nodes=16 << 20):
+                 max_nodes=16 << 20, two_step="calibrate"):
         import torch
         if diag_every % 2:
             raise ValueError("diag_every must be even (graph replays keep the buffer parity)")
@@ -117,6 +133,8 @@ class Server:
         self.max_seen_used = 0            # largest sum of resident footprints (bytes)
         # per-tile cost of every tile shape: measured, given, or None (shape 0)
         self.tile_costs = calibrate_tile_costs(device=device) if tile_costs == "calibrate" else tile_costs
+        # two-step variant of every batch (-1: single steps): measured or given
+        self.two_step = calibrate_two_step(device=device) if two_step == "calibrate" else int(two_step)
         torch.cuda.synchronize(device)
         self.stream = torch.cuda.Stream(device)
 
@@ -174,6 +192,8 @@ class Server:
                 lat = lbm.Lattice(p, rho0, device=self.device, stream=self.stream)
                 if self.tile_costs is not None:
                     lat.tile_shape = pick_tile_shape(req.nx, req.ny, self.tile_costs)
+                if not self.batched:
+                    lat.two_step = self.two_step
                 if self.on_admit is not None:
                     self.on_admit(req, lat)
                 resident.append((req, lat, fp))
@@ -192,6 +212,7 @@ class Server:
                     if batch is not None:
                         batch.close()
                     batch = lbm.Attached([lat for _, lat, _ in resident], device=self.device)
+                    batch.two_step = self.two_step
                 batch.step(self.K, chunk=self.K)
                 diag, code = batch.diagnostics(check=False)
             else:

@@ -147,3 +147,53 @@ def test_oracle_parity_small_drop_two_step():
         e_u = max(np.abs(ux - ux_o).max(), np.abs(uy - uy_o).max()) / cs
         print(f"two-step variant {v}, FP32 drop 64x32 t=2000: rho {e_rho:.3e}, u/c_s {e_u:.3e}", flush=True)
         assert e_rho <= 1e-5 and e_u <= 1e-5
+
+
+def _ensemble(seed, count):
+    cases = I.ensemble_cases(seed=seed, count=count)
+    ps = [lbm.lbm_params_default(nx=c.nx, ny=c.ny, wall_kind=lbm.WALL_FLAT_SLAB, G=c.G, G_R=c.G_R, G_A=c.G_A)
+          for c in cases]
+    return ps, [I.drop_field(c.nx, c.ny, c.radius) for c in cases]
+
+
+def _alone(p, rho, steps):
+    L = lbm.Lattice(lbm.lbm_params_default(nx=p.nx, ny=p.ny, wall_kind=lbm.WALL_FLAT_SLAB, G=p.G, G_R=p.G_R,
+                                           G_A=p.G_A), rho)
+    L.step(steps)
+    s = L.get_state()
+    L.close()
+    return s
+
+
+@pytest.mark.parametrize("variant", [0, 3, 7])
+def test_batch_two_step_bitwise(variant):
+    # graph chunks of 6 steps (3 passes: the buffer parity flips per replay)
+    # and of 4 (2 passes), odd remainders as single steps, plain launches
+    ps, rhos = _ensemble(31, 5)
+    B = lbm.Batch(ps, rhos)
+    B.two_step = variant
+    assert B.two_step == variant
+    B.step(12, chunk=6)
+    B.step(7, chunk=4)
+    B.step(5)
+    for k, (p, r) in enumerate(zip(ps, rhos)):
+        print(f"batch two-step variant {variant}, lattice {k} {p.nx}x{p.ny}", flush=True)
+        assert np.array_equal(B.lattice(k).get_state(), _alone(p, r, 24)), k
+    B.two_step = -1
+    B.step(6, chunk=6)
+    for k, (p, r) in enumerate(zip(ps, rhos)):
+        assert np.array_equal(B.lattice(k).get_state(), _alone(p, r, 30)), k
+    B.close()
+
+
+def test_batch_tune_two_step_is_plain_stepping():
+    ps, rhos = _ensemble(32, 4)
+    B = lbm.Batch(ps, rhos)
+    v, ms = B.tune_two_step(2)
+    assert -1 <= v < len(VARIANTS) and B.two_step == v
+    assert ms.shape == (len(VARIANTS) + 1,) and np.all(np.isfinite(ms)) and ms[v] == ms.min()
+    n = (6 * 2 + 2) * (len(VARIANTS) + 1)
+    B.step(10, chunk=10)
+    for k, (p, r) in enumerate(zip(ps, rhos)):
+        assert np.array_equal(B.lattice(k).get_state(), _alone(p, r, n + 10)), k
+    B.close()
