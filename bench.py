@@ -824,9 +824,15 @@ def main():
                                       f"{SAMPLE_EVERY}th, none with a diagnostic pass), on the launch stream",
                      "bytes_per_update": bpu},
     }
+    if upl == 2:
+        out["roofline"]["note"] = ("achieved counts the algorithmic bytes of a single step (bytes_per_update per "
+                                   "lattice update) for the 2 updates one launch performs; the launch moves only "
+                                   "`traffic` bytes to and from HBM (populations between the two steps stay in "
+                                   "LDS), so frac above 1 means faster than one step per launch could ever be")
     if traffic is not None:
         # bytes that actually crossed to memory per second (counters), beside the algorithmic rate
         out["roofline"]["hbm_gbs_from_traffic"] = round(traffic / (r["kernel_ms_mean"] * 1e-3) / 1e9, 1)
+        out["roofline"]["hbm_frac_from_traffic"] = round(out["roofline"]["hbm_gbs_from_traffic"] / HBM_PEAK_GBS, 4)
     if r["single"] is not None:
         sg = r["single"]
         s_ach = bpu * r["nodes"] / (sg["kernel_ms_mean"] * 1e-3) / 1e9

@@ -8,6 +8,12 @@
 // pseudo-potential in LDS, and after one barrier forms the forces, collides
 // and writes nine aligned rows.  Population planes are SoA [9][ny][nx] with a
 // padded plane stride.  The marching walk (march) serves the diagnostic pass.
+//
+// Two steps per launch, k_step_pass2 (and k_step_pass2_batch): a workgroup
+// reads its block grown by four nodes once, computes the first step on the
+// block grown by two with the populations kept in LDS, and writes the second
+// step of the block: half the memory traffic per update, bitwise the same
+// fields as two launches of k_step_tiles.
 #include <type_traits>
 
 #include <utility>
