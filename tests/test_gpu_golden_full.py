@@ -4,9 +4,11 @@ FP64 oracle wrote (tests/golden/make_golden_full.py):
   - channel 32x256, body force 1e-6, 600000 steps: slip length and the
     x-averaged velocity profile;
   - sessile drop 1024x512, radius 160, 20000 steps: contact angle, totals and
-    rho, u at 256 seeded nodes;
+    rho, u at 256 seeded nodes (binary32 with one and with two steps per
+    launch);
   - periodic 4096x4096 phase separation: rho, u at 1024 seeded nodes and the
-    totals at t = 100 ... 5000;
+    totals at t = 100 ... 5000, the binary32 run also with two steps per
+    launch (the benchmark's configuration; bitwise the single-step run);
   - the same for the paper's fluid (D2Q21, EOS pseudo-potential) at t = 100
     and 300, stepped by the marching variant the benchmark uses (binary32)
     and the one-row tiles (FP64 storage);
@@ -71,13 +73,15 @@ def test_channel_slip_vs_oracle(storage):
         assert slip_err < 1e-2 and prof_err < 1e-2
 
 
-@pytest.mark.parametrize("storage", [lbm.STORE_F64, lbm.STORE_F32])
-def test_drop_1024_vs_oracle(storage):
+@pytest.mark.parametrize("storage,two_step", [(lbm.STORE_F64, -1), (lbm.STORE_F32, -1), (lbm.STORE_F32, 6)])
+def test_drop_1024_vs_oracle(storage, two_step):
+    """two_step 6: the variant the benchmark's autotuner keeps on this lattice."""
     g = _golden("drop_1024x512_fp64.json")
     c = g["params"]
     p = lbm.lbm_params_default(nx=c["nx"], ny=c["ny"], storage=storage, wall_kind=lbm.WALL_FLAT_SLAB,
                                G=c["G"], G_R=c["G_R"], G_A=c["G_A"], eps=c["eps"], diag_interval=0)
     L = lbm.Lattice(p, I.drop_field(c["nx"], c["ny"], c["radius"]))
+    L.two_step = two_step
     L.step(c["steps"])
     ang = L.contact_angle(c["iso"], 0.0)
     rho, ux, uy, tot = L.moments()
@@ -90,7 +94,7 @@ def test_drop_1024_vs_oracle(storage):
     u_err = max(np.abs(ux[ys, xs] - [s["ux"] for s in g["samples"]]).max(),
                 np.abs(uy[ys, xs] - [s["uy"] for s in g["samples"]]).max()) / CS
     a_err = abs(ang[0] - g["contact_angle"][0])
-    print(f"drop storage {storage}: angle {ang[0]:.6f} vs {g['contact_angle'][0]:.6f}; rho rel {r_err:.2e} "
+    print(f"drop storage {storage} two-step {two_step}: angle {ang[0]:.6f} vs {g['contact_angle'][0]:.6f}; rho rel {r_err:.2e} "
           f"(rms {r_rms:.2e}), u/c_s {u_err:.2e}, mass {abs(tot[0] - g['totals'][0]) / g['totals'][0]:.2e}")
     if storage == lbm.STORE_F64:
         assert r_err < 1e-9 and u_err < 1e-9 and a_err < 1e-7
@@ -109,12 +113,19 @@ def test_spinodal_4096_vs_oracle():
     for name, st in (("f64", lbm.STORE_F64), ("f32", lbm.STORE_F32)):
         runs[name] = lbm.Lattice(lbm.lbm_params_default(nx=n, ny=n, storage=st, diag_interval=0), rho0)
     runs["f32"].tile_shape = 8          # one of the two shapes the benchmark's autotuner keeps here (7, 8)
+    # the benchmark's launch configuration: two steps per launch, 64 x 24 blocks
+    # (variant 8; 7 and 8 are the two the autotuner keeps), single steps with shape 8
+    runs["f32_two_step"] = lbm.Lattice(lbm.lbm_params_default(nx=n, ny=n, storage=lbm.STORE_F32, diag_interval=0),
+                                       rho0)
+    runs["f32_two_step"].tile_shape = 8
+    runs["f32_two_step"].two_step = 8
     t0 = 0
     for cp in g["checkpoints"]:
         for L in runs.values():
             L.step(cp["t"] - t0)
         t0 = cp["t"]
         want_r, want_x, want_y = (np.array(cp[k]) for k in ("rho", "ux", "uy"))
+        assert np.array_equal(runs["f32_two_step"].get_state(), runs["f32"].get_state()), cp["t"]
         for name, L in runs.items():
             rho, ux, uy, tot = L.moments()
             dr = rho[ys, xs] - want_r
