@@ -6,7 +6,9 @@ nodes, including the first and last rows and columns, against the oracle's
 one-step update of a patch of the same GPU state (the update of a node
 depends on its radius-2 neighbourhood for D2Q9, radius 6 for D2Q21).  For
 binary32 D2Q21 the step is taken by the marching and by the one-row tile
-variants from the same state, which must agree bit for bit.
+variants from the same state, which must agree bit for bit; for binary32
+D2Q9 two further steps are taken one per launch and, from the same state,
+in one two-step launch, which must also agree bit for bit.
 
 Bars: FP64 storage 1e-12; binary32 2e-6 (one step of binary32 arithmetic);
 FP16 deviations: half of one binary16 unit of the stored deviation
@@ -85,6 +87,17 @@ def test_max_lattice_sampled_one_step(case):
         print(f"{case}: one step by variant 2 (default {shape})", flush=True)
         L.step(1)
         assert np.array_equal(L.get_state(), f1)
+    if q == 9 and st == "f32":
+        # steps 12 and 13 one at a time, then again as one two-step launch
+        # (64 x 24 blocks) from the same state: bitwise the same
+        L.step(2)
+        f3 = L.get_state()
+        L.set_state(f1, 11)
+        L.two_step = 8
+        print(f"{case}: two steps in one launch (variant 8)", flush=True)
+        L.step(2)
+        assert np.array_equal(L.get_state(), f3)
+        del f3
     L.close()
     rng = np.random.Generator(np.random.PCG64(nx + ny))
     ys = np.concatenate([rng.integers(0, ny, 24), [0, 1, ny - 1, ny - SLAB, ny - SLAB - 1, 0, ny - 1]])
