@@ -41,6 +41,23 @@ def test_tile_shape_table_and_null_context():
     assert L.lbm_batch_set_tile_shapes(None, None) == lbm.LBM_EINVAL
 
 
+def test_two_step_table_and_null_context():
+    """Two-steps-per-pass variants (strips, output rows, waves per workgroup)
+    and the NULL-argument errors of their calls (no GPU needed)."""
+    v = lbm.lbm_two_step_variants()
+    assert v == [(1, 8, 4), (1, 8, 8), (2, 8, 8), (1, 12, 6), (1, 12, 12), (1, 16, 8), (1, 16, 16), (1, 24, 8),
+                 (1, 24, 12)]
+    # every block's rows split evenly over the waves of a strip, at most 1024 threads
+    assert all(r % (w // s) == 0 and w * 64 <= 1024 for s, r, w in v)
+    L = lbm.lib()
+    assert L.lbm_get_two_step(None) == -2
+    assert L.lbm_set_two_step(None, 0) == lbm.LBM_EINVAL
+    assert L.lbm_tune_two_step(None, 1, None, None) == lbm.LBM_EINVAL
+    assert L.lbm_batch_get_two_step(None) == -2
+    assert L.lbm_batch_set_two_step(None, 0) == lbm.LBM_EINVAL
+    assert L.lbm_batch_tune_two_step(None, 1, None, None) == lbm.LBM_EINVAL
+
+
 def test_params_struct_matches_header():
     # field order of lbm_params in the header must match the ctypes mirror
     text = open(HEADER).read()

@@ -40,6 +40,16 @@ def test_step_dispatch_names():
     assert bench.traffic_key("spinodal4096", "f32", 8) == "spinodal4096:f32:shape8"
     assert bench.traffic_key("spinodal4096_q21", "f32", 1) == "spinodal4096_q21:f32:k_march_q21"
     assert bench.traffic_key("drop1024_q21", "f32", 2) == "drop1024_q21:f32:k_tile_q21_r1"
+    # two steps per launch: <storage, arithmetic, wall, strips, rows, waves per strip> -> variant
+    assert k("void lbmwet::k_step_pass2<float, float, 0, 1, 24, 8>(lbmwet::LatDev<float>, void const*, void*)") \
+        == "pass2v7"
+    assert k("void lbmwet::k_step_pass2<__half, float, 1, 2, 8, 4>(lbmwet::LatDev<float>, void const*, void*)") \
+        == "pass2v2"
+    assert k("void lbmwet::k_step_pass2_batch<1, 24, 12>(lbmwet::LatDev<float> const*, uint4 const*, int)") is None
+    assert bench.traffic_key("spinodal4096", "f32", "pass2v7") == "spinodal4096:f32:pass2v7"
+    assert bench.PASS2_GEOMETRY == [(s, r, w // s) for s, r, w in
+                                    [(1, 8, 4), (1, 8, 8), (2, 8, 8), (1, 12, 6), (1, 12, 12), (1, 16, 8),
+                                     (1, 16, 16), (1, 24, 8), (1, 24, 12)]]
 
 
 def _write_run(path, counter, copy_kib, steps):
