@@ -153,6 +153,52 @@ def test_external_force_momentum_budget(orc):
         assert abs((f * c).sum() - (f0 * c).sum() - 40 * nx * ny * Fc) < 1e-12
 
 
+@pytest.mark.parametrize("lattice,tau", [(9, 1.0), (9, 0.7), (21, 1.0), (21, 0.8)])
+def test_reported_velocity_uniform_acceleration(orc, lattice, tau):
+    """Reported velocity of the exact difference method (Sec. II.B: u* = u +
+    g dt, the velocity over a step being the average of the pre- and
+    post-force velocities).  A uniform fluid (G = 0, no solid, periodic) from
+    u0 under a uniform force density F gains F per step at every node, so
+    after t steps the momentum is rho u0 + t F and the reported velocity must
+    be u0 + F (t + 1/2) / rho exactly.  Reporting j / rho would give
+    u0 + F t / rho and (j + F) / rho would give u0 + F (t + 1) / rho, both
+    off by F / (2 rho) = 1.9e-5 here, far above the 1e-12 bar."""
+    nx, ny, rho0, u0 = 6, 5, 1.37, (2e-3, -1e-3)
+    F = (5.2e-5, -3.1e-5)
+    p = orc.make_params(nx, ny, tau=tau, G=0.0, F_ext=F, lattice=lattice)
+    walls = orc.Walls.none(nx, ny)
+    f = orc.init(p, np.full((ny, nx), rho0), np.full((ny, nx), u0[0]), np.full((ny, nx), u0[1]))
+    t = 0
+    for t_next in (0, 1, 7, 40):
+        f = orc.run(p, walls, f, t_next - t)
+        t = t_next
+        rho, ux, uy, _ = orc.macros(p, walls, f)
+        assert np.abs(rho - rho0).max() < 1e-13
+        assert np.abs(ux - (u0[0] + F[0] * (t + 0.5) / rho0)).max() < 1e-12, t
+        assert np.abs(uy - (u0[1] + F[1] * (t + 0.5) / rho0)).max() < 1e-12, t
+
+
+def test_reported_velocity_vanishes_at_rest(orc):
+    """At a converged flat interface (periodic liquid slab, G = -5, no solid)
+    nothing flows: the reported velocity (j + F/2)/rho (Sec. II.B) must
+    vanish to well below the force scale, while the pre-force velocity j/rho
+    and the post-force one (j + F)/rho are -F/(2 rho) and +F/(2 rho) there
+    (|F| reaches 0.2 at the interface).  Pins the half-force convention on a
+    state with a strongly non-uniform force."""
+    nx, ny = 4, 128
+    p = orc.make_params(nx, ny, tau=1.0, G=-5.0)
+    walls = orc.Walls.none(nx, ny)
+    f = orc.run(p, walls, orc.init(p, I.slab_field(nx, ny)), 10000)
+    d = orc.forces(p, walls, f)
+    rho, ux, uy, _ = orc.macros(p, walls, f)
+    half = (np.abs(d["F"][..., 1]) / (2 * d["rho"])).max()
+    assert half > 0.05
+    assert np.abs(uy).max() < 1e-2 * half and np.abs(ux).max() < 1e-12
+    # the pre- and post-force velocities are half a force step away
+    assert np.abs(d["uy"] + 0.5 * d["F"][..., 1] / d["rho"] - uy).max() < 1e-14
+    assert np.abs(d["uy"]).max() > 0.9 * half
+
+
 def test_mass_conserved_with_walls(orc):
     """Wall forces exchange momentum but never mass."""
     nx, ny = 20, 24
