@@ -64,17 +64,19 @@ __device__ inline void march(const LatDev<C> &L, const void *src, uint32_t strip
     const uint32_t y0 = seg * L.seg_rows;
     const uint32_t y1 = min(y0 + L.seg_rows, ny);
 
-    const C w1 = C(1.0 / 9.0), w2 = C(1.0 / 36.0);
+    // neighbour sums of psi are formed in binary64 (values and sums)
+    const double w1 = 1.0 / 9.0, w2 = 1.0 / 36.0;
     // loads of row r (its pulled populations come from rows r-1, r, r+1)
     auto load_row = [&](uint32_t r, Raw(&dst)[Q], Raw &g) {
         ld.load(wrap_dec(r, ny) * nx, r * nx, wrap_inc(r, ny) * nx, dst, g);
     };
-    // psi of the two halo nodes of a row, from its gathered populations
+    // psi of the two halo nodes of a row, from its gathered populations: the
+    // binary64 sum in the tree of density(), so equal to the owner's density
     auto halo_psi = [&](Raw g, C &pl, C &pr) {
         const C v = g_on ? Codec<S>::template decode<C>(g, g_q, L.rho_ref) : C(0);
-        const C s = row_sum9<C>(v);
-        pl = psi_of<C>(Lanes<C>::lane(s, 15));
-        pr = psi_of<C>(Lanes<C>::lane(s, 47));
+        const double s = row_sum9<double>(double(v));
+        pl = psi_of<C>(C(Lanes<double>::lane(s, 15)));
+        pr = psi_of<C>(C(Lanes<double>::lane(s, 47)));
     };
 
     C fA[Q], fB[Q];
@@ -120,12 +122,13 @@ __device__ inline void march(const LatDev<C> &L, const void *src, uint32_t strip
         // sum_i w_i psi(x + c_i) c_i, grouped by column:
         //   a(x) = w1 psi(x,y) + w2 (psi(x,y+1) + psi(x,y-1)),  sx = a(x+1) - a(x-1)
         //   b(x) = psi(x,y+1) - psi(x,y-1),  sy = w1 b(x) + w2 (b(x+1) + b(x-1))
-        const C a = w1 * psi_c + w2 * (psi_p + psi_m);
-        const C b = psi_p - psi_m;
-        const C al = w1 * hl_c + w2 * (hl_p + hl_m), ar = w1 * hr_c + w2 * (hr_p + hr_m);
-        const C bl = hl_p - hl_m, br = hr_p - hr_m;
-        const C sx = Lanes<C>::right(a, ar) - Lanes<C>::left(a, al);
-        const C sy = w1 * b + w2 * (Lanes<C>::right(b, br) + Lanes<C>::left(b, bl));
+        const double a = w1 * double(psi_c) + w2 * (double(psi_p) + double(psi_m));
+        const double b = double(psi_p) - double(psi_m);
+        const double al = w1 * double(hl_c) + w2 * (double(hl_p) + double(hl_m));
+        const double ar = w1 * double(hr_c) + w2 * (double(hr_p) + double(hr_m));
+        const double bl = double(hl_p) - double(hl_m), br = double(hr_p) - double(hr_m);
+        const double sx = Lanes<double>::right(a, ar) - Lanes<double>::left(a, al);
+        const double sy = w1 * b + w2 * (Lanes<double>::right(b, br) + Lanes<double>::left(b, bl));
         act.row(L, wall_c, y, x, active, fc, rho_c, psi_c, sx, sy);
         psi_m = psi_c;
         psi_c = psi_p;
@@ -179,7 +182,7 @@ __device__ inline void march(const LatDev<C> &L, const void *src, uint32_t strip
 template <class S, class C, int WALL> struct StepAct {
     PopBuf<S> dst;
     __device__ inline void row(const LatDev<C> &L, const RowWall<C> &rw, uint32_t y, uint32_t x, bool active,
-                               C f[Q], C rho, C psi_c, C sx, C sy) {
+                               C f[Q], C rho, C psi_c, double sx, double sy) {
         const uint32_t n = y * L.nx + x;
         C phie, Sx, Sy;
         wall_terms<C, WALL>(L, rw, n, phie, Sx, Sy);
@@ -199,13 +202,21 @@ template <class S, class C, int WALL> struct DiagAct {
     int write_mom, compare, update;
     double s_rho = 0, s_jx = 0, s_jy = 0, s_du = 0, s_u = 0, s_bad = 0;
     __device__ inline void row(const LatDev<C> &L, const RowWall<C> &rw, uint32_t y, uint32_t x, bool active,
-                               C f[Q], C rho, C psi_c, C sx, C sy) {
+                               C f[Q], C rho, C psi_c, double sx, double sy) {
         const uint32_t n = y * L.nx + x;
         C phie, Sx, Sy;
         wall_terms<C, WALL>(L, rw, n, phie, Sx, Sy);
         NodeState<C> s = node_forces<C>(f, rho, psi_c, sx, sy, phie, Sx, Sy, L.G, L.Ux, L.Uy, L.Fx, L.Fy);
-        const C vx = s.ux + C(0.5) * s.Fx * s.inv_rho;
-        const C vy = s.uy + C(0.5) * s.Fy * s.inv_rho;
+        // reported velocity (j + F/2) / rho; in binary32 arithmetic from the
+        // binary64 momenta (the binary32 reciprocal enters once)
+        C vx, vy;
+        if constexpr (sizeof(C) == 4) {
+            vx = C(0.5 * (s.jxd + s.jsxd) * double(s.inv_rho));
+            vy = C(0.5 * (s.jyd + s.jsyd) * double(s.inv_rho));
+        } else {
+            vx = s.ux + C(0.5) * s.Fx * s.inv_rho;
+            vy = s.uy + C(0.5) * s.Fy * s.inv_rho;
+        }
         if (!active) return;
         if (write_mom) {
             L.mom[n] = rho;
@@ -214,9 +225,15 @@ template <class S, class C, int WALL> struct DiagAct {
         }
         const bool ok = isfinite(double(rho)) && isfinite(double(vx)) && isfinite(double(vy));
         s_bad += ok ? 0.0 : 1.0;
-        s_rho += double(rho);
-        s_jx += double(rho) * double(s.ux);
-        s_jy += double(rho) * double(s.uy);
+        if constexpr (sizeof(C) == 4) {
+            s_rho += s.m;
+            s_jx += s.jxd;
+            s_jy += s.jyd;
+        } else {
+            s_rho += double(rho);
+            s_jx += double(rho) * double(s.ux);
+            s_jy += double(rho) * double(s.uy);
+        }
         if (compare) s_du += fabs(double(vx) - double(L.uprev[n])) + fabs(double(vy) - double(L.uprev[L.plane + n]));
         s_u += fabs(double(vx)) + fabs(double(vy));
         if (update) {
@@ -312,17 +329,18 @@ __device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst,
             psi[j] = psi_of<C>(rho[j]);
             // the halo nodes' density is read out of lanes 15 and 47 by every
             // lane, outside divergent control flow
+            // (binary64 sum in the tree of density(): equal to the owner's)
             const C v = g_on ? Codec<S>::template decode<C>(g[j], g_q, L.rho_ref) : C(0);
-            const C sum = row_sum9<C>(v);
-            const C hl = psi_of<C>(Lanes<C>::lane(sum, 15));
-            const C hr = psi_of<C>(Lanes<C>::lane(sum, 47));
+            const double sum = row_sum9<double>(double(v));
+            const C hl = psi_of<C>(C(Lanes<double>::lane(sum, 15)));
+            const C hr = psi_of<C>(C(Lanes<double>::lane(sum, 47)));
             sm.psi[k][pos] = psi[j];
             if (lane == 0 && sj == 0) sm.hal[k][0] = hl;
             if (lane == 0 && sj == TS - 1) sm.hal[k][1] = hr;
         }
     }
     __syncthreads();
-    const C w1 = C(1.0 / 9.0), w2 = C(1.0 / 36.0);
+    const double w1 = 1.0 / 9.0, w2 = 1.0 / 36.0;
     // pseudo-potential just left of lane 0 / right of lane 63 of this strip
     const int cl = sj * kStripCols - 1, cr = (sj + 1) * kStripCols;
 #pragma unroll
@@ -342,13 +360,14 @@ __device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst,
         } else {
             hr_m = sm.psi[k - 1][cr]; hr_c = sm.psi[k][cr]; hr_p = sm.psi[k + 1][cr];
         }
-        // sum_i w_i psi(x + c_i) c_i, grouped by column (see march)
-        const C a = w1 * psi[j] + w2 * (psi_p + psi_m);
-        const C b = psi_p - psi_m;
-        const C al = w1 * hl_c + w2 * (hl_p + hl_m), ar = w1 * hr_c + w2 * (hr_p + hr_m);
-        const C bl = hl_p - hl_m, br = hr_p - hr_m;
-        const C sx = Lanes<C>::right(a, ar) - Lanes<C>::left(a, al);
-        const C sy = w1 * b + w2 * (Lanes<C>::right(b, br) + Lanes<C>::left(b, bl));
+        // sum_i w_i psi(x + c_i) c_i, grouped by column (see march), binary64
+        const double a = w1 * double(psi[j]) + w2 * (double(psi_p) + double(psi_m));
+        const double b = double(psi_p) - double(psi_m);
+        const double al = w1 * double(hl_c) + w2 * (double(hl_p) + double(hl_m));
+        const double ar = w1 * double(hr_c) + w2 * (double(hr_p) + double(hr_m));
+        const double bl = double(hl_p) - double(hl_m), br = double(hr_p) - double(hr_m);
+        const double sx = Lanes<double>::right(a, ar) - Lanes<double>::left(a, al);
+        const double sy = w1 * b + w2 * (Lanes<double>::right(b, br) + Lanes<double>::left(b, bl));
         StepAct<S, C, WALL> act;
         act.dst.init(dst, 9u * L.pstride * uint32_t(sizeof(S)));
         act.row(L, row_wall<C, WALL>(L, r), r, x, active, f[j], rho[j], psi[j], sx, sy);
@@ -480,7 +499,7 @@ __device__ inline void pass2_block(const LatDev<C> &L, const void *src, void *ds
     }
     __syncthreads();
 
-    const C w1 = C(1.0 / 9.0), w2 = C(1.0 / 36.0);
+    const double w1 = 1.0 / 9.0, w2 = 1.0 / 36.0;
     // R2: forces and collision of step one, in place in LDS (each node reads only its own populations)
 #pragma unroll
     for (int k = 0; k < G::K2; ++k) {
@@ -488,14 +507,14 @@ __device__ inline void pass2_block(const LatDev<C> &L, const void *src, void *ds
         if (!((k + 1) * NT <= N2 || i < N2)) continue;
         const int r2 = i / W2, c2 = i - r2 * W2;
         const C *p = sp + (r2 + 1) * W1 + (c2 + 1);
-        const C pm = p[-W1], pp = p[W1];
-        const C lm = p[-W1 - 1], lc = p[-1], lp = p[W1 - 1];
-        const C rm = p[-W1 + 1], rc = p[1], rp = p[W1 + 1];
+        const double pm = p[-W1], pp = p[W1];
+        const double lm = p[-W1 - 1], lc = p[-1], lp = p[W1 - 1];
+        const double rm = p[-W1 + 1], rc = p[1], rp = p[W1 + 1];
         // sum_i w_i psi(x + c_i) c_i, grouped by column as in tile_step
-        const C al = w1 * lc + w2 * (lp + lm), ar = w1 * rc + w2 * (rp + rm);
-        const C b = pp - pm, bl = lp - lm, br = rp - rm;
-        const C sx = ar - al;
-        const C sy = w1 * b + w2 * (br + bl);
+        const double al = w1 * lc + w2 * (lp + lm), ar = w1 * rc + w2 * (rp + rm);
+        const double b = pp - pm, bl = lp - lm, br = rp - rm;
+        const double sx = ar - al;
+        const double sy = w1 * b + w2 * (br + bl);
         C f[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) f[q] = sf[q * N2 + i];
@@ -553,13 +572,13 @@ __device__ inline void pass2_block(const LatDev<C> &L, const void *src, void *ds
         for (int q = 0; q < Q; ++q) f[q] = sf[q * N2 + j - kCy[q] * W2 - kCx[q]];
         const C rho = density<C>(f);
         const C *p = sp + (r4 + 1) * W3 + (c4 + 1);
-        const C pm = p[-W3], pp = p[W3];
-        const C lm = p[-W3 - 1], lc = p[-1], lp = p[W3 - 1];
-        const C rm = p[-W3 + 1], rc = p[1], rp = p[W3 + 1];
-        const C al = w1 * lc + w2 * (lp + lm), ar = w1 * rc + w2 * (rp + rm);
-        const C b = pp - pm, bl = lp - lm, br = rp - rm;
-        const C sx = ar - al;
-        const C sy = w1 * b + w2 * (br + bl);
+        const double pm = p[-W3], pp = p[W3];
+        const double lm = p[-W3 - 1], lc = p[-1], lp = p[W3 - 1];
+        const double rm = p[-W3 + 1], rc = p[1], rp = p[W3 + 1];
+        const double al = w1 * lc + w2 * (lp + lm), ar = w1 * rc + w2 * (rp + rm);
+        const double b = pp - pm, bl = lp - lm, br = rp - rm;
+        const double sx = ar - al;
+        const double sy = w1 * b + w2 * (br + bl);
         act.row(L, row_wall<C, WALL>(L, y), y, x, active, f, rho, p[0], sx, sy);
     }
 }

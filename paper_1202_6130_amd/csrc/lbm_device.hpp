@@ -297,8 +297,21 @@ __device__ inline void decode_row(const typename Codec<S>::Raw r[Q], C f[Q], C r
     for (int i = 0; i < Q; ++i) f[i] = Codec<S>::template decode<C>(r[i], i, rho_ref);
 }
 
+// Mass of a node's populations (eq. M0).  In binary64 arithmetic the nine
+// populations are summed in the order below.  In binary32 arithmetic they are
+// summed in binary64 (exact: the nine binary32 values span far fewer than the
+// 29 extra bits) and the density is that exact mass rounded once: the same
+// value whatever the order of the populations, so a mirror-symmetric state
+// keeps mirror-symmetric densities.  mass_in returns the sum in binary64.
+template <class C> __device__ inline double mass_in(const C f[Q]) {
+    double d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = double(f[i]);
+    return (((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]))) + d[8];
+}
 template <class C> __device__ inline C density(const C f[Q]) {
-    return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    if constexpr (sizeof(C) == 4) return C(mass_in<C>(f));
+    else return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
 }
 
 // Pseudo-potential of the fluid-fluid force.
@@ -335,13 +348,17 @@ template <class C> __device__ inline C recip(C v);
 template <> __device__ inline float recip<float>(float v) { return __builtin_amdgcn_rcpf(v); }
 template <> __device__ inline double recip<double>(double v) { return 1.0 / v; }
 
-// Everything the collision needs at one node.
+// Everything the collision needs at one node.  The binary64 members carry
+// the node's momentum budget in binary32 arithmetic (below); in binary64
+// arithmetic they equal the members of type C.
 template <class C> struct NodeState {
     C rho, inv_rho;
     C jx, jy;                      // momentum j = sum_i f_i c_i (pre-force)
     C ux, uy;                      // u = j / rho
     C Fx, Fy;                      // total force density
     C jsx, jsy;                    // rho u* = j + F, rounded once
+    double m;                      // mass of the incoming populations (exact in binary32 arithmetic)
+    double jxd, jyd, jsxd, jsyd;   // j and j + F in binary64
 };
 
 // rho u* = j + F with F = F_FF + F_LR + phi^eps [rho (U - u) - F_FF] + F_ext
@@ -349,16 +366,19 @@ template <class C> struct NodeState {
 // as (1 - phi^eps)(j + F_FF) + phi^eps rho U + F_LR + F_ext and formed in
 // binary64 whatever the storage: near a wall F_FF and F_LR reach 0.1-0.2
 // while a driving force is ~1e-6, and binary32 sums of those terms lose the
-// driving force to a rounding that repeats every step.
+// driving force to a rounding that repeats every step.  sx, sy are the
+// neighbour sums of psi (binary64).  Reads s.m, s.jxd, s.jyd; sets the rest.
 template <class C>
-__device__ inline void momentum_after_force(NodeState<C> &s, C psi_c, C sx, C sy, C phie, C Sx, C Sy, C G,
+__device__ inline void momentum_after_force(NodeState<C> &s, C psi_c, double sx, double sy, C phie, C Sx, C Sy, C G,
                                             C Ux, C Uy, C Fxe, C Fye) {
-    const double r = double(s.rho), ph = double(phie), om = 1.0 - ph;
+    const double r = s.m, ph = double(phie), om = 1.0 - ph;
     const double gp = -double(G) * double(psi_c);
-    const double ffx = gp * double(sx), ffy = gp * double(sy);
-    const double jx = double(s.jx), jy = double(s.jy);
+    const double ffx = gp * sx, ffy = gp * sy;
+    const double jx = s.jxd, jy = s.jyd;
     const double jsx = om * (jx + ffx) + ((ph * (r * double(Ux)) + r * double(Sx)) + double(Fxe));
     const double jsy = om * (jy + ffy) + ((ph * (r * double(Uy)) + r * double(Sy)) + double(Fye));
+    s.jsxd = jsx;
+    s.jsyd = jsy;
     s.jsx = C(jsx);
     s.jsy = C(jsy);
     s.Fx = C(jsx - jx);
@@ -366,16 +386,32 @@ __device__ inline void momentum_after_force(NodeState<C> &s, C psi_c, C sx, C sy
 }
 
 // Forces of one node (eqs. force_SC, force_SC_FS, wall_shift) given the
-// neighbour sums of psi.
+// neighbour sums of psi, formed in binary64:
 //   sx = sum_i w_i psi(x+c_i) c_ix,  sy = sum_i w_i psi(x+c_i) c_iy
+// The momentum (eq. M1) is a sum of differences of opposite populations, in
+// binary64 for binary32 arithmetic (exact there).
 template <class C>
-__device__ inline NodeState<C> node_forces(const C f[Q], C rho, C psi_c, C sx, C sy, C phie,
+__device__ inline NodeState<C> node_forces(const C f[Q], C rho, C psi_c, double sx, double sy, C phie,
                                            C Sx, C Sy, C G, C Ux, C Uy, C Fxe, C Fye) {
     NodeState<C> s;
     s.rho = rho;
     s.inv_rho = recip<C>(rho);
-    s.jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-    s.jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    if constexpr (sizeof(C) == 4) {
+        double d[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = double(f[i]);
+        s.m = (((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]))) + d[8];
+        s.jxd = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+        s.jyd = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
+        s.jx = C(s.jxd);
+        s.jy = C(s.jyd);
+    } else {
+        s.m = double(rho);
+        s.jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+        s.jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+        s.jxd = double(s.jx);
+        s.jyd = double(s.jy);
+    }
     s.ux = s.jx * s.inv_rho;
     s.uy = s.jy * s.inv_rho;
     // long-range wall force rho S (S precomputed from the static psi_FS);
@@ -391,8 +427,7 @@ __device__ inline NodeState<C> node_forces(const C f[Q], C rho, C psi_c, C sx, C
 // sum_i feq_i c_i = m exactly in real arithmetic with the constants above.
 // The small velocity terms are formed on their own and added to w_i rho
 // last: folded into (1 - 1.5 u^2) first, they were rounded at the spacing of
-// numbers near 1, the same way at a steady node in every step, and in binary32
-// that bias accumulated (mass drift 3e-5 after 20000 steps of a resting drop).
+// numbers near 1, the same way at a steady node in every step.
 template <class C> __device__ inline void equilibrium(C rho, C inv_rho, C mx, C my, C feq[Q]) {
     using K = LatConst<C>;
     const C ux = mx * inv_rho, uy = my * inv_rho;
@@ -415,10 +450,20 @@ template <class C> __device__ inline void equilibrium(C rho, C inv_rho, C mx, C 
 }
 
 // The rest population closes the mass balance: the collision conserves mass
-// exactly in real arithmetic, and taking f'_0 = rho - sum_{i>0} f'_i keeps the
-// rounding of the nine products from adding up to a steady per-node bias.
-template <class C> __device__ inline void close_mass(C f[Q], C rho) {
-    f[0] = rho - (((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8])));
+// exactly in real arithmetic, so f'_0 = rho - sum_{i>0} f'_i.  In binary32
+// storage the balance is struck in binary64 against the exact incoming mass
+// m and the eight outgoing populations as they will be stored, then rounded
+// once: the stored populations of a node sum to its incoming mass up to the
+// rounding of f'_0 alone.
+template <class C> __device__ inline void close_mass(C f[Q], C rho, double m) {
+    if constexpr (sizeof(C) == 4) {
+        const double s = ((double(f[1]) + double(f[3])) + (double(f[2]) + double(f[4]))) +
+                         ((double(f[5]) + double(f[7])) + (double(f[6]) + double(f[8])));
+        f[0] = C(m - s);
+    } else {
+        (void)m;
+        f[0] = rho - (((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8])));
+    }
 }
 
 // EDM-BGK collision: f' = f - (f - feq(u))/tau + feq(u*) - feq(u)
@@ -446,25 +491,54 @@ template <class C, class VS> __device__ inline void project_neq(C g[VS::Q]) {
     }
 }
 
+// Binary32 arithmetic evaluates the collision in binary64 from the node's
+// exact mass, binary64 momenta and the binary32 reciprocal of the density
+// (which enters only the second-order terms) and rounds every outgoing
+// population once.  In binary32 the rounding of j + F before the
+// equilibrium's momentum terms, and the roundings inside the equilibrium,
+// repeat identically at a quasi-steady node in every step; on the 1024 x 512
+// sessile drop they (with the neighbour sums and the mass closure) moved the
+// interface by ~1e-4 nodes by t = 5000.
 template <class C> __device__ inline void collide(C f[Q], const NodeState<C> &s, C omega, int projected) {
-    C fs[Q];
-    equilibrium<C>(s.rho, s.inv_rho, s.jsx, s.jsy, fs);
-    if (omega == C(1)) {
-        // tau = 1: the factor (1 - 1/tau) is exactly zero, f' = feq(u*)
+    if constexpr (sizeof(C) == 4) {
+        const double m = s.m, inv = double(s.inv_rho);
+        double fs[Q];
+        equilibrium<double>(m, inv, s.jsxd, s.jsyd, fs);
+        if (omega == C(1)) {
+            // tau = 1: the factor (1 - 1/tau) is exactly zero, f' = feq(u*)
 #pragma unroll
-        for (int i = 0; i < Q; ++i) f[i] = fs[i];
-        close_mass<C>(f, s.rho);
+            for (int i = 0; i < Q; ++i) f[i] = C(fs[i]);
+        } else {
+            double fu[Q];
+            equilibrium<double>(m, inv, s.jxd, s.jyd, fu);
+            const double keep = 1.0 - double(omega);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) fu[i] = double(f[i]) - fu[i];
+            if (projected) project_neq<double, VelSet<9>>(fu);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) f[i] = C(keep * fu[i] + fs[i]);
+        }
+        close_mass<C>(f, s.rho, m);
         return;
+    } else {
+        C fs[Q];
+        equilibrium<C>(s.rho, s.inv_rho, s.jsx, s.jsy, fs);
+        if (omega == C(1)) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) f[i] = fs[i];
+            close_mass<C>(f, s.rho, s.m);
+            return;
+        }
+        C fu[Q];
+        equilibrium<C>(s.rho, s.inv_rho, s.jx, s.jy, fu);
+        const C keep = C(1) - omega;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) fu[i] = f[i] - fu[i];
+        if (projected) project_neq<C, VelSet<9>>(fu);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = keep * fu[i] + fs[i];
+        close_mass<C>(f, s.rho, s.m);
     }
-    C fu[Q];
-    equilibrium<C>(s.rho, s.inv_rho, s.jx, s.jy, fu);
-    const C keep = C(1) - omega;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) fu[i] = f[i] - fu[i];
-    if (projected) project_neq<C, VelSet<9>>(fu);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = keep * fu[i] + fs[i];
-    close_mass<C>(f, s.rho);
 }
 
 // Wall terms of one row (WALL_ROW: per-row scalars) or node (WALL_NODE).
