@@ -21,8 +21,9 @@
  *
  * Conventions for every entry point
  *  - Status: 0 = LBM_OK, negative = error.  The library never aborts and never
- *    throws across the ABI; lbm_last_error() returns the calling thread's last
- *    message.
+ *    throws across the ABI; lbm_last_error(ctx) returns the message of the
+ *    last failed call on that context, lbm_last_error(NULL) the calling
+ *    thread's last message (any call, with or without a context).
  *  - Host arrays are float64, row-major [ny][nx] (index y*nx + x), read or
  *    written during the call only and never retained.
  *  - Device memory: the caller owns one workspace (lbm_workspace_bytes) and
@@ -145,11 +146,20 @@ typedef struct lbm_ctx lbm_ctx;
  * U_wall = F_ext = 0, wall_width = 2, core_range = 1, tail_range = 3,
  * rho_ref = 1, slab_rows = 8, storage F32, wall NONE, diag_interval 0,
  * lattice D2Q9, psi EXP, eos = the paper's parameters, collision BGK,
- * filter_core 5, filter_wall 22. */
+ * filter_core 5, filter_wall 22.
+ * Paper: the model parameters of Sec. II (tau of eq. BE-BGK; G of
+ * eq. force_SC; G_R, G_A, eps of eqs. pseudopotential and wall_shift; the
+ * EOS of Sec. II.B; the filter passes 5 and 22 of Appendix A).  The numeric
+ * defaults of the D2Q9 fluid are not the paper's (it uses D2Q21 with the
+ * EOS pseudo-potential). */
 lbm_status lbm_params_default(lbm_params *p);
 
-/* Last error message of the calling thread ("" if none).  Never NULL. */
-const char *lbm_last_error(void);
+/* Error message ("" if none; never NULL).  ctx != NULL: the message of the
+ * last failed call on that context (kept until the next failure on it, valid
+ * until lbm_destroy).  ctx == NULL: the calling thread's last message, for
+ * calls that fail before a context exists (lbm_create, batch calls).
+ * Paper: none (error reporting of the interface). */
+const char *lbm_last_error(const lbm_ctx *ctx);
 
 /* Measurement utility, no lattice involved: copies `bytes` from device
  * memory src to device memory dst on `stream` (a hipStream_t, NULL for the
@@ -158,31 +168,46 @@ const char *lbm_last_error(void);
  * step kernels' HBM roofline (each of them reads and writes every stored
  * population once per step, as a copy does).  src, dst and bytes must be
  * multiples of 16 and the ranges must not overlap (else LBM_EINVAL); the
- * caller owns both buffers.  Asynchronous: returns after the launch. */
+ * caller owns both buffers.  Asynchronous: returns after the launch.
+ * Paper: none (a bandwidth reference for the measurements). */
 lbm_status lbm_device_copy(const void *src, void *dst, size_t bytes, void *stream);
 
-/* Device bytes a context with these parameters needs (written to *bytes). */
+/* Device bytes a context with these parameters needs (written to *bytes).
+ * Paper: none (memory layout of this library). */
 lbm_status lbm_workspace_bytes(const lbm_params *p, size_t *bytes);
 
 /* Creates a context and sets f = feq(rho0, u0) at every node (post-streaming
  * populations at t = 0).
  *  rho0        host [ny][nx], required, every value > 0 and finite.
- *  ux0, uy0    host [ny][nx] or both NULL (fluid at rest).
- *  wall_fields host [3][ny][nx] = (phi, psiR, psiA) for LBM_WALL_FIELDS, else
- *              must be NULL.  phi in [0, 1].
+ *  u0          host [2][ny][nx] = (u_x, u_y), or NULL (fluid at rest).
+ *  wall_fields host [3][ny][nx] = (phi, psiR, psiA) for LBM_WALL_FIELDS, or
+ *              [2][ny][nx] = (solid H, held boundary B) for LBM_WALL_MASK;
+ *              else must be NULL.  phi in [0, 1]; H, B in {0, 1}.
  *  workspace   device pointer, 256-byte aligned, >= lbm_workspace_bytes.
  *  stream      hipStream_t or NULL.
- * Synchronises.  On error *out is NULL and nothing is retained. */
-lbm_status lbm_create(const lbm_params *p, const double *rho0, const double *ux0,
-                      const double *uy0, const double *wall_fields,
-                      void *workspace, size_t workspace_bytes, void *stream,
-                      lbm_ctx **out);
+ * Synchronises.  On error *out is NULL and nothing is retained.
+ * Paper: the lattice and parameters of Sec. II; the wall functions of
+ * Appendix A (eq. iteration for MASK).  The initial state f = feq(rho0, u0)
+ * (eq. f2 at equilibrium) is not in the paper. */
+lbm_status lbm_create(const lbm_params *p, const double *rho0, const double *u0,
+                      const double *wall_fields, void *workspace,
+                      size_t workspace_bytes, void *stream, lbm_ctx **out);
 
 /* Advances nsteps >= 0 time steps (the update above).  With diag_interval K
  * > 0, a diagnostic pass (totals, velocity residual against the previous pass,
  * non-finite count) runs after every step whose index is a multiple of K.
- * Enqueues only. */
-lbm_status lbm_step(lbm_ctx *c, int64_t nsteps);
+ * residual_out == NULL: enqueues only.
+ * residual_out != NULL: synchronises after every diagnostic pass, returns
+ * LBM_EUNSTABLE at the first pass that counts a non-finite density or
+ * velocity (the steps after it are not taken), and writes the residual of
+ * the latest pass (as out[4] of lbm_diagnostics) to *residual_out.  With
+ * K = 0 a pass runs after the last step (unless that step already had one);
+ * with K > 0 only the scheduled passes run, and *residual_out is +inf when
+ * the lattice has had none yet.
+ * Paper: Sec. II (streaming, eqs. force_SC, force_SC_FS, wall_shift,
+ * BE-BGK with the exact difference method); the residual is not in the
+ * paper (a steady-state criterion of this interface). */
+lbm_status lbm_step(lbm_ctx *c, int64_t nsteps, double *residual_out);
 
 /* Runs a diagnostic pass now (unless the last step already had one) and
  * returns, synchronising:
@@ -192,13 +217,17 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps);
  *         t' = the previous pass (+inf if there was none), u = reported
  *         velocity (j + F/2)/rho
  *  out[5] number of nodes with non-finite rho or u
- * Returns LBM_EUNSTABLE if out[5] > 0. */
+ * Returns LBM_EUNSTABLE if out[5] > 0.
+ * Paper: eqs. M0 and M1 for the totals; the residual and the non-finite
+ * count are not in the paper. */
 lbm_status lbm_diagnostics(lbm_ctx *c, double out[6]);
 
 /* Macroscopic fields at the current time (eqs. M0, M1): rho, and the reported
  * velocity u = (j + F/2)/rho (average of the pre- and post-force velocities
  * of the exact difference method).  Any output may be NULL; totals =
- * (sum rho, sum j_x, sum j_y), accumulated in FP64.  Synchronises. */
+ * (sum rho, sum j_x, sum j_y), accumulated in FP64.  Synchronises.
+ * Paper: eqs. M0, M1; the half-force velocity of the exact difference
+ * method (Sec. II.B). */
 lbm_status lbm_moments(lbm_ctx *c, double *rho, double *ux, double *uy,
                        double totals[3]);
 
@@ -209,7 +238,8 @@ lbm_status lbm_moments(lbm_ctx *c, double *rho, double *ux, double *uy,
  * not wrap in y), algebraic start then Gauss-Newton on the geometric
  * distance; theta = acos(1 - h/R) with h = yc + R - y_ref.
  * out = (theta in degrees, R, xc, yc).  LBM_ENOFIT if fewer than 16 points or
- * the fit is degenerate.  Synchronises. */
+ * the fit is degenerate.  Synchronises.
+ * Paper: Sec. III.B (circle fit of the rho isoline, theta = acos(1 - h/R)). */
 lbm_status lbm_contact_angle(lbm_ctx *c, double iso, double y_ref, double out[4]);
 
 /* Dynamic contact angles of a moving drop (Sec. III.C): the rho = iso
@@ -226,7 +256,9 @@ lbm_status lbm_contact_angle(lbm_ctx *c, double iso, double y_ref, double out[4]
  * The capillary number of the paper is Ca = U mu_L / gamma with mu_L =
  * out[7] * theta * (tau - 1/2) and the caller's surface tension gamma.
  * Returns LBM_ENOFIT when a fit has too few points or degenerates.
- * Synchronises. */
+ * Synchronises.
+ * Paper: Sec. III.C (advancing and receding angles of a driven drop, two
+ * circle fits, capillary number). */
 lbm_status lbm_dynamic_angles(lbm_ctx *c, double iso, double y_ref, double out[8]);
 
 /* Slip in a FLAT_SLAB channel (Sec. III.A): the x-averaged reported u_x(y)
@@ -234,25 +266,32 @@ lbm_status lbm_dynamic_angles(lbm_ctx *c, double iso, double y_ref, double out[8
  * and evaluated at the hydrodynamic boundary y_w, phi(y_w) = 0.01, of both
  * walls.  out = (b, u_s, c2): slip length u_s / |du/dy|(y_w), slip velocity
  * and the fit's second derivative.  LBM_EINVAL unless wall_kind is
- * FLAT_SLAB.  Synchronises. */
+ * FLAT_SLAB.  Synchronises.
+ * Paper: Sec. III.A (slip against the Poiseuille profile, hydrodynamic
+ * boundary where phi = 0.01). */
 lbm_status lbm_slip_length(lbm_ctx *c, double out[3]);
 
 /* Populations at the current time, post-streaming, as host float64
  * [Q][ny][nx] (Q = 9 or 21, velocity order of the oracle tables: D2Q9 as
  * above; D2Q21 continues with (2,0) (0,2) (-2,0) (0,-2), (2,2) (-2,2)
- * (-2,-2) (2,-2), (3,0) (0,3) (-3,0) (0,-3)).  Synchronises. */
+ * (-2,-2) (2,-2), (3,0) (0,3) (-3,0) (0,-3)).  Synchronises.
+ * Paper: the populations f_i of Sec. II.A (velocity sets of Tab. I).  Reading
+ * them out (checkpoints, fault injection) is not in the paper. */
 lbm_status lbm_get_state(lbm_ctx *c, double *f);
 
 /* Replaces the populations (same layout as lbm_get_state) and the step index;
  * forgets the previous diagnostic pass.  Values are rounded to the storage
- * type.  Synchronises. */
+ * type.  Synchronises.
+ * Paper: the populations f_i of Sec. II.A; restoring them is not in the
+ * paper. */
 lbm_status lbm_set_state(lbm_ctx *c, const double *f, int64_t step_index);
 
-/* Current step index. */
+/* Current step index (-1 for NULL).  Paper: the time t of Sec. II (dt = 1). */
 int64_t lbm_step_index(const lbm_ctx *c);
 
 /* Frees the host-side context; the workspace returns to the caller.  Waits
- * for the context's stream first.  NULL is accepted. */
+ * for the context's stream first.  NULL is accepted.  LBM_ESTATE while the
+ * context is attached to a batch.  Paper: none (resource handling). */
 lbm_status lbm_destroy(lbm_ctx *c);
 
 /* ------------------------------------------------------------------------
@@ -265,7 +304,8 @@ lbm_status lbm_destroy(lbm_ctx *c);
  * ------------------------------------------------------------------------ */
 
 /* Writes up to cap (waves, rows, strips) triples (any array may be NULL) and
- * returns the number of shapes. */
+ * returns the number of shapes.
+ * Paper: none (execution layout of the step of Sec. II; no effect on results). */
 int32_t lbm_tile_shapes(int32_t *waves, int32_t *rows, int32_t *strips, int32_t cap);
 
 /* Sets / returns the tile shape of a context (not one inside a batch:
@@ -276,7 +316,8 @@ int32_t lbm_tile_shapes(int32_t *waves, int32_t *rows, int32_t *strips, int32_t 
  *     (F32 storage only, else LBM_EINVAL);
  *  2  tiles of 16 waves x 1 row (58 x 10 output nodes), any storage and tau.
  * A new D2Q21 context starts with 1 where it applies and the lattice holds at
- * least 256 such segments, else with 2. */
+ * least 256 such segments, else with 2.
+ * Paper: none (execution layout of the step of Sec. II; no effect on results). */
 lbm_status lbm_set_tile_shape(lbm_ctx *c, int32_t shape);
 int32_t lbm_get_tile_shape(const lbm_ctx *c);
 
@@ -294,7 +335,9 @@ int32_t lbm_get_tile_shape(const lbm_ctx *c);
  * workgroup) triples (any array may be NULL) and returns the number of
  * variants.  lbm_set_two_step(c, -1) returns to single steps (the default);
  * another lattice or storage gives LBM_EINVAL, a batch lattice LBM_ESTATE.
- * lbm_get_two_step returns the variant, -1 when off, -2 for NULL. */
+ * lbm_get_two_step returns the variant, -1 when off, -2 for NULL.
+ * Paper: Sec. II.A (streaming) and eq. BE-BGK, applied twice per launch;
+ * the temporal blocking itself is not in the paper. */
 int32_t lbm_two_step_variants(int32_t *strips, int32_t *rows, int32_t *waves, int32_t cap);
 lbm_status lbm_set_two_step(lbm_ctx *c, int32_t variant);
 int32_t lbm_get_two_step(const lbm_ctx *c);
@@ -307,7 +350,8 @@ int32_t lbm_get_two_step(const lbm_ctx *c);
  * candidate.
  * The candidates are the lbm_tile_shapes(...) shapes, for D2Q21 the three
  * step variants above (ms_out gets INFINITY for variant 1 where it does not
- * apply).  Synchronises. */
+ * apply).  Synchronises.
+ * Paper: none (autotuning of the execution layout). */
 lbm_status lbm_tune(lbm_ctx *c, int32_t steps, int32_t *shape_out, double *ms_out);
 
 /* Autotuner between single steps (with the context's tile shape, so call
@@ -318,7 +362,8 @@ lbm_status lbm_tune(lbm_ctx *c, int32_t steps, int32_t *shape_out, double *ms_ou
  * lbm_two_step_variants(...) + 1 entries: per-step medians of the variants,
  * then of single steps; INFINITY for variants that do not apply to the
  * lattice (then only single steps are timed).  The lattice advances by
- * 6 * steps + 2 steps per timed candidate.  Synchronises. */
+ * 6 * steps + 2 steps per timed candidate.  Synchronises.
+ * Paper: none (autotuning of the execution layout). */
 lbm_status lbm_tune_two_step(lbm_ctx *c, int32_t steps, int32_t *variant_out, double *ms_out);
 
 /* ------------------------------------------------------------------------
@@ -331,36 +376,41 @@ lbm_status lbm_tune_two_step(lbm_ctx *c, int32_t steps, int32_t *variant_out, do
  * ------------------------------------------------------------------------ */
 typedef struct lbm_batch lbm_batch;
 
-/* Device bytes for a batch of n lattices (written to *bytes). */
+/* Device bytes for a batch of n lattices (written to *bytes).
+ * Paper: none (memory layout of this library). */
 lbm_status lbm_batch_workspace_bytes(const lbm_params *ps, int32_t n, size_t *bytes);
 
-/* Creates a batch.  ps[k], rho0s[k], ux0s[k], uy0s[k] describe lattice k as in
- * lbm_create (wall kinds NONE or FLAT_SLAB; ux0s/uy0s may be NULL or hold NULL
- * entries).  seg_rows = rows per wave segment for every lattice (0 = the
- * library's choice).  Synchronises. */
+/* Creates a batch.  ps[k], rho0s[k], u0s[k] describe lattice k as in
+ * lbm_create (wall kinds NONE or FLAT_SLAB; u0s may be NULL or hold NULL
+ * entries, each else [2][ny][nx]).  seg_rows = rows per wave segment for
+ * every lattice (0 = the library's choice).  Synchronises.
+ * Paper: each lattice as lbm_create; batching is not in the paper. */
 lbm_status lbm_batch_create(const lbm_params *ps, int32_t n,
-                            const double *const *rho0s, const double *const *ux0s,
-                            const double *const *uy0s, int32_t seg_rows,
-                            void *workspace, size_t workspace_bytes, void *stream,
-                            lbm_batch **out);
+                            const double *const *rho0s, const double *const *u0s,
+                            int32_t seg_rows, void *workspace, size_t workspace_bytes,
+                            void *stream, lbm_batch **out);
 
 /* Advances every lattice of the batch by nsteps steps.  chunk > 0: the steps
  * are recorded once into a HIP graph of `chunk` steps (even) and replayed;
- * chunk = 0: plain launches.  Enqueues only. */
+ * chunk = 0: plain launches.  Enqueues only.
+ * Paper: Sec. II for each lattice; batching is not in the paper. */
 lbm_status lbm_batch_step(lbm_batch *b, int64_t nsteps, int32_t chunk);
 
 /* Per-lattice diagnostics, as lbm_diagnostics, for every lattice: out[6*k ..]
  * (out[0] is that lattice's step index; the residual compares with the
- * lattice's previous diagnostic pass, +inf if it has none).  Synchronises. */
+ * lattice's previous diagnostic pass, +inf if it has none).  Synchronises.
+ * Paper: eqs. M0, M1 per lattice; the residual is not in the paper. */
 lbm_status lbm_batch_diagnostics(lbm_batch *b, double *out);
 
 /* A context view of lattice k (valid until lbm_batch_destroy) for
  * lbm_moments / lbm_contact_angle / lbm_slip_length / lbm_get_state /
  * lbm_diagnostics.  lbm_step and lbm_set_state on a view return LBM_ESTATE;
- * lbm_destroy on a view is a no-op. */
+ * lbm_destroy on a view is a no-op.
+ * Paper: none (access to a lattice of a batch). */
 lbm_ctx *lbm_batch_lattice(lbm_batch *b, int32_t k);
 
-/* Device bytes of the tables for lbm_batch_attach over these contexts. */
+/* Device bytes of the tables for lbm_batch_attach over these contexts.
+ * Paper: none (memory layout of this library). */
 lbm_status lbm_batch_attach_bytes(lbm_ctx *const *ctxs, int32_t n, size_t *bytes);
 
 /* Groups n existing contexts (from lbm_create: F32 storage, wall kind NONE or
@@ -370,13 +420,15 @@ lbm_status lbm_batch_attach_bytes(lbm_ctx *const *ctxs, int32_t n, size_t *bytes
  * context keeps its own.  While attached, lbm_step, lbm_set_state and
  * lbm_destroy on a context return LBM_ESTATE; the read-out calls remain
  * valid.  This is the primitive of continuous batching: when membership
- * changes, destroy the batch and attach the new set. */
+ * changes, destroy the batch and attach the new set.
+ * Paper: Sec. II for each lattice; continuous batching is not in the paper. */
 lbm_status lbm_batch_attach(lbm_ctx *const *ctxs, int32_t n, void *workspace,
                             size_t workspace_bytes, void *stream, lbm_batch **out);
 
 /* Per-lattice tile shapes of a batch (shapes[k] for lattice k; NULL sets
  * shape 0 everywhere).  A batch starts with each context's own shape (0 for
- * lbm_batch_create).  Recorded graphs are dropped.  Synchronises. */
+ * lbm_batch_create).  Recorded graphs are dropped.  Synchronises.
+ * Paper: none (execution layout; no effect on results). */
 lbm_status lbm_batch_set_tile_shapes(lbm_batch *b, const int32_t *shapes);
 lbm_status lbm_batch_get_tile_shapes(const lbm_batch *b, int32_t *shapes);
 
@@ -388,7 +440,8 @@ lbm_status lbm_batch_get_tile_shapes(const lbm_batch *b, int32_t *shapes);
  * uniform, and keeps the fastest candidate.  shapes_out (nullable, n entries)
  * gets the choice; ms_out (nullable, lbm_tile_shapes() + 1 entries) the
  * median step times of the uniform candidates and of the mixed one (NaN when
- * not timed).  The tuning steps are ordinary time steps.  Synchronises. */
+ * not timed).  The tuning steps are ordinary time steps.  Synchronises.
+ * Paper: none (autotuning of the execution layout). */
 lbm_status lbm_batch_tune(lbm_batch *b, int32_t steps, int32_t *shapes_out, double *ms_out);
 
 /* Two time steps per launch for a whole batch (the single-lattice
@@ -402,14 +455,16 @@ lbm_status lbm_batch_tune(lbm_batch *b, int32_t steps, int32_t *shapes_out, doub
  * blocks of `steps` pairs each), keeps the fastest (variant_out, nullable)
  * and writes lbm_two_step_variants(...) + 1 per-step medians to ms_out
  * (nullable): the variants, then single steps.  Every lattice advances by
- * 6 * steps + 2 steps per candidate.  Synchronises. */
+ * 6 * steps + 2 steps per candidate.  Synchronises.
+ * Paper: Sec. II applied twice per launch; not in the paper as such. */
 lbm_status lbm_batch_set_two_step(lbm_batch *b, int32_t variant);
 int32_t lbm_batch_get_two_step(const lbm_batch *b);
 lbm_status lbm_batch_tune_two_step(lbm_batch *b, int32_t steps, int32_t *variant_out, double *ms_out);
 
 /* Frees the host-side batch (waits for its stream).  A batch from
  * lbm_batch_create frees its contexts; an attached batch hands its contexts
- * back with their state, step index and tile shape.  NULL is accepted. */
+ * back with their state, step index and tile shape.  NULL is accepted.
+ * Paper: none (resource handling). */
 lbm_status lbm_batch_destroy(lbm_batch *b);
 
 #ifdef __cplusplus

@@ -26,14 +26,18 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 
 def build(verbose=False, extra=()):
     os.makedirs(LIBDIR, exist_ok=True)
-    objs = []
+    objs, procs = [], []
+    # the four translation units compile concurrently
     for src in ("kernels.hip", "kernels_q21.hip", "copy.hip", "abi.cpp"):
         obj = os.path.join(LIBDIR, src + ".o")
         cmd = [HIPCC, *FLAGS, *extra, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(obj)
+    failed = [cmd for cmd, pr in procs if pr.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

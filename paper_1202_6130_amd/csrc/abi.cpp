@@ -19,6 +19,9 @@ using namespace lbmwet;
 namespace {
 
 thread_local std::string g_err;
+// Message slot of the context whose entry point is running on this thread
+// (set by CtxScope), so that an error is also kept with its context.
+thread_local std::string *g_ctx_err = nullptr;
 
 lbm_status fail(lbm_status st, const char *fmt, ...) {
     char buf[512];
@@ -27,6 +30,7 @@ lbm_status fail(lbm_status st, const char *fmt, ...) {
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     g_err = buf;
+    if (g_ctx_err) *g_ctx_err = buf;
     return st;
 }
 
@@ -208,6 +212,7 @@ bool solve3(double A[3][3], double b[3], double z[3]) {
 }  // namespace
 
 struct lbm_ctx {
+    std::string err;               // last error message of a call on this context
     lbm_params p;
     Layout lay;
     hipStream_t stream;
@@ -256,6 +261,14 @@ struct lbm_batch {
 
 namespace {
 
+// Routes the error messages of one entry point into its context as well
+// (nested entry points restore the outer context's slot on return).
+struct CtxScope {
+    std::string *prev;
+    explicit CtxScope(const lbm_ctx *c) : prev(g_ctx_err) { g_ctx_err = c ? &const_cast<lbm_ctx *>(c)->err : nullptr; }
+    ~CtxScope() { g_ctx_err = prev; }
+};
+
 lbm_status launch_ok(hipError_t e, const char *what) {
     if (e != hipSuccess) return fail(LBM_EDEVICE, "%s launch failed: %s", what, hipGetErrorString(e));
     return LBM_OK;
@@ -283,7 +296,7 @@ lbm_status sync(lbm_ctx *c) {
 }
 
 // Builds a context inside `ws` (layout already checked).  Synchronises.
-lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const double *ux0, const double *uy0,
+lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const double *u0,
                     const double *wall_fields, char *ws, hipStream_t stream) {
     c->p = *p;
     c->lay = make_layout(*p);
@@ -377,9 +390,8 @@ lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const d
     HIPCHK(hipStreamSynchronize(stream));   // staging is reused below
     HIPCHK(hipMemcpyAsync(stage, rho0, N * sizeof(double), hipMemcpyHostToDevice, stream));
     const double *dux = nullptr, *duy = nullptr;
-    if (ux0 && uy0) {
-        HIPCHK(hipMemcpyAsync(stage + N, ux0, N * sizeof(double), hipMemcpyHostToDevice, stream));
-        HIPCHK(hipMemcpyAsync(stage + 2 * N, uy0, N * sizeof(double), hipMemcpyHostToDevice, stream));
+    if (u0) {
+        HIPCHK(hipMemcpyAsync(stage + N, u0, 2 * N * sizeof(double), hipMemcpyHostToDevice, stream));
         dux = stage + N;
         duy = stage + 2 * N;
     }
@@ -389,16 +401,15 @@ lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const d
     return LBM_OK;
 }
 
-lbm_status check_host_fields(const lbm_params *p, const double *rho0, const double *ux0, const double *uy0,
+lbm_status check_host_fields(const lbm_params *p, const double *rho0, const double *u0,
                              const double *wall_fields) {
     const size_t N = size_t(p->nx) * p->ny;
     if (!rho0) return fail(LBM_EINVAL, "rho0 is NULL");
-    if ((ux0 == nullptr) != (uy0 == nullptr)) return fail(LBM_EINVAL, "ux0 and uy0 must both be given or both NULL");
     for (size_t i = 0; i < N; ++i)
         if (!(rho0[i] > 0) || !isfinite(rho0[i])) return fail(LBM_EINVAL, "rho0[%zu] must be finite and > 0", i);
-    if (ux0)
-        for (size_t i = 0; i < N; ++i)
-            if (!isfinite(ux0[i]) || !isfinite(uy0[i])) return fail(LBM_EINVAL, "non-finite u0 at %zu", i);
+    if (u0)
+        for (size_t i = 0; i < 2 * N; ++i)
+            if (!isfinite(u0[i])) return fail(LBM_EINVAL, "non-finite u0 at %zu", i);
     if (p->wall_kind == LBM_WALL_FIELDS) {
         if (!wall_fields) return fail(LBM_EINVAL, "wall_fields required for LBM_WALL_FIELDS");
         for (size_t i = 0; i < 3 * N; ++i)
@@ -443,7 +454,7 @@ lbm_status lbm_params_default(lbm_params *p) {
     return LBM_OK;
 }
 
-const char *lbm_last_error(void) { return g_err.c_str(); }
+const char *lbm_last_error(const lbm_ctx *c) { return c ? c->err.c_str() : g_err.c_str(); }
 
 lbm_status lbm_device_copy(const void *src, void *dst, size_t bytes, void *stream) {
     if (!src || !dst) return fail(LBM_EINVAL, "NULL pointer");
@@ -462,13 +473,12 @@ lbm_status lbm_workspace_bytes(const lbm_params *p, size_t *bytes) {
     return LBM_OK;
 }
 
-lbm_status lbm_create(const lbm_params *p, const double *rho0, const double *ux0, const double *uy0,
-                      const double *wall_fields, void *workspace, size_t workspace_bytes, void *stream,
-                      lbm_ctx **out) {
+lbm_status lbm_create(const lbm_params *p, const double *rho0, const double *u0, const double *wall_fields,
+                      void *workspace, size_t workspace_bytes, void *stream, lbm_ctx **out) {
     if (!out) return fail(LBM_EINVAL, "out is NULL");
     *out = nullptr;
     TRY(validate(p));
-    TRY(check_host_fields(p, rho0, ux0, uy0, wall_fields));
+    TRY(check_host_fields(p, rho0, u0, wall_fields));
     const Layout Y = make_layout(*p);
     if (!workspace) return fail(LBM_EINVAL, "workspace is NULL");
     if (uintptr_t(workspace) % kAlign) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
@@ -476,7 +486,7 @@ lbm_status lbm_create(const lbm_params *p, const double *rho0, const double *ux0
         return fail(LBM_ENOMEM, "workspace too small: %zu < %zu bytes", workspace_bytes, Y.total);
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(LBM_ENOMEM, "host allocation failed");
-    lbm_status st = init_ctx(c, p, rho0, ux0, uy0, wall_fields, (char *)workspace, (hipStream_t)stream);
+    lbm_status st = init_ctx(c, p, rho0, u0, wall_fields, (char *)workspace, (hipStream_t)stream);
     if (st != LBM_OK) {
         delete c;
         return st;
@@ -485,12 +495,42 @@ lbm_status lbm_create(const lbm_params *p, const double *rho0, const double *ux0
     return LBM_OK;
 }
 
-lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
+// A diagnostic pass after the step just taken (every K-th step index).
+static lbm_status diag_after_step(lbm_ctx *c) {
+    TRY(run_diag(c, 0, c->have_prev ? 1 : 0, 1, 0));
+    c->last_diag_compared = c->have_prev;
+    c->have_prev = true;
+    c->last_diag_step = *c->step;
+    return LBM_OK;
+}
+
+// Reads the last diagnostic pass (synchronising) into out[6] as
+// lbm_diagnostics reports it; LBM_EUNSTABLE when it counted non-finite nodes.
+static lbm_status read_diag(lbm_ctx *c, double out[6]) {
+    double r[8];
+    HIPCHK(hipMemcpyAsync(r, c->d_small, sizeof r, hipMemcpyDeviceToHost, c->stream));
+    TRY(sync(c));
+    out[0] = double(c->last_diag_step);
+    out[1] = r[0];
+    out[2] = r[1];
+    out[3] = r[2];
+    if (!c->last_diag_compared) out[4] = INFINITY;
+    else out[4] = r[4] > 0 ? r[3] / r[4] : (r[3] > 0 ? INFINITY : 0.0);
+    out[5] = r[5];
+    if (r[5] > 0) return fail(LBM_EUNSTABLE, "%.0f nodes with non-finite density or velocity at step %lld", r[5],
+                              (long long)c->last_diag_step);
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx *c, int64_t nsteps, double *residual_out) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    CtxScope scope(c);
     if (c->view) return fail(LBM_ESTATE, "lbm_step on a batch lattice view; use lbm_batch_step");
     if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
     const int ks = kernel_storage(c->p.storage);
     const int K = c->p.diag_interval;
+    double d[6];
+    bool checked = false;
     for (int64_t s = 0; s < nsteps;) {
         // two steps in one pass unless a diagnostic falls after the first
         const bool pair = c->pass2 >= 0 && nsteps - s >= 2 && !(K > 0 && (*c->step + 1) % K == 0);
@@ -504,10 +544,21 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
         *c->step += pair ? 2 : 1;
         s += pair ? 2 : 1;
         if (K > 0 && *c->step % K == 0) {
-            TRY(run_diag(c, 0, c->have_prev ? 1 : 0, 1, 0));
-            c->last_diag_compared = c->have_prev;
-            c->have_prev = true;
-            c->last_diag_step = *c->step;
+            TRY(diag_after_step(c));
+            if (residual_out) {
+                TRY(read_diag(c, d));          // stops at the first pass with non-finite values
+                *residual_out = d[4];
+                checked = true;
+            }
+        }
+    }
+    if (residual_out && !checked) {
+        if (K == 0 && c->last_diag_step != *c->step) TRY(diag_after_step(c));
+        if (c->last_diag_step < 0) {
+            *residual_out = INFINITY;          // K > 0 and no pass yet
+        } else {
+            TRY(read_diag(c, d));
+            *residual_out = d[4];
         }
     }
     return LBM_OK;
@@ -515,29 +566,14 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps) {
 
 lbm_status lbm_diagnostics(lbm_ctx *c, double out[6]) {
     if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
-    if (c->last_diag_step != *c->step) {
-        TRY(run_diag(c, 0, c->have_prev ? 1 : 0, 1, 0));
-        c->last_diag_compared = c->have_prev;
-        c->have_prev = true;
-        c->last_diag_step = *c->step;
-    }
-    double r[8];
-    HIPCHK(hipMemcpyAsync(r, c->d_small, sizeof r, hipMemcpyDeviceToHost, c->stream));
-    TRY(sync(c));
-    out[0] = double(*c->step);
-    out[1] = r[0];
-    out[2] = r[1];
-    out[3] = r[2];
-    if (!c->last_diag_compared) out[4] = INFINITY;
-    else out[4] = r[4] > 0 ? r[3] / r[4] : (r[3] > 0 ? INFINITY : 0.0);
-    out[5] = r[5];
-    if (r[5] > 0) return fail(LBM_EUNSTABLE, "%.0f nodes with non-finite density or velocity at step %lld", r[5],
-                              (long long)*c->step);
-    return LBM_OK;
+    CtxScope scope(c);
+    if (c->last_diag_step != *c->step) TRY(diag_after_step(c));
+    return read_diag(c, out);
 }
 
 lbm_status lbm_moments(lbm_ctx *c, double *rho, double *ux, double *uy, double totals[3]) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    CtxScope scope(c);
     TRY(run_diag(c, 1, 0, 0, 1));
     const size_t N = size_t(c->p.nx) * c->p.ny;
     const int f64 = compute_is_f64(c->p.storage);
@@ -634,6 +670,7 @@ extern "C" {
 
 lbm_status lbm_contact_angle(lbm_ctx *c, double iso, double y_ref, double out[4]) {
     if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
+    CtxScope scope(c);
     if (!isfinite(iso) || !isfinite(y_ref)) return fail(LBM_EINVAL, "iso and y_ref must be finite");
     TRY(run_diag(c, 1, 0, 0, 1));
     IsoParams ip{uint32_t(c->p.nx), uint32_t(c->p.ny), c->wall_mode, 0, iso, 0.01, 0, 0, 0, 0, 0};
@@ -648,6 +685,7 @@ lbm_status lbm_contact_angle(lbm_ctx *c, double iso, double y_ref, double out[4]
 
 lbm_status lbm_dynamic_angles(lbm_ctx *c, double iso, double y_ref, double out[8]) {
     if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
+    CtxScope scope(c);
     if (!isfinite(iso) || !isfinite(y_ref)) return fail(LBM_EINVAL, "iso and y_ref must be finite");
     TRY(run_diag(c, 1, 0, 0, 1));
     const uint32_t nx = uint32_t(c->p.nx), ny = uint32_t(c->p.ny);
@@ -710,6 +748,7 @@ lbm_status lbm_dynamic_angles(lbm_ctx *c, double iso, double y_ref, double out[8
 
 lbm_status lbm_slip_length(lbm_ctx *c, double out[3]) {
     if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
+    CtxScope scope(c);
     if (c->p.wall_kind != LBM_WALL_FLAT_SLAB) return fail(LBM_EINVAL, "slip length needs wall_kind FLAT_SLAB");
     TRY(run_diag(c, 1, 0, 0, 1));
     const int nx = c->p.nx, ny = c->p.ny, P = c->p.slab_rows;
@@ -751,6 +790,7 @@ lbm_status lbm_slip_length(lbm_ctx *c, double out[3]) {
 
 lbm_status lbm_get_state(lbm_ctx *c, double *f) {
     if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
+    CtxScope scope(c);
     const size_t N = size_t(c->p.nx) * c->p.ny;
     void *pop = *c->cur ? c->L.fb : c->L.fa;
     double *stage = (double *)(*c->cur ? c->L.fa : c->L.fb);   // the other buffer is free between steps
@@ -766,6 +806,7 @@ lbm_status lbm_get_state(lbm_ctx *c, double *f) {
 
 lbm_status lbm_set_state(lbm_ctx *c, const double *f, int64_t step_index) {
     if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
+    CtxScope scope(c);
     if (c->view) return fail(LBM_ESTATE, "lbm_set_state on a batch lattice view");
     if (step_index < 0) return fail(LBM_EINVAL, "step_index must be >= 0");
     const size_t N = size_t(c->p.nx) * c->p.ny;
@@ -788,9 +829,11 @@ lbm_status lbm_set_state(lbm_ctx *c, const double *f, int64_t step_index) {
 int64_t lbm_step_index(const lbm_ctx *c) { return c ? *c->step : -1; }
 
 lbm_status lbm_destroy(lbm_ctx *c) {
+    CtxScope scope(c);
     if (c && c->attached) return fail(LBM_ESTATE, "context is attached to a batch; destroy the batch first");
     if (!c || c->view) return LBM_OK;
     hipError_t e = hipStreamSynchronize(c->stream);
+    g_ctx_err = nullptr;                 // the context's slot goes with it
     delete c;
     if (e != hipSuccess) return fail(LBM_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e));
     return LBM_OK;
@@ -982,7 +1025,7 @@ static lbm_status upload_tables(lbm_batch *b) {
 }
 
 lbm_status lbm_batch_create(const lbm_params *ps, int32_t n, const double *const *rho0s,
-                            const double *const *ux0s, const double *const *uy0s, int32_t seg_rows,
+                            const double *const *u0s, int32_t seg_rows,
                             void *workspace, size_t workspace_bytes, void *stream, lbm_batch **out) {
     if (!out) return fail(LBM_EINVAL, "out is NULL");
     *out = nullptr;
@@ -1001,12 +1044,11 @@ lbm_status lbm_batch_create(const lbm_params *ps, int32_t n, const double *const
     for (int32_t k = 0; k < n && stt == LBM_OK; ++k) {
         lbm_params p = ps[k];
         p.seg_rows = seg_rows;
-        stt = check_host_fields(&p, rho0s[k], ux0s ? ux0s[k] : nullptr, uy0s ? uy0s[k] : nullptr, nullptr);
+        stt = check_host_fields(&p, rho0s[k], u0s ? u0s[k] : nullptr, nullptr);
         if (stt != LBM_OK) break;
         lbm_ctx *c = new (std::nothrow) lbm_ctx();
         if (!c) { stt = fail(LBM_ENOMEM, "host allocation failed"); break; }
-        stt = init_ctx(c, &p, rho0s[k], ux0s ? ux0s[k] : nullptr, uy0s ? uy0s[k] : nullptr, nullptr,
-                       ws + B.off[k], st);
+        stt = init_ctx(c, &p, rho0s[k], u0s ? u0s[k] : nullptr, nullptr, ws + B.off[k], st);
         if (stt != LBM_OK) { delete c; break; }
         c->view = true;
         b->lat.push_back(c);
@@ -1203,6 +1245,7 @@ int32_t lbm_tile_shapes(int32_t *waves, int32_t *rows, int32_t *strips, int32_t 
 
 lbm_status lbm_set_tile_shape(lbm_ctx *c, int32_t shape) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    CtxScope scope(c);
     if (c->view) return fail(LBM_ESTATE, "lattice belongs to a batch; use lbm_batch_set_tile_shapes");
     if (c->p.lattice == LBM_D2Q21) {
         if (shape < 0 || shape >= kQ21Variants) return fail(LBM_EINVAL, "D2Q21 step variant %d out of range", shape);
@@ -1229,6 +1272,7 @@ int32_t lbm_two_step_variants(int32_t *strips, int32_t *rows, int32_t *waves, in
 
 lbm_status lbm_set_two_step(lbm_ctx *c, int32_t variant) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    CtxScope scope(c);
     if (c->view) return fail(LBM_ESTATE, "lattice belongs to a batch");
     if (variant < -1 || variant >= kPass2Variants) return fail(LBM_EINVAL, "two-step variant %d out of range", variant);
     if (variant >= 0 && (c->p.lattice != LBM_D2Q9 || !pass2_ok(kernel_storage(c->p.storage))))
@@ -1282,6 +1326,7 @@ extern "C" {
 
 lbm_status lbm_tune(lbm_ctx *c, int32_t steps, int32_t *shape_out, double *ms_out) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    CtxScope scope(c);
     if (c->view) return fail(LBM_ESTATE, "lattice belongs to a batch; use lbm_batch_tune");
     if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
     int best = c->shape;
@@ -1294,9 +1339,9 @@ lbm_status lbm_tune(lbm_ctx *c, int32_t steps, int32_t *shape_out, double *ms_ou
             continue;
         }
         c->shape = s;
-        TRY(lbm_step(c, 1));                      // first launch of this shape: not timed
+        TRY(lbm_step(c, 1, nullptr));             // first launch of this shape: not timed
         double ms = 0;
-        TRY(time_steps(c->stream, steps, [&]() { return lbm_step(c, 1); }, &ms));
+        TRY(time_steps(c->stream, steps, [&]() { return lbm_step(c, 1, nullptr); }, &ms));
         if (ms_out) ms_out[s] = ms;
         if (ms < best_ms) {
             best_ms = ms;
@@ -1310,6 +1355,7 @@ lbm_status lbm_tune(lbm_ctx *c, int32_t steps, int32_t *shape_out, double *ms_ou
 
 lbm_status lbm_tune_two_step(lbm_ctx *c, int32_t steps, int32_t *variant_out, double *ms_out) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    CtxScope scope(c);
     if (c->view) return fail(LBM_ESTATE, "lattice belongs to a batch");
     if (steps < 1) return fail(LBM_EINVAL, "steps must be >= 1");
     const bool ok = c->p.lattice == LBM_D2Q9 && pass2_ok(kernel_storage(c->p.storage));
@@ -1323,9 +1369,9 @@ lbm_status lbm_tune_two_step(lbm_ctx *c, int32_t steps, int32_t *variant_out, do
             continue;
         }
         c->pass2 = v;
-        TRY(lbm_step(c, 2));                      // first pass of this candidate: not timed
+        TRY(lbm_step(c, 2, nullptr));             // first pass of this candidate: not timed
         double ms = 0;
-        TRY(time_steps(c->stream, steps, [&]() { return lbm_step(c, 2); }, &ms));
+        TRY(time_steps(c->stream, steps, [&]() { return lbm_step(c, 2, nullptr); }, &ms));
         ms *= 0.5;                                // per time step
         if (slot) *slot = ms;
         if (ms < best_ms) {

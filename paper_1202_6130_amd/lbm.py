@@ -69,11 +69,11 @@ def lib():
     i64 = ctypes.c_int64
     sig = {
         "lbm_params_default": ([P], ctypes.c_int),
-        "lbm_last_error": ([], ctypes.c_char_p),
+        "lbm_last_error": ([_vp], ctypes.c_char_p),
         "lbm_workspace_bytes": ([P, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "lbm_device_copy": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
-        "lbm_create": ([P, _dp, _dp, _dp, _dp, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
-        "lbm_step": ([_vp, i64], ctypes.c_int),
+        "lbm_create": ([P, _dp, _dp, _dp, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+        "lbm_step": ([_vp, i64, _dp], ctypes.c_int),
         "lbm_diagnostics": ([_vp, _dp], ctypes.c_int),
         "lbm_moments": ([_vp, _dp, _dp, _dp, _dp], ctypes.c_int),
         "lbm_contact_angle": ([_vp, ctypes.c_double, ctypes.c_double, _dp], ctypes.c_int),
@@ -84,7 +84,7 @@ def lib():
         "lbm_step_index": ([_vp], i64),
         "lbm_destroy": ([_vp], ctypes.c_int),
         "lbm_batch_workspace_bytes": ([P, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
-        "lbm_batch_create": ([P, ctypes.c_int32, ctypes.POINTER(_dp), ctypes.POINTER(_dp), ctypes.POINTER(_dp),
+        "lbm_batch_create": ([P, ctypes.c_int32, ctypes.POINTER(_dp), ctypes.POINTER(_dp),
                               ctypes.c_int32, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
         "lbm_batch_step": ([_vp, i64, ctypes.c_int32], ctypes.c_int),
         "lbm_batch_diagnostics": ([_vp, _dp], ctypes.c_int),
@@ -119,8 +119,13 @@ def lib():
 
 def _check(code):
     if code != LBM_OK:
-        raise LbmError(code, lib().lbm_last_error().decode())
+        raise LbmError(code, lib().lbm_last_error(None).decode())
     return code
+
+
+def lbm_last_error(ctx=None):
+    """Message of the last failed call on ctx, or of the calling thread."""
+    return lib().lbm_last_error(ctx).decode()
 
 
 def _ptr(a):
@@ -137,6 +142,15 @@ def _iptr(a):
 
 def _f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _u0(ux0, uy0):
+    """Initial velocity as the [2, ny, nx] array of lbm_create (None at rest)."""
+    if ux0 is None and uy0 is None:
+        return None
+    if ux0 is None or uy0 is None:
+        raise ValueError("give both ux0 and uy0, or neither")
+    return np.ascontiguousarray(np.stack([np.asarray(ux0, dtype=np.float64), np.asarray(uy0, dtype=np.float64)]))
 
 
 # ------------------------------------------------------------ C names
@@ -170,15 +184,24 @@ def lbm_workspace_bytes(p):
     return n.value
 
 
-def lbm_create(p, rho0, ux0, uy0, wall_fields, workspace_ptr, workspace_bytes, stream_ptr):
+def lbm_create(p, rho0, u0, wall_fields, workspace_ptr, workspace_bytes, stream_ptr):
+    """u0: None or float64 [2, ny, nx] (u_x, u_y)."""
     out = _vp()
-    _check(lib().lbm_create(ctypes.byref(p), _ptr(rho0), _ptr(ux0), _ptr(uy0), _ptr(wall_fields),
+    _check(lib().lbm_create(ctypes.byref(p), _ptr(rho0), _ptr(u0), _ptr(wall_fields),
                             _vp(workspace_ptr), workspace_bytes, _vp(stream_ptr), ctypes.byref(out)))
     return out
 
 
-def lbm_step(ctx, nsteps):
-    _check(lib().lbm_step(ctx, int(nsteps)))
+def lbm_step(ctx, nsteps, residual=False):
+    """Enqueues nsteps steps.  residual=True: passes residual_out (the call
+    synchronises after every diagnostic pass and raises LbmError EUNSTABLE at
+    the first non-finite one) and returns the latest residual."""
+    if not residual:
+        _check(lib().lbm_step(ctx, int(nsteps), None))
+        return None
+    r = ctypes.c_double()
+    _check(lib().lbm_step(ctx, int(nsteps), ctypes.byref(r)))
+    return r.value
 
 
 def lbm_diagnostics(ctx, check=True):
@@ -249,7 +272,7 @@ def lbm_batch_workspace_bytes(ps):
     return n.value
 
 
-def lbm_batch_create(ps, rho0s, ux0s, uy0s, seg_rows, workspace_ptr, workspace_bytes, stream_ptr):
+def lbm_batch_create(ps, rho0s, u0s, seg_rows, workspace_ptr, workspace_bytes, stream_ptr):
     n = len(ps)
     arr = (lbm_params * n)(*ps)
 
@@ -259,7 +282,7 @@ def lbm_batch_create(ps, rho0s, ux0s, uy0s, seg_rows, workspace_ptr, workspace_b
         return (_dp * n)(*[_ptr(a) if a is not None else None for a in lst])
 
     out = _vp()
-    _check(lib().lbm_batch_create(arr, n, plist(rho0s), plist(ux0s), plist(uy0s), int(seg_rows),
+    _check(lib().lbm_batch_create(arr, n, plist(rho0s), plist(u0s), int(seg_rows),
                                   _vp(workspace_ptr), workspace_bytes, _vp(stream_ptr), ctypes.byref(out)))
     return out
 
@@ -279,7 +302,7 @@ def lbm_batch_diagnostics(b, n, check=True):
 def lbm_batch_lattice(b, k):
     v = lib().lbm_batch_lattice(b, int(k))
     if not v:
-        raise LbmError(LBM_EINVAL, lib().lbm_last_error().decode())
+        raise LbmError(LBM_EINVAL, lib().lbm_last_error(None).decode())
     return v
 
 
@@ -420,12 +443,19 @@ class Lattice:
         nbytes = lbm_workspace_bytes(params)
         self._ws, ptr = _workspace(nbytes, device)
         self.stream_ptr = _stream(device, stream)
-        self.ctx = lbm_create(params, _f64(rho0), _f64(ux0), _f64(uy0), _f64(wall_fields), ptr, nbytes,
+        self.ctx = lbm_create(params, _f64(rho0), _u0(ux0, uy0), _f64(wall_fields), ptr, nbytes,
                               self.stream_ptr)
         self.workspace_bytes = nbytes
 
-    def step(self, nsteps=1):
-        lbm_step(self.ctx, nsteps)
+    def step(self, nsteps=1, residual=False):
+        """Advance nsteps; residual=True returns the latest diagnostic
+        residual and raises LbmError EUNSTABLE on non-finite values (see
+        lbm_step)."""
+        return lbm_step(self.ctx, nsteps, residual)
+
+    @property
+    def last_error(self):
+        return lbm_last_error(self.ctx)
 
     def diagnostics(self, check=True):
         return lbm_diagnostics(self.ctx, check)[0]
@@ -595,9 +625,10 @@ class Batch:
         self._stream_obj = stream
         self.stream_ptr = _stream(device, stream)
         rho0s = [_f64(r) for r in rho0s]
-        ux0s = None if ux0s is None else [_f64(u) for u in ux0s]
-        uy0s = None if uy0s is None else [_f64(u) for u in uy0s]
-        self.b = lbm_batch_create(self.ps, rho0s, ux0s, uy0s, seg_rows, ptr, nbytes, self.stream_ptr)
+        u0s = None
+        if ux0s is not None or uy0s is not None:
+            u0s = [_u0(a, b) for a, b in zip(ux0s, uy0s)]
+        self.b = lbm_batch_create(self.ps, rho0s, u0s, seg_rows, ptr, nbytes, self.stream_ptr)
         self.workspace_bytes = nbytes
         self.n = len(self.ps)
 

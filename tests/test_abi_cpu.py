@@ -131,24 +131,48 @@ def test_create_rejects_bad_host_inputs_before_device_work():
     p = lbm.lbm_params_default(nx=8, ny=8)
     rho = np.ones((8, 8))
     with pytest.raises(lbm.LbmError) as e:
-        lbm.lbm_create(p, None, None, None, None, 0, 0, 0)
+        lbm.lbm_create(p, None, None, None, 0, 0, 0)
     assert e.value.code == lbm.LBM_EINVAL
     bad = rho.copy(); bad[3, 3] = -1
     with pytest.raises(lbm.LbmError) as e:
-        lbm.lbm_create(p, bad, None, None, None, 0, 0, 0)
+        lbm.lbm_create(p, bad, None, None, 0, 0, 0)
     assert "rho0" in str(e.value)
+    u0 = np.zeros((2, 8, 8)); u0[1, 2, 5] = np.inf
     with pytest.raises(lbm.LbmError) as e:
-        lbm.lbm_create(p, rho, np.zeros((8, 8)), None, None, 0, 0, 0)
-    assert "ux0" in str(e.value)
+        lbm.lbm_create(p, rho, u0, None, 0, 0, 0)
+    assert "u0 at 85" in str(e.value)          # [2][ny][nx]: plane 1 starts at 64, + 2 * 8 + 5
     with pytest.raises(lbm.LbmError) as e:
-        lbm.lbm_create(p, rho, None, None, np.zeros((3, 8, 8)), 0, 0, 0)
+        lbm.lbm_create(p, rho, None, np.zeros((3, 8, 8)), 0, 0, 0)
     assert "wall_fields" in str(e.value)
     with pytest.raises(lbm.LbmError) as e:
-        lbm.lbm_create(p, rho, None, None, None, 0, 0, 0)
+        lbm.lbm_create(p, rho, None, None, 0, 0, 0)
     assert "workspace" in str(e.value)
     with pytest.raises(lbm.LbmError) as e:
-        lbm.lbm_create(p, rho, None, None, None, 256, 16, 0)
+        lbm.lbm_create(p, rho, None, None, 256, 16, 0)
     assert e.value.code == lbm.LBM_ENOMEM
+    # no context exists: the message is the thread's
+    assert "workspace too small" in lbm.lbm_last_error(None)
+
+
+def test_binding_stacks_initial_velocity():
+    ux, uy = np.full((3, 4), 0.1), np.full((3, 4), -0.2)
+    u0 = lbm._u0(ux, uy)
+    assert u0.shape == (2, 3, 4) and u0.flags["C_CONTIGUOUS"]
+    assert (u0[0] == 0.1).all() and (u0[1] == -0.2).all()
+    assert lbm._u0(None, None) is None
+    with pytest.raises(ValueError):
+        lbm._u0(ux, None)
+
+
+def test_null_context_calls_fail_cleanly():
+    L = lbm.lib()
+    out = (ctypes.c_double * 6)()
+    r = ctypes.c_double()
+    assert L.lbm_step(None, 1, None) == lbm.LBM_EINVAL
+    assert L.lbm_step(None, 1, ctypes.byref(r)) == lbm.LBM_EINVAL
+    assert "ctx is NULL" in lbm.lbm_last_error(None)
+    assert L.lbm_diagnostics(None, out) == lbm.LBM_EINVAL
+    assert L.lbm_step_index(None) == -1
 
 
 def test_batch_validation():
