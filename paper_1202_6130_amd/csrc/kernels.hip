@@ -51,10 +51,11 @@ __device__ inline void march(const LatDev<C> &L, const void *src, uint32_t strip
     ld.x = x;
     ld.xm = wrap_dec(x, nx);
     ld.xp = wrap_inc(x, nx);
-    // halo gather lanes
+    // halo gather lanes: slot k = lane (left) or lane - 32 (right) fetches
+    // population gather_pop(k)
     const bool g_left = lane < Q, g_right = lane >= 32 && lane < 32 + Q;
     const bool g_on = g_left || g_right;
-    const int g_q = g_left ? lane : (g_right ? lane - 32 : 0);
+    const int g_q = gather_pop(g_left ? lane : (g_right ? lane - 32 : 8));
     {
         const uint32_t h = g_left ? wrap_fast(x0 + nx - 1, nx) : wrap_fast(x0 + kStripCols, nx);
         const uint32_t hc = wrap_fast(uint32_t(int(h) + int(nx) - cx_dyn(g_q)), nx);   // h - c_x, wrapped
@@ -64,19 +65,17 @@ __device__ inline void march(const LatDev<C> &L, const void *src, uint32_t strip
     const uint32_t y0 = seg * L.seg_rows;
     const uint32_t y1 = min(y0 + L.seg_rows, ny);
 
-    // neighbour sums of psi are formed in binary64 (values and sums)
-    const double w1 = 1.0 / 9.0, w2 = 1.0 / 36.0;
     // loads of row r (its pulled populations come from rows r-1, r, r+1)
     auto load_row = [&](uint32_t r, Raw(&dst)[Q], Raw &g) {
         ld.load(wrap_dec(r, ny) * nx, r * nx, wrap_inc(r, ny) * nx, dst, g);
     };
-    // psi of the two halo nodes of a row, from its gathered populations: the
-    // binary64 sum in the tree of density(), so equal to the owner's density
+    // psi of the two halo nodes of a row, from its gathered populations
+    // (summed in the tree of density(): equal to the owner's density)
     auto halo_psi = [&](Raw g, C &pl, C &pr) {
         const C v = g_on ? Codec<S>::template decode<C>(g, g_q, L.rho_ref) : C(0);
-        const double s = row_sum9<double>(double(v));
-        pl = psi_of<C>(C(Lanes<double>::lane(s, 15)));
-        pr = psi_of<C>(C(Lanes<double>::lane(s, 47)));
+        const C s = row_sum9<C>(v);
+        pl = psi_of<C>(Lanes<C>::lane(s, 15));
+        pr = psi_of<C>(Lanes<C>::lane(s, 47));
     };
 
     C fA[Q], fB[Q];
@@ -119,16 +118,11 @@ __device__ inline void march(const LatDev<C> &L, const void *src, uint32_t strip
         const C psi_p = psi_of<C>(rho_n);
         C hl_p, hr_p;
         halo_psi(gcur, hl_p, hr_p);
-        // sum_i w_i psi(x + c_i) c_i, grouped by column:
-        //   a(x) = w1 psi(x,y) + w2 (psi(x,y+1) + psi(x,y-1)),  sx = a(x+1) - a(x-1)
-        //   b(x) = psi(x,y+1) - psi(x,y-1),  sy = w1 b(x) + w2 (b(x+1) + b(x-1))
-        const double a = w1 * double(psi_c) + w2 * (double(psi_p) + double(psi_m));
-        const double b = double(psi_p) - double(psi_m);
-        const double al = w1 * double(hl_c) + w2 * (double(hl_p) + double(hl_m));
-        const double ar = w1 * double(hr_c) + w2 * (double(hr_p) + double(hr_m));
-        const double bl = double(hl_p) - double(hl_m), br = double(hr_p) - double(hr_m);
-        const double sx = Lanes<double>::right(a, ar) - Lanes<double>::left(a, al);
-        const double sy = w1 * b + w2 * (Lanes<double>::right(b, br) + Lanes<double>::left(b, bl));
+        // sum_i w_i psi(x + c_i) c_i from the neighbours across lanes
+        C sx, sy;
+        psi_sums<C>(psi_p, psi_m, Lanes<C>::left(psi_c, hl_c), Lanes<C>::left(psi_p, hl_p),
+                    Lanes<C>::left(psi_m, hl_m), Lanes<C>::right(psi_c, hr_c), Lanes<C>::right(psi_p, hr_p),
+                    Lanes<C>::right(psi_m, hr_m), sx, sy);
         act.row(L, wall_c, y, x, active, fc, rho_c, psi_c, sx, sy);
         psi_m = psi_c;
         psi_c = psi_p;
@@ -182,7 +176,7 @@ __device__ inline void march(const LatDev<C> &L, const void *src, uint32_t strip
 template <class S, class C, int WALL> struct StepAct {
     PopBuf<S> dst;
     __device__ inline void row(const LatDev<C> &L, const RowWall<C> &rw, uint32_t y, uint32_t x, bool active,
-                               C f[Q], C rho, C psi_c, double sx, double sy) {
+                               C f[Q], C rho, C psi_c, C sx, C sy) {
         const uint32_t n = y * L.nx + x;
         C phie, Sx, Sy;
         wall_terms<C, WALL>(L, rw, n, phie, Sx, Sy);
@@ -202,7 +196,7 @@ template <class S, class C, int WALL> struct DiagAct {
     int write_mom, compare, update;
     double s_rho = 0, s_jx = 0, s_jy = 0, s_du = 0, s_u = 0, s_bad = 0;
     __device__ inline void row(const LatDev<C> &L, const RowWall<C> &rw, uint32_t y, uint32_t x, bool active,
-                               C f[Q], C rho, C psi_c, double sx, double sy) {
+                               C f[Q], C rho, C psi_c, C sx, C sy) {
         const uint32_t n = y * L.nx + x;
         C phie, Sx, Sy;
         wall_terms<C, WALL>(L, rw, n, phie, Sx, Sy);
@@ -217,6 +211,13 @@ template <class S, class C, int WALL> struct DiagAct {
             vx = s.ux + C(0.5) * s.Fx * s.inv_rho;
             vy = s.uy + C(0.5) * s.Fy * s.inv_rho;
         }
+        // totals: the node's populations summed in binary64 (exact for binary32)
+        double d[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = double(f[i]);
+        const double m = (((d[1] + d[3]) + (d[2] + d[4])) + ((d[5] + d[6]) + (d[7] + d[8]))) + d[0];
+        const double mjx = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
+        const double mjy = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
         if (!active) return;
         if (write_mom) {
             L.mom[n] = rho;
@@ -225,15 +226,9 @@ template <class S, class C, int WALL> struct DiagAct {
         }
         const bool ok = isfinite(double(rho)) && isfinite(double(vx)) && isfinite(double(vy));
         s_bad += ok ? 0.0 : 1.0;
-        if constexpr (sizeof(C) == 4) {
-            s_rho += s.m;
-            s_jx += s.jxd;
-            s_jy += s.jyd;
-        } else {
-            s_rho += double(rho);
-            s_jx += double(rho) * double(s.ux);
-            s_jy += double(rho) * double(s.uy);
-        }
+        s_rho += m;
+        s_jx += mjx;
+        s_jy += mjy;
         if (compare) s_du += fabs(double(vx) - double(L.uprev[n])) + fabs(double(vy) - double(L.uprev[L.plane + n]));
         s_u += fabs(double(vx)) + fabs(double(vy));
         if (update) {
@@ -301,7 +296,7 @@ __device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst,
     // of the last strip those of column X0 + 64 TS (both wrapped)
     const bool g_left = lane < Q && sj == 0, g_right = lane >= 32 && lane < 32 + Q && sj == TS - 1;
     const bool g_on = g_left || g_right;
-    const int g_q = g_left ? lane : (g_right ? lane - 32 : 0);
+    const int g_q = gather_pop(g_left ? lane : (g_right ? lane - 32 : 8));
     {
         const uint32_t h = g_left ? wrap_fast(X0 + nx - 1, nx) : wrap_fast(X0 + uint32_t(TS * kStripCols), nx);
         const uint32_t hc = wrap_fast(uint32_t(int(h) + int(nx) - cx_dyn(g_q)), nx);   // h - c_x, wrapped
@@ -329,18 +324,16 @@ __device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst,
             psi[j] = psi_of<C>(rho[j]);
             // the halo nodes' density is read out of lanes 15 and 47 by every
             // lane, outside divergent control flow
-            // (binary64 sum in the tree of density(): equal to the owner's)
             const C v = g_on ? Codec<S>::template decode<C>(g[j], g_q, L.rho_ref) : C(0);
-            const double sum = row_sum9<double>(double(v));
-            const C hl = psi_of<C>(C(Lanes<double>::lane(sum, 15)));
-            const C hr = psi_of<C>(C(Lanes<double>::lane(sum, 47)));
+            const C sum = row_sum9<C>(v);
+            const C hl = psi_of<C>(Lanes<C>::lane(sum, 15));
+            const C hr = psi_of<C>(Lanes<C>::lane(sum, 47));
             sm.psi[k][pos] = psi[j];
             if (lane == 0 && sj == 0) sm.hal[k][0] = hl;
             if (lane == 0 && sj == TS - 1) sm.hal[k][1] = hr;
         }
     }
     __syncthreads();
-    const double w1 = 1.0 / 9.0, w2 = 1.0 / 36.0;
     // pseudo-potential just left of lane 0 / right of lane 63 of this strip
     const int cl = sj * kStripCols - 1, cr = (sj + 1) * kStripCols;
 #pragma unroll
@@ -360,14 +353,11 @@ __device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst,
         } else {
             hr_m = sm.psi[k - 1][cr]; hr_c = sm.psi[k][cr]; hr_p = sm.psi[k + 1][cr];
         }
-        // sum_i w_i psi(x + c_i) c_i, grouped by column (see march), binary64
-        const double a = w1 * double(psi[j]) + w2 * (double(psi_p) + double(psi_m));
-        const double b = double(psi_p) - double(psi_m);
-        const double al = w1 * double(hl_c) + w2 * (double(hl_p) + double(hl_m));
-        const double ar = w1 * double(hr_c) + w2 * (double(hr_p) + double(hr_m));
-        const double bl = double(hl_p) - double(hl_m), br = double(hr_p) - double(hr_m);
-        const double sx = Lanes<double>::right(a, ar) - Lanes<double>::left(a, al);
-        const double sy = w1 * b + w2 * (Lanes<double>::right(b, br) + Lanes<double>::left(b, bl));
+        // sum_i w_i psi(x + c_i) c_i from the neighbours across lanes (see march)
+        C sx, sy;
+        psi_sums<C>(psi_p, psi_m, Lanes<C>::left(psi[j], hl_c), Lanes<C>::left(psi_p, hl_p),
+                    Lanes<C>::left(psi_m, hl_m), Lanes<C>::right(psi[j], hr_c), Lanes<C>::right(psi_p, hr_p),
+                    Lanes<C>::right(psi_m, hr_m), sx, sy);
         StepAct<S, C, WALL> act;
         act.dst.init(dst, 9u * L.pstride * uint32_t(sizeof(S)));
         act.row(L, row_wall<C, WALL>(L, r), r, x, active, f[j], rho[j], psi[j], sx, sy);
@@ -499,7 +489,6 @@ __device__ inline void pass2_block(const LatDev<C> &L, const void *src, void *ds
     }
     __syncthreads();
 
-    const double w1 = 1.0 / 9.0, w2 = 1.0 / 36.0;
     // R2: forces and collision of step one, in place in LDS (each node reads only its own populations)
 #pragma unroll
     for (int k = 0; k < G::K2; ++k) {
@@ -507,14 +496,8 @@ __device__ inline void pass2_block(const LatDev<C> &L, const void *src, void *ds
         if (!((k + 1) * NT <= N2 || i < N2)) continue;
         const int r2 = i / W2, c2 = i - r2 * W2;
         const C *p = sp + (r2 + 1) * W1 + (c2 + 1);
-        const double pm = p[-W1], pp = p[W1];
-        const double lm = p[-W1 - 1], lc = p[-1], lp = p[W1 - 1];
-        const double rm = p[-W1 + 1], rc = p[1], rp = p[W1 + 1];
-        // sum_i w_i psi(x + c_i) c_i, grouped by column as in tile_step
-        const double al = w1 * lc + w2 * (lp + lm), ar = w1 * rc + w2 * (rp + rm);
-        const double b = pp - pm, bl = lp - lm, br = rp - rm;
-        const double sx = ar - al;
-        const double sy = w1 * b + w2 * (br + bl);
+        C sx, sy;
+        psi_sums<C>(p[W1], p[-W1], p[-1], p[W1 - 1], p[-W1 - 1], p[1], p[W1 + 1], p[-W1 + 1], sx, sy);
         C f[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) f[q] = sf[q * N2 + i];
@@ -572,13 +555,8 @@ __device__ inline void pass2_block(const LatDev<C> &L, const void *src, void *ds
         for (int q = 0; q < Q; ++q) f[q] = sf[q * N2 + j - kCy[q] * W2 - kCx[q]];
         const C rho = density<C>(f);
         const C *p = sp + (r4 + 1) * W3 + (c4 + 1);
-        const double pm = p[-W3], pp = p[W3];
-        const double lm = p[-W3 - 1], lc = p[-1], lp = p[W3 - 1];
-        const double rm = p[-W3 + 1], rc = p[1], rp = p[W3 + 1];
-        const double al = w1 * lc + w2 * (lp + lm), ar = w1 * rc + w2 * (rp + rm);
-        const double b = pp - pm, bl = lp - lm, br = rp - rm;
-        const double sx = ar - al;
-        const double sy = w1 * b + w2 * (br + bl);
+        C sx, sy;
+        psi_sums<C>(p[W3], p[-W3], p[-1], p[W3 - 1], p[-W3 - 1], p[1], p[W3 + 1], p[-W3 + 1], sx, sy);
         act.row(L, row_wall<C, WALL>(L, y), y, x, active, f, rho, p[0], sx, sy);
     }
 }

@@ -131,10 +131,9 @@ __device__ inline Node21<C> node21(C rho, C jx, C jy, C psi_c, C sx, C sy, C phi
     s.jy = jy;
     s.ux = jx * s.inv_rho;
     s.uy = jy * s.inv_rho;
-    s.m = double(rho);
     s.jxd = double(jx);
     s.jyd = double(jy);
-    momentum_after_force<C>(s, psi_c, double(sx), double(sy), phie, Sx, Sy, L.G, L.Ux, L.Uy, L.Fx, L.Fy);
+    momentum_after_force<C>(s, psi_c, sx, sy, phie, Sx, Sy, L.G, L.Ux, L.Uy, L.Fx, L.Fy);
     return s;
 }
 

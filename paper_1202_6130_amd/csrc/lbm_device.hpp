@@ -297,21 +297,42 @@ __device__ inline void decode_row(const typename Codec<S>::Raw r[Q], C f[Q], C r
     for (int i = 0; i < Q; ++i) f[i] = Codec<S>::template decode<C>(r[i], i, rho_ref);
 }
 
-// Mass of a node's populations (eq. M0).  In binary64 arithmetic the nine
-// populations are summed in the order below.  In binary32 arithmetic they are
-// summed in binary64 (exact: the nine binary32 values span far fewer than the
-// 29 extra bits) and the density is that exact mass rounded once: the same
-// value whatever the order of the populations, so a mirror-symmetric state
-// keeps mirror-symmetric densities.  mass_in returns the sum in binary64.
-template <class C> __device__ inline double mass_in(const C f[Q]) {
-    double d[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = double(f[i]);
-    return (((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]))) + d[8];
-}
+// Eq. M0 in a fixed order that is mirror-symmetric in x and in y (the
+// populations of each mirror pair are added first), so that a mirror-
+// symmetric state keeps mirror-symmetric densities in binary32.  The halo
+// gathers of the step kernels sum the same nine values in the same tree
+// (gather_pop below).
 template <class C> __device__ inline C density(const C f[Q]) {
-    if constexpr (sizeof(C) == 4) return C(mass_in<C>(f));
-    else return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    return (((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]))) + f[0];
+}
+
+// Population fetched by gather slot k = 0..8 (lanes 0..8 and 32..40 of a
+// halo gather): slots in the order of the tree of density(), so that
+// row_sum9 over the slots reproduces density() bit for bit.
+__host__ __device__ constexpr int gather_pop(int k) { return int((0x087654231ull >> (4 * k)) & 15u); }
+constexpr bool gather_order_ok() {
+    const int want[Q] = {1, 3, 2, 4, 5, 6, 7, 8, 0};
+    for (int k = 0; k < Q; ++k)
+        if (gather_pop(k) != want[k]) return false;
+    return true;
+}
+static_assert(gather_order_ok(), "gather slots must follow the tree of density()");
+
+// Neighbour sums of psi (eq. force_SC) at one node, from the 3 x 3 block of
+// pseudo-potentials around it (p = this column, l = left, r = right; c = this
+// row, n = the row above, s = the row below):
+//   sx = sum_i w_i psi(x + c_i) c_ix = w1 (r_c - l_c) + w2 ((r_n - l_n) + (r_s - l_s))
+//   sy = sum_i w_i psi(x + c_i) c_iy = w1 (p_n - p_s) + w2 ((r_n - r_s) + (l_n - l_s))
+// Differences across the node come first: they are exact for nearby values
+// and exactly zero where psi is uniform, and the sums carry no cancellation.
+// (Grouped by column instead, w1 psi + w2 (psi_n + psi_s) on either side and
+// their difference, binary32 rounding of the column sums acted as a force that
+// repeated at a quasi-steady node in every step.)
+template <class C>
+__device__ inline void psi_sums(C pn, C ps, C lc, C ln, C ls, C rc, C rn, C rs, C &sx, C &sy) {
+    const C w1 = C(1.0 / 9.0), w2 = C(1.0 / 36.0);
+    sx = w1 * (rc - lc) + w2 * ((rn - ln) + (rs - ls));
+    sy = w1 * (pn - ps) + w2 * ((rn - rs) + (ln - ls));
 }
 
 // Pseudo-potential of the fluid-fluid force.
@@ -348,16 +369,15 @@ template <class C> __device__ inline C recip(C v);
 template <> __device__ inline float recip<float>(float v) { return __builtin_amdgcn_rcpf(v); }
 template <> __device__ inline double recip<double>(double v) { return 1.0 / v; }
 
-// Everything the collision needs at one node.  The binary64 members carry
-// the node's momentum budget in binary32 arithmetic (below); in binary64
-// arithmetic they equal the members of type C.
+// Everything the collision needs at one node.  jxd .. jsyd carry the
+// momenta in binary64 (for binary64 arithmetic they equal the members of
+// type C).
 template <class C> struct NodeState {
     C rho, inv_rho;
     C jx, jy;                      // momentum j = sum_i f_i c_i (pre-force)
     C ux, uy;                      // u = j / rho
     C Fx, Fy;                      // total force density
     C jsx, jsy;                    // rho u* = j + F, rounded once
-    double m;                      // mass of the incoming populations (exact in binary32 arithmetic)
     double jxd, jyd, jsxd, jsyd;   // j and j + F in binary64
 };
 
@@ -366,14 +386,14 @@ template <class C> struct NodeState {
 // as (1 - phi^eps)(j + F_FF) + phi^eps rho U + F_LR + F_ext and formed in
 // binary64 whatever the storage: near a wall F_FF and F_LR reach 0.1-0.2
 // while a driving force is ~1e-6, and binary32 sums of those terms lose the
-// driving force to a rounding that repeats every step.  sx, sy are the
-// neighbour sums of psi (binary64).  Reads s.m, s.jxd, s.jyd; sets the rest.
+// driving force to a rounding that repeats every step.  Reads s.rho, s.jxd,
+// s.jyd; sets the rest.
 template <class C>
-__device__ inline void momentum_after_force(NodeState<C> &s, C psi_c, double sx, double sy, C phie, C Sx, C Sy, C G,
+__device__ inline void momentum_after_force(NodeState<C> &s, C psi_c, C sx, C sy, C phie, C Sx, C Sy, C G,
                                             C Ux, C Uy, C Fxe, C Fye) {
-    const double r = s.m, ph = double(phie), om = 1.0 - ph;
+    const double r = double(s.rho), ph = double(phie), om = 1.0 - ph;
     const double gp = -double(G) * double(psi_c);
-    const double ffx = gp * sx, ffy = gp * sy;
+    const double ffx = gp * double(sx), ffy = gp * double(sy);
     const double jx = s.jxd, jy = s.jyd;
     const double jsx = om * (jx + ffx) + ((ph * (r * double(Ux)) + r * double(Sx)) + double(Fxe));
     const double jsy = om * (jy + ffy) + ((ph * (r * double(Uy)) + r * double(Sy)) + double(Fye));
@@ -386,32 +406,18 @@ __device__ inline void momentum_after_force(NodeState<C> &s, C psi_c, double sx,
 }
 
 // Forces of one node (eqs. force_SC, force_SC_FS, wall_shift) given the
-// neighbour sums of psi, formed in binary64:
-//   sx = sum_i w_i psi(x+c_i) c_ix,  sy = sum_i w_i psi(x+c_i) c_iy
-// The momentum (eq. M1) is a sum of differences of opposite populations, in
-// binary64 for binary32 arithmetic (exact there).
+// neighbour sums of psi (psi_sums).  The momentum (eq. M1) is a sum of
+// differences of opposite populations (exact near rest).
 template <class C>
-__device__ inline NodeState<C> node_forces(const C f[Q], C rho, C psi_c, double sx, double sy, C phie,
+__device__ inline NodeState<C> node_forces(const C f[Q], C rho, C psi_c, C sx, C sy, C phie,
                                            C Sx, C Sy, C G, C Ux, C Uy, C Fxe, C Fye) {
     NodeState<C> s;
     s.rho = rho;
     s.inv_rho = recip<C>(rho);
-    if constexpr (sizeof(C) == 4) {
-        double d[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) d[i] = double(f[i]);
-        s.m = (((d[0] + d[1]) + (d[2] + d[3])) + ((d[4] + d[5]) + (d[6] + d[7]))) + d[8];
-        s.jxd = (d[1] - d[3]) + (d[5] - d[6]) + (d[8] - d[7]);
-        s.jyd = (d[2] - d[4]) + (d[5] + d[6]) - (d[7] + d[8]);
-        s.jx = C(s.jxd);
-        s.jy = C(s.jyd);
-    } else {
-        s.m = double(rho);
-        s.jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-        s.jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-        s.jxd = double(s.jx);
-        s.jyd = double(s.jy);
-    }
+    s.jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    s.jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    s.jxd = double(s.jx);
+    s.jyd = double(s.jy);
     s.ux = s.jx * s.inv_rho;
     s.uy = s.jy * s.inv_rho;
     // long-range wall force rho S (S precomputed from the static psi_FS);
@@ -449,19 +455,56 @@ template <class C> __device__ inline void equilibrium(C rho, C inv_rho, C mx, C 
     feq[8] = r2 + (ad - bd);
 }
 
-// The rest population closes the mass balance: the collision conserves mass
-// exactly in real arithmetic, so f'_0 = rho - sum_{i>0} f'_i.  In binary32
-// storage the balance is struck in binary64 against the exact incoming mass
-// m and the eight outgoing populations as they will be stored, then rounded
-// once: the stored populations of a node sum to its incoming mass up to the
-// rounding of f'_0 alone.
-template <class C> __device__ inline void close_mass(C f[Q], C rho, double m) {
+// The moving populations of the equilibrium for binary32 arithmetic, in
+// binary64 and not yet rounded: the rest part w_i rho and the momentum term
+// 3 w_i c_i.m (m = j + F in binary64, never rounded to binary32) in binary64,
+// the small second-order term in binary32; feq[0] is left to the mass
+// closure.  Each outgoing population is then rounded once.  In binary32 the
+// rounding of m and of the rest-plus-second-order part before the momentum
+// term is added repeated identically at a quasi-steady node in every step
+// and moved the interface of the 1024 x 512 sessile drop by ~1e-4 nodes.
+__device__ inline void equilibrium_b32(float rho, float inv_rho, double mx, double my, double feq[Q]) {
+    using K = LatConst<float>;
+    const float ux = float(mx) * inv_rho, uy = float(my) * inv_rho;
+    const float u2 = 1.5f * (ux * ux + uy * uy);
+    const float r1 = K::w1 * rho, r2 = K::w2 * rho;
+    const double R1 = double(rho) * (1.0 / 9.0), R2 = double(rho) * (1.0 / 36.0);
+    const double bx = mx * (1.0 / 3.0), by = my * (1.0 / 3.0);
+    const double bs = (mx + my) * (1.0 / 12.0), bd = (my - mx) * (1.0 / 12.0);
+    const double ex = R1 + double(r1 * (4.5f * ux * ux - u2));
+    feq[1] = ex + bx;
+    feq[3] = ex - bx;
+    const double ey = R1 + double(r1 * (4.5f * uy * uy - u2));
+    feq[2] = ey + by;
+    feq[4] = ey - by;
+    const float su = ux + uy, du = uy - ux;
+    const double es = R2 + double(r2 * (4.5f * su * su - u2));
+    feq[5] = es + bs;
+    feq[7] = es - bs;
+    const double ed = R2 + double(r2 * (4.5f * du * du - u2));
+    feq[6] = ed + bd;
+    feq[8] = ed - bd;
+    feq[0] = 0.0;
+}
+
+// The rest population closes the mass balance (the collision conserves mass
+// exactly in real arithmetic).  Binary64: f'_0 = rho - sum_{i>0} f'_i.
+// Binary32: f'_0 = f_0 + sum_{i>0} (f_i - f'_i) from the incoming populations
+// fin: the eight differences are exact (nearby values) and small, so the
+// stored populations of a node sum to its incoming mass up to the rounding
+// of f'_0 alone.  A binary32 density in f'_0 = rho - ... rounds at the spacing
+// of numbers near rho, the same way at a steady node in every step: such
+// nodes created or destroyed mass at a fixed rate (on a 256 x 128 sessile
+// drop after 20000 steps, 1.2e-4 of the density against 3e-6 with this
+// closure).
+template <class C> __device__ inline void close_mass(C f[Q], C rho, const C fin[Q]) {
     if constexpr (sizeof(C) == 4) {
-        const double s = ((double(f[1]) + double(f[3])) + (double(f[2]) + double(f[4]))) +
-                         ((double(f[5]) + double(f[7])) + (double(f[6]) + double(f[8])));
-        f[0] = C(m - s);
+        (void)rho;
+        const C d = (((fin[1] - f[1]) + (fin[3] - f[3])) + ((fin[2] - f[2]) + (fin[4] - f[4]))) +
+                    (((fin[5] - f[5]) + (fin[6] - f[6])) + ((fin[7] - f[7]) + (fin[8] - f[8])));
+        f[0] = fin[0] + d;
     } else {
-        (void)m;
+        (void)fin;
         f[0] = rho - (((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8])));
     }
 }
@@ -491,42 +534,38 @@ template <class C, class VS> __device__ inline void project_neq(C g[VS::Q]) {
     }
 }
 
-// Binary32 arithmetic evaluates the collision in binary64 from the node's
-// exact mass, binary64 momenta and the binary32 reciprocal of the density
-// (which enters only the second-order terms) and rounds every outgoing
-// population once.  In binary32 the rounding of j + F before the
-// equilibrium's momentum terms, and the roundings inside the equilibrium,
-// repeat identically at a quasi-steady node in every step; on the 1024 x 512
-// sessile drop they (with the neighbour sums and the mass closure) moved the
-// interface by ~1e-4 nodes by t = 5000.
 template <class C> __device__ inline void collide(C f[Q], const NodeState<C> &s, C omega, int projected) {
     if constexpr (sizeof(C) == 4) {
-        const double m = s.m, inv = double(s.inv_rho);
+        C fin[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) fin[i] = f[i];
         double fs[Q];
-        equilibrium<double>(m, inv, s.jsxd, s.jsyd, fs);
+        equilibrium_b32(s.rho, s.inv_rho, s.jsxd, s.jsyd, fs);
         if (omega == C(1)) {
             // tau = 1: the factor (1 - 1/tau) is exactly zero, f' = feq(u*)
 #pragma unroll
-            for (int i = 0; i < Q; ++i) f[i] = C(fs[i]);
+            for (int i = 1; i < Q; ++i) f[i] = C(fs[i]);
         } else {
+            // the non-equilibrium part in binary64 (the rest population's
+            // is not needed: the projection's second moment has no c_0 term,
+            // and f'_0 comes from the mass closure)
             double fu[Q];
-            equilibrium<double>(m, inv, s.jxd, s.jyd, fu);
+            equilibrium_b32(s.rho, s.inv_rho, s.jxd, s.jyd, fu);
             const double keep = 1.0 - double(omega);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) fu[i] = double(f[i]) - fu[i];
+            for (int i = 1; i < Q; ++i) fu[i] = double(f[i]) - fu[i];
             if (projected) project_neq<double, VelSet<9>>(fu);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) f[i] = C(keep * fu[i] + fs[i]);
+            for (int i = 1; i < Q; ++i) f[i] = C(keep * fu[i] + fs[i]);
         }
-        close_mass<C>(f, s.rho, m);
-        return;
+        close_mass<C>(f, s.rho, fin);
     } else {
         C fs[Q];
         equilibrium<C>(s.rho, s.inv_rho, s.jsx, s.jsy, fs);
         if (omega == C(1)) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) f[i] = fs[i];
-            close_mass<C>(f, s.rho, s.m);
+            close_mass<C>(f, s.rho, f);
             return;
         }
         C fu[Q];
@@ -537,7 +576,7 @@ template <class C> __device__ inline void collide(C f[Q], const NodeState<C> &s,
         if (projected) project_neq<C, VelSet<9>>(fu);
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[i] = keep * fu[i] + fs[i];
-        close_mass<C>(f, s.rho, s.m);
+        close_mass<C>(f, s.rho, f);
     }
 }
 
