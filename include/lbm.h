@@ -222,6 +222,23 @@ lbm_status lbm_step(lbm_ctx *c, int64_t nsteps, double *residual_out);
  * count are not in the paper. */
 lbm_status lbm_diagnostics(lbm_ctx *c, double out[6]);
 
+/* lbm_diagnostics for callers that cannot allocate device memory or lend
+ * scratch space (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation): the same pass, results and return codes, but its
+ * per-wave partial sums go to one static device array of the library instead
+ * of the context's workspace (the reported results still go to the
+ * context).  The array holds LBM_NOALLOC_MAX_ROWS rows of 8 doubles (2 MiB);
+ * every GPU the library runs on keeps its own copy until the process ends,
+ * resolved on the first call on that GPU (the device current at lbm_create).
+ * A lattice needing more rows (D2Q9: 64-column strips x segments of
+ * seg_rows rows; D2Q21: one row per step tile) gives LBM_EINVAL.  The call
+ * allocates nothing on the device or the host and synchronises.  Calls on
+ * one GPU share the array: calls that overlap in time on one GPU (other
+ * threads, other streams) race and must not be issued.  The array needs no
+ * clearing: every pass writes each partial row it reads. */
+#define LBM_NOALLOC_MAX_ROWS 32768
+lbm_status lbm_diagnostics_noalloc(lbm_ctx *c, double out[6]);
+
 /* Macroscopic fields at the current time (eqs. M0, M1): rho, and the reported
  * velocity u = (j + F/2)/rho (average of the pre- and post-force velocities
  * of the exact difference method).  Any output may be NULL; totals =

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -213,6 +214,7 @@ bool solve3(double A[3][3], double b[3], double z[3]) {
 
 struct lbm_ctx {
     std::string err;               // last error message of a call on this context
+    int device;                    // HIP device current at lbm_create
     lbm_params p;
     Layout lay;
     hipStream_t stream;
@@ -276,16 +278,19 @@ lbm_status launch_ok(hipError_t e, const char *what) {
 
 // Runs the diagnostic kernel over the current state and reduces it into
 // d_small[slot*8 .. +6].
-lbm_status run_diag(lbm_ctx *c, int write_mom, int compare, int update, int slot) {
+// partials: where the per-wave partial sums go (nullptr: the workspace's).
+lbm_status run_diag(lbm_ctx *c, int write_mom, int compare, int update, int slot, double *partials = nullptr) {
+    LatDevAny L = c->L;
+    if (partials) L.partials = partials;
     if (c->p.lattice == LBM_D2Q21)
-        TRY(launch_ok(launch_diag_q21(kernel_storage(c->p.storage), c->L, c->wall_mode, *c->cur, write_mom, compare,
+        TRY(launch_ok(launch_diag_q21(kernel_storage(c->p.storage), L, c->wall_mode, *c->cur, write_mom, compare,
                                       update, c->stream),
                       "diag_q21"));
     else
-        TRY(launch_ok(launch_diag(kernel_storage(c->p.storage), nullptr, nullptr, 0, c->L, c->wall_mode, *c->cur,
+        TRY(launch_ok(launch_diag(kernel_storage(c->p.storage), nullptr, nullptr, 0, L, c->wall_mode, *c->cur,
                                   write_mom, compare, update, c->stream),
                       "diag"));
-    TRY(launch_ok(launch_reduce(c->L.partials, c->d_ranges, 1, 8, 6, c->d_small + 8 * slot, 8, c->stream),
+    TRY(launch_ok(launch_reduce(L.partials, c->d_ranges, 1, 8, 6, c->d_small + 8 * slot, 8, c->stream),
                   "reduce"));
     return LBM_OK;
 }
@@ -299,6 +304,7 @@ lbm_status sync(lbm_ctx *c) {
 lbm_status init_ctx(lbm_ctx *c, const lbm_params *p, const double *rho0, const double *u0,
                     const double *wall_fields, char *ws, hipStream_t stream) {
     c->p = *p;
+    HIPCHK(hipGetDevice(&c->device));
     c->lay = make_layout(*p);
     c->stream = stream;
     c->ws = ws;
@@ -496,8 +502,8 @@ lbm_status lbm_create(const lbm_params *p, const double *rho0, const double *u0,
 }
 
 // A diagnostic pass after the step just taken (every K-th step index).
-static lbm_status diag_after_step(lbm_ctx *c) {
-    TRY(run_diag(c, 0, c->have_prev ? 1 : 0, 1, 0));
+static lbm_status diag_after_step(lbm_ctx *c, double *partials = nullptr) {
+    TRY(run_diag(c, 0, c->have_prev ? 1 : 0, 1, 0, partials));
     c->last_diag_compared = c->have_prev;
     c->have_prev = true;
     c->last_diag_step = *c->step;
@@ -568,6 +574,58 @@ lbm_status lbm_diagnostics(lbm_ctx *c, double out[6]) {
     if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
     CtxScope scope(c);
     if (c->last_diag_step != *c->step) TRY(diag_after_step(c));
+    return read_diag(c, out);
+}
+
+}  // extern "C"
+
+// ------------------------------------------ diagnostics without workspace scratch
+// The per-wave partial sums of lbm_diagnostics_noalloc live in this array, one
+// copy per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel: it is a host-side stand-in, not a device address;
+// the device address on each GPU comes from hipGetSymbolAddress (scratch_on).
+static __device__ __align__(256) double scratch[size_t(LBM_NOALLOC_MAX_ROWS) * 8];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices];   // device address of `scratch` per device, nullptr until resolved
+
+// Device address of `scratch` on device dev, resolved once per device with
+// that device current.
+lbm_status scratch_on(int dev, double **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBM_EDEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        HIPCHK(hipGetDevice(&cur));
+        if (cur != dev) HIPCHK(hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        const hipError_t e2 = cur != dev ? hipSetDevice(cur) : hipSuccess;
+        if (e != hipSuccess) return fail(LBM_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        if (e2 != hipSuccess) return fail(LBM_EDEVICE, "hipSetDevice: %s", hipGetErrorString(e2));
+        if (!p) return fail(LBM_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_diagnostics_noalloc(lbm_ctx *c, double out[6]) {
+    if (!c || !out) return fail(LBM_EINVAL, "NULL argument");
+    CtxScope scope(c);
+    if (c->lay.waves > uint32_t(LBM_NOALLOC_MAX_ROWS))
+        return fail(LBM_EINVAL, "lattice needs %u partial rows; lbm_diagnostics_noalloc holds at most %d",
+                    c->lay.waves, LBM_NOALLOC_MAX_ROWS);
+    if (c->last_diag_step != *c->step) {
+        double *part = nullptr;
+        TRY(scratch_on(c->device, &part));
+        TRY(diag_after_step(c, part));
+    }
     return read_diag(c, out);
 }
 

@@ -75,6 +75,7 @@ def lib():
         "lbm_create": ([P, _dp, _dp, _dp, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
         "lbm_step": ([_vp, i64, _dp], ctypes.c_int),
         "lbm_diagnostics": ([_vp, _dp], ctypes.c_int),
+        "lbm_diagnostics_noalloc": ([_vp, _dp], ctypes.c_int),
         "lbm_moments": ([_vp, _dp, _dp, _dp, _dp], ctypes.c_int),
         "lbm_contact_angle": ([_vp, ctypes.c_double, ctypes.c_double, _dp], ctypes.c_int),
         "lbm_slip_length": ([_vp, _dp], ctypes.c_int),
@@ -207,6 +208,16 @@ def lbm_step(ctx, nsteps, residual=False):
 def lbm_diagnostics(ctx, check=True):
     out = np.zeros(6)
     code = lib().lbm_diagnostics(ctx, _ptr(out))
+    if check:
+        _check(code)
+    return out, code
+
+
+def lbm_diagnostics_noalloc(ctx, check=True):
+    """lbm_diagnostics with its partial sums in the library's static device
+    array (no workspace scratch); see lbm.h."""
+    out = np.zeros(6)
+    code = lib().lbm_diagnostics_noalloc(ctx, _ptr(out))
     if check:
         _check(code)
     return out, code
