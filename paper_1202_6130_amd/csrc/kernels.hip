@@ -173,7 +173,8 @@ __device__ inline void march(const LatDev<C> &L, const void *src, uint32_t strip
 }
 
 // Collide and store (the time step).
-template <class S, class C, int WALL> struct StepAct {
+// ONE = 1: the collision compiled for tau = 1 only (see collide).
+template <class S, class C, int WALL, int ONE = 0> struct StepAct {
     PopBuf<S> dst;
     __device__ inline void row(const LatDev<C> &L, const RowWall<C> &rw, uint32_t y, uint32_t x, bool active,
                                C f[Q], C rho, C psi_c, C sx, C sy) {
@@ -181,7 +182,7 @@ template <class S, class C, int WALL> struct StepAct {
         C phie, Sx, Sy;
         wall_terms<C, WALL>(L, rw, n, phie, Sx, Sy);
         NodeState<C> s = node_forces<C>(f, rho, psi_c, sx, sy, phie, Sx, Sy, L.G, L.Ux, L.Uy, L.Fx, L.Fy);
-        collide<C>(f, s, L.omega, L.collision);
+        collide<C, ONE>(f, s, L.omega, L.collision);
         if (active) {
             const uint32_t row = y * L.nx;
 #pragma unroll
@@ -267,7 +268,7 @@ template <class C, int ROWS, int COLS> struct TileLds {
     C hal[ROWS][2];
 };
 
-template <class S, class C, int WALL, int TW, int TR, int TS>
+template <class S, class C, int WALL, int TW, int TR, int TS, int ONE>
 __device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst, uint32_t group, uint32_t trow,
                                  TileLds<C, TW / TS * TR, TS * kWave> &sm) {
     using Raw = typename Codec<S>::Raw;
@@ -358,14 +359,14 @@ __device__ inline void tile_step(const LatDev<C> &L, const void *src, void *dst,
         psi_sums<C>(psi_p, psi_m, Lanes<C>::left(psi[j], hl_c), Lanes<C>::left(psi_p, hl_p),
                     Lanes<C>::left(psi_m, hl_m), Lanes<C>::right(psi[j], hr_c), Lanes<C>::right(psi_p, hr_p),
                     Lanes<C>::right(psi_m, hr_m), sx, sy);
-        StepAct<S, C, WALL> act;
+        StepAct<S, C, WALL, ONE> act;
         act.dst.init(dst, 9u * L.pstride * uint32_t(sizeof(S)));
         act.row(L, row_wall<C, WALL>(L, r), r, x, active, f[j], rho[j], psi[j], sx, sy);
     }
 }
 
 // ---------------------------------------------------------------- kernels
-template <class S, class C, int WALL, int SHAPE>
+template <class S, class C, int WALL, int SHAPE, int ONE>
 __global__ __launch_bounds__(kShapeWaves[SHAPE] * kWave) void k_step_tiles(LatDev<C> L, const void *__restrict__ src,
                                                                           void *__restrict__ dst) {
     constexpr int TW = kShapeWaves[SHAPE], TR = kShapeRows[SHAPE], TS = kShapeStrips[SHAPE];
@@ -373,7 +374,7 @@ __global__ __launch_bounds__(kShapeWaves[SHAPE] * kWave) void k_step_tiles(LatDe
     const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const uint32_t groups = (L.strips + TS - 1) / TS;
     const uint32_t trow = lb / groups, group = lb - trow * groups;
-    tile_step<S, C, WALL, TW, TR, TS>(L, src, dst, group, trow, sm);
+    tile_step<S, C, WALL, TW, TR, TS, ONE>(L, src, dst, group, trow, sm);
 }
 
 // Batched step over tiles of one shape: twork[b] = (lattice, strip group, tile
@@ -387,7 +388,7 @@ __global__ __launch_bounds__(kShapeWaves[SHAPE] * kWave) void k_step_tiles_batch
     const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const uint4 wk = twork[lb];
     const LatDev<C> L = lats[wk.x];
-    tile_step<S, C, WALL, TW, TR, TS>(L, parity ? L.fb : L.fa, parity ? L.fa : L.fb, wk.y, wk.z, sm);
+    tile_step<S, C, WALL, TW, TR, TS, 0>(L, parity ? L.fb : L.fa, parity ? L.fa : L.fb, wk.y, wk.z, sm);
 }
 
 // ---------------------------------------------------------------- two steps per pass
@@ -415,7 +416,7 @@ template <int TS, int OH, int WPS> struct Pass2Geo {
 
 // One block (column group `group`, row band `trow`) of lattice L; lds holds
 // Pass2Geo::lds_bytes of dynamic LDS.
-template <class S, class C, int WALL, int TS, int OH, int WPS>
+template <class S, class C, int WALL, int TS, int OH, int WPS, int ONE>
 __device__ inline void pass2_block(const LatDev<C> &L, const void *src, void *dst, uint32_t group, uint32_t trow,
                                    unsigned char *lds) {
     using G = Pass2Geo<TS, OH, WPS>;
@@ -513,7 +514,7 @@ __device__ inline void pass2_block(const LatDev<C> &L, const void *src, void *ds
             wall_terms<C, WALL>(L, RowWall<C>{C(0), C(0)}, y * nx + x, phie, Sx, Sy);
         }
         NodeState<C> s = node_forces<C>(f, rho, p[0], sx, sy, phie, Sx, Sy, L.G, L.Ux, L.Uy, L.Fx, L.Fy);
-        collide<C>(f, s, L.omega, L.collision);
+        collide<C, ONE>(f, s, L.omega, L.collision);
 #pragma unroll
         for (int q = 0; q < Q; ++q)
             sf[q * N2 + i] = Codec<S>::template decode<C>(Codec<S>::template encode<C>(f[q], q, rref), q, rref);
@@ -542,7 +543,7 @@ __device__ inline void pass2_block(const LatDev<C> &L, const void *src, void *ds
     const uint32_t gx = X0 + uint32_t(c4);
     const bool active = gx < nx;
     const uint32_t x = wrap_fast(gx, nx);
-    StepAct<S, C, WALL> act;
+    StepAct<S, C, WALL, ONE> act;
     act.dst.init(dst, 9u * P * uint32_t(sizeof(S)));
 #pragma unroll
     for (int jr = 0; jr < OH / WPS; ++jr) {
@@ -561,14 +562,14 @@ __device__ inline void pass2_block(const LatDev<C> &L, const void *src, void *ds
     }
 }
 
-template <class S, class C, int WALL, int TS, int OH, int WPS>
+template <class S, class C, int WALL, int TS, int OH, int WPS, int ONE>
 __global__ __launch_bounds__(TS * WPS * kWave) void k_step_pass2(LatDev<C> L, const void *__restrict__ src,
                                                                  void *__restrict__ dst) {
     extern __shared__ __align__(16) unsigned char pass2_lds[];
     const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const uint32_t groups = (L.nx + uint32_t(TS * kStripCols) - 1) / uint32_t(TS * kStripCols);
     const uint32_t trow = lb / groups, group = lb - trow * groups;
-    pass2_block<S, C, WALL, TS, OH, WPS>(L, src, dst, group, trow, pass2_lds);
+    pass2_block<S, C, WALL, TS, OH, WPS, ONE>(L, src, dst, group, trow, pass2_lds);
 }
 
 // Two-step passes over the blocks of many lattices: pwork[b] = (lattice,
@@ -580,7 +581,7 @@ __global__ __launch_bounds__(TS * WPS * kWave) void k_step_pass2_batch(const Lat
     const uint32_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const uint4 wk = pwork[lb];
     const LatDev<float> L = lats[wk.x];
-    pass2_block<float, float, WALL_ROW, TS, OH, WPS>(L, parity ? L.fb : L.fa, parity ? L.fa : L.fb, wk.y, wk.z,
+    pass2_block<float, float, WALL_ROW, TS, OH, WPS, 0>(L, parity ? L.fb : L.fa, parity ? L.fa : L.fb, wk.y, wk.z,
                                                      pass2_lds);
 }
 
@@ -1032,14 +1033,20 @@ hipError_t launch_step(int storage, const LatDevAny &L, int wall, int shape, int
         LatDev<C> d = L.get<C>();
         const void *src = parity ? d.fb : d.fa;
         void *dst = parity ? d.fa : d.fb;
+        // tau = 1 runs the instantiation compiled for it (fewer registers)
+        const bool one = L.omega == 1.0;
         return with_shape(shape, [&](auto sh) {
             constexpr int SH = decltype(sh)::value;
             const uint32_t nb = step_tiles(d.nx, d.ny, SH);
             const dim3 block(kShapeWaves[SH] * kWave);
-            if (wall == WALL_ROW)
-                hipLaunchKernelGGL((k_step_tiles<S, C, WALL_ROW, SH>), dim3(nb), block, 0, st, d, src, dst);
+            if (wall == WALL_ROW && one)
+                hipLaunchKernelGGL((k_step_tiles<S, C, WALL_ROW, SH, 1>), dim3(nb), block, 0, st, d, src, dst);
+            else if (wall == WALL_ROW)
+                hipLaunchKernelGGL((k_step_tiles<S, C, WALL_ROW, SH, 0>), dim3(nb), block, 0, st, d, src, dst);
+            else if (one)
+                hipLaunchKernelGGL((k_step_tiles<S, C, WALL_NODE, SH, 1>), dim3(nb), block, 0, st, d, src, dst);
             else
-                hipLaunchKernelGGL((k_step_tiles<S, C, WALL_NODE, SH>), dim3(nb), block, 0, st, d, src, dst);
+                hipLaunchKernelGGL((k_step_tiles<S, C, WALL_NODE, SH, 0>), dim3(nb), block, 0, st, d, src, dst);
             return hipGetLastError();
         });
     });
@@ -1062,11 +1069,18 @@ hipError_t launch_step_pass2(int storage, const LatDevAny &L, int wall, int vari
         void *dst = parity ? d.fa : d.fb;
         const uint32_t nb = pass2_blocks(d.nx, d.ny, V);
         const size_t lds = G::lds_bytes;
-        if (wall == WALL_ROW)
-            hipLaunchKernelGGL((k_step_pass2<S, float, WALL_ROW, PV::TS, PV::OH, PV::WPS>), dim3(nb), dim3(G::NT), lds,
-                               st, d, src, dst);
+        const bool one = L.omega == 1.0;   // tau = 1: the instantiation compiled for it
+        if (wall == WALL_ROW && one)
+            hipLaunchKernelGGL((k_step_pass2<S, float, WALL_ROW, PV::TS, PV::OH, PV::WPS, 1>), dim3(nb), dim3(G::NT),
+                               lds, st, d, src, dst);
+        else if (wall == WALL_ROW)
+            hipLaunchKernelGGL((k_step_pass2<S, float, WALL_ROW, PV::TS, PV::OH, PV::WPS, 0>), dim3(nb), dim3(G::NT),
+                               lds, st, d, src, dst);
+        else if (one)
+            hipLaunchKernelGGL((k_step_pass2<S, float, WALL_NODE, PV::TS, PV::OH, PV::WPS, 1>), dim3(nb), dim3(G::NT),
+                               lds, st, d, src, dst);
         else
-            hipLaunchKernelGGL((k_step_pass2<S, float, WALL_NODE, PV::TS, PV::OH, PV::WPS>), dim3(nb), dim3(G::NT),
+            hipLaunchKernelGGL((k_step_pass2<S, float, WALL_NODE, PV::TS, PV::OH, PV::WPS, 0>), dim3(nb), dim3(G::NT),
                                lds, st, d, src, dst);
         return hipGetLastError();
     };

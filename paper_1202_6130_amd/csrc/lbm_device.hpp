@@ -202,6 +202,15 @@ __device__ inline uint32_t xcd_logical_block(uint32_t b, uint32_t nb) {
 #endif
 }
 
+// Fused multiply-add, written out where the update wants one.  The update's
+// device functions below switch contraction off and fuse only here, so that
+// every kernel that inlines them rounds them the same way (HIP otherwise
+// fuses a multiply and an add across statements after inlining, and kernels
+// sharing a function then disagreed in the last place where their
+// surroundings differed).
+__device__ inline float fmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 template <class C> __device__ inline C cexp(C v);
 template <> __device__ inline float cexp<float>(float v) { return __expf(v); }
 template <> __device__ inline double cexp<double>(double v) { return exp(v); }
@@ -330,9 +339,10 @@ static_assert(gather_order_ok(), "gather slots must follow the tree of density()
 // repeated at a quasi-steady node in every step.)
 template <class C>
 __device__ inline void psi_sums(C pn, C ps, C lc, C ln, C ls, C rc, C rn, C rs, C &sx, C &sy) {
+#pragma clang fp contract(off)
     const C w1 = C(1.0 / 9.0), w2 = C(1.0 / 36.0);
-    sx = w1 * (rc - lc) + w2 * ((rn - ln) + (rs - ls));
-    sy = w1 * (pn - ps) + w2 * ((rn - rs) + (ln - ls));
+    sx = fmac(w1, rc - lc, w2 * ((rn - ln) + (rs - ls)));
+    sy = fmac(w1, pn - ps, w2 * ((rn - rs) + (ln - ls)));
 }
 
 // Pseudo-potential of the fluid-fluid force.
@@ -391,12 +401,15 @@ template <class C> struct NodeState {
 template <class C>
 __device__ inline void momentum_after_force(NodeState<C> &s, C psi_c, C sx, C sy, C phie, C Sx, C Sy, C G,
                                             C Ux, C Uy, C Fxe, C Fye) {
+#pragma clang fp contract(off)
     const double r = double(s.rho), ph = double(phie), om = 1.0 - ph;
     const double gp = -double(G) * double(psi_c);
-    const double ffx = gp * double(sx), ffy = gp * double(sy);
     const double jx = s.jxd, jy = s.jyd;
-    const double jsx = om * (jx + ffx) + ((ph * (r * double(Ux)) + r * double(Sx)) + double(Fxe));
-    const double jsy = om * (jy + ffy) + ((ph * (r * double(Uy)) + r * double(Sy)) + double(Fye));
+    // om (j + F_FF) + ((ph rho U + rho S) + F_ext), with j + F_FF = fma(gp, s, j)
+    const double tx = fmac(r, double(Sx), ph * (r * double(Ux))) + double(Fxe);
+    const double ty = fmac(r, double(Sy), ph * (r * double(Uy))) + double(Fye);
+    const double jsx = fmac(om, fmac(gp, double(sx), jx), tx);
+    const double jsy = fmac(om, fmac(gp, double(sy), jy), ty);
     s.jsxd = jsx;
     s.jsyd = jsy;
     s.jsx = C(jsx);
@@ -411,6 +424,7 @@ __device__ inline void momentum_after_force(NodeState<C> &s, C psi_c, C sx, C sy
 template <class C>
 __device__ inline NodeState<C> node_forces(const C f[Q], C rho, C psi_c, C sx, C sy, C phie,
                                            C Sx, C Sy, C G, C Ux, C Uy, C Fxe, C Fye) {
+#pragma clang fp contract(off)
     NodeState<C> s;
     s.rho = rho;
     s.inv_rho = recip<C>(rho);
@@ -435,6 +449,7 @@ __device__ inline NodeState<C> node_forces(const C f[Q], C rho, C psi_c, C sx, C
 // last: folded into (1 - 1.5 u^2) first, they were rounded at the spacing of
 // numbers near 1, the same way at a steady node in every step.
 template <class C> __device__ inline void equilibrium(C rho, C inv_rho, C mx, C my, C feq[Q]) {
+#pragma clang fp contract(off)
     using K = LatConst<C>;
     const C ux = mx * inv_rho, uy = my * inv_rho;
     const C u2 = C(1.5) * (ux * ux + uy * uy);
@@ -464,26 +479,28 @@ template <class C> __device__ inline void equilibrium(C rho, C inv_rho, C mx, C 
 // term is added repeated identically at a quasi-steady node in every step
 // and moved the interface of the 1024 x 512 sessile drop by ~1e-4 nodes.
 __device__ inline void equilibrium_b32(float rho, float inv_rho, double mx, double my, double feq[Q]) {
+#pragma clang fp contract(off)
     using K = LatConst<float>;
     const float ux = float(mx) * inv_rho, uy = float(my) * inv_rho;
-    const float u2 = 1.5f * (ux * ux + uy * uy);
+    const float u2 = 1.5f * fmac(ux, ux, uy * uy);
     const float r1 = K::w1 * rho, r2 = K::w2 * rho;
     const double R1 = double(rho) * (1.0 / 9.0), R2 = double(rho) * (1.0 / 36.0);
-    const double bx = mx * (1.0 / 3.0), by = my * (1.0 / 3.0);
-    const double bs = (mx + my) * (1.0 / 12.0), bd = (my - mx) * (1.0 / 12.0);
-    const double ex = R1 + double(r1 * (4.5f * ux * ux - u2));
-    feq[1] = ex + bx;
-    feq[3] = ex - bx;
-    const double ey = R1 + double(r1 * (4.5f * uy * uy - u2));
-    feq[2] = ey + by;
-    feq[4] = ey - by;
+    constexpr double k3 = 1.0 / 3.0, k12 = 1.0 / 12.0;
+    // even part, then the momentum term fused in: ex +- m / 3 rounded once
+    const double ex = R1 + double(r1 * fmac(4.5f * ux, ux, -u2));
+    feq[1] = fmac(mx, k3, ex);
+    feq[3] = fmac(-mx, k3, ex);
+    const double ey = R1 + double(r1 * fmac(4.5f * uy, uy, -u2));
+    feq[2] = fmac(my, k3, ey);
+    feq[4] = fmac(-my, k3, ey);
     const float su = ux + uy, du = uy - ux;
-    const double es = R2 + double(r2 * (4.5f * su * su - u2));
-    feq[5] = es + bs;
-    feq[7] = es - bs;
-    const double ed = R2 + double(r2 * (4.5f * du * du - u2));
-    feq[6] = ed + bd;
-    feq[8] = ed - bd;
+    const double ms = mx + my, md = my - mx;
+    const double es = R2 + double(r2 * fmac(4.5f * su, su, -u2));
+    feq[5] = fmac(ms, k12, es);
+    feq[7] = fmac(-ms, k12, es);
+    const double ed = R2 + double(r2 * fmac(4.5f * du, du, -u2));
+    feq[6] = fmac(md, k12, ed);
+    feq[8] = fmac(-md, k12, ed);
     feq[0] = 0.0;
 }
 
@@ -498,6 +515,7 @@ __device__ inline void equilibrium_b32(float rho, float inv_rho, double mx, doub
 // drop after 20000 steps, 1.2e-4 of the density against 3e-6 with this
 // closure).
 template <class C> __device__ inline void close_mass(C f[Q], C rho, const C fin[Q]) {
+#pragma clang fp contract(off)
     if constexpr (sizeof(C) == 4) {
         (void)rho;
         const C d = (((fin[1] - f[1]) + (fin[3] - f[3])) + ((fin[2] - f[2]) + (fin[4] - f[4]))) +
@@ -517,6 +535,7 @@ template <class C> __device__ inline void close_mass(C f[Q], C rho, const C fin[
 // to f; the equilibrium is already of that form): with Pi = sum_i g_i c_i c_i,
 // g_i <- w_i (c_i c_i - theta I) : Pi / (2 theta^2).  Used by both lattices.
 template <class C, class VS> __device__ inline void project_neq(C g[VS::Q]) {
+#pragma clang fp contract(off)
     constexpr double th = VS::theta;
     C pxx = C(0), pxy = C(0), pyy = C(0);
 #pragma unroll
@@ -534,14 +553,18 @@ template <class C, class VS> __device__ inline void project_neq(C g[VS::Q]) {
     }
 }
 
-template <class C> __device__ inline void collide(C f[Q], const NodeState<C> &s, C omega, int projected) {
+// ONE = 1: compiled for tau = 1 only (the caller guarantees omega == 1);
+// ONE = 0: tau taken at run time, the same arithmetic at tau = 1.
+template <class C, int ONE = 0>
+__device__ inline void collide(C f[Q], const NodeState<C> &s, C omega, int projected) {
+#pragma clang fp contract(off)
     if constexpr (sizeof(C) == 4) {
         C fin[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) fin[i] = f[i];
         double fs[Q];
         equilibrium_b32(s.rho, s.inv_rho, s.jsxd, s.jsyd, fs);
-        if (omega == C(1)) {
+        if (ONE || omega == C(1)) {
             // tau = 1: the factor (1 - 1/tau) is exactly zero, f' = feq(u*)
 #pragma unroll
             for (int i = 1; i < Q; ++i) f[i] = C(fs[i]);
@@ -556,13 +579,13 @@ template <class C> __device__ inline void collide(C f[Q], const NodeState<C> &s,
             for (int i = 1; i < Q; ++i) fu[i] = double(f[i]) - fu[i];
             if (projected) project_neq<double, VelSet<9>>(fu);
 #pragma unroll
-            for (int i = 1; i < Q; ++i) f[i] = C(keep * fu[i] + fs[i]);
+            for (int i = 1; i < Q; ++i) f[i] = C(fmac(keep, fu[i], fs[i]));
         }
         close_mass<C>(f, s.rho, fin);
     } else {
         C fs[Q];
         equilibrium<C>(s.rho, s.inv_rho, s.jsx, s.jsy, fs);
-        if (omega == C(1)) {
+        if (ONE || omega == C(1)) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) f[i] = fs[i];
             close_mass<C>(f, s.rho, f);
@@ -575,7 +598,7 @@ template <class C> __device__ inline void collide(C f[Q], const NodeState<C> &s,
         for (int i = 0; i < Q; ++i) fu[i] = f[i] - fu[i];
         if (projected) project_neq<C, VelSet<9>>(fu);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) f[i] = keep * fu[i] + fs[i];
+        for (int i = 0; i < Q; ++i) f[i] = fmac(keep, fu[i], fs[i]);
         close_mass<C>(f, s.rho, f);
     }
 }
