@@ -8,8 +8,9 @@ GPU: more resident work only delays every request without raising
 throughput); all resident lattices advance together, one kernel launch per time
 step (lbm_batch_attach), replayed from a HIP graph in chunks of `diag_every`
 steps.  After every chunk the velocity residual of each lattice is read; a
-lattice whose residual falls below `tol` (or that reaches `max_steps`) is
-measured and retired, and its slot and memory go to the next request.  The
+lattice whose residual falls below `tol`, or reaches its binary32 floor
+(Floor), or reaches `max_steps`, is measured and retired, and its slot and
+memory go to the next request.  The
 batch is rebuilt whenever membership changes; resident lattices keep their
 state across rebuilds.  A request whose lattice turns non-finite fails alone.
 
@@ -48,6 +49,7 @@ class Result:
     finished: float = float("nan")
     steps: int = 0
     converged: bool = False
+    floor: bool = False       # converged at the binary32 floor of the residual, not below tol
     residual: float = float("inf")
     value: tuple = ()
     error: str = ""
@@ -111,10 +113,57 @@ def request_params(req, seg_rows=0):
     return lattice_params(req, seg_rows), rho0
 
 
+def initial_velocity(req, p):
+    """Initial velocity [2, ny, nx] of a request, or None (at rest).  A slip
+    query starts from the no-slip Poiseuille profile between its hydrodynamic
+    boundaries (phi = 0.01, Sec. III.A), u_x = F (y - y_w)(H - y_w - y) /
+    (2 rho nu), so that the run only has to settle the wall region and the
+    slip instead of building the whole profile up from rest (a viscous time
+    H^2 / nu of up to 6e6 steps on the largest channels).  The steady state
+    does not depend on this choice."""
+    if req.kind != "slip":
+        return None
+    nx, ny, P = p.nx, p.ny, p.slab_rows
+    H = ny - P                                       # gap between the two faces
+    yw = p.wall_width * math.atanh(0.98)             # phi(y_w) = 0.01
+    nu = (p.tau - 0.5) / 3.0
+    y = np.arange(ny, dtype=np.float64)
+    prof = p.F_ext[0] * (y - yw) * (H - yw - y) / (2.0 * CHANNEL_RHO * nu)
+    prof[(y < yw) | (y > H - yw)] = 0.0
+    u0 = np.zeros((2, ny, nx))
+    u0[0] = prof[:, None]
+    return u0
+
+
+class Floor:
+    """Detects that a lattice's residual has reached its binary32 floor.
+
+    Storage rounding keeps the residual of a binary32 lattice from falling
+    below a floor that depends on the lattice (measured 5e-7 to 4e-5 on served
+    drops and channels); a tolerance below it would never be met.  The floor
+    counts as reached once the residual is below `ceiling` and the median of
+    the last `window` passes is no smaller than `ratio` times the median of
+    the `window` passes before (a slowly relaxing channel, its residual halving
+    over ~70000 steps, improves by more than 10% over 200 passes of 100
+    steps)."""
+
+    def __init__(self, window=200, ratio=0.9, ceiling=1e-4):
+        self.window, self.ratio, self.ceiling = int(window), float(ratio), float(ceiling)
+        self.hist = collections.deque(maxlen=2 * self.window)
+
+    def add(self, r):
+        self.hist.append(r)
+        if r >= self.ceiling or len(self.hist) < 2 * self.window:
+            return False
+        h = list(self.hist)
+        old, new = np.median(h[:self.window]), np.median(h[self.window:])
+        return new >= self.ratio * old
+
+
 class Server:
-    def __init__(self, budget_bytes=96 << 30, max_resident=64, diag_every=100, max_steps=20000, tol=1e-8,
+    def __init__(self, budget_bytes=96 << 30, max_resident=64, diag_every=100, max_steps=1000000, tol=1e-5,
                  batched=True, device="cuda:0", seg_rows=0, on_admit=None, tile_costs="calibrate",
-                 max_nodes=16 << 20, two_step="calibrate"):
+                 max_nodes=16 << 20, two_step="calibrate", floor_window=200):
         import torch
         if diag_every % 2:
             raise ValueError("diag_every must be even (graph replays keep the buffer parity)")
@@ -124,6 +173,7 @@ class Server:
         self.K = int(diag_every)
         self.max_steps = int(max_steps)
         self.tol = float(tol)
+        self.floor_window = floor_window
         self.batched = bool(batched)
         self.device = device
         self.seg_rows = seg_rows
@@ -157,6 +207,7 @@ class Server:
         results = {r.rid: Result(r.rid, r.kind, r.nx, r.ny, r.arrival) for r in requests}
         waiting = collections.deque()
         resident = []            # [(req, Lattice, footprint)]
+        floors = {}              # rid -> Floor detector
         used = 0
         nodes = 0
         batch = None
@@ -189,7 +240,9 @@ class Server:
                     break
                 waiting.popleft()
                 p, rho0 = request_params(req, self.seg_rows)
-                lat = lbm.Lattice(p, rho0, device=self.device, stream=self.stream)
+                u0 = initial_velocity(req, p)
+                lat = lbm.Lattice(p, rho0, None if u0 is None else u0[0], None if u0 is None else u0[1],
+                                  device=self.device, stream=self.stream)
                 if self.tile_costs is not None:
                     lat.tile_shape = pick_tile_shape(req.nx, req.ny, self.tile_costs)
                 if not self.batched:
@@ -197,6 +250,7 @@ class Server:
                 if self.on_admit is not None:
                     self.on_admit(req, lat)
                 resident.append((req, lat, fp))
+                floors[req.rid] = Floor(self.floor_window) if self.floor_window else None
                 self.max_seen_resident = max(self.max_seen_resident, len(resident))
                 used += fp
                 nodes += req.nx * req.ny
@@ -228,12 +282,15 @@ class Server:
                 res.steps = int(diag[k][0])
                 res.residual = float(diag[k][4])
                 bad = diag[k][5] > 0
-                done = res.residual < self.tol or res.steps >= self.max_steps
+                fl = floors[req.rid]
+                at_floor = fl is not None and fl.add(res.residual)
+                done = res.residual < self.tol or at_floor or res.steps >= self.max_steps
                 if bad:
                     res.error = "non-finite state"
                     retire.append(k)
                 elif done:
-                    res.converged = res.residual < self.tol
+                    res.converged = res.residual < self.tol or at_floor
+                    res.floor = at_floor and not res.residual < self.tol
                     try:
                         res.value = self._measure(req, lat)
                     except lbm.LbmError as e:
@@ -264,6 +321,9 @@ def summarize(results, elapsed):
         "completed": len(done),
         "failed": len(results) - len(done),
         "converged": sum(r.converged for r in done),
+        "converged_below_tol": sum(r.converged and not r.floor for r in done),
+        "converged_at_floor": sum(r.floor for r in done),
+        "at_step_cap": sum(not r.converged for r in done),
         "solves_per_s": len(done) / elapsed if elapsed > 0 else 0.0,
         "p50_s": float(np.percentile(lat, 50)) if lat.size else None,
         "p99_s": float(np.percentile(lat, 99)) if lat.size else None,
