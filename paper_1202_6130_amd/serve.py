@@ -9,8 +9,9 @@ throughput); all resident lattices advance together, one kernel launch per time
 step (lbm_batch_attach), replayed from a HIP graph in chunks of `diag_every`
 steps.  After every chunk the velocity residual of each lattice is read; a
 lattice whose residual falls below `tol`, or reaches its binary32 floor
-(Floor), or reaches `max_steps`, is measured and retired, and its slot and
-memory go to the next request.  The
+(Floor), or is at rest (its residual stalled at the O(1) level of rounding
+noise, every |u| below REST_SPEED), or reaches `max_steps`, is measured and
+retired, and its slot and memory go to the next request.  The
 batch is rebuilt whenever membership changes; resident lattices keep their
 state across rebuilds.  A request whose lattice turns non-finite fails alone.
 
@@ -50,6 +51,7 @@ class Result:
     steps: int = 0
     converged: bool = False
     floor: bool = False       # converged at the binary32 floor of the residual, not below tol
+    rest: bool = False        # converged at rest: the residual is rounding noise of a fluid at rest
     residual: float = float("inf")
     value: tuple = ()
     error: str = ""
@@ -136,28 +138,39 @@ def initial_velocity(req, p):
 
 
 class Floor:
-    """Detects that a lattice's residual has reached its binary32 floor.
+    """Detects that a lattice's residual has stopped falling.
 
     Storage rounding keeps the residual of a binary32 lattice from falling
     below a floor that depends on the lattice (measured 5e-7 to 4e-5 on served
-    drops and channels); a tolerance below it would never be met.  The floor
-    counts as reached once the residual is below `ceiling` and the median of
-    the last `window` passes is no smaller than `ratio` times the median of
-    the `window` passes before (a slowly relaxing channel, its residual halving
-    over ~70000 steps, improves by more than 10% over 200 passes of 100
-    steps)."""
+    drops and channels); a tolerance below it would never be met.  The
+    residual has stalled once the median of the last `window` passes is no
+    smaller than `ratio` times the median of the `window` passes before (a
+    slowly relaxing channel, its residual halving over ~70000 steps, improves
+    by more than 10% over 200 passes of 100 steps).  Below `ceiling` a stalled
+    residual is the floor (`add` returns True); above it the server checks
+    whether the lattice is at rest (`stalled`)."""
 
     def __init__(self, window=200, ratio=0.9, ceiling=1e-4):
         self.window, self.ratio, self.ceiling = int(window), float(ratio), float(ceiling)
         self.hist = collections.deque(maxlen=2 * self.window)
+        self.stalled = False
+        self.level = float("inf")     # median of the last window
 
     def add(self, r):
         self.hist.append(r)
-        if r >= self.ceiling or len(self.hist) < 2 * self.window:
+        if len(self.hist) < 2 * self.window:
             return False
         h = list(self.hist)
-        old, new = np.median(h[:self.window]), np.median(h[self.window:])
-        return new >= self.ratio * old
+        old, new = float(np.median(h[:self.window])), float(np.median(h[self.window:]))
+        self.stalled = bool(new >= self.ratio * old)
+        self.level = new
+        return self.stalled and r < self.ceiling
+
+
+# A lattice at rest: its residual stalled at NOISE_RESIDUAL or above (two
+# independent noise fields give sqrt(2)) and every |u| below REST_SPEED.
+NOISE_RESIDUAL = 0.5
+REST_SPEED = 1e-5
 
 
 class Server:
@@ -194,15 +207,21 @@ class Server:
             fp = self._footprints[req.rid] = lbm.lbm_workspace_bytes(lattice_params(req, self.seg_rows))
         return fp
 
+    @staticmethod
+    def _at_rest(lat):
+        _, ux, uy, _ = lat.moments()
+        return bool(max(np.abs(ux).max(), np.abs(uy).max()) < REST_SPEED)
+
     def _measure(self, req, lat):
         if req.kind == "angle":
             out = lat.contact_angle(I.ISO, 0.0)
             return tuple(out) if out is not None else ()
         return tuple(lat.slip_length())
 
-    def run(self, requests, realtime=True):
+    def run(self, requests, realtime=True, log=None):
         """Serve `requests` (inputs.Request, arrival in seconds from the start).
-        Returns the list of Result in request order."""
+        Returns the list of Result in request order.  log: a file to which
+        one line per retired request is written (progress of long runs)."""
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         results = {r.rid: Result(r.rid, r.kind, r.nx, r.ny, r.arrival) for r in requests}
         waiting = collections.deque()
@@ -239,6 +258,7 @@ class Server:
                 if resident and nodes + req.nx * req.ny > self.max_nodes:
                     break
                 waiting.popleft()
+                t_adm = clock()
                 p, rho0 = request_params(req, self.seg_rows)
                 u0 = initial_velocity(req, p)
                 lat = lbm.Lattice(p, rho0, None if u0 is None else u0[0], None if u0 is None else u0[1],
@@ -255,7 +275,7 @@ class Server:
                 used += fp
                 nodes += req.nx * req.ny
                 self.max_seen_used = max(self.max_seen_used, used)
-                results[req.rid].admitted = clock()
+                results[req.rid].admitted = t_adm
                 changed = True
             if not resident:
                 if pending:
@@ -284,13 +304,22 @@ class Server:
                 bad = diag[k][5] > 0
                 fl = floors[req.rid]
                 at_floor = fl is not None and fl.add(res.residual)
-                done = res.residual < self.tol or at_floor or res.steps >= self.max_steps
+                at_rest = False
+                if fl is not None and fl.stalled and fl.level >= NOISE_RESIDUAL and not bad:
+                    # a residual stalled at O(1): successive velocity fields are
+                    # uncorrelated, as rounding noise of a fluid at rest is
+                    at_rest = self._at_rest(lat)
+                    fl.hist.clear()
+                    fl.stalled = False
+                below = bool(res.residual < self.tol)
+                done = below or at_floor or at_rest or res.steps >= self.max_steps
                 if bad:
                     res.error = "non-finite state"
                     retire.append(k)
                 elif done:
-                    res.converged = res.residual < self.tol or at_floor
-                    res.floor = at_floor and not res.residual < self.tol
+                    res.converged = below or at_floor or at_rest
+                    res.floor = at_floor and not below
+                    res.rest = at_rest and not below
                     try:
                         res.value = self._measure(req, lat)
                     except lbm.LbmError as e:
@@ -304,6 +333,11 @@ class Server:
                 for k in sorted(retire, reverse=True):
                     req, lat, fp = resident.pop(k)
                     results[req.rid].finished = now
+                    if log is not None:
+                        r = results[req.rid]
+                        print(f"t={now:8.2f}s done {r.rid} {r.kind} {r.nx}x{r.ny} steps {r.steps} "
+                              f"residual {r.residual:.2e} converged {r.converged} floor {r.floor} rest {r.rest} "
+                              f"latency {r.latency:.2f}s {r.error}", file=log, flush=True)
                     lat.close()
                     used -= fp
                     nodes -= req.nx * req.ny
@@ -320,13 +354,14 @@ def summarize(results, elapsed):
         "requests": len(results),
         "completed": len(done),
         "failed": len(results) - len(done),
-        "converged": sum(r.converged for r in done),
-        "converged_below_tol": sum(r.converged and not r.floor for r in done),
-        "converged_at_floor": sum(r.floor for r in done),
-        "at_step_cap": sum(not r.converged for r in done),
+        "converged": int(sum(bool(r.converged) for r in done)),
+        "converged_below_tol": int(sum(bool(r.converged and not (r.floor or r.rest)) for r in done)),
+        "converged_at_floor": int(sum(bool(r.floor) for r in done)),
+        "converged_at_rest": int(sum(bool(r.rest) for r in done)),
+        "at_step_cap": int(sum(not r.converged for r in done)),
         "solves_per_s": len(done) / elapsed if elapsed > 0 else 0.0,
         "p50_s": float(np.percentile(lat, 50)) if lat.size else None,
         "p99_s": float(np.percentile(lat, 99)) if lat.size else None,
-        "elapsed_s": elapsed,
+        "elapsed_s": float(elapsed),
         "lattice_updates": int(sum(r.steps * r.nx * r.ny for r in done)),
     }

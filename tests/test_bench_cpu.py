@@ -25,7 +25,13 @@ def test_bytes_per_update():
 
 def test_step_dispatch_names():
     k = bench._step_dispatch_key
-    assert k("void lbmwet::k_step_tiles<float, float, 0, 8>(lbmwet::LatDev<float>, void const*, void*)") == 8
+    assert k("void lbmwet::k_step_tiles<float, float, 0, 8, 1>(lbmwet::LatDev<float>, void const*, void*)") == 8
+    assert k("void lbmwet::k_step_tiles<lbmwet::Dev16, float, 0, 5, 0>(lbmwet::LatDev<float>, void const*, "
+             "void*)") == 5
+    assert k("void lbmwet::k_step_pass2<float, float, 0, 1, 24, 12, 1>(lbmwet::LatDev<float>, void const*, "
+             "void*)") == "pass2v8"
+    assert k("void lbmwet::k_step_pass2<float, float, 1, 2, 8, 4, 0>(lbmwet::LatDev<float>, void const*, "
+             "void*)") == "pass2v2"
     assert k("void lbmwet::k_step_tiles_batch<float, float, 0, 5>(lbmwet::LatDev<float> const*, uint4 const*, int)") \
         is None
     assert k("void lbmwet::(anonymous namespace)::k_march_q21<0, 1, 1>(lbmwet::LatDev<float>, float const*, "
@@ -65,7 +71,7 @@ def _write_run(path, counter, copy_kib, steps):
 
 
 def test_ingest_counters(tmp_path):
-    name = "void lbmwet::k_step_tiles<float, float, 0, 8>(lbmwet::LatDev<float>, void const*, void*)"
+    name = "void lbmwet::k_step_tiles<float, float, 0, 8, 1>(lbmwet::LatDev<float>, void const*, void*)"
     diag = "void lbmwet::k_diag<float, float, 0>(x)"
     # FETCH_SIZE books 128-byte requests as 64 bytes: the 1 GiB copy reads as 524288 KiB
     _write_run(str(tmp_path / "f"), "FETCH_SIZE", 524288.0, [(name, 300000.0), (name, 310000.0), (diag, 9e9)])
@@ -85,7 +91,56 @@ def test_ingest_counters(tmp_path):
     assert bench.stored_traffic(str(out), "spinodal4096:f32:shape8") is None
 
 
+def test_counter_table(tmp_path, capsys):
+    """Per-dispatch means, per-update instruction counts (a two-step pass
+    performs two updates per node) and the VALU issue fraction."""
+    p2 = "void lbmwet::k_step_pass2<float, float, 0, 1, 24, 12, 1>(lbmwet::LatDev<float>, void const*, void*)"
+    nodes = 4096 * 4096
+    _write_run(str(tmp_path / "a"), "SQ_INSTS_VALU", 1.0, [(p2, 100.0 * nodes / 64 * 2), (p2, 100.0 * nodes / 64 * 2)])
+    _write_run(str(tmp_path / "b"), "GRBM_GUI_ACTIVE", 1.0, [(p2, 8 * 1000.0), (p2, 8 * 1000.0)])
+    out = bench.counter_table([str(tmp_path / "a"), str(tmp_path / "b")], "spinodal4096")
+    k = "k_step_pass2<float, float, 0, 1, 24, 12, 1>"
+    assert out[k]["SQ_INSTS_VALU"] == 100.0 * nodes / 32
+    assert out[k]["valu_issue_fraction"] == pytest.approx(100.0 * nodes / 32 / (1000.0 * 256))
+    assert "| 100.0 |" in capsys.readouterr().out
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def _rec(rid, arrival, solve, **kw):
+    r = {"rid": rid, "kind": "angle", "nx": 32, "ny": 32, "arrival": arrival, "solve_s": solve, "steps": 100,
+         "converged": True, "floor": False, "rest": False, "residual": 1e-6, "value": [], "error": ""}
+    r.update(kw)
+    return r
+
+
+def test_fifo_schedule():
+    """One server in arrival order: a request waits for the previous finish or
+    its own arrival, whichever is later."""
+    out = bench.fifo_schedule([_rec(1, 0.5, 2.0), _rec(0, 0.0, 1.0), _rec(2, 10.0, 1.0)])
+    assert [r["rid"] for r in out] == [0, 1, 2]
+    assert [r["finished"] for r in out] == [1.0, 3.0, 11.0]
+    assert [r["latency"] for r in out] == [1.0, 2.5, 1.0]
+    s = bench.summarize_records(out)
+    assert s["completed"] == 3 and s["elapsed_s"] == 11.0 and abs(s["solves_per_s"] - 3 / 11) < 1e-15
+
+
+def test_serving_combine(tmp_path):
+    cont = {"continuous": {"solves_per_s": 2.0, "p99_s": 4.0}}
+    a = {"sequential_records": [_rec(0, 0.0, 1.0), _rec(1, 0.1, 1.0)], "sequential_two_step": 7}
+    b = {"sequential_records": [_rec(2, 0.2, 3.0, rest=True)], "sequential_two_step": 7}
+    paths = []
+    for k, d in enumerate((cont, a, b)):
+        paths.append(str(tmp_path / f"{k}.json"))
+        json.dump(d, open(paths[-1], "w"))
+    out = bench.serving_combine(paths, 3, 1000, 1e-5, 1 << 20)
+    q = out["sequential"]
+    assert q["elapsed_s"] == 5.0 and q["p99_s"] > 4.7 and q["converged_at_rest"] == 1 and q["two_step"] == 7
+    assert out["p99_speedup"] == round(q["p99_s"] / 4.0, 2)
+    json.dumps(out)
+    with pytest.raises(SystemExit):
+        bench.serving_combine(paths[:2], 3, 1000, 1e-5, 1 << 20)

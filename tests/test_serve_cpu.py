@@ -1,5 +1,7 @@
 """Host logic of the server that needs no GPU: the binary32 residual-floor
-detector and the warm start of slip queries."""
+detector, the stalled-noise signal of the rest rule, the warm start of slip
+queries and the JSON-safe summary."""
+import json
 import math
 
 import numpy as np
@@ -28,6 +30,34 @@ def test_floor_not_detected_while_decaying():
 def test_floor_not_detected_above_ceiling():
     f = serve.Floor(window=10, ceiling=1e-4)
     assert not any(f.add(2e-4) for _ in range(100))
+
+
+def test_noise_residual_marks_stalled_not_floor():
+    """Residuals of two independent noise fields hover about sqrt(2): the
+    detector reports a stall at that level (the server then checks |u|), and
+    never a floor (above the ceiling)."""
+    rng = np.random.default_rng(3)
+    f = serve.Floor(window=50)
+    floors = [f.add(v) for v in np.sqrt(2) * (1 + 0.05 * rng.standard_normal(100))]
+    assert not any(floors)
+    assert f.stalled and f.level >= serve.NOISE_RESIDUAL
+
+
+def test_slow_motion_is_not_noise():
+    """A coherent slow flow (residual 1e-3, stalled) stays below the noise
+    level, so the rest rule does not apply to it."""
+    f = serve.Floor(window=50)
+    for _ in range(100):
+        f.add(1e-3)
+    assert f.stalled and f.level < serve.NOISE_RESIDUAL
+
+
+def test_summary_is_json():
+    res = [serve.Result(0, "angle", 8, 8, 0.0, 0.0, 1.0, 100, np.bool_(True), np.bool_(True), False, 1e-5),
+           serve.Result(1, "slip", 8, 8, 0.5, 0.5, 2.0, 200, True, False, True, 1.4)]
+    d = serve.summarize(res, 2.0)
+    json.dumps(d)
+    assert d["converged"] == 2 and d["converged_at_floor"] == 1 and d["converged_at_rest"] == 1
 
 
 def test_slip_warm_start_is_the_no_slip_profile():
