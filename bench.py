@@ -80,17 +80,32 @@ def pass2_desc(v):
             f"({ts * wps} waves), populations between the steps in LDS")
 
 
-def stored_traffic(path, key):
+def stored_traffic(path, key, field="bytes_per_launch"):
     """HBM bytes per launch of the step kernel (workload:storage:shape) from
-    rocprofv3 FETCH_SIZE + WRITE_SIZE runs, scaled by a 1 GiB copy; None if
-    absent or counted on other kernels."""
+    rocprofv3 FETCH_SIZE + WRITE_SIZE runs, scaled by a 1 GiB copy (or another
+    field of the same record: "valu_insts"); None if absent or counted on
+    other kernels."""
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh).get(key)
     if not rec or rec.get("kernel_sources_sha256") != kernel_sources_digest(workload_q(key.split(":")[0])):
         return None
-    return rec["bytes_per_launch"]
+    return rec.get(field)
+
+
+# VALU issue peak: 256 CUs x 2.4 GHz, one wave64 VALU instruction per CU and
+# cycle (four SIMDs, each taking a wave64 instruction every four cycles)
+VALU_PEAK_WAVE_INSTS = 256 * 2.4e9
+
+
+def alu_roofline(valu_insts, kernel_ms):
+    rate = valu_insts / (kernel_ms * 1e-3)
+    return {"bound": "alu", "achieved": round(rate / 1e9, 2), "peak": VALU_PEAK_WAVE_INSTS / 1e9,
+            "unit": "G VALU wave-instructions/s", "frac": round(rate / VALU_PEAK_WAVE_INSTS, 4),
+            "valu_insts_per_launch": valu_insts,
+            "note": "VALU instructions per launch from a rocprofv3 SQ_INSTS_VALU run (profiles/traffic.json) "
+                    "over the live launch time"}
 
 
 def _counter_rows(run_dir):
@@ -123,12 +138,19 @@ def _step_dispatch_key(name):
     return None
 
 
-def ingest_counters(fetch_dir, write_dir, workload, storage, out_json):
+def ingest_counters(fetch_dir, write_dir, workload, storage, out_json, valu_dir=None):
     """Per-launch HBM bytes of the step kernel from one rocprofv3 FETCH_SIZE
     run and one WRITE_SIZE run of `bench.py --copy-ref` on the same workload:
     each counter's KiB scaled by what it reads for the 1 GiB reference copy.
-    Updates out_json and prints a markdown table."""
+    With valu_dir (a run that counted SQ_INSTS_VALU), also the VALU wave
+    instructions per launch.  Updates out_json and prints a markdown table."""
     import collections
+    valu = collections.defaultdict(list)
+    if valu_dir is not None:
+        for r in _counter_rows(valu_dir):
+            k = _step_dispatch_key(r["Kernel_Name"])
+            if k is not None and r["Counter_Name"] == "SQ_INSTS_VALU":
+                valu[k].append(float(r["Counter_Value"]))
 
     def per_key(run_dir):
         by = collections.defaultdict(list)
@@ -166,6 +188,8 @@ def ingest_counters(fetch_dir, write_dir, workload, storage, out_json):
             "bytes_per_launch": round(rd + wr), "read_bytes": round(rd), "write_bytes": round(wr),
             "fetch_kib": round(f, 2), "write_kib": round(w, 2), "fetch_scale": round(fs, 5),
             "write_scale": round(ws, 5), "kernel_sources_sha256": kernel_sources_digest(q)}
+        if valu.get(k):
+            data[traffic_key(workload, storage, k)]["valu_insts"] = round(sum(valu[k]) / len(valu[k]))
         a = alg * (2 if isinstance(k, str) else 1)    # two updates per launch
         print(f"| {k if q == 9 else q21_label(k)} | {len(fb[k])} | {f:,.0f} | {rd:,.0f} | {rd / a:.3f} | {w:,.0f} | {wr / a:.3f} | "
               f"{(rd + wr) / (2 * a):.3f} |")
@@ -215,6 +239,28 @@ def counter_table(run_dirs, workload=None):
             frac = out[k]["SQ_INSTS_VALU"] / (out[k]["GRBM_GUI_ACTIVE"] / 8 * 256)
             out[k]["valu_issue_fraction"] = frac
             print(f"| `{k}` | VALU issue fraction | | {frac:.3f} | |")
+    return out
+
+
+def trace_table(run_dir, top=25):
+    """Markdown table of a rocprofv3 --kernel-trace --stats run (the
+    *_kernel_stats.csv under run_dir): calls and durations per kernel."""
+    import csv
+    import glob
+    files = sorted(glob.glob(os.path.join(run_dir, "**", "*_kernel_stats.csv"), recursive=True))
+    if not files:
+        sys.exit(f"no *_kernel_stats.csv under {run_dir}")
+    with open(files[-1]) as fh:
+        rows = list(csv.DictReader(fh))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    print("| Kernel | Calls | Avg (us) | Min (us) | Max (us) | % time |")
+    print("|---|---|---|---|---|---|")
+    out = {}
+    for r in rows[:top]:
+        k = _short_kernel(r["Name"])
+        out[k] = float(r["AverageNs"]) / 1e3
+        print(f"| `{k}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+              f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
     return out
 
 
@@ -957,22 +1003,33 @@ def main():
                     help="projected: the projection step onto eq. f2 before the collision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--trace-table", default=None,
+                    help="print the kernel statistics of a rocprofv3 --kernel-trace --stats run (directory) as a "
+                         "markdown table (no GPU work)")
     ap.add_argument("--counter-table", nargs="+", default=None,
                     help="print the per-kernel means of rocprofv3 --pmc runs (directories) as a markdown table, "
                          "per lattice update for --workload (no GPU work)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="after timing, run one plain device copy of 1 GiB (reference dispatch for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
-    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="no GPU work: read the rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE output directories of "
-                         "`bench.py --copy-ref` runs on --workload/--storage and record the step kernel's "
-                         "HBM bytes per launch in --traffic-json")
+    ap.add_argument("--ingest-counters", nargs="+", metavar="DIR",
+                    help="no GPU work: FETCH_DIR WRITE_DIR [VALU_DIR]: read the rocprofv3 --pmc FETCH_SIZE and "
+                         "WRITE_SIZE output directories of `bench.py --copy-ref` runs on --workload/--storage (and "
+                         "optionally a run that counted SQ_INSTS_VALU) and record the step kernel's HBM bytes "
+                         "(and VALU instructions) per launch in --traffic-json")
     args = ap.parse_args()
     if args.ingest_counters:
-        ingest_counters(*args.ingest_counters, args.workload, args.storage, args.traffic_json)
+        if len(args.ingest_counters) not in (2, 3):
+            sys.exit("--ingest-counters FETCH_DIR WRITE_DIR [VALU_DIR]")
+        fd, wd = args.ingest_counters[:2]
+        vd = args.ingest_counters[2] if len(args.ingest_counters) == 3 else None
+        ingest_counters(fd, wd, args.workload, args.storage, args.traffic_json, valu_dir=vd)
         return
     if args.counter_table:
         counter_table(args.counter_table, args.workload)
+        return
+    if args.trace_table:
+        trace_table(args.trace_table)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the update is measured on a "
@@ -1027,6 +1084,12 @@ def main():
         "metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.storage, "data": "synthetic",
+        "dtype_note": (("storage type of the populations; per-node arithmetic in binary32 except the momentum after "
+                        "the force and the equilibrium's rest and momentum terms, formed in binary64 and rounded once "
+                        "per population") if args.storage in ("f32", "f16dev") and q == 9 else
+                       ("storage type of the populations; per-node arithmetic in binary32 except the momentum after "
+                        "the force, formed in binary64 and rounded once") if args.storage == "f32" else
+                       "storage and arithmetic type"),
         "config": {"workload": WORKLOADS[args.workload][2], "nx": WORKLOADS[args.workload][0],
                    "ny": WORKLOADS[args.workload][1], "storage": args.storage,
                    "lattice": f"D2Q{q}", "tau": args.tau, "collision": args.collision,
@@ -1050,6 +1113,9 @@ def main():
                                    "advances 2 time steps with the populations between them kept in LDS")
         # the same launch counted as two single steps' algorithmic bytes (can exceed the peak)
         out["roofline"]["equiv_single_step_gbs"] = round(upl * achieved, 1)
+    valu = stored_traffic(args.traffic_json, traffic_key(args.workload, args.storage, key), "valu_insts")
+    if valu is not None:
+        out["roofline"]["alu"] = alu_roofline(valu, r["kernel_ms_mean"])
     if traffic is not None:
         # bytes that actually crossed to memory per second (counters), beside the algorithmic rate
         out["roofline"]["hbm_gbs_from_traffic"] = round(traffic / (r["kernel_ms_mean"] * 1e-3) / 1e9, 1)
@@ -1063,6 +1129,9 @@ def main():
             "achieved": round(s_ach, 1), "frac": round(s_ach / HBM_PEAK_GBS, 4),
             "traffic": stored_traffic(args.traffic_json, traffic_key(args.workload, args.storage, r["tile_shape"])),
             "note": "the same lattice stepped one step per launch right after the timed region, same step count"}
+        sv = stored_traffic(args.traffic_json, traffic_key(args.workload, args.storage, r["tile_shape"]), "valu_insts")
+        if sv is not None:
+            out["single_step"]["alu"] = alu_roofline(sv, sg["kernel_ms_mean"])
     out["copy_ceiling"] = copy_ceiling()
     out["copy_ceiling"]["step_fraction"] = round(achieved / out["copy_ceiling"]["value"], 4)
     out["device_copy"] = device_copy()

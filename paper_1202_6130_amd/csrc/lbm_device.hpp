@@ -9,6 +9,9 @@
 #include "launch.hpp"
 
 // Build-time switches (defaults are the production choice).
+#ifndef LBM_PASS2_PUSH
+#define LBM_PASS2_PUSH 0   // two-step pass: step-one populations pushed into the frame of their pulling nodes
+#endif
 #ifndef LBM_USE_BUFFER
 #define LBM_USE_BUFFER 1   // buffer loads/stores: scalar row offsets, 32-bit lane offsets
 #endif
@@ -87,15 +90,20 @@ enum WallMode : int { WALL_ROW = 0, WALL_NODE = 1 };
 // Raw is the register image of one stored population; decode/encode convert
 // between it and the arithmetic type C.
 template <class S> struct Codec;
+// saturated(v, q, rho_ref): the decoded population v is the image of a value
+// outside the encodable range (never for the floating-point storages, which
+// keep non-finite values as they are).
 template <> struct Codec<float> {
     using Raw = uint32_t;
     template <class C> __device__ static inline C decode(Raw r, int, C) { return C(__builtin_bit_cast(float, r)); }
     template <class C> __device__ static inline Raw encode(C v, int, C) { return __builtin_bit_cast(Raw, float(v)); }
+    template <class C> __device__ static inline bool saturated(C, int, C) { return false; }
 };
 template <> struct Codec<double> {
     using Raw = uint64_t;
     template <class C> __device__ static inline C decode(Raw r, int, C) { return C(__builtin_bit_cast(double, r)); }
     template <class C> __device__ static inline Raw encode(C v, int, C) { return __builtin_bit_cast(Raw, double(v)); }
+    template <class C> __device__ static inline bool saturated(C, int, C) { return false; }
 };
 // 16-bit storage of the deviation from the rest equilibrium, scaled by the
 // weight: h_i = f_i / w_i - rho_ref  <=>  f_i = w_i (rho_ref + h_i), kept as a
@@ -123,12 +131,23 @@ template <> struct Codec<Dev16> {
         const float k = float(int(int16_t(r)));
         return C(__builtin_fmaf(k, w(q) * kUnit, w(q) * float(rho_ref)));
     }
-    // k = rint(f / w 2^12 - rho_ref 2^12) with one rounding before rint (the
-    // scaled weights are exact), saturated to the int16 range.
+    // k = round(f / w 2^12 - rho_ref 2^12), one rounding in the fma (the scaled
+    // weights are exact), saturated to the int16 range (a NaN goes to one of
+    // the two bounds, by the maximum/minimum rules for NaN operands), then
+    // rounded to the nearest integer (ties to even) by adding 1.5 * 2^23: the
+    // sum's mantissa holds 2^22 + k, so its low 16 bits are k in two's
+    // complement.
     template <class C> __device__ static inline Raw encode(C v, int q, C rho_ref) {
 #pragma clang fp contract(off)
-        const float x = __builtin_rintf(__builtin_fmaf(float(v), winv(q) * kScale, -(float(rho_ref) * kScale)));
-        return Raw(int16_t(int(__builtin_fminf(__builtin_fmaxf(x, -32768.0f), 32767.0f))));
+        const float x = __builtin_fmaf(float(v), winv(q) * kScale, -(float(rho_ref) * kScale));
+        const float c = __builtin_fminf(__builtin_fmaxf(x, -32768.0f), 32767.0f) + 0x1.8p23f;
+        return Raw(__builtin_bit_cast(uint32_t, c) & 0xffffu);
+    }
+    // A stored code at either bound (-32768, 32767) is a value that did not
+    // fit: the diagnostic pass counts such nodes as unstable, as it counts
+    // non-finite ones in the floating-point storages.
+    template <class C> __device__ static inline bool saturated(C v, int q, C rho_ref) {
+        return v == decode<C>(Raw(0x8000u), q, rho_ref) || v == decode<C>(Raw(0x7fffu), q, rho_ref);
     }
 };
 

@@ -85,6 +85,15 @@ def test_ingest_counters(tmp_path):
     assert rec["bytes_per_launch"] == rec["read_bytes"] + rec["write_bytes"]
     assert rec["kernel_sources_sha256"] == bench.kernel_sources_digest(9)
     assert bench.stored_traffic(str(out), "spinodal4096:f32:shape8") == rec["bytes_per_launch"]
+    assert "valu_insts" not in rec
+    # with a VALU run the record carries the instructions per launch and the ALU roofline follows
+    _write_run(str(tmp_path / "v"), "SQ_INSTS_VALU", 1.0, [(name, 4.0e7), (name, 5.0e7)])
+    bench.ingest_counters(str(tmp_path / "f"), str(tmp_path / "w"), "spinodal4096", "f32", str(out),
+                          valu_dir=str(tmp_path / "v"))
+    v = bench.stored_traffic(str(out), "spinodal4096:f32:shape8", "valu_insts")
+    assert v == 45000000
+    a = bench.alu_roofline(v, 0.1)
+    assert a["frac"] == round(4.5e7 / 1e-4 / (256 * 2.4e9), 4) and a["bound"] == "alu"
     data = json.loads(out.read_text())
     data["spinodal4096:f32:shape8"]["kernel_sources_sha256"] = "0" * 64
     out.write_text(json.dumps(data))
@@ -144,3 +153,16 @@ def test_serving_combine(tmp_path):
     json.dumps(out)
     with pytest.raises(SystemExit):
         bench.serving_combine(paths[:2], 3, 1000, 1e-5, 1 << 20)
+
+
+def test_trace_table(tmp_path, capsys):
+    d = tmp_path / "t" / "vm"
+    os.makedirs(d)
+    (d / "1_kernel_stats.csv").write_text(
+        '"Name","Calls","TotalDurationNs","AverageNs","Percentage","MinNs","MaxNs","StdDev"\n'
+        '"void lbmwet::k_step_tiles<float, float, 0, 8, 1>(lbmwet::LatDev<float>, void const*, void*)",4,'
+        '900000,225000.0,60.0,224000,226000,1.0\n'
+        '"__amd_rocclr_copyBuffer",2,600000,300000.0,40.0,1000,599000,1.0\n')
+    out = bench.trace_table(str(tmp_path / "t"))
+    assert out == {"k_step_tiles<float, float, 0, 8, 1>": 225.0, "__amd_rocclr_copyBuffer": 300.0}
+    assert "| `k_step_tiles<float, float, 0, 8, 1>` | 4 | 225.0 | 224.0 | 226.0 | 60.00 |" in capsys.readouterr().out

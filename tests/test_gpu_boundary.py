@@ -120,3 +120,32 @@ def test_create_takes_stacked_velocity(storage):
     fo = np.moveaxis(O.init(po, rho, ux, uy), -1, 0)
     tol = 1e-15 if storage == lbm.STORE_F64 else 6e-8
     assert np.abs(fg - fo).max() <= tol * np.abs(fo).max()
+
+
+def test_f16dev_saturation_counts_as_unstable():
+    """16-bit storage holds no non-finite values: a NaN and a population far
+    outside the encodable range (|f/w - rho_ref| >= 8) are stored at the
+    int16 bounds, read back as the bound's value, and the diagnostic pass
+    counts both nodes, as it counts non-finite nodes of the floating-point
+    storages (LBM_EUNSTABLE)."""
+    p, po, w, rho0 = drop(lbm.STORE_F16DEV, K=0)
+    p.rho_ref = 1.0
+    L = lbm.Lattice(p, rho0)
+    L.step(10)
+    f = L.get_state()
+    f[5, 12, 30] = np.nan
+    f[2, 20, 7] = 1e3
+    L.set_state(f, 10)
+    g = L.get_state()
+    w5, w2 = 1.0 / 36.0, 1.0 / 9.0
+    bounds5 = {np.float32(w5) * np.float32(1.0 - 8.0), np.float32(w5) * np.float32(1.0 + 8.0 - 2.0 ** -12)}
+    assert any(abs(g[5, 12, 30] - b) < 1e-6 for b in bounds5), g[5, 12, 30]
+    assert abs(g[2, 20, 7] - w2 * (1.0 + 8.0 - 2.0 ** -12)) < 1e-6
+    out = np.zeros(6)
+    code = lbm.lib().lbm_diagnostics(L.ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert code == lbm.LBM_EUNSTABLE and out[5] == 2, (code, out)
+    # the rest of the lattice is untouched
+    ok = np.ones(f.shape, bool)
+    ok[5, 12, 30] = ok[2, 20, 7] = False
+    assert np.abs(g[ok] - f[ok]).max() < 1e-12
+    L.close()

@@ -144,9 +144,10 @@ def test_spinodal_4096_vs_oracle():
             r_max = np.abs(dr).max() / np.abs(want_r).max()
             r_rms = np.sqrt(np.mean(dr ** 2)) / np.sqrt(np.mean(want_r ** 2))
             u_max = du.max() / CS
+            u_rel = du.max() / np.hypot(want_x, want_y).max()
             mass = abs(tot[0] - cp["totals"][0]) / cp["totals"][0]
             print(f"spinodal t={cp['t']} {name}: rho max rel {r_max:.2e}, rms rel {r_rms:.2e}, u/c_s {u_max:.2e}, "
-                  f"mass {mass:.2e}")
+                  f"u/max|u| {u_rel:.2e}, mass {mass:.2e}")
             if name == "f64":
                 assert r_max < 1e-9 and u_max < 1e-9 and mass < 1e-12
             elif cp["t"] <= 100:
@@ -181,9 +182,10 @@ def test_spinodal21_4096_vs_oracle():
             r_max = np.abs(dr).max() / np.abs(want_r).max()
             r_rms = np.sqrt(np.mean(dr ** 2)) / np.sqrt(np.mean(want_r ** 2))
             u_max = du.max() / cs
+            u_rel = du.max() / np.hypot(want_x, want_y).max()
             mass = abs(tot[0] - cp["totals"][0]) / cp["totals"][0]
             print(f"spinodal21 t={cp['t']} {name}: rho max rel {r_max:.2e}, rms rel {r_rms:.2e}, u/c_s {u_max:.2e}, "
-                  f"mass {mass:.2e}")
+                  f"u/max|u| {u_rel:.2e}, mass {mass:.2e}")
             if name == "f64":
                 assert r_max < 1e-9 and u_max < 1e-9 and mass < 1e-12
             elif cp["t"] <= 100:
@@ -223,12 +225,14 @@ def test_paper650_vs_oracle():
         for name, L in runs.items():
             rho, ux, uy, tot = L.moments()
             r_max = np.abs(rho[ys, xs] - want_r).max() / np.abs(want_r).max()
-            u_max = np.hypot(ux[ys, xs] - want_x, uy[ys, xs] - want_y).max() / cs
+            du = np.hypot(ux[ys, xs] - want_x, uy[ys, xs] - want_y).max()
+            u_max = du / cs
+            u_rel = du / np.hypot(want_x, want_y).max()
             mass = abs(tot[0] - cp["totals"][0]) / cp["totals"][0]
             ang = L.contact_angle(c["iso"], 0.0)
             d_ang = abs(ang[0] - cp["contact_angle"][0])
-            print(f"paper650 t={cp['t']} {name}: rho max rel {r_max:.2e}, u/c_s {u_max:.2e}, mass {mass:.2e}, "
-                  f"theta {ang[0]:.6f} (oracle {cp['contact_angle'][0]:.6f})")
+            print(f"paper650 t={cp['t']} {name}: rho max rel {r_max:.2e}, u/c_s {u_max:.2e}, u/max|u| {u_rel:.2e}, "
+                  f"mass {mass:.2e}, theta {ang[0]:.6f} (oracle {cp['contact_angle'][0]:.6f})")
             if name == "f64":
                 assert r_max < 1e-9 and u_max < 1e-9 and mass < 1e-12 and d_ang < 1e-6
             else:

@@ -101,8 +101,10 @@ def test_f32_drop_2000_steps_tolerance():
     fo = O.run(po, w, O.init(po, rho0), 2000)
     r_o, ux_o, uy_o, tot_o = O.macros(po, w, fo)
     e_rho = np.abs(rho - r_o).max() / np.abs(r_o).max()
-    e_u = max(np.abs(ux - ux_o).max(), np.abs(uy - uy_o).max()) / CS
-    print(f"FP32 drop 64x32 t=2000: rel rho err {e_rho:.3e}, u err / c_s {e_u:.3e}")
+    du = np.hypot(ux - ux_o, uy - uy_o).max()
+    e_u = du / CS
+    print(f"FP32 drop 64x32 t=2000: rel rho err {e_rho:.3e}, u err / c_s {e_u:.3e}, "
+          f"u err / max|u| {du / np.hypot(ux_o, uy_o).max():.3e}")
     assert e_rho <= 1e-5
     assert e_u <= 1e-5
     assert abs(tot[0] - tot_o[0]) / tot_o[0] < 1e-5
@@ -112,9 +114,13 @@ def test_f32_drop_2000_steps_tolerance():
 
 
 def test_f16dev_drop_error_bounded():
-    """FP16 deviation storage (rho_ref = mean density) with FP32 arithmetic:
-    the binary16 grid (~5e-4 relative) snaps bulk densities, so the bound is
-    the measured one with margin, not the FP32 bar."""
+    """16-bit storage (h = f/w - rho_ref as int16 fixed point in units of
+    2^-12, rho_ref = mean density) with FP32 arithmetic.  The storage grid
+    moves a node's density by up to 2^-13 per step from rounding alone, so
+    the bar is set by the storage, not by the FP32 arithmetic: density within
+    2e-2 of its maximum and velocity within 1e-2 of c_s after 2000 steps
+    (measured 8.2e-3 and 4.1e-3; at 4096^2 the density L2 error reaches 9e-5
+    within 100 steps)."""
     p, po, w, rho0 = drop_case(lbm.STORE_F16DEV)
     p.rho_ref = float(rho0.mean())
     L = lbm.Lattice(p, rho0)
@@ -125,7 +131,7 @@ def test_f16dev_drop_error_bounded():
     e_rho = np.abs(rho - r_o).max() / np.abs(r_o).max()
     e_u = max(np.abs(ux - ux_o).max(), np.abs(uy - uy_o).max()) / CS
     print(f"FP16-dev drop 64x32 t=2000: rel rho err {e_rho:.3e}, u err / c_s {e_u:.3e}")
-    assert e_rho < 3e-2 and e_u < 1e-2
+    assert e_rho < 2e-2 and e_u < 1e-2
     L.close()
 
 
