@@ -412,12 +412,7 @@ template <int TS, int OH, int WPS> struct Pass2Geo {
     static constexpr int W2 = OW + 4, H2 = OH + 4, N2 = W2 * H2;   // populations after step one
     static constexpr int W3 = OW + 2, H3 = OH + 2, N3 = W3 * H3;   // psi, step two
     static constexpr int K1 = (N1 + NT - 1) / NT, K2 = (N2 + NT - 1) / NT, K3 = (N3 + NT - 1) / NT;
-#if LBM_PASS2_PUSH
-    // step-one populations kept in the frame of the nodes that pull them (R3)
-    static constexpr size_t lds_bytes = sizeof(float) * (size_t(Q) * N3 + N1 + 2 * H2);
-#else
     static constexpr size_t lds_bytes = sizeof(float) * (size_t(Q) * N2 + N1 + 2 * H2);
-#endif
     static_assert(OH % WPS == 0, "output rows must split evenly over the waves of a strip");
 };
 
@@ -429,13 +424,8 @@ __device__ inline void pass2_block(const LatDev<C> &L, const void *src, void *ds
     using G = Pass2Geo<TS, OH, WPS>;
     using Raw = typename Codec<S>::Raw;
     constexpr int NT = G::NT, W1 = G::W1, W2 = G::W2, W3 = G::W3, N2 = G::N2;
-#if LBM_PASS2_PUSH
-    C *sf = reinterpret_cast<C *>(lds);          // [Q][N3] populations of step one, by pulling node
-    C *sp = sf + Q * G::N3;                      // [N1] psi of step one, then [N3] psi of step two
-#else
     C *sf = reinterpret_cast<C *>(lds);          // [Q][N2] populations of step one
     C *sp = sf + Q * N2;                         // [N1] psi of step one, then [N3] psi of step two
-#endif
     C *sw = sp + G::N1;                          // [H2][2] row wall terms of step one (WALL_ROW)
     const uint32_t nx = L.nx, ny = L.ny, P = L.pstride;
     const uint32_t X0 = group * uint32_t(G::OW), Y0 = trow * uint32_t(OH);
@@ -459,96 +449,6 @@ __device__ inline void pass2_block(const LatDev<C> &L, const void *src, void *ds
         sw[2 * tid + 1] = rw.Sy;
     }
 
-#if LBM_PASS2_PUSH
-    // R1: pulled populations, density and psi of step one.  The populations of
-    // the R2 nodes stay in registers: the same thread collides them after the
-    // barrier.
-    constexpr int N3 = G::N3;
-    C fk[G::K1][Q];
-    {
-        PopBuf<S> in;
-        in.init(src, 9u * P * uint32_t(sizeof(S)));
-        Raw raw[G::K1][Q];
-#pragma unroll
-        for (int k = 0; k < G::K1; ++k) {
-            const int i = tid + k * NT;
-            if ((k + 1) * NT <= G::N1 || i < G::N1) {
-                const int r = i / W1, c = i - r * W1;
-                const uint32_t x = wrap(X0 + kx - 3u + uint32_t(c), nx);
-                const uint32_t y = wrap(Y0 + ky - 3u + uint32_t(r), ny);
-                const uint32_t xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
-                const uint32_t r0 = y * nx, rm = wrap_dec(y, ny) * nx, rp = wrap_inc(y, ny) * nx;
-                raw[k][0] = in.load(r0 + x, 0);
-                raw[k][1] = in.load(r0 + xm, P);
-                raw[k][2] = in.load(rm + x, 2 * P);
-                raw[k][3] = in.load(r0 + xp, 3 * P);
-                raw[k][4] = in.load(rp + x, 4 * P);
-                raw[k][5] = in.load(rm + xm, 5 * P);
-                raw[k][6] = in.load(rm + xp, 6 * P);
-                raw[k][7] = in.load(rp + xp, 7 * P);
-                raw[k][8] = in.load(rp + xm, 8 * P);
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < G::K1; ++k) {
-            const int i = tid + k * NT;
-            if ((k + 1) * NT <= G::N1 || i < G::N1) {
-                decode_row<S, C>(raw[k], fk[k], rref);
-                sp[i] = psi_of<C>(density<C>(fk[k]));
-            }
-        }
-    }
-    __syncthreads();
-
-    // R2: forces and collision of step one; each outgoing population goes to
-    // the R3 node that pulls it (R3 frame, plane-major), after the storage
-    // round trip a store and the next load would make
-#pragma unroll
-    for (int k = 0; k < G::K1; ++k) {
-        const int i = tid + k * NT;
-        if (!((k + 1) * NT <= G::N1 || i < G::N1)) continue;
-        const int r = i / W1, c = i - r * W1;
-        if (r < 1 || r >= G::H1 - 1 || c < 1 || c >= W1 - 1) continue;
-        const int r2 = r - 1, c2 = c - 1;
-        const C *p = sp + i;
-        C sx, sy;
-        psi_sums<C>(p[W1], p[-W1], p[-1], p[W1 - 1], p[-W1 - 1], p[1], p[W1 + 1], p[-W1 + 1], sx, sy);
-        C *f = fk[k];
-        const C rho = density<C>(f);
-        C phie, Sx, Sy;
-        if (WALL == WALL_ROW) {
-            phie = sw[2 * r2];
-            Sx = C(0);
-            Sy = sw[2 * r2 + 1];
-        } else {
-            const uint32_t x = wrap(X0 + kx - 2u + uint32_t(c2), nx);
-            const uint32_t y = wrap(Y0 + ky - 2u + uint32_t(r2), ny);
-            wall_terms<C, WALL>(L, RowWall<C>{C(0), C(0)}, y * nx + x, phie, Sx, Sy);
-        }
-        NodeState<C> s = node_forces<C>(f, rho, p[0], sx, sy, phie, Sx, Sy, L.G, L.Ux, L.Uy, L.Fx, L.Fy);
-        collide<C, ONE>(f, s, L.omega, L.collision);
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int r3 = r2 - 1 + kCy[q], c3 = c2 - 1 + kCx[q];
-            if (r3 >= 0 && r3 < G::H3 && c3 >= 0 && c3 < W3)
-                sf[q * N3 + r3 * W3 + c3] =
-                    Codec<S>::template decode<C>(Codec<S>::template encode<C>(f[q], q, rref), q, rref);
-        }
-    }
-    __syncthreads();
-
-    // R3: populations of step two (own slots), density and psi of step two
-#pragma unroll
-    for (int k = 0; k < G::K3; ++k) {
-        const int i = tid + k * NT;
-        if (!((k + 1) * NT <= G::N3 || i < G::N3)) continue;
-        C f[Q];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) f[q] = sf[q * N3 + i];
-        sp[i] = psi_of<C>(density<C>(f));
-    }
-    __syncthreads();
-#else
     // R1: pulled populations, density and psi of step one; populations of R2 to LDS
     {
         PopBuf<S> in;
@@ -654,16 +554,10 @@ __device__ inline void pass2_block(const LatDev<C> &L, const void *src, void *ds
         const int r4 = wr * (OH / WPS) + jr;
         const uint32_t y = Y0 + uint32_t(r4);
         if (y >= ny) break;
-        C f[Q];
-#if LBM_PASS2_PUSH
-        const int j = (r4 + 1) * W3 + (c4 + 1);
-#pragma unroll
-        for (int q = 0; q < Q; ++q) f[q] = sf[q * G::N3 + j];
-#else
         const int j = (r4 + 2) * W2 + (c4 + 2);
+        C f[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) f[q] = sf[q * N2 + j - kCy[q] * W2 - kCx[q]];
-#endif
         const C rho = density<C>(f);
         const C *p = sp + (r4 + 1) * W3 + (c4 + 1);
         C sx, sy;

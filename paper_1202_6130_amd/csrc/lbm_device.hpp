@@ -9,9 +9,6 @@
 #include "launch.hpp"
 
 // Build-time switches (defaults are the production choice).
-#ifndef LBM_PASS2_PUSH
-#define LBM_PASS2_PUSH 0   // two-step pass: step-one populations pushed into the frame of their pulling nodes
-#endif
 #ifndef LBM_USE_BUFFER
 #define LBM_USE_BUFFER 1   // buffer loads/stores: scalar row offsets, 32-bit lane offsets
 #endif
