@@ -94,9 +94,11 @@ def stored_traffic(path, key, field="bytes_per_launch"):
     return rec.get(field)
 
 
-# VALU issue peak: 256 CUs x 2.4 GHz, one wave64 VALU instruction per CU and
-# cycle (four SIMDs, each taking a wave64 instruction every four cycles)
-VALU_PEAK_WAVE_INSTS = 256 * 2.4e9
+# VALU issue peak from the FP32 vector rate (157.3 TFLOP/s = 256 CUs x 2.4 GHz
+# x 2 wave64 FMA instructions per CU and cycle x 64 lanes x 2 flops): two
+# wave64 VALU instructions per CU and cycle; binary64 arithmetic issues at half
+# that rate (78.6 TFLOP/s), so a mix with binary64 work tops out lower
+VALU_PEAK_WAVE_INSTS = 256 * 2.4e9 * 2
 
 
 def alu_roofline(valu_insts, kernel_ms):
@@ -176,9 +178,10 @@ def ingest_counters(fetch_dir, write_dir, workload, storage, out_json, valu_dir=
         with open(out_json) as fh:
             data = json.load(fh)
     print(f"FETCH_SIZE copy {fc:,.1f} KiB (scale {fs:.4f}), WRITE_SIZE copy {wc:,.1f} KiB (scale {ws:.4f}); "
-          f"algorithmic {alg:,} B each way per launch of one time step (twice that for a two-step pass)\n")
-    print("| Kernel / shape | dispatches | FETCH_SIZE KiB | read bytes (scaled) | read / algorithmic | "
-          "WRITE_SIZE KiB | write / algorithmic | total / algorithmic |")
+          f"compulsory {alg:,} B each way per launch (every stored population read once and written once, "
+          f"for one time step or two)\n")
+    print("| Kernel / shape | dispatches | FETCH_SIZE KiB | read bytes (scaled) | read / compulsory | "
+          "WRITE_SIZE KiB | write / compulsory | total / compulsory |")
     print("|---|---|---|---|---|---|---|---|")
     for k in sorted(fb, key=str):
         f = sum(fb[k]) / len(fb[k])
@@ -190,7 +193,7 @@ def ingest_counters(fetch_dir, write_dir, workload, storage, out_json, valu_dir=
             "write_scale": round(ws, 5), "kernel_sources_sha256": kernel_sources_digest(q)}
         if valu.get(k):
             data[traffic_key(workload, storage, k)]["valu_insts"] = round(sum(valu[k]) / len(valu[k]))
-        a = alg * (2 if isinstance(k, str) else 1)    # two updates per launch
+        a = alg
         print(f"| {k if q == 9 else q21_label(k)} | {len(fb[k])} | {f:,.0f} | {rd:,.0f} | {rd / a:.3f} | {w:,.0f} | {wr / a:.3f} | "
               f"{(rd + wr) / (2 * a):.3f} |")
     with open(out_json, "w") as fh:
@@ -207,9 +210,9 @@ def counter_table(run_dirs, workload=None):
     counter per dispatch.  With a single-lattice workload, the SQ instruction
     counts per lattice update (wave instructions x 64 lanes / (nodes x
     updates per launch)) and the VALU issue fraction: SQ_INSTS_VALU over
-    (GRBM_GUI_ACTIVE / 8 XCDs) x 256 CUs, a CU issuing at most one VALU
-    instruction per cycle (four SIMDs, a wave64 instruction each every four
-    cycles).  Prints the table; returns {kernel: {counter: mean}}."""
+    (GRBM_GUI_ACTIVE / 8 XCDs) x 256 CUs x 2, a CU issuing at most two wave64
+    VALU instructions per cycle (the FP32 vector rate).  Prints the table;
+    returns {kernel: {counter: mean}}."""
     import collections
     vals = collections.defaultdict(lambda: collections.defaultdict(list))
     for d in run_dirs:
@@ -236,7 +239,7 @@ def counter_table(run_dirs, workload=None):
                 per = f"{m * 64 / (nodes * ups):.1f}"
             print(f"| `{k}` | {c} | {len(v)} | {m:,.0f} | {per} |")
         if "SQ_INSTS_VALU" in out[k] and "GRBM_GUI_ACTIVE" in out[k]:
-            frac = out[k]["SQ_INSTS_VALU"] / (out[k]["GRBM_GUI_ACTIVE"] / 8 * 256)
+            frac = out[k]["SQ_INSTS_VALU"] / (out[k]["GRBM_GUI_ACTIVE"] / 8 * 256 * 2)
             out[k]["valu_issue_fraction"] = frac
             print(f"| `{k}` | VALU issue fraction | | {frac:.3f} | |")
     return out

@@ -93,7 +93,7 @@ def test_ingest_counters(tmp_path):
     v = bench.stored_traffic(str(out), "spinodal4096:f32:shape8", "valu_insts")
     assert v == 45000000
     a = bench.alu_roofline(v, 0.1)
-    assert a["frac"] == round(4.5e7 / 1e-4 / (256 * 2.4e9), 4) and a["bound"] == "alu"
+    assert a["frac"] == round(4.5e7 / 1e-4 / (256 * 2.4e9 * 2), 4) and a["bound"] == "alu"
     data = json.loads(out.read_text())
     data["spinodal4096:f32:shape8"]["kernel_sources_sha256"] = "0" * 64
     out.write_text(json.dumps(data))
@@ -110,7 +110,7 @@ def test_counter_table(tmp_path, capsys):
     out = bench.counter_table([str(tmp_path / "a"), str(tmp_path / "b")], "spinodal4096")
     k = "k_step_pass2<float, float, 0, 1, 24, 12, 1>"
     assert out[k]["SQ_INSTS_VALU"] == 100.0 * nodes / 32
-    assert out[k]["valu_issue_fraction"] == pytest.approx(100.0 * nodes / 32 / (1000.0 * 256))
+    assert out[k]["valu_issue_fraction"] == pytest.approx(100.0 * nodes / 32 / (1000.0 * 256 * 2))
     assert "| 100.0 |" in capsys.readouterr().out
 
 
