@@ -537,8 +537,6 @@ __device__ inline void pass2_block(const LatDev<C> &L, const void *src, void *ds
     }
     __syncthreads();
 
-#endif
-
     // output block: lane = column, WPS waves per 64-column strip, OH / WPS rows each
     const int lane = tid & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(tid / kWave);
