@@ -21,6 +21,18 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
 
 
+def test_library_built_from_current_sources():
+    """The library that the tests load is newer than every source it is built
+    from (a stale library would hide a source that no longer compiles)."""
+    if not os.path.exists(lbm.LIB_PATH):
+        pytest.skip("library not built")
+    csrc = os.path.join(ROOT, "paper_1202_6130_amd", "csrc")
+    srcs = [os.path.join(csrc, f) for f in os.listdir(csrc)] + [HEADER]
+    built = os.path.getmtime(lbm.LIB_PATH)
+    newer = [os.path.relpath(f, ROOT) for f in srcs if os.path.getmtime(f) > built]
+    assert not newer, f"rebuild (python -m paper_1202_6130_amd.build): newer sources {newer}"
+
+
 def test_library_exports_every_declared_symbol():
     L = ctypes.CDLL(lbm.LIB_PATH)
     names = declared_functions()
