@@ -6,7 +6,7 @@ A "step" is one time step of the whole update (pull-stream, moments,
 pseudo-potential forces, wall forces, EDM-BGK collision, store) on the
 workload lattice, with the diagnostic pass (FP64 totals, residual, non-finite
 check) every 100 steps inside the timed region.  Inputs are resident in HBM
-before timing starts.  On D2Q9 lattices with F32 or F16DEV storage the
+before timing starts.  On D2Q9 lattices (F32, F16DEV or F64 storage) the
 warm-up autotunes the tile shape and then the choice between one step per
 launch and two steps per launch (temporal blocking: the populations between
 the two steps stay in LDS; bitwise the same fields).  Prints one JSON line.
@@ -401,7 +401,7 @@ def time_gpu(name, storage, steps, warmup, seg_rows, tile=None, tau=1.0, collisi
     """tile None: the autotuner picks the D2Q9 tile shape during the
     warm-up (its steps count as warm-up), and a D2Q21 lattice keeps the step
     variant a new context starts with; else the given shape or variant.
-    two_step None: for D2Q9 with F32 or F16DEV storage, a second autotuner
+    two_step None: for D2Q9 with F32, F16DEV or F64 storage, a second autotuner
     chooses between single steps and two steps per pass; -1: single steps;
     V >= 0: that two-step variant.  With two steps per pass, the same number
     of single steps is timed afterwards as well (the "single" entry)."""
@@ -411,7 +411,7 @@ def time_gpu(name, storage, steps, warmup, seg_rows, tile=None, tau=1.0, collisi
     nodes = p.nx * p.ny
     q = workload_q(name)
     tune_ms = two_ms = None
-    pass2_ok = q == 9 and storage in ("f32", "f16dev")
+    pass2_ok = q == 9 and storage in ("f32", "f16dev", "f64")
     budget = warmup // 2 if (two_step is None and pass2_ok) else warmup
     if tile is not None:
         L.tile_shape = tile
@@ -986,7 +986,7 @@ def main():
                     help="D2Q9 tile shape index (default: autotuned in the warm-up), or D2Q21 step variant "
                          "(default: the one a new context starts with)")
     ap.add_argument("--two-step", type=int, default=None,
-                    help="D2Q9 F32/F16DEV: two time steps per launch with this variant (lbm_two_step_variants), "
+                    help="D2Q9 F32/F16DEV/F64: two time steps per launch with this variant (lbm_two_step_variants), "
                          "-1 for single steps (default: autotuned in the warm-up)")
     ap.add_argument("--seq-steps", type=int, default=500, help="ensemble: steps per lattice of the sequential leg")
     ap.add_argument("--requests", type=int, default=300, help="serve: number of requests")

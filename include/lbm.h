@@ -340,7 +340,7 @@ int32_t lbm_get_tile_shape(const lbm_ctx *c);
 
 /* Two time steps per pass (temporal blocking; Sec. II.A streaming and the
  * collision of eq. BE-BGK applied twice).  With a variant v >= 0 set,
- * lbm_step advances D2Q9 lattices with F32 or F16DEV storage two steps per
+ * lbm_step advances D2Q9 lattices with F32, F16DEV or F64 storage two steps per
  * kernel launch: each workgroup reads a block of 64 * strips[v] columns x
  * rows[v] rows plus a halo of four nodes, computes the first step on the
  * block grown by two nodes with the populations kept in on-chip memory, and

@@ -1334,7 +1334,7 @@ lbm_status lbm_set_two_step(lbm_ctx *c, int32_t variant) {
     if (c->view) return fail(LBM_ESTATE, "lattice belongs to a batch");
     if (variant < -1 || variant >= kPass2Variants) return fail(LBM_EINVAL, "two-step variant %d out of range", variant);
     if (variant >= 0 && (c->p.lattice != LBM_D2Q9 || !pass2_ok(kernel_storage(c->p.storage))))
-        return fail(LBM_EINVAL, "two steps per pass need a D2Q9 lattice with F32 or F16DEV storage");
+        return fail(LBM_EINVAL, "two steps per pass need a D2Q9 lattice with F32, F16DEV or F64 storage");
     c->pass2 = variant;
     return LBM_OK;
 }

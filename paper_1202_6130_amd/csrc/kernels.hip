@@ -412,7 +412,8 @@ template <int TS, int OH, int WPS> struct Pass2Geo {
     static constexpr int W2 = OW + 4, H2 = OH + 4, N2 = W2 * H2;   // populations after step one
     static constexpr int W3 = OW + 2, H3 = OH + 2, N3 = W3 * H3;   // psi, step two
     static constexpr int K1 = (N1 + NT - 1) / NT, K2 = (N2 + NT - 1) / NT, K3 = (N3 + NT - 1) / NT;
-    static constexpr size_t lds_bytes = sizeof(float) * (size_t(Q) * N2 + N1 + 2 * H2);
+    static constexpr size_t lds_words = size_t(Q) * N2 + N1 + 2 * H2;   // in elements of the arithmetic type
+    static constexpr size_t lds_bytes = sizeof(float) * lds_words;
     static_assert(OH % WPS == 0, "output rows must split evenly over the waves of a strip");
 };
 
@@ -1063,26 +1064,27 @@ hipError_t launch_step_pass2(int storage, const LatDevAny &L, int wall, int vari
     if (!pass2_ok(storage) || L.lattice != 9) return hipErrorInvalidValue;
     auto go = [&](auto s, auto vc) -> hipError_t {
         using S = decltype(s);
+        using C = std::conditional_t<std::is_same_v<S, double>, double, float>;
         constexpr int V = decltype(vc)::value;
         using PV = Pass2Var<V>;
         using G = typename PV::G;
-        LatDev<float> d = L.get<float>();
+        LatDev<C> d = L.get<C>();
         const void *src = parity ? d.fb : d.fa;
         void *dst = parity ? d.fa : d.fb;
         const uint32_t nb = pass2_blocks(d.nx, d.ny, V);
-        const size_t lds = G::lds_bytes;
+        const size_t lds = G::lds_words * sizeof(C);
         const bool one = L.omega == 1.0;   // tau = 1: the instantiation compiled for it
         if (wall == WALL_ROW && one)
-            hipLaunchKernelGGL((k_step_pass2<S, float, WALL_ROW, PV::TS, PV::OH, PV::WPS, 1>), dim3(nb), dim3(G::NT),
+            hipLaunchKernelGGL((k_step_pass2<S, C, WALL_ROW, PV::TS, PV::OH, PV::WPS, 1>), dim3(nb), dim3(G::NT),
                                lds, st, d, src, dst);
         else if (wall == WALL_ROW)
-            hipLaunchKernelGGL((k_step_pass2<S, float, WALL_ROW, PV::TS, PV::OH, PV::WPS, 0>), dim3(nb), dim3(G::NT),
+            hipLaunchKernelGGL((k_step_pass2<S, C, WALL_ROW, PV::TS, PV::OH, PV::WPS, 0>), dim3(nb), dim3(G::NT),
                                lds, st, d, src, dst);
         else if (one)
-            hipLaunchKernelGGL((k_step_pass2<S, float, WALL_NODE, PV::TS, PV::OH, PV::WPS, 1>), dim3(nb), dim3(G::NT),
+            hipLaunchKernelGGL((k_step_pass2<S, C, WALL_NODE, PV::TS, PV::OH, PV::WPS, 1>), dim3(nb), dim3(G::NT),
                                lds, st, d, src, dst);
         else
-            hipLaunchKernelGGL((k_step_pass2<S, float, WALL_NODE, PV::TS, PV::OH, PV::WPS, 0>), dim3(nb), dim3(G::NT),
+            hipLaunchKernelGGL((k_step_pass2<S, C, WALL_NODE, PV::TS, PV::OH, PV::WPS, 0>), dim3(nb), dim3(G::NT),
                                lds, st, d, src, dst);
         return hipGetLastError();
     };
@@ -1102,6 +1104,7 @@ hipError_t launch_step_pass2(int storage, const LatDevAny &L, int wall, int vari
     };
     static_assert(kPass2Variants == 9, "launch_step_pass2 lists every variant");
     if (storage == STORE_F32) return with_var(float{});
+    if (storage == STORE_F64) return with_var(double{});
     return with_var(Dev16{});
 }
 

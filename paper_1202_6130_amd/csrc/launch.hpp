@@ -126,7 +126,7 @@ constexpr int kPass2Variants = 9;
 constexpr int kPass2Strips[kPass2Variants] = {1, 1, 2, 1, 1, 1, 1, 1, 1};
 constexpr int kPass2Rows[kPass2Variants] = {8, 8, 8, 12, 12, 16, 16, 24, 24};
 constexpr int kPass2WavesPerStrip[kPass2Variants] = {4, 8, 4, 6, 12, 8, 16, 8, 12};
-inline bool pass2_ok(int storage) { return storage == STORE_F32 || storage == STORE_F16; }
+inline bool pass2_ok(int storage) { return storage == STORE_F32 || storage == STORE_F16 || storage == STORE_F64; }
 constexpr uint32_t pass2_blocks(uint32_t nx, uint32_t ny, int v) {
     return ((nx + 64u * uint32_t(kPass2Strips[v]) - 1) / (64u * uint32_t(kPass2Strips[v]))) *
            ((ny + uint32_t(kPass2Rows[v]) - 1) / uint32_t(kPass2Rows[v]));

@@ -71,7 +71,8 @@ def test_channel_slip_vs_oracle(storage):
         assert slip_err < 1e-2 and prof_err < 1e-2
 
 
-@pytest.mark.parametrize("storage,two_step", [(lbm.STORE_F64, -1), (lbm.STORE_F32, -1), (lbm.STORE_F32, 6)])
+@pytest.mark.parametrize("storage,two_step", [(lbm.STORE_F64, -1), (lbm.STORE_F64, 1), (lbm.STORE_F32, -1),
+                                               (lbm.STORE_F32, 6)])
 def test_drop_1024_vs_oracle(storage, two_step):
     """Every node of the 1024x512 drop after 20000 steps against the oracle's
     full fields.  two_step 6: the variant the benchmark's autotuner keeps on

@@ -39,7 +39,7 @@ def test_variant_table():
     assert lbm.lbm_two_step_variants() == VARIANTS
 
 
-@pytest.mark.parametrize("storage", [lbm.STORE_F32, lbm.STORE_F16DEV])
+@pytest.mark.parametrize("storage", [lbm.STORE_F32, lbm.STORE_F16DEV, lbm.STORE_F64])
 @pytest.mark.parametrize("nx,ny", [(200, 96), (130, 71), (64, 15), (5, 6), (70, 1), (1, 40)])
 def test_every_variant_same_update(storage, nx, ny):
     wall = lbm.WALL_FLAT_SLAB if ny > 9 else lbm.WALL_NONE
@@ -51,15 +51,16 @@ def test_every_variant_same_update(storage, nx, ny):
         assert np.array_equal(got, ref), (storage, nx, ny, v)
 
 
-@pytest.mark.parametrize("tau,collision", [(1.0, lbm.COLL_BGK), (0.7, lbm.COLL_PROJECTED)])
-def test_every_variant_node_fields(tau, collision):
+@pytest.mark.parametrize("storage", [lbm.STORE_F32, lbm.STORE_F64])
+@pytest.mark.parametrize("tau,collision", [(1.0, lbm.COLL_BGK), (0.7, lbm.COLL_PROJECTED), (0.9, lbm.COLL_BGK)])
+def test_every_variant_node_fields(storage, tau, collision):
     nx, ny = 150, 77
     rho0 = I.random_state_field(nx, ny, 4)[0]
     fields = _fields(nx, ny, 5)
-    ref, _ = _run(nx, ny, lbm.STORE_F32, lbm.WALL_FIELDS, -1, 20, rho0, fields, tau=tau, collision=collision)
+    ref, _ = _run(nx, ny, storage, lbm.WALL_FIELDS, -1, 20, rho0, fields, tau=tau, collision=collision)
     for v in range(len(VARIANTS)):
-        print(f"two-step variant {v} node fields tau {tau}", flush=True)
-        got, _ = _run(nx, ny, lbm.STORE_F32, lbm.WALL_FIELDS, v, 20, rho0, fields, tau=tau, collision=collision)
+        print(f"two-step variant {v} node fields storage {storage} tau {tau}", flush=True)
+        got, _ = _run(nx, ny, storage, lbm.WALL_FIELDS, v, 20, rho0, fields, tau=tau, collision=collision)
         assert np.array_equal(got, ref), v
 
 
@@ -78,7 +79,7 @@ def test_diagnostic_schedule_kept():
 def test_refused_where_not_built():
     nx, ny = 64, 32
     rho0 = I.drop_field(nx, ny, 12.0)
-    for storage in (lbm.STORE_F64, lbm.STORE_F32X):
+    for storage in (lbm.STORE_F32X,):
         L = lbm.Lattice(lbm.lbm_params_default(nx=nx, ny=ny, storage=storage), rho0)
         with pytest.raises(lbm.LbmError):
             L.two_step = 0
@@ -115,7 +116,7 @@ def test_tune_two_step_is_plain_stepping():
 def test_tune_two_step_single_only_where_not_built():
     nx, ny = 96, 48
     rho0 = I.drop_field(nx, ny, 14.0)
-    L = lbm.Lattice(lbm.lbm_params_default(nx=nx, ny=ny, storage=lbm.STORE_F64), rho0)
+    L = lbm.Lattice(lbm.lbm_params_default(nx=nx, ny=ny, storage=lbm.STORE_F32X), rho0)
     v, ms = L.tune_two_step(2)
     assert v == -1 and L.two_step == -1
     assert np.all(np.isinf(ms[:-1])) and np.isfinite(ms[-1])
