@@ -131,6 +131,10 @@ def _step_dispatch_key(name):
         # <S, C, WALL, TS, OH, WPS, ONE>
         args = [a.strip() for a in name.split("k_step_pass2<")[1].split(">")[0].split(",")]
         return f"pass2v{PASS2_GEOMETRY.index((int(args[3]), int(args[4]), int(args[5])))}"
+    if "k_step_pass2_batch<" in name:
+        # <TS, OH, WPS>
+        args = [int(a) for a in name.split("k_step_pass2_batch<")[1].split(">")[0].split(",")]
+        return f"batch_pass2v{PASS2_GEOMETRY.index(tuple(args))}"
     if "k_march_q21<" in name:
         return 1
     if "k_tile_q21<" in name:
@@ -171,8 +175,7 @@ def ingest_counters(fetch_dir, write_dir, workload, storage, out_json, valu_dir=
     wb, wc = per_key(write_dir)
     fs, ws = COPY_REF_BYTES / 1024 / fc, COPY_REF_BYTES / 1024 / wc
     q = workload_q(workload)
-    nx, ny, _ = WORKLOADS[workload]
-    alg = bytes_per_update(storage, q) // 2 * nx * ny
+    alg = bytes_per_update(storage, q) // 2 * workload_nodes(workload)
     data = {}
     if os.path.exists(out_json):
         with open(out_json) as fh:
@@ -184,6 +187,8 @@ def ingest_counters(fetch_dir, write_dir, workload, storage, out_json, valu_dir=
           "WRITE_SIZE KiB | write / compulsory | total / compulsory |")
     print("|---|---|---|---|---|---|---|---|")
     for k in sorted(fb, key=str):
+        if (workload == "ensemble256") != str(k).startswith("batch_"):
+            continue        # the ensemble's batch kernel only; single lattices' kernels only
         f = sum(fb[k]) / len(fb[k])
         w = sum(wb[k]) / len(wb[k])
         rd, wr = f * fs * 1024, w * ws * 1024
@@ -219,23 +224,26 @@ def counter_table(run_dirs, workload=None):
         for r in _counter_rows(d):
             vals[_short_kernel(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
     nodes = None
-    if workload is not None and workload in WORKLOADS:
-        nx, ny, _ = WORKLOADS[workload]
-        nodes = nx * ny
+    if workload is not None and (workload in WORKLOADS or workload == "ensemble256"):
+        nodes = workload_nodes(workload)
     out = {}
     print("| Kernel | counter | dispatches | mean per dispatch | per lattice update |")
     print("|---|---|---|---|---|")
     for k in sorted(vals):
         if not (k.startswith("k_step") or k.startswith("k_march") or k.startswith("k_tile")):
             continue
-        ups = 2 if k.startswith("k_step_pass2<") else 1
+        ups = 2 if k.startswith("k_step_pass2") else 1
+        # per lattice update: single-lattice kernels of a single-lattice
+        # workload, or the two-step batch kernel (one launch over every
+        # lattice) of the ensemble
+        whole = ("batch" in k) == (workload == "ensemble256") and not k.startswith("k_step_tiles_batch")
         out[k] = {}
         for c in sorted(vals[k]):
             v = vals[k][c]
             m = sum(v) / len(v)
             out[k][c] = m
             per = ""
-            if nodes and c.startswith("SQ_INSTS") and "batch" not in k:
+            if nodes and c.startswith("SQ_INSTS") and whole:
                 per = f"{m * 64 / (nodes * ups):.1f}"
             print(f"| `{k}` | {c} | {len(v)} | {m:,.0f} | {per} |")
         if "SQ_INSTS_VALU" in out[k] and "GRBM_GUI_ACTIVE" in out[k]:
@@ -303,6 +311,19 @@ Q21_TILE = {0: "tiles of 16 waves x 2 rows: 58 output columns x 26 output rows p
 
 def workload_q(name):
     return 21 if name.endswith("_q21") else 9
+
+
+ENSEMBLE_SEED, ENSEMBLE_COUNT = 0, 256
+
+
+def workload_nodes(name):
+    """Lattice nodes of a single-lattice workload, or of all lattices of the
+    256-drop ensemble."""
+    if name == "ensemble256":
+        from paper_1202_6130_amd import inputs as I
+        return sum(c.nx * c.ny for c in I.ensemble_cases(seed=ENSEMBLE_SEED, count=ENSEMBLE_COUNT))
+    nx, ny, _ = WORKLOADS[name]
+    return nx * ny
 
 
 def make_lattice(name, storage, seg_rows, tau=1.0, collision=0):
@@ -586,10 +607,14 @@ def cpu_baseline_omp(q=9, threads=None, seconds_hint=10.0):
             "sample": f"same 1024x1024 lattice, {s} steps"}
 
 
-def ensemble(steps, seq_steps, seed=0, count=256, chunk=100, tune_steps=5, two_step=None):
+def ensemble(steps, seq_steps, seed=ENSEMBLE_SEED, count=ENSEMBLE_COUNT, chunk=100, tune_steps=5, two_step=None,
+             traffic_json=None, copy_ref=False):
     """Batched ensemble of `count` sessile drops of uneven size and wall
     parameters: one launch per time step over all lattices, replayed from a
-    HIP graph, against the same lattices stepped one after another alone."""
+    HIP graph, against the same lattices stepped one after another alone.
+    With two steps per launch (one kernel over every lattice) the roofline's
+    traffic is the HBM bytes of one launch recorded from rocprofv3 counters of
+    the same ensemble, when current."""
     import torch
     from paper_1202_6130_amd import inputs as I
     from paper_1202_6130_amd import lbm
@@ -620,6 +645,11 @@ def ensemble(steps, seq_steps, seed=0, count=256, chunk=100, tune_steps=5, two_s
     diag = B.diagnostics()
     bad = int(diag[:, 5].sum())
     B.close()
+    if copy_ref:
+        copy_reference()
+    traffic = None
+    if traffic_json and (seed, count) == (ENSEMBLE_SEED, ENSEMBLE_COUNT) and variant >= 0:
+        traffic = stored_traffic(traffic_json, traffic_key("ensemble256", "f32", f"batch_pass2v{variant}"))
     # sequential baseline: each lattice alone, plain launches, seq_steps steps
     seq_ms = 0.0
     for p, rho, shape in zip(ps, rhos, shapes):
@@ -648,7 +678,7 @@ def ensemble(steps, seq_steps, seed=0, count=256, chunk=100, tune_steps=5, two_s
                        None if two_ms is None else [round(float(v), 4) for v in two_ms]},
         "mlups": round(nodes * steps / (ms_batch * 1e-3) / 1e6, 1),
         "roofline": {"bound": "hbm", "achieved": round(ens_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ens_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(ens_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_step_pass2_batch" if variant >= 0 else "k_step_tiles_batch",
                      "updates_per_launch": upl, "launch_ms_mean": round(ms_batch / launches, 5),
                      "algorithmic_bytes_per_launch": 72 * nodes,
@@ -1040,7 +1070,8 @@ def main():
         sys.exit(2)
 
     if args.workload == "ensemble256":
-        print(json.dumps(ensemble(args.steps, args.seq_steps, two_step=args.two_step)), flush=True)
+        print(json.dumps(ensemble(args.steps, args.seq_steps, two_step=args.two_step, traffic_json=args.traffic_json,
+                                  copy_ref=args.copy_ref)), flush=True)
         return
     if args.serve_combine:
         print(json.dumps(serving_combine(args.serve_combine, args.requests, args.max_steps, args.serve_tol,

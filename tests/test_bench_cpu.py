@@ -32,6 +32,7 @@ def test_step_dispatch_names():
              "void*)") == "pass2v8"
     assert k("void lbmwet::k_step_pass2<float, float, 1, 2, 8, 4, 0>(lbmwet::LatDev<float>, void const*, "
              "void*)") == "pass2v2"
+    # single-step batches launch one kernel per tile shape over a subset of the lattices: not keyed
     assert k("void lbmwet::k_step_tiles_batch<float, float, 0, 5>(lbmwet::LatDev<float> const*, uint4 const*, int)") \
         is None
     assert k("void lbmwet::(anonymous namespace)::k_march_q21<0, 1, 1>(lbmwet::LatDev<float>, float const*, "
@@ -51,7 +52,10 @@ def test_step_dispatch_names():
         == "pass2v7"
     assert k("void lbmwet::k_step_pass2<__half, float, 1, 2, 8, 4>(lbmwet::LatDev<float>, void const*, void*)") \
         == "pass2v2"
-    assert k("void lbmwet::k_step_pass2_batch<1, 24, 12>(lbmwet::LatDev<float> const*, uint4 const*, int)") is None
+    assert k("void lbmwet::k_step_pass2_batch<1, 24, 12>(lbmwet::LatDev<float> const*, uint4 const*, int)") \
+        == "batch_pass2v8"
+    assert k("void lbmwet::k_step_pass2_batch<2, 8, 4>(lbmwet::LatDev<float> const*, uint4 const*, int)") \
+        == "batch_pass2v2"
     assert bench.traffic_key("spinodal4096", "f32", "pass2v7") == "spinodal4096:f32:pass2v7"
     assert bench.PASS2_GEOMETRY == [(s, r, w // s) for s, r, w in
                                     [(1, 8, 4), (1, 8, 8), (2, 8, 8), (1, 12, 6), (1, 12, 12), (1, 16, 8),
@@ -98,6 +102,27 @@ def test_ingest_counters(tmp_path):
     data["spinodal4096:f32:shape8"]["kernel_sources_sha256"] = "0" * 64
     out.write_text(json.dumps(data))
     assert bench.stored_traffic(str(out), "spinodal4096:f32:shape8") is None
+
+
+def test_ingest_counters_ensemble(tmp_path, capsys):
+    """The ensemble's two-step batch kernel is keyed by variant; compulsory
+    bytes count every lattice's nodes."""
+    p2 = "void lbmwet::k_step_pass2_batch<1, 24, 8>(lbmwet::LatDev<float> const*, uint4 const*, int)"
+    t4 = "void lbmwet::k_step_tiles_batch<float, float, 0, 4>(lbmwet::LatDev<float> const*, uint4 const*, int)"
+    nodes = bench.workload_nodes("ensemble256")
+    assert nodes == 44916736
+    one = "void lbmwet::k_step_pass2<float, float, 0, 1, 24, 8, 1>(lbmwet::LatDev<float>, void const*, void*)"
+    _write_run(str(tmp_path / "f"), "FETCH_SIZE", 524288.0,
+               [(p2, nodes * 36 / 1024 / 2 * 1.5), (t4, 1000.0), (one, 50.0)])
+    _write_run(str(tmp_path / "w"), "WRITE_SIZE", 1048576.0, [(p2, nodes * 36 / 1024), (t4, 2000.0), (one, 60.0)])
+    out = tmp_path / "traffic.json"
+    bench.ingest_counters(str(tmp_path / "f"), str(tmp_path / "w"), "ensemble256", "f32", str(out))
+    data = json.loads(out.read_text())
+    rec = data["ensemble256:f32:batch_pass2v7"]
+    assert rec["read_bytes"] == round(nodes * 36 * 1.5) and rec["write_bytes"] == nodes * 36
+    assert "| batch_pass2v7 | 1 |" in capsys.readouterr().out
+    # the sequential leg's single-lattice launches are not the ensemble's kernel
+    assert sorted(data) == ["ensemble256:f32:batch_pass2v7"]
 
 
 def test_counter_table(tmp_path, capsys):
