@@ -149,3 +149,40 @@ def test_f16dev_saturation_counts_as_unstable():
     ok[5, 12, 30] = ok[2, 20, 7] = False
     assert np.abs(g[ok] - f[ok]).max() < 1e-12
     L.close()
+
+
+@pytest.mark.parametrize("storage", [lbm.STORE_F32, lbm.STORE_F16DEV])
+def test_zero_and_negative_step_counts(storage):
+    """lbm_step with nsteps = 0 leaves the state and the step index as they
+    were (with or without a residual request); a negative count is
+    LBM_EINVAL and changes nothing.  The batch call likewise, and rejects an
+    odd graph chunk."""
+    p, _, _, rho0 = drop(storage, K=10)
+    L = lbm.Lattice(p, rho0)
+    L.step(7)
+    f = L.get_state()
+    L.step(0)
+    assert L.step_index == 7 and np.array_equal(L.get_state(), f)
+    r = ctypes.c_double(-1.0)
+    assert lbm.lib().lbm_step(L.ctx, 0, ctypes.byref(r)) == lbm.LBM_OK
+    assert L.step_index == 7 and np.array_equal(L.get_state(), f)
+    assert lbm.lib().lbm_step(L.ctx, -1, None) == lbm.LBM_EINVAL
+    assert "nsteps" in lbm.lib().lbm_last_error(L.ctx).decode()
+    assert L.step_index == 7 and np.array_equal(L.get_state(), f)
+    L.close()
+    if storage != lbm.STORE_F32:
+        return
+    ps = [lbm.lbm_params_default(nx=64, ny=32, wall_kind=lbm.WALL_FLAT_SLAB, G_R=0.5, G_A=0.3),
+          lbm.lbm_params_default(nx=96, ny=64, wall_kind=lbm.WALL_FLAT_SLAB, G_R=0.2, G_A=0.1)]
+    rhos = [I.drop_field(64, 32, 12.0), I.drop_field(96, 64, 18.0)]
+    B = lbm.Batch(ps, rhos)
+    B.step(4)
+    before = [B.lattice(k).get_state() for k in range(2)]
+    B.step(0)
+    for bad in ((-2, 0), (4, 3)):
+        with pytest.raises(lbm.LbmError) as e:
+            B.step(*bad)
+        assert e.value.code == lbm.LBM_EINVAL
+    for k in range(2):
+        assert np.array_equal(B.lattice(k).get_state(), before[k])
+    B.close()
